@@ -1,0 +1,177 @@
+/*
+ * qiral.h -- C ABI of the MI355X (gfx950) even-odd Wilson-Dirac library.
+ *
+ * The problem statement follows the goal of the paper (Barthou et al.,
+ * arXiv:1401.2039, Sec. 2): xx[L (x) C (x) S] = Dirac^{-1} * bb[L (x) C (x) S],
+ * with Dirac the Wilson operator of Fig. "dirac", solved by the CGNR template
+ * (Fig. "CG") composed with the Schur-complement template ("schur").  The
+ * paper's generated function takes bb and xx and keeps every other constant
+ * (lattice, kappa, links) global; here those constants live in an opaque
+ * lattice handle.
+ *
+ * Conventions (all calls):
+ *   dims[4] = {Lx, Ly, Lz, Lt}; every L_mu must be even and >= 2 (the
+ *   checkerboard index needs even extents).  Direction mu = 0..3 = x, y, z, t.
+ *   Periodic boundaries in all four directions (Fig. "id": isPeriodic(L)).
+ *   Parity of a site = (x + y + z + t) mod 2, even = 0.
+ *
+ *   Canonical gauge field: device memory, complex128 (re, im interleaved
+ *   doubles), index order [t][z][y][x][mu][row][col]; U[x][mu] is the link
+ *   from x to x + mu_hat; the backward link is its adjoint one site back.
+ *   Canonical spinor field: device memory, complex128, index order
+ *   [rhs][t][z][y][x][colour][spin] (spin fastest).
+ *
+ *   Internal ("packed") fields are opaque device buffers whose size is given
+ *   by qiral_field_bytes().  A half-field holds the sites of one parity; a
+ *   full field is the even half followed by the odd half; nrhs fields follow
+ *   one another.  Storage classes: QIRAL_F64 (complex128), QIRAL_F32
+ *   (complex64) and QIRAL_F16S (FP16 with one FP32 scale per site).
+ *
+ *   Streams: every call that takes a stream enqueues its GPU work on it and
+ *   returns without waiting, except qiral_lattice_create, qiral_solve and
+ *   qiral_solve_batch, which synchronise the stream before returning.  A NULL
+ *   stream is the default stream.
+ *
+ *   Errors: every call returns a status.  All argument checks run before any
+ *   HIP call, so an invalid call has no effect on the device.  No C++
+ *   exception crosses the ABI.  qiral_last_error() gives a thread-local
+ *   description of the last failure.
+ *
+ *   Memory: a lattice handle owns the device memory of its packed links and
+ *   of the solver workspace (grown on demand, released by
+ *   qiral_lattice_destroy).  Every other device buffer belongs to the caller.
+ *   Calls on one handle must not overlap in time (they share its workspace).
+ */
+#ifndef QIRAL_H
+#define QIRAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;
+typedef struct ihipStream_t *qiral_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+  QIRAL_OK = 0,
+  QIRAL_ERR_INVALID_ARG = 1,   /* null pointer, bad enum, nrhs < 1, ...            */
+  QIRAL_ERR_BAD_DIMS = 2,      /* an extent odd or < 2, or the lattice too large    */
+  QIRAL_ERR_UNSUPPORTED = 3,   /* valid request this build does not implement       */
+  QIRAL_ERR_HIP = 4,           /* a HIP runtime call failed (text in last_error)    */
+  QIRAL_ERR_NOT_CONVERGED = 5, /* tolerance not met within maxiter; x and info hold
+                                  the last iterate and its residual                */
+  QIRAL_ERR_NONFINITE = 6,     /* a NaN or Inf appeared in a reduction              */
+  QIRAL_ERR_WORKSPACE = 7      /* device memory for the workspace not available    */
+} qiral_status;
+
+typedef enum { QIRAL_F64 = 0, QIRAL_F32 = 1, QIRAL_F16S = 2 } qiral_prec;
+typedef enum { QIRAL_RECON18 = 18, QIRAL_RECON12 = 12 } qiral_recon;
+typedef enum { QIRAL_EVEN = 0, QIRAL_ODD = 1, QIRAL_FULL = 2 } qiral_subset;
+typedef enum {
+  QIRAL_OP_D = 0,        /* full-lattice D = 1 - kappa H                           */
+  QIRAL_OP_DDAG = 1,     /* D^dagger = 1 - kappa H^dagger                          */
+  QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = 1 - kappa^2 H_oe H_eo    */
+  QIRAL_OP_SCHUR_DAG = 3 /* S^dagger = 1 - kappa^2 H^dagger_oe H^dagger_eo         */
+} qiral_op;
+typedef enum {
+  QIRAL_CGNR_EO = 0,     /* CGNR (Fig. "CG") on the Schur system ("schur" template) */
+  QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system      */
+  QIRAL_FGMRES_NN = 2    /* FGMRES(m) on D with the learned preconditioner          */
+} qiral_solver;
+
+/* Bit i of lo_precs asks lattice_create for a packed link store of precision i. */
+#define QIRAL_LINKS_F32 (1u << QIRAL_F32)
+#define QIRAL_LINKS_F16 (1u << QIRAL_F16S)
+
+typedef struct qiral_lattice qiral_lattice; /* opaque, host-side */
+typedef struct qiral_nn qiral_nn;           /* opaque, learned preconditioner */
+
+const char *qiral_status_string(qiral_status s);
+const char *qiral_last_error(void);
+
+/* Bytes of a packed field: sites of one parity (EVEN/ODD) or both (FULL), padded
+ * to whole 64-site blocks, times nrhs.  Returns 0 on invalid arguments. */
+size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec prec, int32_t nrhs);
+
+/* Create a lattice: packs the canonical links (device, complex128, see above)
+ * into an FP64 reconstruct-18 store and, for each bit of lo_precs, a
+ * reduced-precision store (FP32 or FP16 links, lo_recon = 12 keeps rows 0 and 1
+ * and rebuilds row 2 = conj(row0 x row1), exact for SU(3)).  gauge_canon may be
+ * freed once the call returns.  kappa is the hopping parameter of Fig. "dirac";
+ * mu is its twisted-mass parameter: mu != 0 returns QIRAL_ERR_UNSUPPORTED. */
+qiral_status qiral_lattice_create(qiral_lattice **lat, const int32_t dims[4], double kappa, double mu,
+                                  const double *gauge_canon, uint32_t lo_precs, qiral_recon lo_recon,
+                                  qiral_stream_t stream);
+qiral_status qiral_lattice_destroy(qiral_lattice *lat);
+/* Sites per parity and bytes of device memory held by the handle. */
+qiral_status qiral_lattice_query(const qiral_lattice *lat, int64_t *sites_per_parity, int64_t *device_bytes);
+
+/* Canonical (device complex128, [rhs][t][z][y][x][c][s]) <-> packed.  Import reads
+ * the sites of the subset and writes dst; export writes only the canonical sites
+ * of the subset and leaves the others untouched.  F16S import quantises each
+ * site as: reals rounded to FP32, scale = max |real|, half = RNE(real / scale). */
+qiral_status qiral_field_import(const qiral_lattice *lat, void *dst, const double *src_canon,
+                                qiral_subset subset, qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
+qiral_status qiral_field_export(const qiral_lattice *lat, double *dst_canon, const void *src,
+                                qiral_subset subset, qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
+
+/* Hopping term between the parities (the 8-neighbour stencil of Fig. "dirac"):
+ *   out = H_{p,1-p} in        with p = out_parity, in a half-field of parity 1-p,
+ *   H psi(x) = sum_mu (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu);
+ * dagger != 0 applies H^dagger = g5 H g5 instead.  in and out are packed
+ * half-fields of precision prec (links of the same precision must exist), nrhs
+ * consecutive fields each; they must not overlap. */
+qiral_status qiral_dslash_eo(const qiral_lattice *lat, void *out, const void *in, int32_t out_parity,
+                             int32_t dagger, qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
+
+/* out = op(in) for packed fields of precision prec: FULL fields for OP_D/OP_DDAG,
+ * ODD half-fields for OP_SCHUR/OP_SCHUR_DAG.  tmp is an EVEN half-field of the
+ * same precision and nrhs (used by the Schur ops; may be NULL for D/D^dagger). */
+qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, void *tmp, qiral_op op,
+                           qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
+
+typedef struct {
+  qiral_solver solver; /* QIRAL_CGNR_EO (default) or QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN        */
+  double tol;          /* relative FP64 residual ||b - D x|| / ||b|| to reach (e.g. 1e-10)   */
+  int32_t maxiter;     /* iteration limit (outer iterations of the solver)                    */
+  qiral_prec inner_prec; /* F64: plain solve.  F32/F16S: reduced-precision iterations with
+                            FP64 reliable updates; needs links of that precision             */
+  double delta;        /* reliable-update trigger: ||r|| < delta * max ||r|| since last one   */
+  int32_t restart;     /* FGMRES restart length m                                            */
+  const qiral_nn *precond; /* learned preconditioner for QIRAL_FGMRES_NN                       */
+  int32_t fallback_cg; /* FGMRES: on stagnation continue with eo-CGNR from the current x      */
+  int32_t x0_is_guess; /* start from the x passed in instead of 0                              */
+  int32_t use_graph;   /* capture the iteration in a HIP graph and replay it                   */
+  int32_t check_every; /* iterations enqueued between convergence checks (0: automatic)        */
+} qiral_solve_params;
+
+typedef struct {
+  int32_t iterations;        /* solver iterations                                   */
+  int32_t reliable_updates;  /* FP64 residual replacements (mixed precision)        */
+  int32_t converged;         /* 1 if true_rel_resid <= tol                          */
+  int32_t fell_back;         /* FGMRES switched to CGNR                             */
+  double true_rel_resid;     /* ||b - D x|| / ||b|| recomputed in FP64 at the end   */
+  double seconds;            /* wall time of the call                               */
+  int64_t hop_applications;  /* H_eo / H_oe applications (units of V/2 sites)       */
+} qiral_solve_info;
+
+/* Solve D x = b for nrhs right-hand sides on one lattice.  x_canon and b_canon are
+ * canonical full fields (device); info points to nrhs host structs.  Blocking:
+ * returns after the stream has drained.  Returns QIRAL_ERR_NOT_CONVERGED if any
+ * right-hand side missed the tolerance. */
+qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                         const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream);
+
+/* Solve nsys independent systems D_i x_i = b_i (one right-hand side each, each on
+ * its own lattice, of any size) in one set of grouped launches. */
+qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_canon, const double *const *b_canon,
+                               int32_t nsys, const qiral_solve_params *params, qiral_solve_info *info,
+                               qiral_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QIRAL_H */

@@ -1,0 +1,105 @@
+"""ctypes binding of libqiral_hip.so: argument marshalling only.
+
+Every function here forwards to the C ABI declared in include/qiral.h with the
+same name; all work runs in the library's HIP kernels.  torch is imported first
+so that the library binds to the HIP runtime torch already loaded (both carry
+the soname libamdhip64.so.7), and torch provides device memory and streams.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading the library: shared HIP runtime)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqiral_hip.so")
+
+# enums (include/qiral.h)
+OK, ERR_INVALID_ARG, ERR_BAD_DIMS, ERR_UNSUPPORTED, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_WORKSPACE = range(8)
+F64, F32, F16S = 0, 1, 2
+RECON18, RECON12 = 18, 12
+EVEN, ODD, FULL = 0, 1, 2
+OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG = 0, 1, 2, 3
+CGNR_EO, BICGSTAB_EO, FGMRES_NN = 0, 1, 2
+LINKS_F32, LINKS_F16 = 1 << F32, 1 << F16S
+
+STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR_BAD_DIMS",
+                ERR_UNSUPPORTED: "ERR_UNSUPPORTED", ERR_HIP: "ERR_HIP", ERR_NOT_CONVERGED: "ERR_NOT_CONVERGED",
+                ERR_NONFINITE: "ERR_NONFINITE", ERR_WORKSPACE: "ERR_WORKSPACE"}
+
+# Every function the header declares (checked by the tests against the library's exports).
+EXPORTS = [
+    "qiral_status_string", "qiral_last_error", "qiral_field_bytes", "qiral_lattice_create",
+    "qiral_lattice_destroy", "qiral_lattice_query", "qiral_field_import", "qiral_field_export",
+    "qiral_dslash_eo", "qiral_apply_M", "qiral_solve", "qiral_solve_batch",
+]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int), ("delta", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("precond", ctypes.c_void_p), ("fallback_cg", ctypes.c_int32), ("x0_is_guess", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("fell_back", ctypes.c_int32),
+                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("hop_applications", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class QiralError(RuntimeError):
+    def __init__(self, status, func, detail):
+        self.status = status
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(or python -m paper_1401_2039_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dims_t = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "qiral_status_string": (ctypes.c_char_p, [I]),
+        "qiral_last_error": (ctypes.c_char_p, []),
+        "qiral_field_bytes": (S, [dims_t, I, I, I]),
+        "qiral_lattice_create": (I, [ctypes.POINTER(P), dims_t, D, D, P, ctypes.c_uint32, I, P]),
+        "qiral_lattice_destroy": (I, [P]),
+        "qiral_lattice_query": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "qiral_field_import": (I, [P, P, P, I, I, I, P]),
+        "qiral_field_export": (I, [P, P, P, I, I, I, P]),
+        "qiral_dslash_eo": (I, [P, P, P, I, I, I, I, P]),
+        "qiral_apply_M": (I, [P, P, P, P, I, I, I, P]),
+        "qiral_solve": (I, [P, P, P, I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
+        "qiral_solve_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I,
+                                  ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status, func):
+    if status != OK:
+        detail = load().qiral_last_error().decode(errors="replace")
+        raise QiralError(status, func, detail)
+    return status
+
+
+def dims_arg(dims):
+    return (ctypes.c_int32 * 4)(*[int(d) for d in dims])

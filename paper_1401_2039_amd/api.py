@@ -1,0 +1,179 @@
+"""Python-side names of the C ABI (include/qiral.h), taking torch tensors.
+
+Canonical fields are contiguous complex128 CUDA tensors shaped
+(nrhs, Lt, Lz, Ly, Lx, 3, 4) (colour, spin); canonical links are contiguous
+complex128 CUDA tensors shaped (Lt, Lz, Ly, Lx, 4, 3, 3).  Packed fields are
+uint8 CUDA tensors of qiral_field_bytes() bytes.  These wrappers check tensor
+types and sizes, pass raw pointers and the current torch stream, and raise
+QiralError on a non-OK status; they compute nothing themselves.
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _need_cuda(t, name, dtype=None, nbytes=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, not {t.dtype}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _volume(dims):
+    v = 1
+    for d in dims:
+        v *= int(d)
+    return v
+
+
+def qiral_field_bytes(dims, subset, prec, nrhs=1):
+    return int(L.load().qiral_field_bytes(L.dims_arg(dims), subset, prec, nrhs))
+
+
+def qiral_lattice_create(dims, kappa, gauge_canon, lo_precs=L.LINKS_F32 | L.LINKS_F16, lo_recon=L.RECON12, mu=0.0,
+                         stream=None):
+    lib = L.load()
+    ptr = _need_cuda(gauge_canon, "gauge_canon", torch.complex128, _volume(dims) * 4 * 9 * 16)
+    h = ctypes.c_void_p()
+    L.check(lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), float(kappa), float(mu), ptr,
+                                     int(lo_precs), int(lo_recon), _stream(stream)), "qiral_lattice_create")
+    return h.value
+
+
+def qiral_lattice_destroy(handle):
+    L.check(L.load().qiral_lattice_destroy(ctypes.c_void_p(handle)), "qiral_lattice_destroy")
+
+
+def qiral_field_import(handle, dims, dst, src_canon, subset, prec, nrhs=1, stream=None):
+    need = qiral_field_bytes(dims, subset, prec, nrhs)
+    d = _need_cuda(dst, "dst", nbytes=need)
+    s = _need_cuda(src_canon, "src_canon", torch.complex128, _volume(dims) * 12 * 16 * nrhs)
+    L.check(L.load().qiral_field_import(ctypes.c_void_p(handle), d, s, subset, prec, nrhs, _stream(stream)),
+            "qiral_field_import")
+
+
+def qiral_field_export(handle, dims, dst_canon, src, subset, prec, nrhs=1, stream=None):
+    need = qiral_field_bytes(dims, subset, prec, nrhs)
+    d = _need_cuda(dst_canon, "dst_canon", torch.complex128, _volume(dims) * 12 * 16 * nrhs)
+    s = _need_cuda(src, "src", nbytes=need)
+    L.check(L.load().qiral_field_export(ctypes.c_void_p(handle), d, s, subset, prec, nrhs, _stream(stream)),
+            "qiral_field_export")
+
+
+def qiral_dslash_eo(handle, dims, out, inp, out_parity, dagger, prec, nrhs=1, stream=None):
+    need = qiral_field_bytes(dims, L.EVEN, prec, nrhs)
+    o = _need_cuda(out, "out", nbytes=need)
+    i = _need_cuda(inp, "in", nbytes=need)
+    L.check(L.load().qiral_dslash_eo(ctypes.c_void_p(handle), o, i, int(out_parity), int(dagger), prec, nrhs,
+                                     _stream(stream)), "qiral_dslash_eo")
+
+
+def qiral_apply_M(handle, dims, out, inp, tmp, op, prec, nrhs=1, stream=None):
+    subset = L.FULL if op in (L.OP_D, L.OP_DDAG) else L.ODD
+    need = qiral_field_bytes(dims, subset, prec, nrhs)
+    o = _need_cuda(out, "out", nbytes=need)
+    i = _need_cuda(inp, "in", nbytes=need)
+    t = ctypes.c_void_p(None) if tmp is None else _need_cuda(tmp, "tmp", nbytes=qiral_field_bytes(dims, L.EVEN, prec, nrhs))
+    L.check(L.load().qiral_apply_M(ctypes.c_void_p(handle), o, i, t, int(op), prec, nrhs, _stream(stream)),
+            "qiral_apply_M")
+
+
+def solve_params(solver=L.CGNR_EO, tol=1e-10, maxiter=10000, inner_prec=L.F64, delta=0.1, restart=20, precond=None,
+                 fallback_cg=1, x0_is_guess=0, use_graph=0, check_every=0):
+    return L.SolveParams(solver, tol, maxiter, inner_prec, delta, restart, precond, fallback_cg, x0_is_guess,
+                         use_graph, check_every)
+
+
+def qiral_solve(handle, dims, x_canon, b_canon, nrhs, params, stream=None):
+    n = _volume(dims) * 12 * 16 * nrhs
+    x = _need_cuda(x_canon, "x_canon", torch.complex128, n)
+    b = _need_cuda(b_canon, "b_canon", torch.complex128, n)
+    infos = (L.SolveInfo * nrhs)()
+    st = L.load().qiral_solve(ctypes.c_void_p(handle), x, b, nrhs, ctypes.byref(params), infos, _stream(stream))
+    if st not in (L.OK, L.ERR_NOT_CONVERGED):
+        L.check(st, "qiral_solve")
+    return st, [i.as_dict() for i in infos]
+
+
+def qiral_solve_batch(handles, dims_list, xs, bs, params, stream=None):
+    n = len(handles)
+    hp = (ctypes.c_void_p * n)(*handles)
+    xp = (ctypes.c_void_p * n)(*[_need_cuda(x, "x", torch.complex128, _volume(d) * 192).value
+                                 for x, d in zip(xs, dims_list)])
+    bp = (ctypes.c_void_p * n)(*[_need_cuda(b, "b", torch.complex128, _volume(d) * 192).value
+                                 for b, d in zip(bs, dims_list)])
+    infos = (L.SolveInfo * n)()
+    st = L.load().qiral_solve_batch(hp, xp, bp, n, ctypes.byref(params), infos, _stream(stream))
+    if st not in (L.OK, L.ERR_NOT_CONVERGED):
+        L.check(st, "qiral_solve_batch")
+    return st, [i.as_dict() for i in infos]
+
+
+class Lattice:
+    """A lattice handle: dims, kappa and packed links on the current CUDA device."""
+
+    def __init__(self, dims, kappa, gauge, lo_precs=L.LINKS_F32 | L.LINKS_F16, device="cuda"):
+        self.dims = tuple(int(d) for d in dims)
+        self.kappa = float(kappa)
+        g = gauge if isinstance(gauge, torch.Tensor) else torch.from_numpy(gauge)
+        g = g.to(device=device, dtype=torch.complex128).contiguous()
+        self.handle = qiral_lattice_create(self.dims, self.kappa, g, lo_precs)
+
+    def close(self):
+        if self.handle:
+            qiral_lattice_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, subset, prec, nrhs=1):
+        n = qiral_field_bytes(self.dims, subset, prec, nrhs)
+        return torch.zeros(n, dtype=torch.uint8, device="cuda")
+
+    def canon(self, nrhs=1):
+        lx, ly, lz, lt = self.dims
+        return torch.zeros((nrhs, lt, lz, ly, lx, 3, 4), dtype=torch.complex128, device="cuda")
+
+    def import_field(self, canon, subset, prec):
+        canon = canon.contiguous()
+        nrhs = canon.shape[0]
+        dst = self.field(subset, prec, nrhs)
+        qiral_field_import(self.handle, self.dims, dst, canon, subset, prec, nrhs)
+        return dst
+
+    def export_field(self, packed, subset, prec, nrhs=1, out=None):
+        out = self.canon(nrhs) if out is None else out
+        qiral_field_export(self.handle, self.dims, out, packed, subset, prec, nrhs)
+        return out
+
+    def dslash_eo(self, out, inp, out_parity, dagger, prec, nrhs=1):
+        qiral_dslash_eo(self.handle, self.dims, out, inp, out_parity, dagger, prec, nrhs)
+
+    def apply_M(self, out, inp, tmp, op, prec, nrhs=1):
+        qiral_apply_M(self.handle, self.dims, out, inp, tmp, op, prec, nrhs)
+
+    def solve(self, b_canon, x_canon=None, **kw):
+        b_canon = b_canon.contiguous()
+        nrhs = b_canon.shape[0]
+        x = self.canon(nrhs) if x_canon is None else x_canon
+        st, info = qiral_solve(self.handle, self.dims, x, b_canon, nrhs, solve_params(**kw))
+        return x, st, info

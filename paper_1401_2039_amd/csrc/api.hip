@@ -1,0 +1,445 @@
+// C ABI of the library: argument validation, lattice handles, packing of links
+// and fields, the hopping-term and operator entry points.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "qiral_int.h"
+
+using namespace qiral;
+
+// ---------------------------------------------------------------------------
+// errors
+namespace qiral {
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+qiral_status hip_fail(hipError_t e, const char *what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return QIRAL_ERR_HIP;
+}
+}  // namespace qiral
+
+extern "C" const char *qiral_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *qiral_status_string(qiral_status s) {
+  switch (s) {
+    case QIRAL_OK: return "ok";
+    case QIRAL_ERR_INVALID_ARG: return "invalid argument";
+    case QIRAL_ERR_BAD_DIMS: return "bad lattice dimensions";
+    case QIRAL_ERR_UNSUPPORTED: return "unsupported";
+    case QIRAL_ERR_HIP: return "HIP runtime error";
+    case QIRAL_ERR_NOT_CONVERGED: return "not converged";
+    case QIRAL_ERR_NONFINITE: return "non-finite value";
+    case QIRAL_ERR_WORKSPACE: return "workspace allocation failed";
+  }
+  return "unknown status";
+}
+
+static qiral_status fail(qiral_status s, const char *msg) {
+  set_error(msg);
+  return s;
+}
+
+static qiral_status check_dims(const int32_t *d) {
+  if (!d) return fail(QIRAL_ERR_INVALID_ARG, "dims is NULL");
+  int64_t v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (d[i] < 2 || (d[i] & 1)) return fail(QIRAL_ERR_BAD_DIMS, "every lattice extent must be even and >= 2");
+    v *= d[i];
+  }
+  if (v / 2 > (1ll << 30)) return fail(QIRAL_ERR_BAD_DIMS, "lattice too large (more than 2^30 sites per parity)");
+  return QIRAL_OK;
+}
+
+static bool valid_prec(int p) { return p == QIRAL_F64 || p == QIRAL_F32 || p == QIRAL_F16S; }
+
+namespace qiral {
+static size_t site_bytes(int prec) {
+  return prec == QIRAL_F64 ? SpinorIO<S_F64>::SITE_BYTES
+       : prec == QIRAL_F32 ? SpinorIO<S_F32>::SITE_BYTES : SpinorIO<S_F16S>::SITE_BYTES;
+}
+size_t half_bytes(const Geo &g, int prec) { return npad_of(g) * site_bytes(prec); }
+const void *links_for(const qiral_lattice *lat, int prec) {
+  return prec == QIRAL_F64 ? lat->g64 : prec == QIRAL_F32 ? lat->g32 : lat->g16;
+}
+qiral_status ensure_workspace(qiral_lattice *lat, size_t bytes) {
+  if (bytes <= lat->ws_bytes) return QIRAL_OK;
+  if (lat->ws) {
+    hipError_t e = hipFree(lat->ws);
+    lat->ws = nullptr;
+    lat->ws_bytes = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+  }
+  hipError_t e = hipMalloc(&lat->ws, bytes);
+  if (e != hipSuccess) {
+    lat->ws = nullptr;
+    set_error(std::string("hipMalloc(workspace): ") + hipGetErrorString(e));
+    return QIRAL_ERR_WORKSPACE;
+  }
+  lat->ws_bytes = bytes;
+  return QIRAL_OK;
+}
+}  // namespace qiral
+
+extern "C" size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec prec, int32_t nrhs) {
+  if (check_dims(dims) != QIRAL_OK || !valid_prec(prec) || nrhs < 1) return 0;
+  if (subset != QIRAL_EVEN && subset != QIRAL_ODD && subset != QIRAL_FULL) return 0;
+  Geo g = make_geo(dims);
+  size_t h = half_bytes(g, prec);
+  return (subset == QIRAL_FULL ? 2 * h : h) * (size_t)nrhs;
+}
+
+// ---------------------------------------------------------------------------
+// kernels: packing
+__device__ __forceinline__ void site_coords(const Geo &g, int s, int p, int &x, int &y, int &z, int &t) {
+  int xh = s % g.lxh;
+  int r = s / g.lxh;
+  y = r % g.ly; r /= g.ly;
+  z = r % g.lz;
+  t = r / g.lz;
+  x = 2 * xh + ((p + y + z + t) & 1);
+}
+
+__device__ __forceinline__ size_t lex_of(const Geo &g, int x, int y, int z, int t) {
+  return (((size_t)t * g.lz + z) * g.ly + y) * g.lx + x;
+}
+
+template <int L>
+__global__ __launch_bounds__(WG) void k_pack_gauge(Geo g, const double *__restrict__ canon, void *__restrict__ dst) {
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 8 * npad) return;
+  const int s = (int)(i % npad);
+  const int pm = (int)(i / npad);   // parity * 4 + mu
+  const int p = pm >> 2, mu = pm & 3;
+  if (s >= g.vh) return;
+  int x, y, z, t;
+  site_coords(g, s, p, x, y, z, t);
+  const double *src = canon + (lex_of(g, x, y, z, t) * 4 + mu) * 18;
+  const size_t blk = (size_t)pm * g.nb + (s >> 6);
+  if (L == L_F64R18) {
+    double2 *d = (double2 *)dst + blk * 9 * WAVE + (s & 63);
+    for (int j = 0; j < 9; ++j) d[j * WAVE] = make_double2(src[2 * j], src[2 * j + 1]);
+  } else if (L == L_F32R12) {
+    float4 *d = (float4 *)dst + blk * 3 * WAVE + (s & 63);
+    for (int j = 0; j < 3; ++j)
+      d[j * WAVE] = make_float4((float)src[4 * j], (float)src[4 * j + 1], (float)src[4 * j + 2], (float)src[4 * j + 3]);
+  } else {
+    uint2 *d = (uint2 *)dst + blk * 3 * WAVE + (s & 63);
+    for (int j = 0; j < 3; ++j) {
+      unsigned a = f2h((float)src[4 * j]) | ((unsigned)f2h((float)src[4 * j + 1]) << 16);
+      unsigned b = f2h((float)src[4 * j + 2]) | ((unsigned)f2h((float)src[4 * j + 3]) << 16);
+      d[j * WAVE] = make_uint2(a, b);
+    }
+  }
+}
+
+// Note on FP16 links: each real is rounded FP64 -> FP32 -> FP16, both steps RNE.
+
+template <int S>
+__global__ __launch_bounds__(WG) void k_import(Geo g, const double *__restrict__ canon, size_t canon_stride,
+                                               void *__restrict__ dst, size_t dst_stride, int p, int nrhs) {
+  using R = typename SpinorIO<S>::R;
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad * nrhs) return;
+  const int s = (int)(i % npad);
+  const int r = (int)(i / npad);
+  cpx<R> v[12];
+  if (s < g.vh) {
+    int x, y, z, t;
+    site_coords(g, s, p, x, y, z, t);
+    const double2 *src = (const double2 *)(canon + r * canon_stride) + lex_of(g, x, y, z, t) * 12;
+    for (int k = 0; k < 12; ++k) { double2 q = src[k]; v[k] = cmake((R)q.x, (R)q.y); }
+  } else {
+    for (int k = 0; k < 12; ++k) v[k] = cmake((R)0, (R)0);
+  }
+  SpinorIO<S>::store((char *)dst + r * dst_stride, s, npad, v);
+}
+
+template <int S>
+__global__ __launch_bounds__(WG) void k_export(Geo g, double *__restrict__ canon, size_t canon_stride,
+                                               const void *__restrict__ src, size_t src_stride, int p, int nrhs) {
+  using R = typename SpinorIO<S>::R;
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad * nrhs) return;
+  const int s = (int)(i % npad);
+  const int r = (int)(i / npad);
+  if (s >= g.vh) return;
+  cpx<R> v[12];
+  SpinorIO<S>::load((const char *)src + r * src_stride, s, npad, v);
+  int x, y, z, t;
+  site_coords(g, s, p, x, y, z, t);
+  double2 *d = (double2 *)(canon + r * canon_stride) + lex_of(g, x, y, z, t) * 12;
+  for (int k = 0; k < 12; ++k) d[k] = make_double2((double)v[k].re, (double)v[k].im);
+}
+
+// ---------------------------------------------------------------------------
+// kernel: hopping term on one lattice, nrhs consecutive fields.  Work-group L
+// (after the XCD remap) handles right-hand side L % nrhs and four consecutive
+// 64-site blocks, so the work-groups that run together on one XCD share links.
+template <int S, int L, bool DAG, int EPI>
+__global__ __launch_bounds__(WG) void k_hop(Geo g, const void *__restrict__ gauge, const void *__restrict__ in,
+                                            void *__restrict__ out, const void *__restrict__ xin, size_t fstride,
+                                            int nrhs, int p, double a) {
+  using R = typename SpinorIO<S>::R;
+  const int nwg = gridDim.x;
+  const int wg = xcd_remap(blockIdx.x, nwg);
+  const int rhs = wg % nrhs;
+  const int sb = (wg / nrhs) * 4 + (threadIdx.x >> 6);
+  if (sb >= g.nb) return;
+  const int s = sb * WAVE + lane_id();
+  if (s >= g.vh) return;
+  const size_t npad = (size_t)g.nb * WAVE;
+  cpx<R> acc[12];
+  FieldLd<S> ld{(const char *)in + rhs * fstride, npad};
+  hop_site<L, DAG>(g, gauge, ld, s, p, acc);
+  const R ar = (R)a;
+  if (EPI == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cscale(ar, acc[k]);
+  } else {
+    cpx<R> xv[12];
+    SpinorIO<S>::load((const char *)xin + rhs * fstride, s, npad, xv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cadd(xv[k], cscale(ar, acc[k]));
+  }
+  SpinorIO<S>::store((char *)out + rhs * fstride, s, npad, acc);
+}
+
+namespace qiral {
+template <int S, int L>
+static hipError_t launch_hop_t(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
+                               void *out, const void *x, int nrhs, hipStream_t st) {
+  const Geo &g = lat->geo;
+  const size_t fstride = half_bytes(g, S);
+  const void *gauge = links_for(lat, S);
+  const int nwg = ((g.nb + 3) / 4) * nrhs;
+  dim3 grid(nwg), block(WG);
+  if (!dagger) {
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+  } else {
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a, const void *in,
+                      void *out, const void *x, int nrhs, hipStream_t st) {
+  if (prec == QIRAL_F64) return launch_hop_t<S_F64, L_F64R18>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  if (prec == QIRAL_F32) return launch_hop_t<S_F32, L_F32R12>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  return launch_hop_t<S_F16S, L_F16R12>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+}
+}  // namespace qiral
+
+// ---------------------------------------------------------------------------
+// lattice handle
+extern "C" qiral_status qiral_lattice_create(qiral_lattice **out, const int32_t dims[4], double kappa, double mu,
+                                             const double *gauge_canon, uint32_t lo_precs, qiral_recon lo_recon,
+                                             qiral_stream_t stream) {
+  if (!out) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  *out = nullptr;
+  qiral_status st = check_dims(dims);
+  if (st != QIRAL_OK) return st;
+  if (!gauge_canon) return fail(QIRAL_ERR_INVALID_ARG, "gauge_canon is NULL");
+  if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(QIRAL_ERR_INVALID_ARG, "kappa and mu must be finite");
+  if (lo_precs & ~(uint32_t)(QIRAL_LINKS_F32 | QIRAL_LINKS_F16))
+    return fail(QIRAL_ERR_INVALID_ARG, "lo_precs may only hold QIRAL_LINKS_F32 and QIRAL_LINKS_F16");
+  if (lo_recon != QIRAL_RECON12 && lo_recon != QIRAL_RECON18)
+    return fail(QIRAL_ERR_INVALID_ARG, "lo_recon must be QIRAL_RECON12 or QIRAL_RECON18");
+  if (mu != 0.0) return fail(QIRAL_ERR_UNSUPPORTED, "twisted mass (mu != 0) is not implemented on the GPU");
+  if (lo_precs && lo_recon != QIRAL_RECON12)
+    return fail(QIRAL_ERR_UNSUPPORTED, "reduced-precision links are stored reconstruct-12 only");
+
+  qiral_lattice *lat = new qiral_lattice();
+  for (int i = 0; i < 4; ++i) lat->dims[i] = dims[i];
+  lat->geo = make_geo(dims);
+  lat->kappa = kappa;
+  lat->mu = mu;
+  hipStream_t s = (hipStream_t)stream;
+  const Geo &g = lat->geo;
+  const size_t nlinks = 8 * npad_of(g);
+  auto cleanup = [&](qiral_status r) {
+    if (lat->g64) (void)hipFree(lat->g64);
+    if (lat->g32) (void)hipFree(lat->g32);
+    if (lat->g16) (void)hipFree(lat->g16);
+    delete lat;
+    return r;
+  };
+  hipError_t e = hipGetDevice(&lat->device);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+  const int nblk = (int)((nlinks + WG - 1) / WG);
+  e = hipMalloc(&lat->g64, nlinks * LinkIO<L_F64R18>::LINK_BYTES);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f64)"));
+  hipLaunchKernelGGL(k_pack_gauge<L_F64R18>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g64);
+  lat->gauge_bytes = nlinks * LinkIO<L_F64R18>::LINK_BYTES;
+  if (lo_precs & QIRAL_LINKS_F32) {
+    e = hipMalloc(&lat->g32, nlinks * LinkIO<L_F32R12>::LINK_BYTES);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f32)"));
+    hipLaunchKernelGGL(k_pack_gauge<L_F32R12>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g32);
+    lat->gauge_bytes += nlinks * LinkIO<L_F32R12>::LINK_BYTES;
+  }
+  if (lo_precs & QIRAL_LINKS_F16) {
+    e = hipMalloc(&lat->g16, nlinks * LinkIO<L_F16R12>::LINK_BYTES);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f16)"));
+    hipLaunchKernelGGL(k_pack_gauge<L_F16R12>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g16);
+    lat->gauge_bytes += nlinks * LinkIO<L_F16R12>::LINK_BYTES;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return cleanup(hip_fail(e, "pack links"));
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamSynchronize(lattice_create)"));
+  *out = lat;
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_lattice_destroy(qiral_lattice *lat) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  hipError_t e1 = lat->g64 ? hipFree(lat->g64) : hipSuccess;
+  hipError_t e2 = lat->g32 ? hipFree(lat->g32) : hipSuccess;
+  hipError_t e3 = lat->g16 ? hipFree(lat->g16) : hipSuccess;
+  hipError_t e4 = lat->ws ? hipFree(lat->ws) : hipSuccess;
+  delete lat;
+  if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+  if (e3 != hipSuccess) return hip_fail(e3, "hipFree");
+  if (e4 != hipSuccess) return hip_fail(e4, "hipFree");
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_lattice_query(const qiral_lattice *lat, int64_t *vh, int64_t *bytes) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  if (vh) *vh = lat->geo.vh;
+  if (bytes) *bytes = (int64_t)(lat->gauge_bytes + lat->ws_bytes);
+  return QIRAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// field import / export
+static qiral_status check_field_args(const qiral_lattice *lat, const void *a, const void *b, int subset, int prec,
+                                     int nrhs) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  if (!a || !b) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
+  if (subset != QIRAL_EVEN && subset != QIRAL_ODD && subset != QIRAL_FULL)
+    return fail(QIRAL_ERR_INVALID_ARG, "bad subset");
+  if (!valid_prec(prec)) return fail(QIRAL_ERR_INVALID_ARG, "bad precision");
+  if (nrhs < 1) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be >= 1");
+  return QIRAL_OK;
+}
+
+template <int S>
+static void launch_import(const Geo &g, const double *src, void *dst, int subset, int nrhs, hipStream_t s) {
+  const size_t canon_stride = (size_t)g.vh * 2 * 24;   // doubles per canonical field
+  const size_t hb = half_bytes(g, S);
+  const size_t dstride = subset == QIRAL_FULL ? 2 * hb : hb;
+  const size_t n = npad_of(g) * nrhs;
+  const int nblk = (int)((n + WG - 1) / WG);
+  for (int p = 0; p < 2; ++p) {
+    if (subset != QIRAL_FULL && subset != p) continue;
+    void *d = (char *)dst + (subset == QIRAL_FULL ? p * hb : 0);
+    hipLaunchKernelGGL(k_import<S>, dim3(nblk), dim3(WG), 0, s, g, src, canon_stride, d, dstride, p, nrhs);
+  }
+}
+
+template <int S>
+static void launch_export(const Geo &g, double *dst, const void *src, int subset, int nrhs, hipStream_t s) {
+  const size_t canon_stride = (size_t)g.vh * 2 * 24;
+  const size_t hb = half_bytes(g, S);
+  const size_t sstride = subset == QIRAL_FULL ? 2 * hb : hb;
+  const size_t n = npad_of(g) * nrhs;
+  const int nblk = (int)((n + WG - 1) / WG);
+  for (int p = 0; p < 2; ++p) {
+    if (subset != QIRAL_FULL && subset != p) continue;
+    const void *sp = (const char *)src + (subset == QIRAL_FULL ? p * hb : 0);
+    hipLaunchKernelGGL(k_export<S>, dim3(nblk), dim3(WG), 0, s, g, dst, canon_stride, sp, sstride, p, nrhs);
+  }
+}
+
+namespace qiral {
+void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s) {
+  if (prec == QIRAL_F64) launch_import<S_F64>(g, src, dst, subset, nrhs, s);
+  else if (prec == QIRAL_F32) launch_import<S_F32>(g, src, dst, subset, nrhs, s);
+  else launch_import<S_F16S>(g, src, dst, subset, nrhs, s);
+}
+void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s) {
+  if (prec == QIRAL_F64) launch_export<S_F64>(g, dst, src, subset, nrhs, s);
+  else if (prec == QIRAL_F32) launch_export<S_F32>(g, dst, src, subset, nrhs, s);
+  else launch_export<S_F16S>(g, dst, src, subset, nrhs, s);
+}
+}  // namespace qiral
+
+extern "C" qiral_status qiral_field_import(const qiral_lattice *lat, void *dst, const double *src_canon,
+                                           qiral_subset subset, qiral_prec prec, int32_t nrhs, qiral_stream_t stream) {
+  qiral_status st = check_field_args(lat, dst, src_canon, subset, prec, nrhs);
+  if (st != QIRAL_OK) return st;
+  import_field(lat->geo, src_canon, dst, subset, prec, nrhs, (hipStream_t)stream);
+  QIRAL_HIP(hipGetLastError());
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_field_export(const qiral_lattice *lat, double *dst_canon, const void *src,
+                                           qiral_subset subset, qiral_prec prec, int32_t nrhs, qiral_stream_t stream) {
+  qiral_status st = check_field_args(lat, dst_canon, src, subset, prec, nrhs);
+  if (st != QIRAL_OK) return st;
+  export_field(lat->geo, dst_canon, src, subset, prec, nrhs, (hipStream_t)stream);
+  QIRAL_HIP(hipGetLastError());
+  return QIRAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operators
+static qiral_status check_op_prec(const qiral_lattice *lat, int prec) {
+  if (!valid_prec(prec)) return fail(QIRAL_ERR_INVALID_ARG, "bad precision");
+  if (!links_for(lat, prec))
+    return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of this precision (see lo_precs)");
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_dslash_eo(const qiral_lattice *lat, void *out, const void *in, int32_t out_parity,
+                                        int32_t dagger, qiral_prec prec, int32_t nrhs, qiral_stream_t stream) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  if (!out || !in) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
+  if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
+  if (out_parity != 0 && out_parity != 1) return fail(QIRAL_ERR_INVALID_ARG, "out_parity must be 0 or 1");
+  if (nrhs < 1) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be >= 1");
+  qiral_status st = check_op_prec(lat, prec);
+  if (st != QIRAL_OK) return st;
+  QIRAL_HIP(launch_hop(lat, prec, dagger != 0, out_parity, 0, 1.0, in, out, nullptr, nrhs, (hipStream_t)stream));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, void *tmp, qiral_op op,
+                                      qiral_prec prec, int32_t nrhs, qiral_stream_t stream) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  if (!out || !in) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
+  if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
+  if (nrhs < 1) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (op != QIRAL_OP_D && op != QIRAL_OP_DDAG && op != QIRAL_OP_SCHUR && op != QIRAL_OP_SCHUR_DAG)
+    return fail(QIRAL_ERR_INVALID_ARG, "bad operator");
+  if ((op == QIRAL_OP_SCHUR || op == QIRAL_OP_SCHUR_DAG) && (!tmp || tmp == in || tmp == out))
+    return fail(QIRAL_ERR_INVALID_ARG, "the Schur operators need a separate tmp half-field");
+  qiral_status st = check_op_prec(lat, prec);
+  if (st != QIRAL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const double k = lat->kappa;
+  const int dag = (op == QIRAL_OP_DDAG || op == QIRAL_OP_SCHUR_DAG);
+  if (op == QIRAL_OP_D || op == QIRAL_OP_DDAG) {
+    // full fields: [rhs][even | odd]; handle one right-hand side per pair of launches
+    const size_t hb = half_bytes(lat->geo, prec);
+    for (int r = 0; r < nrhs; ++r) {
+      const char *ie = (const char *)in + 2 * hb * r, *io = ie + hb;
+      char *oe = (char *)out + 2 * hb * r, *oo = oe + hb;
+      QIRAL_HIP(launch_hop(lat, prec, dag, 0, 1, -k, io, oe, ie, 1, s));
+      QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k, ie, oo, io, 1, s));
+    }
+  } else {
+    QIRAL_HIP(launch_hop(lat, prec, dag, 0, 0, 1.0, in, tmp, nullptr, nrhs, s));
+    QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k * k, tmp, out, in, nrhs, s));
+  }
+  return QIRAL_OK;
+}

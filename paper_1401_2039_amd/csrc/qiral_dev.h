@@ -1,0 +1,427 @@
+// Device-side building blocks of the even-odd Wilson-Dirac library for gfx950:
+// packed layouts, link decompression, the spin-projected 8-neighbour hop and
+// deterministic wave/grid reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace qiral {
+
+constexpr int WAVE = 64;   // CDNA wavefront; also the site-block of the packed layouts
+constexpr int WG = 256;    // work-group: 4 waves
+
+// ---------------------------------------------------------------------------
+// Lattice geometry of one parity-checkerboarded lattice.
+// Sites of one parity are numbered by the checkerboard index
+// s = lex(x,y,z,t) >> 1 with lex = ((t*Lz + z)*Ly + y)*Lx + x (x fastest).
+struct Geo {
+  int lx, ly, lz, lt;
+  int lxh;     // Lx / 2
+  int vh;      // sites per parity
+  int nb;      // 64-site blocks per parity (vh rounded up)
+  int sy, sz, st;  // checkerboard-index strides of y, z, t
+};
+
+inline Geo make_geo(const int32_t d[4]) {
+  Geo g;
+  g.lx = d[0]; g.ly = d[1]; g.lz = d[2]; g.lt = d[3];
+  g.lxh = d[0] / 2;
+  g.vh = (int)((int64_t)d[0] * d[1] * d[2] * d[3] / 2);
+  g.nb = (g.vh + WAVE - 1) / WAVE;
+  g.sy = g.lxh; g.sz = g.lxh * g.ly; g.st = g.sz * g.lz;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic
+template <class R> struct cpx { R re, im; };
+
+template <class R> __device__ __forceinline__ cpx<R> cmake(R a, R b) { cpx<R> c; c.re = a; c.im = b; return c; }
+template <class R> __device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return cmake(a.re + b.re, a.im + b.im); }
+template <class R> __device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return cmake(a.re - b.re, a.im - b.im); }
+template <class R> __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return cmake(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// conj(a) * b
+template <class R> __device__ __forceinline__ cpx<R> cjmul(cpx<R> a, cpx<R> b) {
+  return cmake(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class R> __device__ __forceinline__ cpx<R> cscale(R s, cpx<R> a) { return cmake(s * a.re, s * a.im); }
+// multiply by +i and -i
+template <class R> __device__ __forceinline__ cpx<R> ci(cpx<R> a) { return cmake(-a.im, a.re); }
+template <class R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) { return cmake(a.im, -a.re); }
+
+// ---------------------------------------------------------------------------
+// Packed spinor half-fields.  Blocks of 64 sites; inside a block, "unit" j of
+// lane l sits at ((block * UNITS + j) * 64 + l), so a wavefront reads each unit
+// of 64 consecutive sites as one contiguous, fully coalesced segment.
+//   F64 : unit = 16 B = one complex128,         12 units per site
+//   F32 : unit = 16 B = two complex64,            6 units
+//   F16S: unit = 16 B = four complex FP16,        3 units, then one FP32 scale
+//         per site stored after all units of the half-field.
+// Component order inside a site is k = 4 * colour + spin.
+enum { S_F64 = 0, S_F32 = 1, S_F16S = 2 };
+
+template <int S> struct SpinorIO;
+
+template <> struct SpinorIO<S_F64> {
+  using R = double;
+  static constexpr int UNITS = 12;
+  static constexpr size_t SITE_BYTES = 192;
+  __device__ static void load(const void *base, int s, size_t npad, cpx<double> v[12]) {
+    (void)npad;
+    const double2 *p = (const double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) { double2 q = p[k * WAVE]; v[k] = cmake(q.x, q.y); }
+  }
+  __device__ static void store(void *base, int s, size_t npad, const cpx<double> v[12]) {
+    (void)npad;
+    double2 *p = (double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k * WAVE] = make_double2(v[k].re, v[k].im);
+  }
+};
+
+template <> struct SpinorIO<S_F32> {
+  using R = float;
+  static constexpr int UNITS = 6;
+  static constexpr size_t SITE_BYTES = 96;
+  __device__ static void load(const void *base, int s, size_t npad, cpx<float> v[12]) {
+    (void)npad;
+    const float4 *p = (const float4 *)base + (size_t)(s >> 6) * (6 * WAVE) + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float4 q = p[j * WAVE];
+      v[2 * j] = cmake(q.x, q.y);
+      v[2 * j + 1] = cmake(q.z, q.w);
+    }
+  }
+  __device__ static void store(void *base, int s, size_t npad, const cpx<float> v[12]) {
+    (void)npad;
+    float4 *p = (float4 *)base + (size_t)(s >> 6) * (6 * WAVE) + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) p[j * WAVE] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+  }
+};
+
+__device__ __forceinline__ float h2f(unsigned short h) { return __half2float(__ushort_as_half(h)); }
+__device__ __forceinline__ unsigned short f2h(float f) { return __half_as_ushort(__float2half_rn(f)); }
+
+template <> struct SpinorIO<S_F16S> {
+  using R = float;
+  static constexpr int UNITS = 3;
+  static constexpr size_t SITE_BYTES = 52;
+  __device__ static float *scale_ptr(const void *base, size_t npad) {
+    return (float *)((char *)base + npad * 48);
+  }
+  __device__ static void load(const void *base, int s, size_t npad, cpx<float> v[12]) {
+    const uint4 *p = (const uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
+    const float sc = scale_ptr(base, npad)[s];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint4 q = p[j * WAVE];
+      unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        v[4 * j + c] = cmake(h2f((unsigned short)(w[c] & 0xffffu)) * sc, h2f((unsigned short)(w[c] >> 16)) * sc);
+    }
+  }
+  // Quantise: scale = max |real| over the site's 24 reals, half = RNE(real / scale).
+  __device__ static void store(void *base, int s, size_t npad, const cpx<float> v[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+    uint4 *p = (uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
+    const bool zero = !(m > 0.f);
+    const float d = zero ? 1.f : m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      unsigned w[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        unsigned lo = zero ? 0u : f2h(v[4 * j + c].re / d);
+        unsigned hi = zero ? 0u : f2h(v[4 * j + c].im / d);
+        w[c] = lo | (hi << 16);
+      }
+      p[j * WAVE] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    scale_ptr(base, npad)[s] = zero ? 0.f : m;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Packed links.  Forward links U_mu(x) of the sites of parity p, in the same
+// 64-site blocking; block index ((p * 4 + mu) * nb + (s >> 6)).
+//   L_F64R18: 9 units of 16 B (complex128), row-major
+//   L_F32R12: 3 units of 16 B (rows 0-1, six complex64)
+//   L_F16R12: 3 units of 8 B  (rows 0-1, six complex FP16)
+// Row 2 of a reconstruct-12 link is conj(row0 x row1).
+enum { L_F64R18 = 0, L_F32R12 = 1, L_F16R12 = 2 };
+
+template <class R> __device__ __forceinline__ void recon_row2(cpx<R> u[9]) {
+  // u[6 + c] = conj( (row0 x row1)_c )
+  cpx<R> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
+  cpx<R> c0 = csub(cmul(a1, b2), cmul(a2, b1));
+  cpx<R> c1 = csub(cmul(a2, b0), cmul(a0, b2));
+  cpx<R> c2 = csub(cmul(a0, b1), cmul(a1, b0));
+  u[6] = cmake(c0.re, -c0.im);
+  u[7] = cmake(c1.re, -c1.im);
+  u[8] = cmake(c2.re, -c2.im);
+}
+
+template <int L> struct LinkIO;
+
+template <> struct LinkIO<L_F64R18> {
+  using R = double;
+  static constexpr size_t LINK_BYTES = 144;
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {
+    const double2 *p = (const double2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 9) * WAVE + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) { double2 q = p[j * WAVE]; u[j] = cmake(q.x, q.y); }
+  }
+};
+
+template <> struct LinkIO<L_F32R12> {
+  using R = float;
+  static constexpr size_t LINK_BYTES = 48;
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+    const float4 *p = (const float4 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float4 q = p[j * WAVE];
+      u[2 * j] = cmake(q.x, q.y);
+      u[2 * j + 1] = cmake(q.z, q.w);
+    }
+    recon_row2(u);
+  }
+};
+
+template <> struct LinkIO<L_F16R12> {
+  using R = float;
+  static constexpr size_t LINK_BYTES = 24;
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+    const uint2 *p = (const uint2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint2 q = p[j * WAVE];
+      u[2 * j] = cmake(h2f((unsigned short)(q.x & 0xffffu)), h2f((unsigned short)(q.x >> 16)));
+      u[2 * j + 1] = cmake(h2f((unsigned short)(q.y & 0xffffu)), h2f((unsigned short)(q.y >> 16)));
+    }
+    recon_row2(u);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Spin projection in the chiral basis gamma_mu = [[0, B_mu], [B_mu^+, 0]] with
+// B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1.
+// (1 + S gamma_mu) psi has upper half h = psi_up + S B psi_lo and lower half
+// S B^+ h, so each hop term needs two colour products (one per component of h).
+
+// h[2c + a] = psi[4c + a] + S (B_mu psi_lo)_a
+template <int MU, int S, class R>
+__device__ __forceinline__ void spin_project(const cpx<R> psi[12], cpx<R> h[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cpx<R> u0 = psi[4 * c + 0], u1 = psi[4 * c + 1], l0 = psi[4 * c + 2], l1 = psi[4 * c + 3];
+    cpx<R> b0, b1;
+    if (MU == 0) { b0 = cmi(l1); b1 = cmi(l0); }            // -i sigma_x
+    else if (MU == 1) { b0 = cmake(-l1.re, -l1.im); b1 = l0; } // -i sigma_y
+    else if (MU == 2) { b0 = cmi(l0); b1 = ci(l1); }        // -i sigma_z
+    else { b0 = l0; b1 = l1; }                              // 1
+    if (S > 0) { h[2 * c] = cadd(u0, b0); h[2 * c + 1] = cadd(u1, b1); }
+    else { h[2 * c] = csub(u0, b0); h[2 * c + 1] = csub(u1, b1); }
+  }
+}
+
+// acc += (upper = w, lower = S B_mu^+ w); FIRST assigns instead of adding.
+template <int MU, int S, bool FIRST, class R>
+__device__ __forceinline__ void spin_accumulate(const cpx<R> w[6], cpx<R> acc[12]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cpx<R> w0 = w[2 * c], w1 = w[2 * c + 1];
+    cpx<R> l0, l1;   // B^+ w
+    if (MU == 0) { l0 = ci(w1); l1 = ci(w0); }              // (-i sigma_x)^+ = i sigma_x
+    else if (MU == 1) { l0 = w1; l1 = cmake(-w0.re, -w0.im); }
+    else if (MU == 2) { l0 = ci(w0); l1 = cmi(w1); }
+    else { l0 = w0; l1 = w1; }
+    if (S < 0) { l0 = cmake(-l0.re, -l0.im); l1 = cmake(-l1.re, -l1.im); }
+    if (FIRST) {
+      acc[4 * c + 0] = w0; acc[4 * c + 1] = w1; acc[4 * c + 2] = l0; acc[4 * c + 3] = l1;
+    } else {
+      acc[4 * c + 0] = cadd(acc[4 * c + 0], w0);
+      acc[4 * c + 1] = cadd(acc[4 * c + 1], w1);
+      acc[4 * c + 2] = cadd(acc[4 * c + 2], l0);
+      acc[4 * c + 3] = cadd(acc[4 * c + 3], l1);
+    }
+  }
+}
+
+// w = U h (ADJ = false) or U^+ h (ADJ = true) for both spin components of h.
+template <bool ADJ, class R>
+__device__ __forceinline__ void su3_mul(const cpx<R> u[9], const cpx<R> h[6], cpx<R> w[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      cpx<R> r;
+      if (!ADJ) {
+        r = cmul(u[3 * a + 0], h[0 + sp]);
+        r = cadd(r, cmul(u[3 * a + 1], h[2 + sp]));
+        r = cadd(r, cmul(u[3 * a + 2], h[4 + sp]));
+      } else {
+        r = cjmul(u[0 + a], h[0 + sp]);
+        r = cadd(r, cjmul(u[3 + a], h[2 + sp]));
+        r = cadd(r, cjmul(u[6 + a], h[4 + sp]));
+      }
+      w[2 * a + sp] = r;
+    }
+  }
+}
+
+template <class Rd, class Rs> __device__ __forceinline__ void cvt12(const cpx<Rs> a[12], cpx<Rd> b[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = cmake((Rd)a[k].re, (Rd)a[k].im);
+}
+
+// Neighbour checkerboard indices of output site s (parity p) in the 8 directions.
+struct Nbr { int fwd[4], bwd[4]; };
+
+__device__ __forceinline__ Nbr neighbours(const Geo &g, int s, int p) {
+  int xh = s % g.lxh;
+  int r = s / g.lxh;
+  int y = r % g.ly; r /= g.ly;
+  int z = r % g.lz;
+  int t = r / g.lz;
+  int x = 2 * xh + ((p + y + z + t) & 1);
+  int base = s - xh;
+  Nbr n;
+  n.fwd[0] = base + ((x + 1 == g.lx ? 0 : x + 1) >> 1);
+  n.bwd[0] = base + ((x == 0 ? g.lx - 1 : x - 1) >> 1);
+  n.fwd[1] = (y + 1 == g.ly) ? s - (g.ly - 1) * g.sy : s + g.sy;
+  n.bwd[1] = (y == 0) ? s + (g.ly - 1) * g.sy : s - g.sy;
+  n.fwd[2] = (z + 1 == g.lz) ? s - (g.lz - 1) * g.sz : s + g.sz;
+  n.bwd[2] = (z == 0) ? s + (g.lz - 1) * g.sz : s - g.sz;
+  n.fwd[3] = (t + 1 == g.lt) ? s - (g.lt - 1) * g.st : s + g.st;
+  n.bwd[3] = (t == 0) ? s + (g.lt - 1) * g.st : s - g.st;
+  return n;
+}
+
+// Field loaders: a loader reads the 12 components of site s of a packed field
+// and converts them to the compute type R.
+template <int S> struct FieldLd {
+  using R = typename SpinorIO<S>::R;
+  const void *base;
+  size_t npad;
+  __device__ __forceinline__ void operator()(int s, cpx<R> v[12]) const { SpinorIO<S>::load(base, s, npad, v); }
+};
+
+// Sum of an FP64 field and an FP32 field (the solution of a mixed-precision
+// solve: FP64 accumulated part plus the FP32 part not yet folded in).
+struct SumLd {
+  using R = double;
+  const void *a;   // F64
+  const void *b;   // F32, or null
+  size_t npad;
+  __device__ __forceinline__ void operator()(int s, cpx<double> v[12]) const {
+    SpinorIO<S_F64>::load(a, s, npad, v);
+    if (b) {
+      cpx<float> w[12];
+      SpinorIO<S_F32>::load(b, s, npad, w);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = cadd(v[k], cmake((double)w[k].re, (double)w[k].im));
+    }
+  }
+};
+
+// One direction: forward term (spin sign SF) and backward term (sign SB).
+template <class Ld, int L, int MU, int SF, int SB, bool FIRST>
+__device__ __forceinline__ void hop_dir(const Geo &g, const void *gauge, const Ld &ld, int s, int p, const Nbr &n,
+                                        cpx<typename Ld::R> acc[12]) {
+  using R = typename Ld::R;
+  cpx<R> psi[12], h[6], w[6];
+  cpx<typename LinkIO<L>::R> u0[9];
+  cpx<R> u[9];
+  // forward: (1 + SF g_mu) U_mu(x) psi(x + mu)
+  ld(n.fwd[MU], psi);
+  LinkIO<L>::load(gauge, p, MU, s, g.nb, u0);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+  spin_project<MU, SF>(psi, h);
+  su3_mul<false>(u, h, w);
+  spin_accumulate<MU, SF, FIRST>(w, acc);
+  // backward: (1 + SB g_mu) U_mu(x - mu)^+ psi(x - mu)
+  ld(n.bwd[MU], psi);
+  LinkIO<L>::load(gauge, 1 - p, MU, n.bwd[MU], g.nb, u0);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+  spin_project<MU, SB>(psi, h);
+  su3_mul<true>(u, h, w);
+  spin_accumulate<MU, SB, false>(w, acc);
+}
+
+// acc = (H psi)(s) for output parity p (DAG: H^dagger, which flips the spin signs).
+template <int L, bool DAG, class Ld>
+__device__ __forceinline__ void hop_site(const Geo &g, const void *gauge, const Ld &ld, int s, int p,
+                                         cpx<typename Ld::R> acc[12]) {
+  const Nbr n = neighbours(g, s, p);
+  constexpr int SF = DAG ? 1 : -1;   // forward: 1 - gamma (H), 1 + gamma (H^dagger)
+  constexpr int SB = DAG ? -1 : 1;
+  hop_dir<Ld, L, 0, SF, SB, true>(g, gauge, ld, s, p, n, acc);
+  hop_dir<Ld, L, 1, SF, SB, false>(g, gauge, ld, s, p, n, acc);
+  hop_dir<Ld, L, 2, SF, SB, false>(g, gauge, ld, s, p, n, acc);
+  hop_dir<Ld, L, 3, SF, SB, false>(g, gauge, ld, s, p, n, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  A wave sums its 64 lanes with a fixed xor butterfly; every wave
+// of a grid-wide reduction stores its partial; the wave that completes the
+// count sums the partials in index order.  The result does not depend on
+// scheduling, so repeated runs are bitwise identical.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+// Commit NV wave-summed values as partial `part` (of nparts) of a reduction.
+// Returns true in every lane of the wave that completed the reduction, with the
+// totals in tot[] (valid in all lanes of that wave).
+template <int NV>
+__device__ __forceinline__ bool grid_reduce(double v[NV], double *partials, unsigned *counter, int part, int nparts,
+                                            double tot[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  int last = 0;
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      __hip_atomic_store(&partials[(size_t)i * nparts + part], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == (unsigned)(nparts - 1));
+  }
+  last = __shfl(last, 0, WAVE);
+  if (!last) return false;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double a = 0.0;
+    for (int k = lane_id(); k < nparts; k += WAVE)
+      a += __hip_atomic_load(&partials[(size_t)i * nparts + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tot[i] = wave_sum(a);
+  }
+  if (lane_id() == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// XCD-aware block order: the hardware hands consecutive work-group ids to the 8
+// XCDs in turn; this remap gives each XCD one contiguous range of logical
+// blocks, so neighbouring sites share an L2.
+__device__ __forceinline__ int xcd_remap(int hw, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int xcd = hw & 7, idx = hw >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+}  // namespace qiral

@@ -1,0 +1,49 @@
+// Host-side internals shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <string>
+#include <vector>
+
+#include "../../include/qiral.h"
+#include "qiral_dev.h"
+
+struct qiral_lattice {
+  int32_t dims[4];
+  qiral::Geo geo;
+  double kappa, mu;
+  void *g64 = nullptr;   // FP64 reconstruct-18 links
+  void *g32 = nullptr;   // FP32 reconstruct-12 links (optional)
+  void *g16 = nullptr;   // FP16 reconstruct-12 links (optional)
+  size_t gauge_bytes = 0;
+  void *ws = nullptr;    // solver workspace, grown on demand
+  size_t ws_bytes = 0;
+  int device = 0;
+};
+
+namespace qiral {
+
+void set_error(const std::string &msg);
+qiral_status hip_fail(hipError_t e, const char *what);
+
+#define QIRAL_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return qiral::hip_fail(e_, #call); \
+  } while (0)
+
+inline size_t npad_of(const Geo &g) { return (size_t)g.nb * WAVE; }
+size_t half_bytes(const Geo &g, int prec);
+const void *links_for(const qiral_lattice *lat, int prec);
+
+// Grid of ceil(nwaves / 4) work-groups (4 waves of 64 lanes each).
+inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }
+
+// Launchers implemented in api.hip (single lattice, nrhs consecutive fields).
+// epi = 0: out = a * H in;  epi = 1: out = x + a * H in.
+hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi, double a,
+                      const void *in, void *out, const void *x, int nrhs, hipStream_t s);
+
+// Ensure the handle's workspace holds at least `bytes`.
+qiral_status ensure_workspace(qiral_lattice *lat, size_t bytes);
+
+}  // namespace qiral

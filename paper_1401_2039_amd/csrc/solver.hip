@@ -1,0 +1,372 @@
+// Host drivers of the even-odd solvers.
+//
+// The goal xx = Dirac^{-1} bb with the template chain "CGNR schur" (Sec. 2) is
+// run as: b_hat = b_o + kappa H_oe b_e (the Schur source), CGNR (Fig. "CG") on
+// S x_o = b_hat with S = 1 - kappa^2 H_oe H_eo, x_e = b_e + kappa H_eo x_o (the
+// reconstruction, with v1 = P_e b), and a final FP64 true residual
+// ||b - D x|| / ||b||.  The paper's loop condition (r|r) > eps uses
+// eps = (tol ||b||)^2.  BiCGStab replaces CGNR on the same Schur system.
+//
+// Mixed precision: the Krylov vectors live in FP32 or F16S and the operator runs
+// in FP32; the solution is kept as an FP64 part plus an FP32 part, and when the
+// iterated residual has dropped by delta since the last update (or claims
+// convergence) the FP32 part is folded in and the residual is recomputed in
+// FP64 from the FP64 operator (reliable updates, Sleijpen & van der Vorst 1996;
+// Clark et al., Comput. Phys. Commun. 181 (2010) 1517).  Convergence is only
+// declared on such an FP64 residual.
+//
+// Several systems (right-hand sides of one lattice, or different lattices) run
+// in the same launches: every kernel walks one work table over all of them and
+// each system carries its own scalars and state on the device.  The host only
+// enqueues iterations and reads the states every few iterations.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "qiral_int.h"
+#include "solver_dev.h"
+#include "solver_kernels.h"
+
+namespace qiral {
+void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
+void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
+}  // namespace qiral
+
+using namespace qiral;
+
+namespace {
+
+struct SysIn {
+  qiral_lattice *lat;
+  double *x;
+  const double *b;
+};
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+qiral_status fail(qiral_status s, const char *msg) {
+  set_error(msg);
+  return s;
+}
+
+struct Layout {
+  size_t off_desc, off_work, off_state, off_cnt, off_part, total;
+  std::vector<size_t> off_sys;   // per system: start of its fields
+  std::vector<size_t> part_off;  // per system: offset of its partials (doubles) inside the partial region
+};
+
+// Per-system field sizes
+struct SysSizes {
+  size_t hb_it, hb_x, hb64;
+  size_t bytes;
+};
+
+SysSizes sys_sizes(const Geo &g, int prec, bool bicg) {
+  SysSizes z;
+  z.hb_it = align_up(half_bytes(g, prec));
+  z.hb64 = align_up(half_bytes(g, QIRAL_F64));
+  const bool mixed = prec != QIRAL_F64;
+  z.hb_x = mixed ? align_up(half_bytes(g, QIRAL_F32)) : 0;
+  const int nit = bicg ? 7 : 5;   // R P Z AP TMP (+ RT T)
+  // F64: BH T64, [BE|BO] full, [XE|XH] full
+  z.bytes = nit * z.hb_it + z.hb_x + 2 * z.hb64 + 2 * (2 * z.hb64);
+  return z;
+}
+
+qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, const qiral_solve_params *prm,
+                       qiral_solve_info *info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int nsys = (int)sys.size();
+  const int prec = prm->inner_prec;
+  const bool mixed = prec != QIRAL_F64;
+  const bool bicg = prm->solver == QIRAL_BICGSTAB_EO;
+
+  // ---- layout
+  Layout lay;
+  std::vector<SysSizes> sz(nsys);
+  long nwork = 0;
+  size_t nparts = 0;
+  lay.part_off.resize(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    sz[i] = sys_sizes(sys[i].lat->geo, prec, bicg);
+    nwork += sys[i].lat->geo.nb;
+    lay.part_off[i] = nparts;
+    nparts += (size_t)NSLOT * NV * sys[i].lat->geo.nb;
+  }
+  if (nwork > (1l << 30)) return fail(QIRAL_ERR_UNSUPPORTED, "too many work items");
+  size_t off = 0;
+  lay.off_desc = off; off = align_up(off + sizeof(SysDesc) * nsys);
+  lay.off_work = off; off = align_up(off + sizeof(uint32_t) * nwork);
+  lay.off_state = off; off = align_up(off + sizeof(SysState) * nsys);
+  lay.off_cnt = off; off = align_up(off + sizeof(unsigned) * NSLOT * nsys);
+  lay.off_part = off; off = align_up(off + sizeof(double) * nparts);
+  lay.off_sys.resize(nsys);
+  for (int i = 0; i < nsys; ++i) { lay.off_sys[i] = off; off += sz[i].bytes; }
+  lay.total = off;
+  qiral_status st = ensure_workspace(owner, lay.total);
+  if (st != QIRAL_OK) return st;
+  char *ws = (char *)owner->ws;
+
+  // ---- system table
+  std::vector<SysDesc> desc(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    const qiral_lattice *lat = sys[i].lat;
+    SysDesc &d = desc[i];
+    memset(&d, 0, sizeof(d));
+    d.g = lat->geo;
+    d.kappa = lat->kappa;
+    d.g64 = lat->g64;
+    d.glo = links_for(lat, prec);
+    d.npad = npad_of(lat->geo);
+    d.st = (SysState *)(ws + lay.off_state) + i;
+    d.cnt = (unsigned *)(ws + lay.off_cnt) + (size_t)NSLOT * i;
+    d.part = (double *)(ws + lay.off_part) + lay.part_off[i];
+    char *p = ws + lay.off_sys[i];
+    const int it_fields[] = {F_R, F_P, F_Z, F_AP, F_TMP, F_RT, F_T};
+    for (int k = 0; k < (bicg ? 7 : 5); ++k) { d.f[it_fields[k]] = p; p += sz[i].hb_it; }
+    if (mixed) { d.f[F_X] = p; p += sz[i].hb_x; }
+    d.f[F_BH] = p; p += sz[i].hb64;
+    d.f[F_T64] = p; p += sz[i].hb64;
+    d.f[F_BE] = p; d.f[F_BO] = p + half_bytes(lat->geo, QIRAL_F64); p += 2 * sz[i].hb64;
+    d.f[F_XE] = p; d.f[F_XH] = p + half_bytes(lat->geo, QIRAL_F64); p += 2 * sz[i].hb64;
+    if (!mixed) d.f[F_X] = d.f[F_XH];
+  }
+  // ---- work table: right-hand sides of one lattice interleave per block (they share links)
+  std::vector<uint32_t> work;
+  work.reserve(nwork);
+  bool same_lattice = true;
+  for (int i = 1; i < nsys; ++i) same_lattice = same_lattice && sys[i].lat == sys[0].lat;
+  if (same_lattice && nsys > 1) {
+    for (int b = 0; b < sys[0].lat->geo.nb; ++b)
+      for (int i = 0; i < nsys; ++i) work.push_back(((uint32_t)i << 24) | (uint32_t)b);
+  } else {
+    for (int i = 0; i < nsys; ++i)
+      for (int b = 0; b < sys[i].lat->geo.nb; ++b) work.push_back(((uint32_t)i << 24) | (uint32_t)b);
+  }
+  std::vector<SysState> hst(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    SysState &x = hst[i];
+    memset(&x, 0, sizeof(x));
+    x.tol2 = prm->tol * prm->tol;
+    x.delta2 = prm->delta * prm->delta;
+    x.maxiter = prm->maxiter;
+    x.mixed = mixed;
+    x.solver = bicg ? SOLVER_BICG : SOLVER_CG;
+    x.status = ST_UPDATE;
+  }
+  QIRAL_HIP(hipMemcpyAsync(ws + lay.off_desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
+  QIRAL_HIP(hipMemcpyAsync(ws + lay.off_work, work.data(), sizeof(uint32_t) * nwork, hipMemcpyHostToDevice, s));
+  QIRAL_HIP(hipMemcpyAsync(ws + lay.off_state, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, s));
+  QIRAL_HIP(hipMemsetAsync(ws + lay.off_cnt, 0, sizeof(unsigned) * NSLOT * nsys, s));
+
+  Launch L;
+  L.desc = (const SysDesc *)(ws + lay.off_desc);
+  L.work = (const uint32_t *)(ws + lay.off_work);
+  L.nwork = (int)nwork;
+  L.stream = s;
+
+  // ---- inputs
+  for (int i = 0; i < nsys; ++i) {
+    const SysDesc &d = desc[i];
+    const Geo &g = sys[i].lat->geo;
+    import_field(g, sys[i].b, d.f[F_BE], QIRAL_FULL, QIRAL_F64, 1, s);
+    if (prm->x0_is_guess) import_field(g, sys[i].x, d.f[F_XE], QIRAL_FULL, QIRAL_F64, 1, s);
+    else QIRAL_HIP(hipMemsetAsync(d.f[F_XH], 0, half_bytes(g, QIRAL_F64), s));
+    if (mixed) QIRAL_HIP(hipMemsetAsync(d.f[F_X], 0, half_bytes(g, QIRAL_F32), s));
+    QIRAL_HIP(hipMemsetAsync(d.f[F_P], 0, half_bytes(g, prec), s));
+    QIRAL_HIP(hipMemsetAsync(d.f[F_AP], 0, half_bytes(g, prec), s));
+  }
+  bnorm(L);
+  hop_sys(L, S_F64, false, 1, F_BE, F_BH, F_BO, 1, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);   // b_hat
+  QIRAL_HIP(hipGetLastError());
+
+  auto start_krylov = [&]() {
+    // r = b_hat - S x (FP64), then the solver's own start
+    hop_sum(L, mixed);
+    hop_upd(L, prec, bicg);
+    if (!bicg) {
+      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
+      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_NZ_INIT);
+      cg2(L, prec);   // p = z (beta = 0, p = 0)
+    } else {
+      copy_field(L, prec, F_R, F_RT, ST_RUN);
+      bi_init(L, nsys);
+    }
+  };
+  auto iteration = [&]() {
+    if (!bicg) {
+      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
+      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 1, SL_AP, FIN_ALPHA);
+      cg1(L, prec);
+      if (mixed) { hop_sum(L, true); hop_upd(L, prec, false); }
+      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
+      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_BETA);
+      cg2(L, prec);
+    } else {
+      bi_p(L, prec);
+      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
+      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 2, SL_BI1, FIN_BI_ALPHA);
+      bi_s(L, prec);
+      hop_sys(L, prec, false, 0, F_Z, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
+      hop_sys(L, prec, false, 1, F_TMP, F_T, F_Z, 1, A_MKAPPA2, ST_RUN, 3, SL_BI2, FIN_BI_OMEGA);
+      bi_xr(L, prec);
+      if (mixed) { hop_sum(L, true); hop_upd(L, prec, true); }
+    }
+  };
+
+  const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  const bool use_graph = prm->use_graph && s != nullptr;
+  auto free_graph = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  };
+  auto read_states = [&]() -> qiral_status {
+    QIRAL_HIP(hipMemcpyAsync(hst.data(), ws + lay.off_state, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
+    QIRAL_HIP(hipStreamSynchronize(s));
+    return QIRAL_OK;
+  };
+
+  int restarts = 0;
+  std::vector<double> true_rel(nsys, 0.0);
+  qiral_status result = QIRAL_OK;
+  while (true) {
+    start_krylov();
+    QIRAL_HIP(hipGetLastError());
+    long enqueued = 0;
+    // iterations until every system is done
+    while (true) {
+      if (use_graph) {
+        if (!gexec) {
+          hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+          if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+          for (int k = 0; k < chunk; ++k) iteration();
+          e = hipStreamEndCapture(s, &graph);
+          if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipStreamEndCapture"); }
+          e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+          if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphInstantiate"); }
+        }
+        hipError_t e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
+      } else {
+        for (int k = 0; k < chunk; ++k) iteration();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "solver iteration");
+      }
+      enqueued += chunk;
+      st = read_states();
+      if (st != QIRAL_OK) { free_graph(); return st; }
+      bool all_done = true;
+      for (int i = 0; i < nsys; ++i) all_done = all_done && (hst[i].status & ST_DONE);
+      if (all_done) break;
+      if (enqueued > (long)prm->maxiter + 4l * chunk) break;   // device stops at maxiter; safety net
+    }
+    // reconstruct x_e, export, FP64 true residual
+    hop_sys(L, S_F64, false, 1, F_XH, F_XE, F_BE, 0, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);
+    hop_res(L, 0);
+    hop_res(L, 1);
+    QIRAL_HIP(hipGetLastError());
+    st = read_states();
+    if (st != QIRAL_OK) { free_graph(); return st; }
+    bool again = false;
+    for (int i = 0; i < nsys; ++i) {
+      const SysState &x = hst[i];
+      const double r2 = x.res[SL_RES_E][0] + x.res[SL_RES_O][0];
+      true_rel[i] = x.bnorm2 > 0 ? std::sqrt(r2 / x.bnorm2) : std::sqrt(r2);
+      if (!x.nonfinite && true_rel[i] > prm->tol && x.iter < prm->maxiter) again = true;
+    }
+    if (!again || restarts >= 2) break;
+    ++restarts;
+    for (int i = 0; i < nsys; ++i) {
+      if (!hst[i].nonfinite && true_rel[i] > prm->tol && hst[i].iter < prm->maxiter) {
+        hst[i].status = ST_UPDATE;
+        hst[i].final_update = 0;
+      }
+    }
+    QIRAL_HIP(hipMemcpyAsync(ws + lay.off_state, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, s));
+  }
+  free_graph();
+  for (int i = 0; i < nsys; ++i) {
+    const SysDesc &d = desc[i];
+    export_field(sys[i].lat->geo, sys[i].x, d.f[F_XE], QIRAL_FULL, QIRAL_F64, 1, s);
+  }
+  QIRAL_HIP(hipGetLastError());
+  QIRAL_HIP(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < nsys; ++i) {
+    const SysState &x = hst[i];
+    if (info) {
+      info[i].iterations = x.iter;
+      info[i].reliable_updates = mixed ? x.nupdates - 1 - restarts : 0;
+      if (info[i].reliable_updates < 0) info[i].reliable_updates = 0;
+      info[i].true_rel_resid = true_rel[i];
+      info[i].converged = x.nonfinite ? 0 : (true_rel[i] <= prm->tol);
+      info[i].fell_back = 0;
+      info[i].seconds = secs;
+      info[i].hop_applications = x.hops + 4 + (long long)restarts * 2;
+    }
+    if (x.nonfinite) result = QIRAL_ERR_NONFINITE;
+    else if (true_rel[i] > prm->tol && result == QIRAL_OK) result = QIRAL_ERR_NOT_CONVERGED;
+  }
+  if (result == QIRAL_ERR_NONFINITE) set_error("a NaN or Inf appeared in a reduction");
+  else if (result == QIRAL_ERR_NOT_CONVERGED) set_error("tolerance not reached within maxiter");
+  return result;
+}
+
+qiral_status check_params(const qiral_solve_params *p) {
+  if (!p) return fail(QIRAL_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(QIRAL_ERR_INVALID_ARG, "tol must be positive");
+  if (p->maxiter < 1) return fail(QIRAL_ERR_INVALID_ARG, "maxiter must be >= 1");
+  if (p->solver != QIRAL_CGNR_EO && p->solver != QIRAL_BICGSTAB_EO && p->solver != QIRAL_FGMRES_NN)
+    return fail(QIRAL_ERR_INVALID_ARG, "bad solver");
+  if (p->inner_prec != QIRAL_F64 && p->inner_prec != QIRAL_F32 && p->inner_prec != QIRAL_F16S)
+    return fail(QIRAL_ERR_INVALID_ARG, "bad inner precision");
+  if (p->inner_prec != QIRAL_F64 && !(p->delta > 0.0 && p->delta < 1.0))
+    return fail(QIRAL_ERR_INVALID_ARG, "delta must lie in (0, 1) for a mixed-precision solve");
+  if (p->check_every < 0) return fail(QIRAL_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (p->solver == QIRAL_FGMRES_NN) return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES needs qiral_solve_nn");
+  return QIRAL_OK;
+}
+
+}  // namespace
+
+extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                                    const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream) {
+  if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
+  if (!x_canon || !b_canon) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
+  if (nrhs < 1 || nrhs > 255) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be in [1, 255]");
+  if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
+  qiral_status st = check_params(params);
+  if (st != QIRAL_OK) return st;
+  if (!links_for(lat, params->inner_prec))
+    return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (see lo_precs)");
+  std::vector<SysIn> sys(nrhs);
+  const size_t stride = (size_t)lat->geo.vh * 2 * 24;
+  for (int r = 0; r < nrhs; ++r) sys[r] = SysIn{lat, x_canon + r * stride, b_canon + r * stride};
+  return run_solve(lat, sys, params, info, (hipStream_t)stream);
+}
+
+extern "C" qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_canon,
+                                          const double *const *b_canon, int32_t nsys,
+                                          const qiral_solve_params *params, qiral_solve_info *info,
+                                          qiral_stream_t stream) {
+  if (!lats || !x_canon || !b_canon) return fail(QIRAL_ERR_INVALID_ARG, "array pointer is NULL");
+  if (nsys < 1 || nsys > 255) return fail(QIRAL_ERR_INVALID_ARG, "nsys must be in [1, 255]");
+  if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
+  qiral_status st = check_params(params);
+  if (st != QIRAL_OK) return st;
+  std::vector<SysIn> sys(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    if (!lats[i] || !x_canon[i] || !b_canon[i]) return fail(QIRAL_ERR_INVALID_ARG, "a system pointer is NULL");
+    if (!links_for(lats[i], params->inner_prec))
+      return fail(QIRAL_ERR_INVALID_ARG, "a lattice holds no links of the inner precision (see lo_precs)");
+    sys[i] = SysIn{lats[i], x_canon[i], b_canon[i]};
+  }
+  return run_solve(lats[0], sys, params, info, (hipStream_t)stream);
+}

@@ -1,0 +1,240 @@
+// Device side of the solvers: per-system state, the system table, solver
+// scalar updates, and the grouped (table-driven) kernels.  One launch covers
+// every system of a solve (the right-hand sides of one lattice, or the
+// independent lattices of a batch); a work item is one wavefront of 64 sites of
+// one system, and a system whose state does not match a kernel's mask skips it.
+#pragma once
+#include "qiral_dev.h"
+
+namespace qiral {
+
+enum : int { ST_RUN = 1, ST_UPDATE = 2, ST_DONE = 4, ST_ANY = 7 };
+
+enum : int { SL_AP = 0, SL_R, SL_Z, SL_UPD, SL_B, SL_RES_E, SL_RES_O, SL_BI1, SL_BI2, SL_BI3, NSLOT };
+constexpr int NV = 3;   // values per reduction
+
+enum : int {
+  FIN_NONE = 0, FIN_BNORM, FIN_NZ_INIT, FIN_ALPHA, FIN_NR, FIN_BETA, FIN_UPDATE,
+  FIN_BI_ALPHA, FIN_BI_OMEGA, FIN_BI_RHO
+};
+
+enum : int { SOLVER_CG = 0, SOLVER_BICG = 1 };
+
+// Vectors of one system.  Odd half-fields unless noted.  "it" = iterate
+// precision (FP64 for a plain solve, FP32 or F16S for a mixed one).
+enum : int {
+  F_X = 0,   // iterated solution: FP64 (plain) or FP32 (mixed, not yet folded into XH)
+  F_R,       // residual (it)
+  F_P,       // search direction (it)
+  F_Z,       // S^dagger r (CG) / s (BiCGStab) (it)
+  F_AP,      // S p (CG) / v (BiCGStab) (it)
+  F_TMP,     // even half-field temporary (it)
+  F_XH,      // FP64 solution (mixed: accumulated; plain: unused)
+  F_BH,      // FP64 Schur source b_hat
+  F_T64,     // FP64 even temporary
+  F_BE,      // FP64 even half of b
+  F_BO,      // FP64 odd half of b
+  F_XE,      // FP64 even half of x
+  F_RT,      // BiCGStab shadow residual (it)
+  F_T,       // BiCGStab t = S s (it)
+  NF
+};
+
+struct SysState {
+  double tol2, thr2, bnorm2, delta2;
+  double nz, nr, nAp, alpha, beta, max_nr;
+  double rho_re, rho_im, rho0_re, rho0_im, al_re, al_im, om_re, om_im, be_re, be_im;
+  double res[NSLOT][NV];
+  int status, iter, maxiter, nupdates, nonfinite, mixed, final_update, solver;
+  long long hops;
+};
+
+struct SysDesc {
+  Geo g;
+  double kappa;
+  const void *g64;    // FP64 links
+  const void *glo;    // links in the iterate precision (== g64 for a plain solve)
+  void *f[NF];
+  SysState *st;
+  double *part;       // [NSLOT][NV][nb]
+  unsigned *cnt;      // [NSLOT]
+  size_t npad;
+};
+
+__device__ __forceinline__ bool cfinite(double a) { return isfinite(a); }
+
+// Solver scalar step run by the single lane that completed a reduction.
+__device__ inline void finalize(SysState *st, int fin, int slot, const double t[NV]) {
+  for (int i = 0; i < NV; ++i) st->res[slot][i] = t[i];
+  switch (fin) {
+    case FIN_BNORM:
+      st->bnorm2 = t[0];
+      st->thr2 = st->tol2 * t[0];
+      if (!cfinite(t[0])) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    case FIN_NZ_INIT:
+      st->nz = t[0];
+      st->beta = 0.0;
+      st->hops += 2;
+      if (!cfinite(t[0])) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    case FIN_ALPHA: {
+      st->nAp = t[0];
+      double a = st->nz / t[0];
+      st->alpha = a;
+      st->hops += 2;
+      if (!cfinite(a)) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    }
+    case FIN_NR: {
+      const double nr = t[0];
+      st->nr = nr;
+      st->iter += 1;
+      if (!cfinite(nr)) { st->nonfinite = 1; st->status = ST_DONE; break; }
+      const bool out_of_iters = st->iter >= st->maxiter;
+      if (!st->mixed) {
+        if (nr <= st->thr2 || out_of_iters) st->status = ST_DONE;
+      } else {
+        if (nr > st->max_nr) st->max_nr = nr;
+        if (nr <= st->thr2 || nr < st->delta2 * st->max_nr || out_of_iters) {
+          st->status = ST_UPDATE;
+          st->final_update = out_of_iters;
+        }
+      }
+      break;
+    }
+    case FIN_BETA: {
+      const double b = t[0] / st->nz;
+      st->beta = b;
+      st->nz = t[0];
+      st->hops += 2;
+      if (!cfinite(b)) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    }
+    case FIN_UPDATE: {
+      // t[0] = ||b_hat - S x||^2 in FP64; t[1], t[2] = (r~, r) for BiCGStab
+      const double nr = t[0];
+      st->nr = nr;
+      st->max_nr = nr;
+      st->nupdates += 1;
+      st->hops += 2;
+      if (st->solver == SOLVER_BICG && st->iter > 0) {
+        // keep the recurrence consistent with the replaced residual
+        const double nre = t[1], nim = t[2];
+        const double ore = st->rho0_re, oim = st->rho0_im;   // rho of the previous iteration
+        const double d = ore * ore + oim * oim;
+        const double qre = (nre * ore + nim * oim) / d, qim = (nim * ore - nre * oim) / d;   // rho_new / rho_old
+        const double od = st->om_re * st->om_re + st->om_im * st->om_im;
+        const double are = (st->al_re * st->om_re + st->al_im * st->om_im) / od;
+        const double aim = (st->al_im * st->om_re - st->al_re * st->om_im) / od;        // alpha / omega
+        st->be_re = qre * are - qim * aim;
+        st->be_im = qre * aim + qim * are;
+        st->rho_re = nre;
+        st->rho_im = nim;
+      }
+      if (!cfinite(nr)) { st->nonfinite = 1; st->status = ST_DONE; }
+      else if (nr <= st->thr2 || st->final_update || st->iter >= st->maxiter) st->status = ST_DONE;
+      else st->status = ST_RUN;
+      break;
+    }
+    case FIN_BI_ALPHA: {
+      // alpha = rho / (r~, v)
+      const double dre = t[0], dim = t[1];
+      const double d = dre * dre + dim * dim;
+      st->al_re = (st->rho_re * dre + st->rho_im * dim) / d;
+      st->al_im = (st->rho_im * dre - st->rho_re * dim) / d;
+      st->hops += 2;
+      if (!cfinite(st->al_re) || !cfinite(st->al_im)) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    }
+    case FIN_BI_OMEGA: {
+      // omega = (t, s) / (t, t)
+      st->om_re = t[0] / t[2];
+      st->om_im = t[1] / t[2];
+      st->hops += 2;
+      if (!cfinite(st->om_re) || !cfinite(st->om_im)) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    }
+    case FIN_BI_RHO: {
+      // rho_new = (r~, r), beta = (rho_new / rho) (alpha / omega), convergence test on (r, r)
+      const double nre = t[0], nim = t[1], nr = t[2];
+      const double ore = st->rho_re, oim = st->rho_im;
+      const double d = ore * ore + oim * oim;
+      const double qre = (nre * ore + nim * oim) / d, qim = (nim * ore - nre * oim) / d;
+      const double od = st->om_re * st->om_re + st->om_im * st->om_im;
+      const double are = (st->al_re * st->om_re + st->al_im * st->om_im) / od;
+      const double aim = (st->al_im * st->om_re - st->al_re * st->om_im) / od;
+      st->be_re = qre * are - qim * aim;
+      st->be_im = qre * aim + qim * are;
+      st->rho0_re = ore;
+      st->rho0_im = oim;
+      st->rho_re = nre;
+      st->rho_im = nim;
+      st->nr = nr;
+      st->iter += 1;
+      if (!cfinite(nr) || !cfinite(st->be_re)) { st->nonfinite = 1; st->status = ST_DONE; break; }
+      const bool out_of_iters = st->iter >= st->maxiter;
+      if (!st->mixed) {
+        if (nr <= st->thr2 || out_of_iters) st->status = ST_DONE;
+      } else {
+        if (nr > st->max_nr) st->max_nr = nr;
+        if (nr <= st->thr2 || nr < st->delta2 * st->max_nr || out_of_iters) {
+          st->status = ST_UPDATE;
+          st->final_update = out_of_iters;
+        }
+      }
+      break;
+    }
+    default: break;
+  }
+}
+
+// Per-wave context of a table-driven kernel.
+struct Item {
+  int sys, sb, s;
+  bool active;
+};
+
+__device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
+  Item it;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = wg * 4 + (threadIdx.x >> 6);
+  if (w >= nwork) { it.active = false; it.sys = 0; it.sb = 0; it.s = 0; return it; }
+  const uint32_t v = work[w];
+  it.sys = (int)(v >> 24);
+  it.sb = (int)(v & 0xffffffu);
+  it.s = it.sb * WAVE + lane_id();
+  it.active = true;
+  return it;
+}
+
+// Commit NV per-lane values of a system's reduction; the completing wave runs
+// the solver scalar step.
+__device__ __forceinline__ void sys_reduce(const SysDesc &d, int slot, int fin, int sb, double v[NV]) {
+  double tot[NV];
+  if (grid_reduce<NV>(v, d.part + (size_t)slot * NV * d.g.nb, d.cnt + slot, sb, d.g.nb, tot)) {
+    if (lane_id() == 0) finalize(d.st, fin, slot, tot);
+  }
+}
+
+template <class R> __device__ __forceinline__ double norm12(const cpx<R> v[12]) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+  return a;
+}
+
+// (a | b) = sum conj(a) b, accumulated in FP64
+template <class R> __device__ __forceinline__ void dot12(const cpx<R> a[12], const cpx<R> b[12], double &re, double &im) {
+  double r = 0.0, i = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const double ar = a[k].re, ai = a[k].im, br = b[k].re, bi = b[k].im;
+    r += ar * br + ai * bi;
+    i += ar * bi - ai * br;
+  }
+  re = r;
+  im = i;
+}
+
+}  // namespace qiral

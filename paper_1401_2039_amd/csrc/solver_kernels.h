@@ -1,0 +1,33 @@
+// Launchers of the grouped solver kernels (solver_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qiral {
+
+struct SysDesc;
+
+struct Launch {
+  const SysDesc *desc;   // device system table
+  const uint32_t *work;  // device work table: (system << 24) | 64-site block
+  int nwork;
+  hipStream_t stream;
+};
+
+enum : int { A_ONE = 0, A_KAPPA = 1, A_MKAPPA2 = 2, A_MKAPPA = 3 };
+
+void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
+             int red, int slot, int fin);
+void hop_sum(const Launch &l, bool haslo);
+void hop_upd(const Launch &l, int prec, bool bicg);
+void hop_res(const Launch &l, int par);
+void bnorm(const Launch &l);
+void cg1(const Launch &l, int prec);
+void cg2(const Launch &l, int prec);
+void bi_p(const Launch &l, int prec);
+void bi_s(const Launch &l, int prec);
+void bi_xr(const Launch &l, int prec);
+void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask);
+void bi_init(const Launch &l, int nsys);
+
+}  // namespace qiral

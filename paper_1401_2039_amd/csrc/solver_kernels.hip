@@ -1,0 +1,399 @@
+// Grouped kernels of the even-odd solvers (CGNR of Fig. "CG" on the Schur
+// system of the "schur" template, and BiCGStab), plus the FP64 reliable update
+// and true-residual kernels.  Every kernel takes the system table and the work
+// table; see solver_dev.h.
+#include "qiral_int.h"
+#include "solver_dev.h"
+#include "solver_kernels.h"
+
+namespace qiral {
+
+__device__ __forceinline__ double coef(int amode, double k) {
+  return amode == A_ONE ? 1.0 : amode == A_KAPPA ? k : amode == A_MKAPPA2 ? -k * k : -k;
+}
+
+template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &d) {
+  return S == S_F64 ? d.g64 : d.glo;
+}
+
+// out = a H in (EPI 0) or out = x + a H in (EPI 1), parity `par` out.
+// red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
+template <int S, int L, bool DAG, int EPI>
+__global__ __launch_bounds__(WG) void k_hop_sys(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                                int nwork, int fin_id, int fout, int fx, int par, int amode, int mask,
+                                                int red, int slot, int fin) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & mask)) return;
+  const bool live = it.s < d.g.vh;
+  cpx<R> acc[12];
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (live) {
+    FieldLd<S> ld{d.f[fin_id], d.npad};
+    hop_site<L, DAG>(d.g, links_of<S>(d), ld, it.s, par, acc);
+    const R a = (R)coef(amode, d.kappa);
+    if (EPI == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = cscale(a, acc[k]);
+    } else {
+      cpx<R> xv[12];
+      SpinorIO<S>::load(d.f[fx], it.s, d.npad, xv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = cadd(xv[k], cscale(a, acc[k]));
+      if (red == 3) { dot12(acc, xv, v[0], v[1]); v[2] = norm12(acc); }
+    }
+    SpinorIO<S>::store(d.f[fout], it.s, d.npad, acc);
+    if (red == 1) v[0] = norm12(acc);
+    if (red == 2) {
+      cpx<R> rt[12];
+      SpinorIO<S>::load(d.f[F_RT], it.s, d.npad, rt);
+      dot12(rt, acc, v[0], v[1]);
+    }
+  }
+  if (red) sys_reduce(d, slot, fin, it.sb, v);
+}
+
+// T64 = H_eo (XH + X): the hop of the current solution for the FP64 residual.
+template <bool HASLO>
+__global__ __launch_bounds__(WG) void k_hop_sum(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                                int nwork) {
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_UPDATE)) return;
+  if (it.s >= d.g.vh) return;
+  cpx<double> acc[12];
+  SumLd ld{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
+  hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, 0, acc);
+  SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc);
+}
+
+// Reliable update on the odd sites: y = XH + X; XH = y; X = 0;
+// r_hat = BH - (y - kappa^2 H_oe T64) in FP64; R = r_hat rounded to the iterate
+// precision; reduces ||r_hat||^2 (and (rt | r_hat) for BiCGStab).
+template <int SO, bool HASLO, bool BICG>
+__global__ __launch_bounds__(WG) void k_hop_upd(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                                int nwork) {
+  using RO = typename SpinorIO<SO>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_UPDATE)) return;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    cpx<double> acc[12], y[12], b[12];
+    FieldLd<S_F64> ld{d.f[F_T64], d.npad};
+    hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, 1, acc);
+    SumLd yl{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
+    yl(it.s, y);
+    if (HASLO) {
+      SpinorIO<S_F64>::store(d.f[F_XH], it.s, d.npad, y);
+      cpx<float> z[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) z[k] = cmake(0.f, 0.f);
+      SpinorIO<S_F32>::store(d.f[F_X], it.s, d.npad, z);
+    }
+    SpinorIO<S_F64>::load(d.f[F_BH], it.s, d.npad, b);
+    const double k2 = d.kappa * d.kappa;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], y[k]), cscale(k2, acc[k]));
+    v[0] = norm12(acc);
+    cpx<RO> r[12];
+    cvt12(acc, r);
+    SpinorIO<SO>::store(d.f[F_R], it.s, d.npad, r);
+    if (BICG && d.st->iter > 0) {
+      cpx<RO> rt[12];
+      SpinorIO<SO>::load(d.f[F_RT], it.s, d.npad, rt);
+      cpx<double> rtd[12];
+      cvt12(rt, rtd);
+      dot12(rtd, acc, v[1], v[2]);
+    }
+  }
+  sys_reduce(d, SL_UPD, FIN_UPDATE, it.sb, v);
+}
+
+// ||b - D x||^2 on the sites of parity p: B_p - X_p + kappa H X_{1-p}.
+__global__ __launch_bounds__(WG) void k_hop_res(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                                int nwork, int par) {
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  const int fin_id = par ? F_XE : F_XH, fb = par ? F_BO : F_BE, fx = par ? F_XH : F_XE;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    cpx<double> acc[12], x[12], b[12];
+    FieldLd<S_F64> ld{d.f[fin_id], d.npad};
+    hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, par, acc);
+    SpinorIO<S_F64>::load(d.f[fx], it.s, d.npad, x);
+    SpinorIO<S_F64>::load(d.f[fb], it.s, d.npad, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], x[k]), cscale(d.kappa, acc[k]));
+    v[0] = norm12(acc);
+  }
+  sys_reduce(d, par ? SL_RES_O : SL_RES_E, FIN_NONE, it.sb, v);
+}
+
+// ||b||^2 over both parities.
+__global__ __launch_bounds__(WG) void k_bnorm(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                              int nwork) {
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    cpx<double> a[12];
+    SpinorIO<S_F64>::load(d.f[F_BE], it.s, d.npad, a);
+    v[0] = norm12(a);
+    SpinorIO<S_F64>::load(d.f[F_BO], it.s, d.npad, a);
+    v[0] += norm12(a);
+  }
+  sys_reduce(d, SL_B, FIN_BNORM, it.sb, v);
+}
+
+// CGNR: X += alpha P; R -= alpha AP; ||R||^2
+template <int S, int XS>
+__global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                            int nwork) {
+  using R = typename SpinorIO<S>::R;
+  using RX = typename SpinorIO<XS>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    const double al = d.st->alpha;
+    cpx<R> p[12], r[12], ap[12];
+    cpx<RX> x[12];
+    SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+    SpinorIO<XS>::load(d.f[F_X], it.s, d.npad, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale((RX)al, cmake((RX)p[k].re, (RX)p[k].im)));
+    SpinorIO<XS>::store(d.f[F_X], it.s, d.npad, x);
+    SpinorIO<S>::load(d.f[F_R], it.s, d.npad, r);
+    SpinorIO<S>::load(d.f[F_AP], it.s, d.npad, ap);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[k] = csub(r[k], cscale((R)al, ap[k]));
+    SpinorIO<S>::store(d.f[F_R], it.s, d.npad, r);
+    v[0] = norm12(r);
+  }
+  sys_reduce(d, SL_R, FIN_NR, it.sb, v);
+}
+
+// CGNR: P = Z + beta P
+template <int S>
+__global__ __launch_bounds__(WG) void k_cg2(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                            int nwork) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  if (it.s >= d.g.vh) return;
+  const R be = (R)d.st->beta;
+  cpx<R> p[12], z[12];
+  SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+  SpinorIO<S>::load(d.f[F_Z], it.s, d.npad, z);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = cadd(z[k], cscale(be, p[k]));
+  SpinorIO<S>::store(d.f[F_P], it.s, d.npad, p);
+}
+
+// BiCGStab: P = R + beta (P - omega V)    (V lives in F_AP)
+template <int S>
+__global__ __launch_bounds__(WG) void k_bi_p(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                             int nwork) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  if (it.s >= d.g.vh) return;
+  const cpx<R> be = cmake((R)d.st->be_re, (R)d.st->be_im), om = cmake((R)d.st->om_re, (R)d.st->om_im);
+  cpx<R> p[12], r[12], vv[12];
+  SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+  SpinorIO<S>::load(d.f[F_R], it.s, d.npad, r);
+  SpinorIO<S>::load(d.f[F_AP], it.s, d.npad, vv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = cadd(r[k], cmul(be, csub(p[k], cmul(om, vv[k]))));
+  SpinorIO<S>::store(d.f[F_P], it.s, d.npad, p);
+}
+
+// BiCGStab: S = R - alpha V    (S lives in F_Z)
+template <int S>
+__global__ __launch_bounds__(WG) void k_bi_s(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                             int nwork) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  if (it.s >= d.g.vh) return;
+  const cpx<R> al = cmake((R)d.st->al_re, (R)d.st->al_im);
+  cpx<R> r[12], vv[12];
+  SpinorIO<S>::load(d.f[F_R], it.s, d.npad, r);
+  SpinorIO<S>::load(d.f[F_AP], it.s, d.npad, vv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r[k] = csub(r[k], cmul(al, vv[k]));
+  SpinorIO<S>::store(d.f[F_Z], it.s, d.npad, r);
+}
+
+// BiCGStab: X += alpha P + omega S; R = S - omega T; reduces (rt | R) and ||R||^2
+template <int S, int XS>
+__global__ __launch_bounds__(WG) void k_bi_xr(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                              int nwork) {
+  using R = typename SpinorIO<S>::R;
+  using RX = typename SpinorIO<XS>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    const cpx<RX> al = cmake((RX)d.st->al_re, (RX)d.st->al_im), om = cmake((RX)d.st->om_re, (RX)d.st->om_im);
+    cpx<R> p[12], s[12], t[12], rt[12];
+    cpx<RX> x[12];
+    SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+    SpinorIO<S>::load(d.f[F_Z], it.s, d.npad, s);
+    SpinorIO<XS>::load(d.f[F_X], it.s, d.npad, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      x[k] = cadd(x[k], cadd(cmul(al, cmake((RX)p[k].re, (RX)p[k].im)), cmul(om, cmake((RX)s[k].re, (RX)s[k].im))));
+    SpinorIO<XS>::store(d.f[F_X], it.s, d.npad, x);
+    SpinorIO<S>::load(d.f[F_T], it.s, d.npad, t);
+    const cpx<R> omr = cmake((R)d.st->om_re, (R)d.st->om_im);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = csub(s[k], cmul(omr, t[k]));
+    SpinorIO<S>::store(d.f[F_R], it.s, d.npad, s);
+    SpinorIO<S>::load(d.f[F_RT], it.s, d.npad, rt);
+    dot12(rt, s, v[0], v[1]);
+    v[2] = norm12(s);
+  }
+  sys_reduce(d, SL_BI3, FIN_BI_RHO, it.sb, v);
+}
+
+// copy a half-field of the iterate precision: dst = src
+template <int S>
+__global__ __launch_bounds__(WG) void k_copy(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                             int nwork, int fsrc, int fdst, int mask) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & mask)) return;
+  if (it.s >= d.g.vh) return;
+  cpx<R> a[12];
+  SpinorIO<S>::load(d.f[fsrc], it.s, d.npad, a);
+  SpinorIO<S>::store(d.f[fdst], it.s, d.npad, a);
+}
+
+// BiCGStab start: rho = (r~ | r) = ||r||^2 with r~ = r, alpha = omega = 1, beta = 0.
+__global__ void k_bi_init(const SysDesc *__restrict__ sdesc, int nsys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsys) return;
+  SysState *st = sdesc[i].st;
+  if (!(st->status & ST_RUN)) return;
+  st->rho_re = st->nr; st->rho_im = 0.0;
+  st->rho0_re = st->nr; st->rho0_im = 0.0;
+  st->al_re = 1.0; st->al_im = 0.0;
+  st->om_re = 1.0; st->om_im = 0.0;
+  st->be_re = 0.0; st->be_im = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+static inline dim3 grid_of(int nwork) { return dim3(wg_count(nwork)); }
+
+template <int S, int L>
+static void hop_sys_t(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
+                      int slot, int fin) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+#define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot, fin
+  if (!dag) {
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1>), g, b, 0, l.stream, QARGS);
+  } else {
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1>), g, b, 0, l.stream, QARGS);
+  }
+#undef QARGS
+}
+
+void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
+             int red, int slot, int fin) {
+  if (prec == S_F64) hop_sys_t<S_F64, L_F64R18>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
+  else if (prec == S_F32) hop_sys_t<S_F32, L_F32R12>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
+  else hop_sys_t<S_F16S, L_F16R12>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
+}
+
+void hop_sum(const Launch &l, bool haslo) {
+  if (haslo) hipLaunchKernelGGL(k_hop_sum<true>, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL(k_hop_sum<false>, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void hop_upd(const Launch &l, int prec, bool bicg) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+#define QU(SO, LO, BI) hipLaunchKernelGGL((k_hop_upd<SO, LO, BI>), g, b, 0, l.stream, l.desc, l.work, l.nwork)
+  if (prec == S_F64) { if (bicg) QU(S_F64, false, true); else QU(S_F64, false, false); }
+  else if (prec == S_F32) { if (bicg) QU(S_F32, true, true); else QU(S_F32, true, false); }
+  else { if (bicg) QU(S_F16S, true, true); else QU(S_F16S, true, false); }
+#undef QU
+}
+
+void hop_res(const Launch &l, int par) {
+  hipLaunchKernelGGL(k_hop_res, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork, par);
+}
+
+void bnorm(const Launch &l) {
+  hipLaunchKernelGGL(k_bnorm, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void cg1(const Launch &l, int prec) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL((k_cg1<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else if (prec == S_F32) hipLaunchKernelGGL((k_cg1<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_cg1<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void cg2(const Launch &l, int prec) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL(k_cg2<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else if (prec == S_F32) hipLaunchKernelGGL(k_cg2<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL(k_cg2<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void bi_p(const Launch &l, int prec) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL(k_bi_p<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else if (prec == S_F32) hipLaunchKernelGGL(k_bi_p<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL(k_bi_p<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void bi_s(const Launch &l, int prec) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL(k_bi_s<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else if (prec == S_F32) hipLaunchKernelGGL(k_bi_s<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL(k_bi_s<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void bi_xr(const Launch &l, int prec) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL((k_bi_xr<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else if (prec == S_F32) hipLaunchKernelGGL((k_bi_xr<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_bi_xr<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask) {
+  const dim3 g = grid_of(l.nwork), b(WG);
+  if (prec == S_F64) hipLaunchKernelGGL(k_copy<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
+  else if (prec == S_F32) hipLaunchKernelGGL(k_copy<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
+  else hipLaunchKernelGGL(k_copy<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
+}
+
+void bi_init(const Launch &l, int nsys) {
+  hipLaunchKernelGGL(k_bi_init, dim3((nsys + 63) / 64), dim3(64), 0, l.stream, l.desc, nsys);
+}
+
+}  // namespace qiral

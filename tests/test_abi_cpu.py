@@ -1,0 +1,88 @@
+"""The C ABI library on a machine without a GPU: it loads, exports every function
+include/qiral.h declares, sizes packed fields correctly, and rejects invalid
+arguments with the right status before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1401_2039_amd import _lib as L
+from paper_1401_2039_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qiral.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built (run __graft_entry__.build())")
+
+
+def header_functions():
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(qiral_[a-z_A-Z0-9]+)\s*\(", txt)))
+
+
+def test_exports_match_header():
+    lib = L.load()
+    names = header_functions()
+    assert names and set(names) == set(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    lib = L.load()
+    for s in range(8):
+        assert lib.qiral_status_string(s)
+    assert lib.qiral_status_string(99) == b"unknown status"
+
+
+def test_field_bytes():
+    # 4^4: 128 sites per parity -> 2 blocks of 64
+    assert api.qiral_field_bytes((4, 4, 4, 4), L.ODD, L.F64) == 128 * 192
+    assert api.qiral_field_bytes((4, 4, 4, 4), L.FULL, L.F32, 3) == 2 * 128 * 96 * 3
+    assert api.qiral_field_bytes((4, 4, 4, 4), L.EVEN, L.F16S) == 128 * 52
+    # 2^4: 8 sites per parity, padded to one block of 64
+    assert api.qiral_field_bytes((2, 2, 2, 2), L.EVEN, L.F64) == 64 * 192
+    assert api.qiral_field_bytes((24, 24, 24, 48), L.ODD, L.F16S) == 331776 * 52
+    # invalid -> 0
+    assert api.qiral_field_bytes((3, 4, 4, 4), L.ODD, L.F64) == 0
+    assert api.qiral_field_bytes((4, 4, 4, 4), 7, L.F64) == 0
+    assert api.qiral_field_bytes((4, 4, 4, 4), L.ODD, 9) == 0
+    assert api.qiral_field_bytes((4, 4, 4, 4), L.ODD, L.F64, 0) == 0
+
+
+def _create(dims, gauge=1, kappa=0.12, mu=0.0, lo=0, recon=L.RECON12):
+    lib = L.load()
+    h = ctypes.c_void_p()
+    return lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), kappa, mu,
+                                    ctypes.c_void_p(gauge), lo, recon, None), h
+
+
+def test_create_validation():
+    lib = L.load()
+    assert lib.qiral_lattice_create(None, L.dims_arg((4, 4, 4, 4)), 0.1, 0.0, ctypes.c_void_p(1), 0, 12, None) == L.ERR_INVALID_ARG
+    assert _create((3, 4, 4, 4))[0] == L.ERR_BAD_DIMS
+    assert _create((4, 4, 0, 4))[0] == L.ERR_BAD_DIMS
+    assert _create((4, 4, 4, 4), gauge=0)[0] == L.ERR_INVALID_ARG
+    assert _create((4, 4, 4, 4), kappa=float("nan"))[0] == L.ERR_INVALID_ARG
+    assert _create((4, 4, 4, 4), lo=8)[0] == L.ERR_INVALID_ARG
+    assert _create((4, 4, 4, 4), recon=7)[0] == L.ERR_INVALID_ARG
+    assert _create((4, 4, 4, 4), mu=0.1)[0] == L.ERR_UNSUPPORTED
+    st, h = _create((4, 4, 4, 4), lo=L.LINKS_F32, recon=L.RECON18)
+    assert st == L.ERR_UNSUPPORTED and h.value is None
+    assert b"twisted" in lib.qiral_last_error() or b"reconstruct" in lib.qiral_last_error()
+
+
+def test_null_handles_rejected():
+    lib = L.load()
+    one = ctypes.c_void_p(1)
+    assert lib.qiral_lattice_destroy(None) == L.ERR_INVALID_ARG
+    assert lib.qiral_field_import(None, one, one, L.ODD, L.F64, 1, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_field_export(None, one, one, L.ODD, L.F64, 1, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_dslash_eo(None, one, one, 0, 0, L.F64, 1, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_apply_M(None, one, one, one, L.OP_D, L.F64, 1, None) == L.ERR_INVALID_ARG
+    p = api.solve_params()
+    info = (L.SolveInfo * 1)()
+    assert lib.qiral_solve(None, one, one, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_solve_batch(None, None, None, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_lattice_query(None, None, None) == L.ERR_INVALID_ARG

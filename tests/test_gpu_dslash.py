@@ -1,0 +1,157 @@
+"""GPU parity of the packed layouts, the hopping term H_{p,1-p} and the operators
+D, D^dagger, S, S^dagger against the complex128 oracle, element by element.
+
+Bars: FP64 within 1e-12 relative (and 1e-12 of the largest element); FP32 with
+reconstruct-12 links against the oracle applied to the same rounded inputs
+within 2e-6; F16S against the oracle on the same rounded inputs within the FP16
+quantisation of the output (2^-11 of each site's scale, plus FP32 rounding).
+Sizes: 4^4 (two blocks), 2^4 and 4x2x2x4 (a block only partly filled), 6x4x2x4
+(a ragged last block), and 16^3x32; 24^3x48 on sampled sites."""
+import numpy as np
+import pytest
+import torch
+
+import latgen
+from oracle import storage, wilson as W
+import paper_1401_2039_amd as q
+from gpu_util import say, dev, host, parity_rel, parity_maxabs
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 4, 4), (2, 2, 2, 2), (4, 2, 2, 4), (6, 4, 2, 4), (16, 16, 16, 32)]
+
+
+def _cfg(dims, seed=0, kind="haar"):
+    return latgen.small_config(dims, seed=seed, kind=kind, eps=0.4, nrhs=2)
+
+
+@pytest.fixture(scope="module", params=DIMS, ids=lambda d: "x".join(map(str, d)))
+def setup(request):
+    dims = request.param
+    say("dslash setup", dims)
+    cfg = _cfg(dims, kind="expih" if dims[0] >= 16 else "haar")
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    return dims, cfg, lat
+
+
+def test_import_export_roundtrip(setup):
+    dims, cfg, lat = setup
+    say("roundtrip", dims)
+    b = dev(cfg["b"])
+    for prec, rounder in ((q.F64, lambda a: a), (q.F32, storage.round_f32), (q.F16S, storage.round_f16s)):
+        packed = lat.import_field(b, q.FULL, prec)
+        back = host(lat.export_field(packed, q.FULL, prec, nrhs=2))
+        want = rounder(cfg["b"])
+        assert np.array_equal(back, want), prec   # the rounding decisions are bit-exact
+        for par in (0, 1):
+            half = lat.import_field(b, par, prec)
+            out = lat.canon(2)
+            lat.export_field(half, par, prec, nrhs=2, out=out)
+            got = host(out)
+            for r in range(2):
+                assert np.array_equal(W.project(got[r], par), W.project(want[r], par))
+                assert np.count_nonzero(W.project(got[r], 1 - par)) == 0
+
+
+@pytest.mark.parametrize("prec", [q.F64, q.F32, q.F16S], ids=["f64", "f32", "f16s"])
+@pytest.mark.parametrize("dag", [0, 1])
+def test_dslash_eo(setup, prec, dag):
+    dims, cfg, lat = setup
+    say("dslash_eo", dims, prec, dag)
+    U, b = cfg["U"], cfg["b"]
+    if prec == q.F64:
+        Ur, br = U, b
+    elif prec == q.F32:
+        Ur, br = storage.round_links_r12(U, np.complex64), storage.round_f32(b)
+    else:
+        Ur, br = storage.round_links_r12(U, "f16"), storage.round_f16s(b)
+    inp = lat.import_field(dev(b), q.FULL, prec)
+    hb = q.qiral_field_bytes(dims, q.EVEN, prec)
+    for p in (0, 1):
+        # input: the (1-p) halves of both right-hand sides, packed consecutively
+        src = torch.cat([inp[r * 2 * hb + (1 - p) * hb: r * 2 * hb + (2 - p) * hb] for r in range(2)])
+        out = lat.field(q.EVEN, prec, nrhs=2)
+        lat.dslash_eo(out, src, p, dag, prec, nrhs=2)
+        got = host(lat.export_field(out, p, prec, nrhs=2))
+        for r in range(2):
+            want = W.hop_eo(Ur, br[r], p, dagger=bool(dag))
+            rel = parity_rel(got[r], want, p)
+            if prec == q.F64:
+                assert rel < 1e-12 and parity_maxabs(got[r], want, p) < 1e-12 * np.abs(want).max(), rel
+            elif prec == q.F32:
+                assert rel < 2e-6, rel
+            else:
+                # output quantised to FP16 with a per-site scale
+                diff = np.abs(W.project(got[r], p) - want).reshape(-1, 12).max(axis=1)
+                scale = np.abs(np.stack([want.real, want.imag])).reshape(2, -1, 12).max(axis=(0, 2))
+                assert np.all(diff <= (2.0 ** -11) * scale * 1.01 + 1e-6 * scale.max()), diff.max()
+            assert np.count_nonzero(W.project(got[r], 1 - p)) == 0
+
+
+@pytest.mark.parametrize("op", [q.OP_D, q.OP_DDAG, q.OP_SCHUR, q.OP_SCHUR_DAG], ids=["D", "Ddag", "S", "Sdag"])
+def test_apply_M_f64(setup, op):
+    dims, cfg, lat = setup
+    say("apply_M", dims, op)
+    U, b, k = cfg["U"], cfg["b"][0], 0.12
+    if op in (q.OP_D, q.OP_DDAG):
+        inp = lat.import_field(dev(b[None]), q.FULL, q.F64)
+        out = lat.field(q.FULL, q.F64)
+        lat.apply_M(out, inp, None, op, q.F64)
+        got = host(lat.export_field(out, q.FULL, q.F64))[0]
+        want = W.apply_D(U, k, 0.0, b) if op == q.OP_D else W.apply_Ddag(U, k, 0.0, b)
+        rel = np.sqrt(W.norm2(got - want) / W.norm2(want))
+    else:
+        bo = W.project(b, 1)
+        inp = lat.import_field(dev(b[None]), q.ODD, q.F64)
+        out = lat.field(q.ODD, q.F64)
+        tmp = lat.field(q.EVEN, q.F64)
+        lat.apply_M(out, inp, tmp, op, q.F64)
+        got = host(lat.export_field(out, q.ODD, q.F64))[0]
+        want = W.schur(U, k, 0.0, bo, dagger=(op == q.OP_SCHUR_DAG))
+        rel = parity_rel(got, want, 1)
+    assert rel < 1e-12, rel
+
+
+def test_dslash_sampled_24x48():
+    """24^3x48 in the launch configuration of the benchmarks, checked on sampled
+    sites against the oracle's single-site hop."""
+    dims = (24, 24, 24, 48)
+    say("dslash sampled", dims)
+    cfg = latgen.make_config(2, with_source=False)
+    U = cfg["U"]
+    psi = latgen.gaussian_source(2, 0, dims, 1)
+    lat = q.Lattice(dims, cfg["kappa"], U)
+    rng = np.random.default_rng(5)
+    for prec in (q.F64, q.F32):
+        inp = lat.import_field(dev(psi), q.FULL, prec)
+        hb = q.qiral_field_bytes(dims, q.EVEN, prec)
+        Ur, pr = (U, psi[0]) if prec == q.F64 else (None, storage.round_f32(psi[0]))
+        for p in (0, 1):
+            out = lat.field(q.EVEN, prec)
+            lat.dslash_eo(out, inp[(1 - p) * hb:(2 - p) * hb], p, 0, prec)
+            got = host(lat.export_field(out, p, prec))[0]
+            for _ in range(40):
+                x = [int(rng.integers(0, L)) for L in dims]
+                x[0] = (x[0] & ~1) | ((p + x[1] + x[2] + x[3]) & 1)
+                src = W.project(pr, 1 - p)
+                if prec == q.F64:
+                    want = W.hop_site(U, src, tuple(x))
+                    tol = 1e-12
+                else:
+                    # FP32 links rounded through reconstruct-12, only around this site
+                    want = W.hop_site(_r12_near(U, x), src, tuple(x))
+                    tol = 2e-6
+                g = got[x[3], x[2], x[1], x[0]]
+                assert np.abs(g - want).max() <= tol * np.abs(want).max() * 4, (prec, x)
+
+
+def _r12_near(U, x):
+    """Links rounded as an FP32 reconstruct-12 store on the 9 sites a hop at x reads."""
+    Ur = U.copy()
+    for mu in range(4):
+        for dx in (0, -1):
+            y = list(x)
+            y[mu] = (y[mu] + dx) % U.shape[3 - mu]
+            t, z, yy, xx = y[3], y[2], y[1], y[0]
+            Ur[t, z, yy, xx] = storage.round_links_r12(U[t, z, yy, xx], np.complex64)
+    return Ur

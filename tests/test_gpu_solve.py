@@ -1,0 +1,138 @@
+"""GPU solves through qiral_solve / qiral_solve_batch, judged by the oracle.
+
+Every solve must reach the requested true residual ||b - D x|| / ||b|| <= tol,
+computed by the oracle's complex128 operator from the exported x; the plain
+FP64 even-odd CGNR must also take the oracle's iteration count within 2 and
+agree with the oracle's solution to the error the residual allows."""
+import numpy as np
+import pytest
+import torch
+
+import latgen
+from oracle import solvers as S, wilson as W
+import paper_1401_2039_amd as q
+from gpu_util import say, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c0():
+    say("solve setup C0")
+    cfg = latgen.make_config(0)
+    lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
+    xo, info = S.solve_eo_cgnr(cfg["U"], cfg["kappa"], 0.0, cfg["b"][0], tol=1e-10)
+    return cfg, lat, xo, info
+
+
+def _resid(cfg, x, r=0):
+    return S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, x, cfg["b"][r])
+
+
+def test_cgnr_f64_c0(c0):
+    cfg, lat, xo, oinfo = c0
+    say("cgnr f64 C0")
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10)
+    xg = host(x)[0]
+    assert st == 0 and info[0]["converged"] == 1
+    res = _resid(cfg, xg)
+    assert res <= 1e-10 and abs(res - info[0]["true_rel_resid"]) <= 1e-3 * res
+    assert abs(info[0]["iterations"] - oinfo["iterations"]) <= 2
+    assert np.sqrt(W.norm2(xg - xo) / W.norm2(xo)) < 1e-9
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_bicgstab_f64_c0(c0, graph):
+    cfg, lat, xo, _ = c0
+    say("bicgstab f64 C0 graph", graph)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.BICGSTAB_EO, use_graph=graph)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert _resid(cfg, host(x)[0]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [q.F32, q.F16S], ids=["f32", "f16s"])
+@pytest.mark.parametrize("solver", [q.CGNR_EO, q.BICGSTAB_EO], ids=["cgnr", "bicgstab"])
+def test_mixed_c0(c0, prec, solver):
+    cfg, lat, xo, _ = c0
+    say("mixed C0", prec, solver)
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, inner_prec=prec, solver=solver, delta=0.1)
+    assert st == 0, info
+    assert info[0]["reliable_updates"] >= 1
+    assert _resid(cfg, host(x)[0]) <= 1e-10
+
+
+def test_multi_rhs_equals_single():
+    dims = (4, 4, 2, 4)
+    say("multi-rhs", dims)
+    cfg = latgen.small_config(dims, seed=31, kind="expih", eps=0.4, nrhs=5)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    for prec in (q.F64, q.F32):
+        x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, inner_prec=prec)
+        assert st == 0
+        xs = host(x)
+        for r in range(5):
+            assert S.true_rel_residual(cfg["U"], 0.12, 0.0, xs[r], cfg["b"][r]) <= 1e-10
+            x1, st1, _ = lat.solve(dev(cfg["b"][r:r + 1]), tol=1e-10, inner_prec=prec)
+            assert st1 == 0
+            if prec == q.F64:
+                # same reductions in the same order: the batch solve equals the single one bit for bit
+                assert np.array_equal(host(x1)[0], xs[r])
+
+
+def test_batch_uneven():
+    say("batch uneven")
+    dimss = [(4, 4, 4, 4), (2, 2, 4, 2), (6, 4, 2, 4)]
+    cfgs = [latgen.small_config(d, seed=40 + i, kind="expih", eps=0.3, kappa=0.10 + 0.01 * i) for i, d in enumerate(dimss)]
+    lats = [q.Lattice(c["dims"], c["kappa"], c["U"]) for c in cfgs]
+    bs = [dev(c["b"]) for c in cfgs]
+    xs = [torch.zeros_like(b) for b in bs]
+    for prec in (q.F64, q.F32):
+        st, info = q.qiral_solve_batch([l.handle for l in lats], dimss, xs, bs, q.solve_params(tol=1e-10, inner_prec=prec))
+        assert st == 0
+        for c, x, inf in zip(cfgs, xs, info):
+            res = S.true_rel_residual(c["U"], c["kappa"], 0.0, host(x)[0], c["b"][0])
+            assert res <= 1e-10 and inf["converged"] == 1
+
+
+def test_deterministic(c0):
+    cfg, lat, _, _ = c0
+    say("determinism")
+    a, _, ia = lat.solve(dev(cfg["b"]), tol=1e-10, inner_prec=q.F32)
+    b, _, ib = lat.solve(dev(cfg["b"]), tol=1e-10, inner_prec=q.F32)
+    assert torch.equal(a, b) and ia[0]["iterations"] == ib[0]["iterations"]
+
+
+def test_not_converged_and_nonfinite(c0):
+    cfg, lat, _, _ = c0
+    say("failure paths")
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, maxiter=1)
+    assert st == q._lib.ERR_NOT_CONVERGED and info[0]["iterations"] == 1 and info[0]["true_rel_resid"] > 1e-10
+    bad = cfg["b"].copy()
+    bad[0, 0, 0, 0, 1, 2, 3] = np.nan
+    with pytest.raises(q.QiralError) as e:
+        lat.solve(dev(bad), tol=1e-10)
+    assert e.value.status == q._lib.ERR_NONFINITE
+
+
+def test_x0_guess(c0):
+    cfg, lat, xo, _ = c0
+    say("x0 guess")
+    x = dev(xo[None])
+    x, st, info = lat.solve(dev(cfg["b"]), x_canon=x, tol=1e-10, x0_is_guess=1)
+    assert st == 0 and info[0]["iterations"] <= 2
+
+
+def test_cgnr_c1_mixed_vs_f64():
+    """16^3x32, exp(0.3 i H) links: FP64 eo-CGNR and the FP32 reconstruct-12 solve with
+    FP64 reliable updates both reach 1e-10, judged by the oracle."""
+    say("C1 solves")
+    cfg = latgen.make_config(1)
+    lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
+    for prec in (q.F64, q.F32, q.F16S):
+        x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, inner_prec=prec)
+        say("C1", prec, info[0])
+        assert st == 0
+        assert _resid(cfg, host(x)[0]) <= 1e-10
