@@ -1,0 +1,359 @@
+"""Benchmark of the even-odd Wilson-Dirac solve on one MI355X.
+
+A step is one whole solve of the 16^3x32 workload (exp(0.3 i H) links, kappa
+0.12, one Gaussian source): import of the canonical source, Schur source,
+even-odd CGNR with the hop in FP32 (reconstruct-12 links) and FP64 reliable
+updates, reconstruction of the even sites, FP64 true residual and export of the
+canonical solution, to ||b - D x|| / ||b|| <= 1e-10.  Inputs are resident in
+device memory before the timed region.
+
+value: Dslash GFLOP/s sustained over the solve, i.e. 1320 flop per output site
+and hop application times the hop applications the solve made, divided by the
+solve's wall time.  The JSON line also carries the solve's time to solution, the
+plain FP64 even-odd CGNR on the same GPU for comparison, a roofline entry for the
+dominant kernel (the FP32 reconstruct-12 even-odd hop, timed with HIP events on
+the stream it runs on) and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--suite]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FLOP_PER_SITE = 1320           # one even-odd hop, per output site
+# algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output spinor
+HOP_BYTES = {"f64": 8 * 144 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--hop-reps", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle CGNR iterations timed for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--suite", action="store_true", help="also measure the other workloads (stderr JSON lines)")
+    ap.add_argument("--suite-out", default=None, help="append the suite's JSON lines to this file")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import latgen
+    import paper_1401_2039_amd as q
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    t_gen = time.time()
+    cfg = latgen.make_config(1)
+    log(f"[bench] generated 16^3x32 inputs in {time.time() - t_gen:.1f}s")
+    dims, kappa = cfg["dims"], cfg["kappa"]
+    vh = int(np.prod(dims)) // 2
+    lat = q.Lattice(dims, kappa, cfg["U"])
+    b = torch.from_numpy(cfg["b"]).to(dev)
+    x = torch.zeros_like(b)
+    stream = torch.cuda.current_stream()
+
+    def solve(prec, use_graph=0):
+        st, info = q.qiral_solve(lat.handle, dims, x, b, 1,
+                                 q.solve_params(tol=1e-10, inner_prec=prec, delta=0.1, use_graph=use_graph))
+        if st != 0:
+            raise RuntimeError(f"solve failed: status {st} {info}")
+        return info[0]
+
+    # ---- timed steps: mixed-precision solve
+    for _ in range(args.warmup):
+        solve(q.F32)
+    torch.cuda.synchronize()
+    hops, times, infos = 0, [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        info = solve(q.F32)
+        times.append(time.perf_counter() - ts)
+        hops += info["hop_applications"]
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = FLOP_PER_SITE * vh * hops / elapsed / 1e9
+    log(f"[bench] mixed F32 solve: {elapsed / args.steps * 1e3:.2f} ms/solve, iterations {infos[-1]['iterations']}, "
+        f"reliable updates {infos[-1]['reliable_updates']}, true residual {infos[-1]['true_rel_resid']:.2e}")
+
+    # ---- plain FP64 even-odd CGNR on the same GPU (comparison, outside the timed region)
+    f64_times = []
+    for k in range(3):
+        ts = time.perf_counter()
+        i64 = solve(q.F64)
+        if k:
+            f64_times.append(time.perf_counter() - ts)
+    log(f"[bench] FP64 solve: {statistics.median(f64_times) * 1e3:.2f} ms, iterations {i64['iterations']}")
+
+    # ---- roofline of the dominant kernel: the FP32 reconstruct-12 even-odd hop
+    psi = torch.from_numpy(latgen.gaussian_source(1, 0, dims, 1)).to(dev)
+    src = lat.import_field(psi, q.ODD, q.F32)
+    out = lat.field(q.EVEN, q.F32)
+    for _ in range(10):
+        lat.dslash_eo(out, src, 0, 0, q.F32)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.hop_reps):
+        lat.dslash_eo(out, src, 0, 0, q.F32)
+    e1.record(stream)
+    e1.synchronize()
+    hop_us = e0.elapsed_time(e1) * 1e3 / args.hop_reps
+    hop_bytes = HOP_BYTES["f32"] * vh
+    achieved = hop_bytes / (hop_us * 1e-6) / 1e9
+    dslash_gflops = FLOP_PER_SITE * vh / (hop_us * 1e-6) / 1e9
+    log(f"[bench] F32 hop 16^3x32: {hop_us:.2f} us/launch, {achieved:.0f} GB/s algorithmic, {dslash_gflops:.0f} GFLOP/s")
+
+    # ---- CPU oracle on a bounded sample: a few CGNR iterations of the same workload
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, args.cpu_iters)
+
+    res = {
+        "metric": "Dslash GFLOP/s + %HBM roofline; time-to-1e-10 solve, mixed/learned vs FP64 CG",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16^3x32 lattice, exp(0.3iH) links, kappa=0.12, 1 Gaussian RHS: even-odd CGNR, "
+                               "FP32 reconstruct-12 hop + FP64 reliable updates, to 1e-10 true residual",
+                   "dims": list(dims), "kappa": kappa, "nrhs": 1, "tol": 1e-10},
+        "time_to_solution_s": round(statistics.median(times), 6),
+        "fp64_time_to_solution_s": round(statistics.median(f64_times), 6),
+        "speedup_vs_fp64_cg": round(statistics.median(f64_times) / statistics.median(times), 3),
+        "iterations": infos[-1]["iterations"],
+        "fp64_iterations": i64["iterations"],
+        "reliable_updates": infos[-1]["reliable_updates"],
+        "true_rel_resid": infos[-1]["true_rel_resid"],
+        "dslash_gflops": round(dslash_gflops, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_hop<S_F32,L_F32R12,false,0> (qiral_dslash_eo, F32)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launch_us": round(hop_us, 3), "bytes_per_launch": hop_bytes,
+                     "fits_last_level_cache": True},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    if args.suite:
+        suite(lat, q, latgen, np, torch, args.suite_out)
+    lat.close()
+
+
+def cpu_baseline(cfg, iters):
+    """The oracle as it is, single thread, on `iters` CGNR iterations of the same lattice."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import solvers, wilson
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    vh = int(np.prod(cfg["dims"])) // 2
+    with threadpool_limits(limits=1):
+        bhat = wilson.schur_source(U, k, 0.0, b)
+        A = lambda v: wilson.schur(U, k, 0.0, v)
+        Ad = lambda v: wilson.schur(U, k, 0.0, v, dagger=True)
+        t0 = time.perf_counter()
+        solvers.cgnr(A, Ad, bhat, eps=0.0, maxiter=iters)
+        dt = time.perf_counter() - t0
+    hops = 2 + 4 * iters   # initial S^dagger r, then S and S^dagger per iteration
+    val = FLOP_PER_SITE * vh * hops / dt / 1e9
+    log(f"[bench] oracle: {iters} CGNR iterations on 16^3x32 in {dt:.1f}s ({val:.3f} GFLOP/s)")
+    return {"value": round(val, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} CGNR iterations (plus the initial S^dagger r) of the oracle on the same 16^3x32 "
+                      f"Schur system, {dt:.1f}s, BLAS limited to 1 thread",
+            "seconds": round(dt, 3)}
+
+
+def _emit(rec, path):
+    log("[suite] " + json.dumps(rec))
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+
+
+def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None):
+    """Average duration of one even-odd hop launch (HIP events on the launch stream):
+    warm (back to back) and, with a flush buffer, cold (the 256 MB last-level
+    cache overwritten before every launch)."""
+    import numpy as np
+    import latgen
+    vh = int(np.prod(dims)) // 2
+    psi = torch.from_numpy(latgen.gaussian_source(5, 0, dims, nrhs)).cuda()
+    src = lat.import_field(psi, q.ODD, prec)
+    out = lat.field(q.EVEN, prec, nrhs)
+    del psi
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lat.dslash_eo(out, src, 0, 0, prec, nrhs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lat.dslash_eo(out, src, 0, 0, prec, nrhs)
+    e1.record(stream)
+    e1.synchronize()
+    warm = e0.elapsed_time(e1) * 1e3 / reps
+    cold = None
+    if flush is not None:
+        tot = 0.0
+        n = max(5, reps // 10)
+        for _ in range(n):
+            flush.add_(1)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.dslash_eo(out, src, 0, 0, prec, nrhs)
+            b.record(stream)
+            b.synchronize()
+            tot += a.elapsed_time(b) * 1e3
+        cold = tot / n
+    key = {q.F64: "f64", q.F32: "f32", q.F16S: "f16s"}[prec]
+    link_b = {"f64": 144, "f32": 48, "f16s": 24}[key] * 8
+    sp_b = {"f64": 192, "f32": 96, "f16s": 52}[key]
+    bytes_ = vh * (link_b + 2 * sp_b * nrhs)
+    res = {"kind": "hop", "dims": list(dims), "prec": key, "nrhs": nrhs, "bytes_per_launch": bytes_,
+           "warm_us": round(warm, 3), "warm_GBs": round(bytes_ / warm / 1e3, 1),
+           "warm_GFLOPs": round(FLOP_PER_SITE * vh * nrhs / warm / 1e3, 1),
+           "warm_frac_hbm": round(bytes_ / warm / 1e3 / HBM_PEAK_GBS, 4),
+           "fits_last_level_cache": bytes_ < 256e6}
+    if cold is not None:
+        res.update({"cold_us": round(cold, 3), "cold_GBs": round(bytes_ / cold / 1e3, 1),
+                    "cold_GFLOPs": round(FLOP_PER_SITE * vh * nrhs / cold / 1e3, 1),
+                    "cold_frac_hbm": round(bytes_ / cold / 1e3 / HBM_PEAK_GBS, 4)})
+    return res
+
+
+def suite(lat1, q, latgen, np, torch, path=None):
+    """Extra measurements: hop throughput of every storage class on the workloads'
+    lattices (warm and cache-flushed) and time to solution of each solver form."""
+    import time as _t
+    flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    dims1 = (16, 16, 16, 32)
+    for prec in (q.F64, q.F32, q.F16S):
+        _emit(hop_rates(q, lat1, dims1, torch, prec, flush=flush), path)
+
+    def timed_solve(lat, b, reps=2, **kw):
+        x = torch.zeros_like(b)
+        st, info = q.qiral_solve(lat.handle, lat.dims, x, b, b.shape[0], q.solve_params(**kw))
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = _t.perf_counter()
+            st, info = q.qiral_solve(lat.handle, lat.dims, x, b, b.shape[0], q.solve_params(**kw))
+            ts.append(_t.perf_counter() - t0)
+        return min(ts), st, info, x
+
+    # 16^3x32 solver forms
+    cfg = latgen.make_config(1)
+    b1 = torch.from_numpy(cfg["b"]).cuda()
+    for name, kw in [("cgnr_f64", dict(inner_prec=q.F64)), ("cgnr_f32", dict(inner_prec=q.F32)),
+                     ("cgnr_f16s", dict(inner_prec=q.F16S)), ("bicgstab_f64", dict(solver=q.BICGSTAB_EO)),
+                     ("bicgstab_f32", dict(solver=q.BICGSTAB_EO, inner_prec=q.F32)),
+                     ("cgnr_f32_graph", dict(inner_prec=q.F32, use_graph=1))]:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            t, st, info, _ = timed_solve(lat1, b1, tol=1e-10, **kw)
+        _emit({"kind": "solve", "workload": "16^3x32 eps0.3 k0.12 1rhs", "form": name, "seconds": round(t, 6),
+               "status": st, "iterations": info[0]["iterations"], "reliable_updates": info[0]["reliable_updates"],
+               "true_rel_resid": info[0]["true_rel_resid"], "hops": info[0]["hop_applications"]}, path)
+
+    # 4^4 Haar (plain method): GPU FP64 eo-CGNR vs the oracle in CPU seconds
+    c0 = latgen.make_config(0)
+    lat0 = q.Lattice(c0["dims"], c0["kappa"], c0["U"])
+    b0 = torch.from_numpy(c0["b"]).cuda()
+    t, st, info, _ = timed_solve(lat0, b0, reps=5, tol=1e-10)
+    from oracle import solvers
+    t0 = _t.perf_counter()
+    _, oinfo = solvers.solve_eo_cgnr(c0["U"], c0["kappa"], 0.0, c0["b"][0], tol=1e-10)
+    tcpu = _t.perf_counter() - t0
+    _emit({"kind": "solve", "workload": "4^4 haar k0.12 1rhs", "form": "cgnr_f64", "seconds": round(t, 6),
+           "iterations": info[0]["iterations"], "oracle_seconds": round(tcpu, 4),
+           "oracle_iterations": oinfo["iterations"], "true_rel_resid": info[0]["true_rel_resid"]}, path)
+    lat0.close()
+
+    # 24^3x48: hop rates (1 RHS all classes, 12 RHS F16S), 12 point sources
+    c2 = latgen.make_config(2)
+    lat2 = q.Lattice(c2["dims"], c2["kappa"], c2["U"])
+    for prec in (q.F64, q.F32, q.F16S):
+        _emit(hop_rates(q, lat2, c2["dims"], torch, prec, flush=flush), path)
+    _emit(hop_rates(q, lat2, c2["dims"], torch, q.F16S, nrhs=12, reps=50, flush=flush), path)
+    _emit(hop_rates(q, lat2, c2["dims"], torch, q.F32, nrhs=12, reps=50, flush=flush), path)
+    b2 = torch.from_numpy(c2["b"]).cuda()
+    for name, kw in [("batched12_f16s", dict(inner_prec=q.F16S)), ("batched12_f32", dict(inner_prec=q.F32)),
+                     ("batched12_f64", dict(inner_prec=q.F64))]:
+        t, st, info, _ = timed_solve(lat2, b2, reps=1, tol=1e-10, **kw)
+        _emit({"kind": "solve", "workload": "24^3x48 eps0.4 k0.12 12 point sources", "form": name,
+               "seconds": round(t, 4), "status": st, "iterations": [i["iterations"] for i in info],
+               "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    tseq = 0.0
+    its = []
+    for r in range(12):
+        t, st, info, _ = timed_solve(lat2, b2[r:r + 1].contiguous(), reps=1, tol=1e-10)
+        tseq += t
+        its.append(info[0]["iterations"])
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.4 k0.12 12 point sources", "form": "sequential12_f64",
+           "seconds": round(tseq, 4), "iterations": its}, path)
+    lat2.close()
+    del b2
+
+    # uneven batch of 32 systems
+    cfgs = [latgen.make_config(3, s) for s in range(32)]
+    lats = [q.Lattice(c["dims"], c["kappa"], c["U"]) for c in cfgs]
+    bs = [torch.from_numpy(c["b"]).cuda() for c in cfgs]
+    xs = [torch.zeros_like(b) for b in bs]
+    for name, kw in [("batch32_mixed_f32", dict(inner_prec=q.F32)), ("batch32_f64", dict(inner_prec=q.F64)),
+                     ("batch32_mixed_f32_graph", dict(inner_prec=q.F32, use_graph=1))]:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            q.qiral_solve_batch([l.handle for l in lats], [l.dims for l in lats], xs, bs, q.solve_params(tol=1e-10, **kw))
+            torch.cuda.synchronize()
+            t0 = _t.perf_counter()
+            st, info = q.qiral_solve_batch([l.handle for l in lats], [l.dims for l in lats], xs, bs,
+                                           q.solve_params(tol=1e-10, **kw))
+            t = _t.perf_counter() - t0
+        _emit({"kind": "solve", "workload": "uneven batch 32 systems", "form": name, "seconds": round(t, 4),
+               "status": st, "max_true_rel_resid": max(i["true_rel_resid"] for i in info),
+               "iterations": [i["iterations"] for i in info]}, path)
+    tseq = 0.0
+    for l, b in zip(lats, bs):
+        t, st, info, _ = timed_solve(l, b, reps=1, tol=1e-10)
+        tseq += t
+    _emit({"kind": "solve", "workload": "uneven batch 32 systems", "form": "sequential32_f64", "seconds": round(tseq, 4)},
+          path)
+    for l in lats:
+        l.close()
+    del bs, xs
+
+    # 32^3x64: beyond the last-level cache
+    c99 = latgen.make_config(99, with_source=False)
+    lat99 = q.Lattice(c99["dims"], c99["kappa"], c99["U"])
+    del c99
+    for prec in (q.F64, q.F32, q.F16S):
+        _emit(hop_rates(q, lat99, (32, 32, 32, 64), torch, prec, reps=50, flush=flush), path)
+    lat99.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -63,19 +63,36 @@ def haar_su3(g: np.random.Generator, n: int) -> np.ndarray:
     return q / (det ** (1.0 / 3.0))[:, None, None]
 
 
-def expih_su3(g: np.random.Generator, n: int, eps, chunk: int = 1 << 18) -> np.ndarray:
+def _expih_chunk(a, eps):
+    h = 0.5 * (a + np.conj(np.swapaxes(a, 1, 2)))
+    tr = np.trace(h, axis1=1, axis2=2).real / 3.0
+    h = h - tr[:, None, None] * np.eye(3)
+    w, v = np.linalg.eigh(h)
+    return (v * np.exp(1j * eps * w)[:, None, :]) @ np.conj(np.swapaxes(v, 1, 2))
+
+
+def expih_su3(g: np.random.Generator, n: int, eps, chunk: int = 1 << 16) -> np.ndarray:
     """n links U = exp(i eps H), H a traceless Hermitian 3x3 built from a complex
     Gaussian A as H = (A + A^dagger)/2 - tr/3; the exponential is taken through
-    the eigen-decomposition of H.  ``eps`` is a scalar."""
+    the eigen-decomposition of H.  ``eps`` is a scalar.  The random numbers are
+    drawn in one stream; the per-matrix decompositions run on a thread pool
+    (NumPy's linalg releases the GIL), which does not change any value."""
+    import concurrent.futures
+    import os
     a = complex_gaussian(g, (n, 3, 3))
     out = np.empty_like(a)
-    eye = np.eye(3)
-    for s in range(0, n, chunk):
-        h = 0.5 * (a[s:s + chunk] + np.conj(np.swapaxes(a[s:s + chunk], 1, 2)))
-        tr = np.trace(h, axis1=1, axis2=2).real / 3.0
-        h = h - tr[:, None, None] * eye
-        w, v = np.linalg.eigh(h)
-        out[s:s + chunk] = (v * np.exp(1j * eps * w)[:, None, :]) @ np.conj(np.swapaxes(v, 1, 2))
+    starts = list(range(0, n, chunk))
+
+    def work(s0):
+        out[s0:s0 + chunk] = _expih_chunk(a[s0:s0 + chunk], eps)
+
+    nthr = max(1, min(16, len(os.sched_getaffinity(0)), len(starts)))
+    if nthr == 1:
+        for s0 in starts:
+            work(s0)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(work, starts))
     return out
 
 

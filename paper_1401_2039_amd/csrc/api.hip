@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -178,25 +179,31 @@ __global__ __launch_bounds__(WG) void k_export(Geo g, double *__restrict__ canon
 }
 
 // ---------------------------------------------------------------------------
-// kernel: hopping term on one lattice, nrhs consecutive fields.  Work-group L
-// (after the XCD remap) handles right-hand side L % nrhs and four consecutive
-// 64-site blocks, so the work-groups that run together on one XCD share links.
-template <int S, int L, bool DAG, int EPI>
-__global__ __launch_bounds__(WG) void k_hop(Geo g, const void *__restrict__ gauge, const void *__restrict__ in,
+// kernel: hopping term on one lattice, nrhs consecutive fields.  A work item
+// is one 64-site block of one right-hand side; items are numbered with the
+// right-hand side fastest, so the waves that run together (same work-group,
+// and after the XCD remap the same XCD) read the same links.  T lanes share a
+// site (hop_part), so T waves cover an item.
+template <int S, int L, bool DAG, int EPI, int T>
+__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S)) void k_hop(Geo g, const void *__restrict__ gauge, const void *__restrict__ in,
                                             void *__restrict__ out, const void *__restrict__ xin, size_t fstride,
                                             int nrhs, int p, double a) {
   using R = typename SpinorIO<S>::R;
-  const int nwg = gridDim.x;
-  const int wg = xcd_remap(blockIdx.x, nwg);
-  const int rhs = wg % nrhs;
-  const int sb = (wg / nrhs) * 4 + (threadIdx.x >> 6);
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+  const int item = wg * (4 / T) + w / T;
+  const int rhs = item % nrhs;
+  const int sb = item / nrhs;
   if (sb >= g.nb) return;
-  const int s = sb * WAVE + lane_id();
-  if (s >= g.vh) return;
+  int sib, grp;
+  split_lane<T>(w % T, sib, grp);
+  const int s = sb * WAVE + sib;
+  const bool site_ok = s < g.vh;
   const size_t npad = (size_t)g.nb * WAVE;
   cpx<R> acc[12];
   FieldLd<S> ld{(const char *)in + rhs * fstride, npad};
-  hop_site<L, DAG>(g, gauge, ld, s, p, acc);
+  hop_part<L, DAG, T>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
+  if (!site_ok || grp != 0) return;
   const R ar = (R)a;
   if (EPI == 0) {
 #pragma unroll
@@ -211,22 +218,47 @@ __global__ __launch_bounds__(WG) void k_hop(Geo g, const void *__restrict__ gaug
 }
 
 namespace qiral {
-template <int S, int L>
-static hipError_t launch_hop_t(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
-                               void *out, const void *x, int nrhs, hipStream_t st) {
+int hop_split(int prec, long nwork) {
+  if (const char *e = getenv("QIRAL_HOP_SPLIT")) {
+    const int t = atoi(e);
+    if (t == 4 || (t == 2 && prec != QIRAL_F64)) return t;
+  }
+  // A whole site per lane needs ~256 VGPRs (one wave per SIMD) and the FP64
+  // hop spills below 4 lanes per site, so the split is 4 (FP64, and lattices
+  // with at most one 64-site block per SIMD) or 2.
+  const long simds = 1024;   // 256 compute units x 4 SIMDs
+  if (prec == QIRAL_F64 || nwork <= simds) return 4;
+  return 2;
+}
+
+template <int S, int L, int T>
+static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
+                                void *out, const void *x, int nrhs, hipStream_t st) {
   const Geo &g = lat->geo;
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
-  const int nwg = ((g.nb + 3) / 4) * nrhs;
+  const long nitems = (long)g.nb * nrhs;
+  const int nwg = (int)((nitems * T + 3) / 4);
   dim3 grid(nwg), block(WG);
   if (!dagger) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
-    else hipLaunchKernelGGL((k_hop<S, L, false, 1>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
-    else hipLaunchKernelGGL((k_hop<S, L, true, 1>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
   }
   return hipGetLastError();
+}
+
+template <int S, int L>
+static hipError_t launch_hop_t(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
+                               void *out, const void *x, int nrhs, hipStream_t st) {
+  const int T = hop_split(S, (long)lat->geo.nb * nrhs);
+  if constexpr (S == S_F64) return launch_hop_tt<S, L, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  else {
+    if (T == 4) return launch_hop_tt<S, L, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    return launch_hop_tt<S, L, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  }
 }
 
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a, const void *in,

@@ -10,6 +10,9 @@ namespace qiral {
 
 constexpr int WAVE = 64;   // CDNA wavefront; also the site-block of the packed layouts
 constexpr int WG = 256;    // work-group: 4 waves
+// Minimum waves per SIMD asked of the compiler for a hop kernel: caps the VGPR
+// budget (512 / waves) so enough waves stay resident to cover memory latency.
+#define HOP_MIN_WAVES(S) ((S) == 0 ? 2 : 4)
 
 // ---------------------------------------------------------------------------
 // Lattice geometry of one parity-checkerboarded lattice.
@@ -374,9 +377,139 @@ __device__ __forceinline__ void hop_site(const Geo &g, const void *gauge, const 
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  A wave sums its 64 lanes with a fixed xor butterfly; every wave
-// of a grid-wide reduction stores its partial; the wave that completes the
-// count sums the partials in index order.  The result does not depend on
+// Direction-generic variant for splitting one site over T lanes (T = 2 or 4):
+// each lane group takes 4/T directions, chosen at run time from its lane
+// index, so the spin matrices are applied through small phase tables instead of
+// compile-time specialisation (all lanes run the same instructions).
+// Phase codes: 0 -> 1, 1 -> i, 2 -> -1, 3 -> -i.
+template <class R> __device__ __forceinline__ cpx<R> cphase(cpx<R> z, int f) {
+  const bool sw = f & 1;
+  R re = sw ? z.im : z.re, im = sw ? z.re : z.im;
+  re = (f == 1 || f == 2) ? -re : re;
+  im = (f >= 2) ? -im : im;
+  return cmake(re, im);
+}
+
+// B_mu (lower -> upper) and B_mu^+ as (source index, phase) per output row:
+// B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1.
+__device__ __forceinline__ void bmat(int mu, int &j0, int &f0, int &j1, int &f1) {
+  j0 = (mu == 0 || mu == 1) ? 1 : 0;
+  j1 = 1 - j0;
+  f0 = mu == 0 ? 3 : mu == 1 ? 2 : mu == 2 ? 3 : 0;
+  f1 = mu == 0 ? 3 : mu == 1 ? 0 : mu == 2 ? 1 : 0;
+}
+__device__ __forceinline__ void bdag(int mu, int &j0, int &f0, int &j1, int &f1) {
+  j0 = (mu == 0 || mu == 1) ? 1 : 0;
+  j1 = 1 - j0;
+  f0 = mu == 0 ? 1 : mu == 1 ? 0 : mu == 2 ? 1 : 0;
+  f1 = mu == 0 ? 1 : mu == 1 ? 2 : mu == 2 ? 3 : 0;
+}
+
+// Checkerboard index of the neighbour of s (parity p) in direction mu, forward
+// (fwd = true) or backward.
+__device__ __forceinline__ int neighbour(const Geo &g, int s, int p, int mu, bool fwd) {
+  const int xh = s % g.lxh;
+  int r = s / g.lxh;
+  const int y = r % g.ly; r /= g.ly;
+  const int z = r % g.lz;
+  const int t = r / g.lz;
+  if (mu == 0) {
+    const int x = 2 * xh + ((p + y + z + t) & 1);
+    const int xn = fwd ? (x + 1 == g.lx ? 0 : x + 1) : (x == 0 ? g.lx - 1 : x - 1);
+    return s - xh + (xn >> 1);
+  }
+  const int c = mu == 1 ? y : mu == 2 ? z : t;
+  const int L = mu == 1 ? g.ly : mu == 2 ? g.lz : g.lt;
+  const int st = mu == 1 ? g.sy : mu == 2 ? g.sz : g.st;
+  if (fwd) return (c + 1 == L) ? s - (L - 1) * st : s + st;
+  return (c == 0) ? s + (L - 1) * st : s - st;
+}
+
+// One direction with run-time mu; spin signs sf (forward) and sb (backward).
+template <class Ld, int L>
+__device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int mu, int sf,
+                                           int sb, bool first, cpx<typename Ld::R> acc[12]) {
+  using R = typename Ld::R;
+  int j0, f0, j1, f1, k0, e0, k1, e1;
+  bmat(mu, j0, f0, j1, f1);
+  bdag(mu, k0, e0, k1, e1);
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const int sg = dir == 0 ? sf : sb;
+    const int ph = sg > 0 ? 0 : 2;           // the projection sign as a phase
+    const int nb = neighbour(g, s, p, mu, dir == 0);
+    cpx<R> psi[12], h[6], w[6], u[9];
+    cpx<typename LinkIO<L>::R> u0[9];
+    ld(nb, psi);
+    if (dir == 0) LinkIO<L>::load(gauge, p, mu, s, g.nb, u0);
+    else LinkIO<L>::load(gauge, 1 - p, mu, nb, g.nb, u0);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cpx<R> l0 = psi[4 * c + 2], l1 = psi[4 * c + 3];
+      h[2 * c] = cadd(psi[4 * c], cphase(j0 ? l1 : l0, (f0 + ph) & 3));
+      h[2 * c + 1] = cadd(psi[4 * c + 1], cphase(j1 ? l1 : l0, (f1 + ph) & 3));
+    }
+    if (dir == 0) su3_mul<false>(u, h, w);
+    else su3_mul<true>(u, h, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cpx<R> w0 = w[2 * c], w1 = w[2 * c + 1];
+      const cpx<R> lo0 = cphase(k0 ? w1 : w0, (e0 + ph) & 3);
+      const cpx<R> lo1 = cphase(k1 ? w1 : w0, (e1 + ph) & 3);
+      if (first && dir == 0) {
+        acc[4 * c] = w0; acc[4 * c + 1] = w1; acc[4 * c + 2] = lo0; acc[4 * c + 3] = lo1;
+      } else {
+        acc[4 * c] = cadd(acc[4 * c], w0);
+        acc[4 * c + 1] = cadd(acc[4 * c + 1], w1);
+        acc[4 * c + 2] = cadd(acc[4 * c + 2], lo0);
+        acc[4 * c + 3] = cadd(acc[4 * c + 3], lo1);
+      }
+    }
+  }
+}
+
+// Sum the accumulators of the T lane groups of a site (groups are 64/T lanes apart).
+template <int T, class R> __device__ __forceinline__ void group_sum(cpx<R> acc[12]) {
+#pragma unroll
+  for (int m = 32; m >= 64 / T; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      acc[k].re += __shfl_xor(acc[k].re, m, WAVE);
+      acc[k].im += __shfl_xor(acc[k].im, m, WAVE);
+    }
+  }
+}
+
+// Hop on T lanes per site: lane group t (0..T-1) takes directions t, t+T, ...
+// and every group ends with the full sum.  (T = 1, the whole site in one lane,
+// is kept for reference but not launched: it needs ~256 VGPRs.)
+template <int L, bool DAG, int T, class Ld>
+__device__ __forceinline__ void hop_part(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int t,
+                                         cpx<typename Ld::R> acc[12]) {
+  if constexpr (T == 1) {
+    hop_site<L, DAG>(g, gauge, ld, s, p, acc);
+  } else {
+    constexpr int SF = DAG ? 1 : -1, SB = DAG ? -1 : 1;
+#pragma unroll
+    for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L>(g, gauge, ld, s, p, t + k * T, SF, SB, k == 0, acc);
+    group_sum<T>(acc);
+  }
+}
+
+// Lane -> (site within a 64-site block, lane group) for T lanes per site; the T
+// waves of a block take sub-blocks sub = 0..T-1.
+template <int T> __device__ __forceinline__ void split_lane(int sub, int &site_in_block, int &grp) {
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
+  site_in_block = sub * (WAVE / T) + lane % (WAVE / T);
+  grp = lane / (WAVE / T);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  A wave sums its 64 lanes with a fixed xor butterfly and stores
+// one partial per wave; a separate kernel sums a system's partials in index
+// order (the kernel boundary makes them visible).  Nothing depends on
 // scheduling, so repeated runs are bitwise identical.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -385,35 +518,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
-
-// Commit NV wave-summed values as partial `part` (of nparts) of a reduction.
-// Returns true in every lane of the wave that completed the reduction, with the
-// totals in tot[] (valid in all lanes of that wave).
-template <int NV>
-__device__ __forceinline__ bool grid_reduce(double v[NV], double *partials, unsigned *counter, int part, int nparts,
-                                            double tot[NV]) {
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  int last = 0;
-  if (lane_id() == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-      __hip_atomic_store(&partials[(size_t)i * nparts + part], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)(nparts - 1));
-  }
-  last = __shfl(last, 0, WAVE);
-  if (!last) return false;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double a = 0.0;
-    for (int k = lane_id(); k < nparts; k += WAVE)
-      a += __hip_atomic_load(&partials[(size_t)i * nparts + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tot[i] = wave_sum(a);
-  }
-  if (lane_id() == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
-}
 
 // XCD-aware block order: the hardware hands consecutive work-group ids to the 8
 // XCDs in turn; this remap gives each XCD one contiguous range of logical

@@ -35,6 +35,10 @@ inline size_t npad_of(const Geo &g) { return (size_t)g.nb * WAVE; }
 size_t half_bytes(const Geo &g, int prec);
 const void *links_for(const qiral_lattice *lat, int prec);
 
+// Lanes per site of a hop launch over `nwork` 64-site work items: enough waves
+// to give every SIMD (256 CUs x 4) a few.  QIRAL_HOP_SPLIT=2|4 overrides.
+int hop_split(int prec, long nwork);
+
 // Grid of ceil(nwaves / 4) work-groups (4 waves of 64 lanes each).
 inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }
 

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -53,7 +54,7 @@ qiral_status fail(qiral_status s, const char *msg) {
 }
 
 struct Layout {
-  size_t off_desc, off_work, off_state, off_cnt, off_part, total;
+  size_t off_desc, off_work, off_state, off_part, total;
   std::vector<size_t> off_sys;   // per system: start of its fields
   std::vector<size_t> part_off;  // per system: offset of its partials (doubles) inside the partial region
 };
@@ -94,14 +95,13 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     sz[i] = sys_sizes(sys[i].lat->geo, prec, bicg);
     nwork += sys[i].lat->geo.nb;
     lay.part_off[i] = nparts;
-    nparts += (size_t)NSLOT * NV * sys[i].lat->geo.nb;
+    nparts += (size_t)NSLOT * NV * 4 * sys[i].lat->geo.nb;
   }
   if (nwork > (1l << 30)) return fail(QIRAL_ERR_UNSUPPORTED, "too many work items");
   size_t off = 0;
   lay.off_desc = off; off = align_up(off + sizeof(SysDesc) * nsys);
   lay.off_work = off; off = align_up(off + sizeof(uint32_t) * nwork);
   lay.off_state = off; off = align_up(off + sizeof(SysState) * nsys);
-  lay.off_cnt = off; off = align_up(off + sizeof(unsigned) * NSLOT * nsys);
   lay.off_part = off; off = align_up(off + sizeof(double) * nparts);
   lay.off_sys.resize(nsys);
   for (int i = 0; i < nsys; ++i) { lay.off_sys[i] = off; off += sz[i].bytes; }
@@ -122,7 +122,6 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     d.glo = links_for(lat, prec);
     d.npad = npad_of(lat->geo);
     d.st = (SysState *)(ws + lay.off_state) + i;
-    d.cnt = (unsigned *)(ws + lay.off_cnt) + (size_t)NSLOT * i;
     d.part = (double *)(ws + lay.off_part) + lay.part_off[i];
     char *p = ws + lay.off_sys[i];
     const int it_fields[] = {F_R, F_P, F_Z, F_AP, F_TMP, F_RT, F_T};
@@ -160,12 +159,14 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_work, work.data(), sizeof(uint32_t) * nwork, hipMemcpyHostToDevice, s));
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_state, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, s));
-  QIRAL_HIP(hipMemsetAsync(ws + lay.off_cnt, 0, sizeof(unsigned) * NSLOT * nsys, s));
 
   Launch L;
   L.desc = (const SysDesc *)(ws + lay.off_desc);
   L.work = (const uint32_t *)(ws + lay.off_work);
   L.nwork = (int)nwork;
+  L.nsys = nsys;
+  L.T = hop_split(prec, nwork);
+  L.T64 = hop_split(QIRAL_F64, nwork);
   L.stream = s;
 
   // ---- inputs

@@ -56,8 +56,7 @@ struct SysDesc {
   const void *glo;    // links in the iterate precision (== g64 for a plain solve)
   void *f[NF];
   SysState *st;
-  double *part;       // [NSLOT][NV][nb]
-  unsigned *cnt;      // [NSLOT]
+  double *part;       // [NSLOT][NV][4 nb] per-wave partial sums
   size_t npad;
 };
 
@@ -189,31 +188,46 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
   }
 }
 
-// Per-wave context of a table-driven kernel.
+// Per-wave context of a table-driven kernel.  With T lanes per site, T waves
+// share one 64-site work item (sub = 0..T-1 picks the wave's part of it) and a
+// work-group of 4 waves takes 4/T items.
 struct Item {
-  int sys, sb, s;
+  int sys, sb, sub, s, grp;
   bool active;
 };
 
+template <int T>
 __device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
   Item it;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int w = wg * 4 + (threadIdx.x >> 6);
-  if (w >= nwork) { it.active = false; it.sys = 0; it.sb = 0; it.s = 0; return it; }
-  const uint32_t v = work[w];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+  const int idx = wg * (4 / T) + w / T;
+  it.sub = w % T;
+  if (idx >= nwork) { it.active = false; it.sys = 0; it.sb = 0; it.s = 0; it.grp = 0; return it; }
+  const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)work[idx]);
   it.sys = (int)(v >> 24);
   it.sb = (int)(v & 0xffffffu);
-  it.s = it.sb * WAVE + lane_id();
+  int sib;
+  split_lane<T>(it.sub, sib, it.grp);
+  it.s = it.sb * WAVE + sib;
   it.active = true;
   return it;
 }
 
-// Commit NV per-lane values of a system's reduction; the completing wave runs
-// the solver scalar step.
-__device__ __forceinline__ void sys_reduce(const SysDesc &d, int slot, int fin, int sb, double v[NV]) {
-  double tot[NV];
-  if (grid_reduce<NV>(v, d.part + (size_t)slot * NV * d.g.nb, d.cnt + slot, sb, d.g.nb, tot)) {
-    if (lane_id() == 0) finalize(d.st, fin, slot, tot);
+inline int grid_for(int nwork, int T) { return (nwork * T + 3) / 4; }
+
+// Store a wave's partial sums (partial index sb * T + sub of nb * T, each of
+// the NV values in its own row of 4 nb); the
+// reduce kernel sums them.  Lanes of groups other than 0 must pass zeros.
+template <int T>
+__device__ __forceinline__ void sys_partial(const SysDesc &d, int slot, const Item &it, double v[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane_id() == 0) {
+    const size_t stride = (size_t)d.g.nb * 4;   // room for 4 partials per block (T <= 4)
+    double *p = d.part + (size_t)slot * NV * stride;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) p[i * stride + it.sb * T + it.sub] = v[i];
   }
 }
 

@@ -11,6 +11,9 @@ struct Launch {
   const SysDesc *desc;   // device system table
   const uint32_t *work;  // device work table: (system << 24) | 64-site block
   int nwork;
+  int nsys;
+  int T;                 // lanes per site of the iterate-precision hop (1, 2 or 4)
+  int T64;               // lanes per site of the FP64 hop
   hipStream_t stream;
 };
 

@@ -18,74 +18,78 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
 
 // out = a H in (EPI 0) or out = x + a H in (EPI 1), parity `par` out.
 // red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
-template <int S, int L, bool DAG, int EPI>
-__global__ __launch_bounds__(WG) void k_hop_sys(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+// T lanes per site (see hop_part); padded lanes compute on site 0 and store nothing.
+template <int S, int L, bool DAG, int EPI, int T>
+__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S)) void k_hop_sys(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork, int fin_id, int fout, int fx, int par, int amode, int mask,
-                                                int red, int slot, int fin) {
+                                                int red, int slot) {
   using R = typename SpinorIO<S>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<T>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & mask)) return;
-  const bool live = it.s < d.g.vh;
-  cpx<R> acc[12];
+  const bool site_ok = it.s < d.g.vh;
+  const size_t npad = d.npad;
   double v[NV] = {0.0, 0.0, 0.0};
-  if (live) {
-    FieldLd<S> ld{d.f[fin_id], d.npad};
-    hop_site<L, DAG>(d.g, links_of<S>(d), ld, it.s, par, acc);
+  cpx<R> acc[12];
+  FieldLd<S> ld{d.f[fin_id], npad};
+  hop_part<L, DAG, T>(d.g, links_of<S>(d), ld, site_ok ? it.s : 0, par, it.grp, acc);
+  if (site_ok && it.grp == 0) {
     const R a = (R)coef(amode, d.kappa);
     if (EPI == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[k] = cscale(a, acc[k]);
     } else {
       cpx<R> xv[12];
-      SpinorIO<S>::load(d.f[fx], it.s, d.npad, xv);
+      SpinorIO<S>::load(d.f[fx], it.s, npad, xv);
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[k] = cadd(xv[k], cscale(a, acc[k]));
       if (red == 3) { dot12(acc, xv, v[0], v[1]); v[2] = norm12(acc); }
     }
-    SpinorIO<S>::store(d.f[fout], it.s, d.npad, acc);
+    SpinorIO<S>::store(d.f[fout], it.s, npad, acc);
     if (red == 1) v[0] = norm12(acc);
     if (red == 2) {
       cpx<R> rt[12];
-      SpinorIO<S>::load(d.f[F_RT], it.s, d.npad, rt);
+      SpinorIO<S>::load(d.f[F_RT], it.s, npad, rt);
       dot12(rt, acc, v[0], v[1]);
     }
   }
-  if (red) sys_reduce(d, slot, fin, it.sb, v);
+  if (red) sys_partial<T>(d, slot, it, v);
 }
 
 // T64 = H_eo (XH + X): the hop of the current solution for the FP64 residual.
-template <bool HASLO>
-__global__ __launch_bounds__(WG) void k_hop_sum(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+template <bool HASLO, int T>
+__global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork) {
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<T>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_UPDATE)) return;
-  if (it.s >= d.g.vh) return;
+  const bool site_ok = it.s < d.g.vh;
   cpx<double> acc[12];
   SumLd ld{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
-  hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, 0, acc);
-  SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc);
+  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
+  if (site_ok && it.grp == 0) SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc);
 }
 
 // Reliable update on the odd sites: y = XH + X; XH = y; X = 0;
 // r_hat = BH - (y - kappa^2 H_oe T64) in FP64; R = r_hat rounded to the iterate
 // precision; reduces ||r_hat||^2 (and (rt | r_hat) for BiCGStab).
-template <int SO, bool HASLO, bool BICG>
-__global__ __launch_bounds__(WG) void k_hop_upd(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+template <int SO, bool HASLO, bool BICG, int T>
+__global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork) {
   using RO = typename SpinorIO<SO>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<T>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_UPDATE)) return;
+  const bool site_ok = it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
-  if (it.s < d.g.vh) {
-    cpx<double> acc[12], y[12], b[12];
-    FieldLd<S_F64> ld{d.f[F_T64], d.npad};
-    hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, 1, acc);
+  cpx<double> acc[12];
+  FieldLd<S_F64> ld{d.f[F_T64], d.npad};
+  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc);
+  if (site_ok && it.grp == 0) {
+    cpx<double> y[12], b[12];
     SumLd yl{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
     yl(it.s, y);
     if (HASLO) {
@@ -111,34 +115,82 @@ __global__ __launch_bounds__(WG) void k_hop_upd(const SysDesc *__restrict__ sdes
       dot12(rtd, acc, v[1], v[2]);
     }
   }
-  sys_reduce(d, SL_UPD, FIN_UPDATE, it.sb, v);
+  sys_partial<T>(d, SL_UPD, it, v);
 }
 
 // ||b - D x||^2 on the sites of parity p: B_p - X_p + kappa H X_{1-p}.
-__global__ __launch_bounds__(WG) void k_hop_res(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+template <int T>
+__global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork, int par) {
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<T>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   const int fin_id = par ? F_XE : F_XH, fb = par ? F_BO : F_BE, fx = par ? F_XH : F_XE;
+  const bool site_ok = it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
-  if (it.s < d.g.vh) {
-    cpx<double> acc[12], x[12], b[12];
-    FieldLd<S_F64> ld{d.f[fin_id], d.npad};
-    hop_site<L_F64R18, false>(d.g, d.g64, ld, it.s, par, acc);
+  cpx<double> acc[12];
+  FieldLd<S_F64> ld{d.f[fin_id], d.npad};
+  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, par, it.grp, acc);
+  if (site_ok && it.grp == 0) {
+    cpx<double> x[12], b[12];
     SpinorIO<S_F64>::load(d.f[fx], it.s, d.npad, x);
     SpinorIO<S_F64>::load(d.f[fb], it.s, d.npad, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], x[k]), cscale(d.kappa, acc[k]));
     v[0] = norm12(acc);
   }
-  sys_reduce(d, par ? SL_RES_O : SL_RES_E, FIN_NONE, it.sb, v);
+  sys_partial<T>(d, par ? SL_RES_O : SL_RES_E, it, v);
+}
+
+// Sum a system's partials of one reduction slot and run the solver's scalar
+// step (one work-group of RED_WG threads per system).  Each thread adds a fixed
+// strided subset with independent 16-byte loads, then waves and the work-group
+// combine in a fixed order: the result does not depend on scheduling.
+constexpr int RED_WG = 1024;
+__global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int tmul, int fin,
+                                                   int mask) {
+  const SysDesc &d = sdesc[blockIdx.x];
+  if (!(d.st->status & mask)) return;
+  const int np = d.g.nb * tmul;
+  const double *p = d.part + (size_t)slot * NV * (d.g.nb * 4);
+  __shared__ double red[NV][RED_WG / WAVE];
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int npair = np >> 1;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double *q = p + (size_t)i * d.g.nb * 4;   // 32-byte aligned rows
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = tid;
+    // pairs k, k + RED_WG, ... ; four independent loads in flight per step
+    for (; k + 3 * RED_WG < npair; k += 4 * RED_WG) {
+      const double2 x0 = ((const double2 *)q)[k];
+      const double2 x1 = ((const double2 *)q)[k + RED_WG];
+      const double2 x2 = ((const double2 *)q)[k + 2 * RED_WG];
+      const double2 x3 = ((const double2 *)q)[k + 3 * RED_WG];
+      a0 += x0.x + x0.y; a1 += x1.x + x1.y; a2 += x2.x + x2.y; a3 += x3.x + x3.y;
+    }
+    for (; k < npair; k += RED_WG) { const double2 x0 = ((const double2 *)q)[k]; a0 += x0.x + x0.y; }
+    if (tid == 0 && (np & 1)) a0 += q[np - 1];
+    double a = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane_id() == 0) red[i][w] = a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < RED_WG / WAVE; ++j) s += red[i][j];
+      t[i] = s;
+    }
+    finalize(d.st, fin, slot, t);
+  }
 }
 
 // ||b||^2 over both parities.
 __global__ __launch_bounds__(WG) void k_bnorm(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                               int nwork) {
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   double v[NV] = {0.0, 0.0, 0.0};
@@ -149,7 +201,7 @@ __global__ __launch_bounds__(WG) void k_bnorm(const SysDesc *__restrict__ sdesc,
     SpinorIO<S_F64>::load(d.f[F_BO], it.s, d.npad, a);
     v[0] += norm12(a);
   }
-  sys_reduce(d, SL_B, FIN_BNORM, it.sb, v);
+  sys_partial<1>(d, SL_B, it, v);
 }
 
 // CGNR: X += alpha P; R -= alpha AP; ||R||^2
@@ -158,7 +210,7 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
                                             int nwork) {
   using R = typename SpinorIO<S>::R;
   using RX = typename SpinorIO<XS>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_RUN)) return;
@@ -179,7 +231,7 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
     SpinorIO<S>::store(d.f[F_R], it.s, d.npad, r);
     v[0] = norm12(r);
   }
-  sys_reduce(d, SL_R, FIN_NR, it.sb, v);
+  sys_partial<1>(d, SL_R, it, v);
 }
 
 // CGNR: P = Z + beta P
@@ -187,7 +239,7 @@ template <int S>
 __global__ __launch_bounds__(WG) void k_cg2(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                             int nwork) {
   using R = typename SpinorIO<S>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_RUN)) return;
@@ -206,7 +258,7 @@ template <int S>
 __global__ __launch_bounds__(WG) void k_bi_p(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                              int nwork) {
   using R = typename SpinorIO<S>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_RUN)) return;
@@ -226,7 +278,7 @@ template <int S>
 __global__ __launch_bounds__(WG) void k_bi_s(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                              int nwork) {
   using R = typename SpinorIO<S>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_RUN)) return;
@@ -246,7 +298,7 @@ __global__ __launch_bounds__(WG) void k_bi_xr(const SysDesc *__restrict__ sdesc,
                                               int nwork) {
   using R = typename SpinorIO<S>::R;
   using RX = typename SpinorIO<XS>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_RUN)) return;
@@ -271,7 +323,7 @@ __global__ __launch_bounds__(WG) void k_bi_xr(const SysDesc *__restrict__ sdesc,
     dot12(rt, s, v[0], v[1]);
     v[2] = norm12(s);
   }
-  sys_reduce(d, SL_BI3, FIN_BI_RHO, it.sb, v);
+  sys_partial<1>(d, SL_BI3, it, v);
 }
 
 // copy a half-field of the iterate precision: dst = src
@@ -279,7 +331,7 @@ template <int S>
 __global__ __launch_bounds__(WG) void k_copy(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                              int nwork, int fsrc, int fdst, int mask) {
   using R = typename SpinorIO<S>::R;
-  const Item it = fetch_item(work, nwork);
+  const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & mask)) return;
@@ -304,50 +356,74 @@ __global__ void k_bi_init(const SysDesc *__restrict__ sdesc, int nsys) {
 
 // ---------------------------------------------------------------------------
 // launchers
-static inline dim3 grid_of(int nwork) { return dim3(wg_count(nwork)); }
+static inline dim3 grid_of(int nwork, int T = 1) { return dim3(grid_for(nwork, T)); }
 
-template <int S, int L>
+template <int S, int L, int T>
 static void hop_sys_t(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
-                      int slot, int fin) {
-  const dim3 g = grid_of(l.nwork), b(WG);
-#define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot, fin
+                      int slot) {
+  const dim3 g = grid_of(l.nwork, T), b(WG);
+#define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot
   if (!dag) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T>), g, b, 0, l.stream, QARGS);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0, T>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1, T>), g, b, 0, l.stream, QARGS);
   }
 #undef QARGS
 }
 
+template <int S, int L>
+static void hop_sys_p(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
+                      int slot) {
+  if constexpr (S == S_F64) hop_sys_t<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else if (l.T == 4) hop_sys_t<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else hop_sys_t<S, L, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+}
+
+void reduce(const Launch &l, int slot, int tmul, int fin, int mask) {
+  hipLaunchKernelGGL(k_reduce, dim3(l.nsys), dim3(RED_WG), 0, l.stream, l.desc, slot, tmul, fin, mask);
+}
+
 void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
              int red, int slot, int fin) {
-  if (prec == S_F64) hop_sys_t<S_F64, L_F64R18>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
-  else if (prec == S_F32) hop_sys_t<S_F32, L_F32R12>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
-  else hop_sys_t<S_F16S, L_F16R12>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot, fin);
+  const Launch lp = {l.desc, l.work, l.nwork, l.nsys, prec == S_F64 ? l.T64 : l.T, l.T64, l.stream};
+  if (prec == S_F64) hop_sys_p<S_F64, L_F64R18>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else if (prec == S_F32) hop_sys_p<S_F32, L_F32R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else hop_sys_p<S_F16S, L_F16R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  if (red) reduce(l, slot, lp.T, fin, mask);
 }
 
+template <int T> static void hop_sum_t(const Launch &l, bool haslo) {
+  if (haslo) hipLaunchKernelGGL((k_hop_sum<true, T>), grid_of(l.nwork, T), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_hop_sum<false, T>), grid_of(l.nwork, T), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+}
 void hop_sum(const Launch &l, bool haslo) {
-  if (haslo) hipLaunchKernelGGL(k_hop_sum<true>, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
-  else hipLaunchKernelGGL(k_hop_sum<false>, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  hop_sum_t<4>(l, haslo);
 }
 
-void hop_upd(const Launch &l, int prec, bool bicg) {
-  const dim3 g = grid_of(l.nwork), b(WG);
-#define QU(SO, LO, BI) hipLaunchKernelGGL((k_hop_upd<SO, LO, BI>), g, b, 0, l.stream, l.desc, l.work, l.nwork)
+template <int T> static void hop_upd_t(const Launch &l, int prec, bool bicg) {
+  const dim3 g = grid_of(l.nwork, T), b(WG);
+#define QU(SO, LO, BI) hipLaunchKernelGGL((k_hop_upd<SO, LO, BI, T>), g, b, 0, l.stream, l.desc, l.work, l.nwork)
   if (prec == S_F64) { if (bicg) QU(S_F64, false, true); else QU(S_F64, false, false); }
   else if (prec == S_F32) { if (bicg) QU(S_F32, true, true); else QU(S_F32, true, false); }
   else { if (bicg) QU(S_F16S, true, true); else QU(S_F16S, true, false); }
 #undef QU
 }
+void hop_upd(const Launch &l, int prec, bool bicg) {
+  hop_upd_t<4>(l, prec, bicg);
+  reduce(l, SL_UPD, l.T64, FIN_UPDATE, ST_UPDATE);
+}
 
 void hop_res(const Launch &l, int par) {
-  hipLaunchKernelGGL(k_hop_res, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork, par);
+  const dim3 g = grid_of(l.nwork, l.T64), b(WG);
+  hipLaunchKernelGGL(k_hop_res<4>, g, b, 0, l.stream, l.desc, l.work, l.nwork, par);
+  reduce(l, par ? SL_RES_O : SL_RES_E, l.T64, FIN_NONE, ST_ANY);
 }
 
 void bnorm(const Launch &l) {
   hipLaunchKernelGGL(k_bnorm, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  reduce(l, SL_B, 1, FIN_BNORM, ST_ANY);
 }
 
 void cg1(const Launch &l, int prec) {
@@ -355,6 +431,7 @@ void cg1(const Launch &l, int prec) {
   if (prec == S_F64) hipLaunchKernelGGL((k_cg1<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else if (prec == S_F32) hipLaunchKernelGGL((k_cg1<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else hipLaunchKernelGGL((k_cg1<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  reduce(l, SL_R, 1, FIN_NR, ST_RUN);
 }
 
 void cg2(const Launch &l, int prec) {
@@ -383,6 +460,7 @@ void bi_xr(const Launch &l, int prec) {
   if (prec == S_F64) hipLaunchKernelGGL((k_bi_xr<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else if (prec == S_F32) hipLaunchKernelGGL((k_bi_xr<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else hipLaunchKernelGGL((k_bi_xr<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  reduce(l, SL_BI3, 1, FIN_BI_RHO, ST_RUN);
 }
 
 void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask) {
