@@ -133,6 +133,15 @@ qiral_status qiral_dslash_eo(const qiral_lattice *lat, void *out, const void *in
 qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, void *tmp, qiral_op op,
                            qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
 
+/* Autotune the hop's launch shape for this lattice, precision and number of
+ * right-hand sides (lanes per site 2 or 4, right-hand sides per lane 1..4) by
+ * timing each candidate on the stream; later hops and solves on this handle use
+ * the fastest.  If the environment variable QIRAL_TUNE_CACHE names a file, the
+ * result is looked up there first and stored there (JSON).  Allocates and frees
+ * two temporary fields.  Outputs may be NULL; best_us is 0 on a cache hit. */
+qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, int32_t *best_t, int32_t *best_nr,
+                        double *best_us, qiral_stream_t stream);
+
 typedef struct {
   qiral_solver solver; /* QIRAL_CGNR_EO (default) or QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN        */
   double tol;          /* relative FP64 residual ||b - D x|| / ||b|| to reach (e.g. 1e-10)   */

@@ -10,7 +10,7 @@ the C calls; nothing is computed in Python.
 """
 from .api import (  # noqa: F401
     Lattice, qiral_field_bytes, qiral_lattice_create, qiral_lattice_destroy, qiral_field_import,
-    qiral_field_export, qiral_dslash_eo, qiral_apply_M, qiral_solve, qiral_solve_batch, solve_params,
+    qiral_field_export, qiral_dslash_eo, qiral_apply_M, qiral_tune, qiral_solve, qiral_solve_batch, solve_params,
 )
 from ._lib import (  # noqa: F401
     F64, F32, F16S, EVEN, ODD, FULL, OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG, CGNR_EO, BICGSTAB_EO,

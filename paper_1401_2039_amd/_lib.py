@@ -30,7 +30,7 @@ STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR
 EXPORTS = [
     "qiral_status_string", "qiral_last_error", "qiral_field_bytes", "qiral_lattice_create",
     "qiral_lattice_destroy", "qiral_lattice_query", "qiral_field_import", "qiral_field_export",
-    "qiral_dslash_eo", "qiral_apply_M", "qiral_solve", "qiral_solve_batch",
+    "qiral_dslash_eo", "qiral_apply_M", "qiral_tune", "qiral_solve", "qiral_solve_batch",
 ]
 
 
@@ -82,6 +82,8 @@ def load():
         "qiral_field_export": (I, [P, P, P, I, I, I, P]),
         "qiral_dslash_eo": (I, [P, P, P, I, I, I, I, P]),
         "qiral_apply_M": (I, [P, P, P, P, I, I, I, P]),
+        "qiral_tune": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_double), P]),
         "qiral_solve": (I, [P, P, P, I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
         "qiral_solve_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I,
                                   ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),

@@ -93,6 +93,14 @@ def qiral_apply_M(handle, dims, out, inp, tmp, op, prec, nrhs=1, stream=None):
             "qiral_apply_M")
 
 
+def qiral_tune(handle, prec, nrhs=1, stream=None):
+    """Autotune the hop launch shape; returns (lanes per site, rhs per lane, microseconds)."""
+    t, nr, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    L.check(L.load().qiral_tune(ctypes.c_void_p(handle), int(prec), int(nrhs), ctypes.byref(t), ctypes.byref(nr),
+                                ctypes.byref(us), _stream(stream)), "qiral_tune")
+    return t.value, nr.value, us.value
+
+
 def solve_params(solver=L.CGNR_EO, tol=1e-10, maxiter=10000, inner_prec=L.F64, delta=0.1, restart=20, precond=None,
                  fallback_cg=1, x0_is_guess=0, use_graph=0, check_every=0):
     return L.SolveParams(solver, tol, maxiter, inner_prec, delta, restart, precond, fallback_cg, x0_is_guess,
@@ -170,6 +178,9 @@ class Lattice:
 
     def apply_M(self, out, inp, tmp, op, prec, nrhs=1):
         qiral_apply_M(self.handle, self.dims, out, inp, tmp, op, prec, nrhs)
+
+    def tune(self, prec, nrhs=1):
+        return qiral_tune(self.handle, prec, nrhs)
 
     def solve(self, b_canon, x_canon=None, **kw):
         b_canon = b_canon.contiguous()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -180,44 +181,80 @@ __global__ __launch_bounds__(WG) void k_export(Geo g, double *__restrict__ canon
 
 // ---------------------------------------------------------------------------
 // kernel: hopping term on one lattice, nrhs consecutive fields.  A work item
-// is one 64-site block of one right-hand side; items are numbered with the
-// right-hand side fastest, so the waves that run together (same work-group,
-// and after the XCD remap the same XCD) read the same links.  T lanes share a
-// site (hop_part), so T waves cover an item.
-template <int S, int L, bool DAG, int EPI, int T>
-__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S)) void k_hop(Geo g, const void *__restrict__ gauge, const void *__restrict__ in,
-                                            void *__restrict__ out, const void *__restrict__ xin, size_t fstride,
-                                            int nrhs, int p, double a) {
+// is one 64-site block of a group of NR right-hand sides (each lane applies
+// every link it loads to all NR of them).  Items run tile by tile: within a
+// tile of at least two t-slices, every group sweeps the tile's blocks in turn,
+// so a group's neighbour spinors are re-read while still cached and the tile's
+// links are re-read from cache by the next group.  T lanes share a site
+// (hop_part), so T waves cover an item.
+template <int S, int L, bool DAG, int EPI, int T, int NR>
+__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, const void *__restrict__ gauge,
+                                                             const void *__restrict__ in, void *__restrict__ out,
+                                                             const void *__restrict__ xin, size_t fstride, int nrhs,
+                                                             int p, double a, int tile) {
   using R = typename SpinorIO<S>::R;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
   const int item = wg * (4 / T) + w / T;
-  const int rhs = item % nrhs;
-  const int sb = item / nrhs;
+  // item order: (tile of `tile` blocks, right-hand-side group, block in tile)
+  const int ngr = (nrhs + NR - 1) / NR;
+  const int per_tile = ngr * tile;
+  const int ti = item / per_tile, rem = item - ti * per_tile;
+  const int rg = rem / tile;
+  const int sb = ti * tile + (rem - rg * tile);
   if (sb >= g.nb) return;
+  const int r0 = rg * NR;
+  const int cnt = min(NR, nrhs - r0);
   int sib, grp;
   split_lane<T>(w % T, sib, grp);
   const int s = sb * WAVE + sib;
   const bool site_ok = s < g.vh;
   const size_t npad = (size_t)g.nb * WAVE;
-  cpx<R> acc[12];
-  FieldLd<S> ld{(const char *)in + rhs * fstride, npad};
+  FieldLd<S, NR> ld;
+  ld.npad = npad;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) ld.base[r] = (const char *)in + (size_t)(r0 + min(r, cnt - 1)) * fstride;
+  cpx<R> acc[NR][12];
   hop_part<L, DAG, T>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
   if (!site_ok || grp != 0) return;
   const R ar = (R)a;
-  if (EPI == 0) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = cscale(ar, acc[k]);
-  } else {
-    cpx<R> xv[12];
-    SpinorIO<S>::load((const char *)xin + rhs * fstride, s, npad, xv);
+  for (int r = 0; r < NR; ++r) {
+    if (r >= cnt) break;
+    if (EPI == 0) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = cadd(xv[k], cscale(ar, acc[k]));
+      for (int k = 0; k < 12; ++k) acc[r][k] = cscale(ar, acc[r][k]);
+    } else {
+      cpx<R> xv[12];
+      SpinorIO<S>::load((const char *)xin + (size_t)(r0 + r) * fstride, s, npad, xv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(ar, acc[r][k]));
+    }
+    SpinorIO<S>::store_fast((char *)out + (size_t)(r0 + r) * fstride, s, npad, acc[r]);
   }
-  SpinorIO<S>::store((char *)out + rhs * fstride, s, npad, acc);
 }
 
 namespace qiral {
+HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
+  HopCfg c;
+  const long nb = lat->geo.nb;
+  if (const char *e = getenv("QIRAL_HOP_NR")) c.nr = atoi(e);
+  else c.nr = tuned_nr(lat, prec, (int)nrhs);
+  c.nr = std::max(1, std::min(c.nr, prec == QIRAL_F64 ? 1 : 4));   // FP64 with 2 per lane spills
+  if (c.nr > nrhs) c.nr = (int)nrhs;
+  const long nitems = nb * ((nrhs + c.nr - 1) / c.nr);
+  c.t = hop_split(prec, nitems);
+  const int tt = lat->tuned_t[prec][nrhs < 4 ? nrhs : 4];
+  if (tt && !getenv("QIRAL_HOP_SPLIT") && !(prec == QIRAL_F64 && tt != 4)) c.t = tt;
+  return c;
+}
+
+int hop_tile(const Geo &g, int ngroups) {
+  if (ngroups <= 1) return g.nb;   // one group: plain block order
+  const int slice = (g.st + WAVE - 1) / WAVE;   // blocks per t-slice
+  return std::min(g.nb, std::max(64, 2 * slice));
+}
+
 int hop_split(int prec, long nwork) {
   if (const char *e = getenv("QIRAL_HOP_SPLIT")) {
     const int t = atoi(e);
@@ -231,41 +268,62 @@ int hop_split(int prec, long nwork) {
   return 2;
 }
 
-template <int S, int L, int T>
+template <int S, int L, int T, int NR>
 static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
                                 void *out, const void *x, int nrhs, hipStream_t st) {
   const Geo &g = lat->geo;
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
-  const long nitems = (long)g.nb * nrhs;
+  const int tile = hop_tile(g, (nrhs + NR - 1) / NR);
+  const long ntile = (g.nb + tile - 1) / tile;
+  const long nitems = ntile * tile * ((nrhs + NR - 1) / NR);
   const int nwg = (int)((nitems * T + 3) / 4);
   dim3 grid(nwg), block(WG);
   if (!dagger) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
-    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
-    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
   }
   return hipGetLastError();
 }
 
-template <int S, int L>
-static hipError_t launch_hop_t(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
-                               void *out, const void *x, int nrhs, hipStream_t st) {
-  const int T = hop_split(S, (long)lat->geo.nb * nrhs);
-  if constexpr (S == S_F64) return launch_hop_tt<S, L, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  else {
-    if (T == 4) return launch_hop_tt<S, L, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    return launch_hop_tt<S, L, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+template <int S, int L, int T>
+static hipError_t launch_hop_n(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
+                               const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
+  if constexpr (S == S_F64) {
+    return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  } else {
+    switch (c.nr) {
+      case 4: return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+      case 3: return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+      case 2: return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+      default: return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    }
   }
+}
+
+template <int S, int L>
+static hipError_t launch_hop_t(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
+                               const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
+  if constexpr (S == S_F64) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  else {
+    if (c.t == 4) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    return launch_hop_n<S, L, 2>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  }
+}
+
+hipError_t launch_hop_cfg(const HopCfg &c, const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a,
+                          const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
+  if (prec == QIRAL_F64) return launch_hop_t<S_F64, L_F64R18>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  if (prec == QIRAL_F32) return launch_hop_t<S_F32, L_F32R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  return launch_hop_t<S_F16S, L_F16R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
 }
 
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a, const void *in,
                       void *out, const void *x, int nrhs, hipStream_t st) {
-  if (prec == QIRAL_F64) return launch_hop_t<S_F64, L_F64R18>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  if (prec == QIRAL_F32) return launch_hop_t<S_F32, L_F32R12>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  return launch_hop_t<S_F16S, L_F16R12>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  return launch_hop_cfg(hop_config(lat, prec, nrhs), lat, prec, dagger, p, epi, a, in, out, x, nrhs, st);
 }
 }  // namespace qiral
 

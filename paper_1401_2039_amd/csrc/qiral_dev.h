@@ -10,9 +10,11 @@ namespace qiral {
 
 constexpr int WAVE = 64;   // CDNA wavefront; also the site-block of the packed layouts
 constexpr int WG = 256;    // work-group: 4 waves
-// Minimum waves per SIMD asked of the compiler for a hop kernel: caps the VGPR
-// budget (512 / waves) so enough waves stay resident to cover memory latency.
-#define HOP_MIN_WAVES(S) ((S) == 0 ? 2 : 4)
+// Minimum waves per SIMD asked of the compiler for a hop kernel (storage S, T
+// lanes per site, NR right-hand sides per lane): caps the VGPR budget at
+// 512 / waves so enough waves stay resident to cover memory latency, while
+// leaving the larger NR / smaller T variants room to avoid spilling.
+#define HOP_MIN_WAVES(S, T, NR) ((S) == 0 ? 2 : (NR) == 1 ? ((T) == 4 ? 4 : 3) : (NR) == 2 ? ((T) == 4 ? 3 : 2) : 2)
 
 // ---------------------------------------------------------------------------
 // Lattice geometry of one parity-checkerboarded lattice.
@@ -24,6 +26,7 @@ struct Geo {
   int vh;      // sites per parity
   int nb;      // 64-site blocks per parity (vh rounded up)
   int sy, sz, st;  // checkerboard-index strides of y, z, t
+  double rlxh, rly, rlz;   // 1 / (Lx/2), 1 / Ly, 1 / Lz for the coordinate divisions
 };
 
 inline Geo make_geo(const int32_t d[4]) {
@@ -33,6 +36,7 @@ inline Geo make_geo(const int32_t d[4]) {
   g.vh = (int)((int64_t)d[0] * d[1] * d[2] * d[3] / 2);
   g.nb = (g.vh + WAVE - 1) / WAVE;
   g.sy = g.lxh; g.sz = g.lxh * g.ly; g.st = g.sz * g.lz;
+  g.rlxh = 1.0 / g.lxh; g.rly = 1.0 / g.ly; g.rlz = 1.0 / g.lz;
   return g;
 }
 
@@ -66,6 +70,39 @@ template <class R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) { return cmak
 // Component order inside a site is k = 4 * colour + spin.
 enum { S_F64 = 0, S_F32 = 1, S_F16S = 2 };
 
+// Non-temporal (streaming) 16- and 8-byte accesses: data read or written once
+// per launch (links, hop outputs) is marked so that it does not displace the
+// neighbour spinors that other sites re-read from L2.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+  const f32x4 v = __builtin_nontemporal_load((const f32x4 *)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+  const f64x2 v = __builtin_nontemporal_load((const f64x2 *)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ uint2 ld_nt(const uint2 *p) {
+  const u32x2 v = __builtin_nontemporal_load((const u32x2 *)p);
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v) {
+  f32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, (f32x4 *)p);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+  f64x2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, (f64x2 *)p);
+}
+__device__ __forceinline__ void st_nt(uint4 *p, uint4 v) {
+  u32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, (u32x4 *)p);
+}
+__device__ __forceinline__ void st_nt(float *p, float v) { __builtin_nontemporal_store(v, p); }
+
 template <int S> struct SpinorIO;
 
 template <> struct SpinorIO<S_F64> {
@@ -83,6 +120,11 @@ template <> struct SpinorIO<S_F64> {
     double2 *p = (double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
 #pragma unroll
     for (int k = 0; k < 12; ++k) p[k * WAVE] = make_double2(v[k].re, v[k].im);
+  }
+  __device__ static void store_fast(void *base, int s, size_t npad, const cpx<double> v[12]) {
+    double2 *p = (double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) st_nt(p + k * WAVE, make_double2(v[k].re, v[k].im));
   }
 };
 
@@ -106,10 +148,16 @@ template <> struct SpinorIO<S_F32> {
 #pragma unroll
     for (int j = 0; j < 6; ++j) p[j * WAVE] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
   }
+  __device__ static void store_fast(void *base, int s, size_t npad, const cpx<float> v[12]) {
+    float4 *p = (float4 *)base + (size_t)(s >> 6) * (6 * WAVE) + (s & 63);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) st_nt(p + j * WAVE, make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im));
+  }
 };
 
 __device__ __forceinline__ float h2f(unsigned short h) { return __half2float(__ushort_as_half(h)); }
 __device__ __forceinline__ unsigned short f2h(float f) { return __half_as_ushort(__float2half_rn(f)); }
+
 
 template <> struct SpinorIO<S_F16S> {
   using R = float;
@@ -151,6 +199,25 @@ template <> struct SpinorIO<S_F16S> {
     }
     scale_ptr(base, npad)[s] = zero ? 0.f : m;
   }
+  // Same format, quantised with one reciprocal per site (values may differ from
+  // store() in the last FP16 bit); used for the outputs of the hot kernels.
+  __device__ static void store_fast(void *base, int s, size_t npad, const cpx<float> v[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+    uint4 *p = (uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
+    const bool zero = !(m > 0.f);
+    const float r = zero ? 0.f : 1.f / m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      unsigned w[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        w[c] = (unsigned)f2h(v[4 * j + c].re * r) | ((unsigned)f2h(v[4 * j + c].im * r) << 16);
+      st_nt(p + j * WAVE, make_uint4(w[0], w[1], w[2], w[3]));
+    }
+    st_nt(scale_ptr(base, npad) + s, m);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -181,7 +248,7 @@ template <> struct LinkIO<L_F64R18> {
   __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {
     const double2 *p = (const double2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 9) * WAVE + (s & 63);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) { double2 q = p[j * WAVE]; u[j] = cmake(q.x, q.y); }
+    for (int j = 0; j < 9; ++j) { double2 q = ld_nt(p + j * WAVE); u[j] = cmake(q.x, q.y); }
   }
 };
 
@@ -192,7 +259,7 @@ template <> struct LinkIO<L_F32R12> {
     const float4 *p = (const float4 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float4 q = p[j * WAVE];
+      float4 q = ld_nt(p + j * WAVE);
       u[2 * j] = cmake(q.x, q.y);
       u[2 * j + 1] = cmake(q.z, q.w);
     }
@@ -207,7 +274,7 @@ template <> struct LinkIO<L_F16R12> {
     const uint2 *p = (const uint2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint2 q = p[j * WAVE];
+      uint2 q = ld_nt(p + j * WAVE);
       u[2 * j] = cmake(h2f((unsigned short)(q.x & 0xffffu)), h2f((unsigned short)(q.x >> 16)));
       u[2 * j + 1] = cmake(h2f((unsigned short)(q.y & 0xffffu)), h2f((unsigned short)(q.y >> 16)));
     }
@@ -216,49 +283,17 @@ template <> struct LinkIO<L_F16R12> {
 };
 
 // ---------------------------------------------------------------------------
-// Spin projection in the chiral basis gamma_mu = [[0, B_mu], [B_mu^+, 0]] with
-// B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1.
+// The hop.  Chiral basis gamma_mu = [[0, B_mu], [B_mu^+, 0]] with
+// B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1:
 // (1 + S gamma_mu) psi has upper half h = psi_up + S B psi_lo and lower half
-// S B^+ h, so each hop term needs two colour products (one per component of h).
-
-// h[2c + a] = psi[4c + a] + S (B_mu psi_lo)_a
-template <int MU, int S, class R>
-__device__ __forceinline__ void spin_project(const cpx<R> psi[12], cpx<R> h[6]) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    cpx<R> u0 = psi[4 * c + 0], u1 = psi[4 * c + 1], l0 = psi[4 * c + 2], l1 = psi[4 * c + 3];
-    cpx<R> b0, b1;
-    if (MU == 0) { b0 = cmi(l1); b1 = cmi(l0); }            // -i sigma_x
-    else if (MU == 1) { b0 = cmake(-l1.re, -l1.im); b1 = l0; } // -i sigma_y
-    else if (MU == 2) { b0 = cmi(l0); b1 = ci(l1); }        // -i sigma_z
-    else { b0 = l0; b1 = l1; }                              // 1
-    if (S > 0) { h[2 * c] = cadd(u0, b0); h[2 * c + 1] = cadd(u1, b1); }
-    else { h[2 * c] = csub(u0, b0); h[2 * c + 1] = csub(u1, b1); }
-  }
-}
-
-// acc += (upper = w, lower = S B_mu^+ w); FIRST assigns instead of adding.
-template <int MU, int S, bool FIRST, class R>
-__device__ __forceinline__ void spin_accumulate(const cpx<R> w[6], cpx<R> acc[12]) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    cpx<R> w0 = w[2 * c], w1 = w[2 * c + 1];
-    cpx<R> l0, l1;   // B^+ w
-    if (MU == 0) { l0 = ci(w1); l1 = ci(w0); }              // (-i sigma_x)^+ = i sigma_x
-    else if (MU == 1) { l0 = w1; l1 = cmake(-w0.re, -w0.im); }
-    else if (MU == 2) { l0 = ci(w0); l1 = cmi(w1); }
-    else { l0 = w0; l1 = w1; }
-    if (S < 0) { l0 = cmake(-l0.re, -l0.im); l1 = cmake(-l1.re, -l1.im); }
-    if (FIRST) {
-      acc[4 * c + 0] = w0; acc[4 * c + 1] = w1; acc[4 * c + 2] = l0; acc[4 * c + 3] = l1;
-    } else {
-      acc[4 * c + 0] = cadd(acc[4 * c + 0], w0);
-      acc[4 * c + 1] = cadd(acc[4 * c + 1], w1);
-      acc[4 * c + 2] = cadd(acc[4 * c + 2], l0);
-      acc[4 * c + 3] = cadd(acc[4 * c + 3], l1);
-    }
-  }
-}
+// S B^+ h, so each of the 8 terms is one spin projection to a half spinor (6
+// complex), two SU(3) x colour-vector products, and a reconstruction.
+//
+// A site's 8 terms are shared by T lanes (T = 2 or 4): lane group g takes the
+// directions g, g + T, ...; the groups' sums are combined with cross-lane
+// shuffles.  Because lanes of one wave take different directions, the spin
+// matrices are applied through small (source, phase) tables rather than
+// compile-time specialisation, so all lanes run the same instructions.
 
 // w = U h (ADJ = false) or U^+ h (ADJ = true) for both spin components of h.
 template <bool ADJ, class R>
@@ -287,100 +322,6 @@ template <class Rd, class Rs> __device__ __forceinline__ void cvt12(const cpx<Rs
   for (int k = 0; k < 12; ++k) b[k] = cmake((Rd)a[k].re, (Rd)a[k].im);
 }
 
-// Neighbour checkerboard indices of output site s (parity p) in the 8 directions.
-struct Nbr { int fwd[4], bwd[4]; };
-
-__device__ __forceinline__ Nbr neighbours(const Geo &g, int s, int p) {
-  int xh = s % g.lxh;
-  int r = s / g.lxh;
-  int y = r % g.ly; r /= g.ly;
-  int z = r % g.lz;
-  int t = r / g.lz;
-  int x = 2 * xh + ((p + y + z + t) & 1);
-  int base = s - xh;
-  Nbr n;
-  n.fwd[0] = base + ((x + 1 == g.lx ? 0 : x + 1) >> 1);
-  n.bwd[0] = base + ((x == 0 ? g.lx - 1 : x - 1) >> 1);
-  n.fwd[1] = (y + 1 == g.ly) ? s - (g.ly - 1) * g.sy : s + g.sy;
-  n.bwd[1] = (y == 0) ? s + (g.ly - 1) * g.sy : s - g.sy;
-  n.fwd[2] = (z + 1 == g.lz) ? s - (g.lz - 1) * g.sz : s + g.sz;
-  n.bwd[2] = (z == 0) ? s + (g.lz - 1) * g.sz : s - g.sz;
-  n.fwd[3] = (t + 1 == g.lt) ? s - (g.lt - 1) * g.st : s + g.st;
-  n.bwd[3] = (t == 0) ? s + (g.lt - 1) * g.st : s - g.st;
-  return n;
-}
-
-// Field loaders: a loader reads the 12 components of site s of a packed field
-// and converts them to the compute type R.
-template <int S> struct FieldLd {
-  using R = typename SpinorIO<S>::R;
-  const void *base;
-  size_t npad;
-  __device__ __forceinline__ void operator()(int s, cpx<R> v[12]) const { SpinorIO<S>::load(base, s, npad, v); }
-};
-
-// Sum of an FP64 field and an FP32 field (the solution of a mixed-precision
-// solve: FP64 accumulated part plus the FP32 part not yet folded in).
-struct SumLd {
-  using R = double;
-  const void *a;   // F64
-  const void *b;   // F32, or null
-  size_t npad;
-  __device__ __forceinline__ void operator()(int s, cpx<double> v[12]) const {
-    SpinorIO<S_F64>::load(a, s, npad, v);
-    if (b) {
-      cpx<float> w[12];
-      SpinorIO<S_F32>::load(b, s, npad, w);
-#pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] = cadd(v[k], cmake((double)w[k].re, (double)w[k].im));
-    }
-  }
-};
-
-// One direction: forward term (spin sign SF) and backward term (sign SB).
-template <class Ld, int L, int MU, int SF, int SB, bool FIRST>
-__device__ __forceinline__ void hop_dir(const Geo &g, const void *gauge, const Ld &ld, int s, int p, const Nbr &n,
-                                        cpx<typename Ld::R> acc[12]) {
-  using R = typename Ld::R;
-  cpx<R> psi[12], h[6], w[6];
-  cpx<typename LinkIO<L>::R> u0[9];
-  cpx<R> u[9];
-  // forward: (1 + SF g_mu) U_mu(x) psi(x + mu)
-  ld(n.fwd[MU], psi);
-  LinkIO<L>::load(gauge, p, MU, s, g.nb, u0);
-#pragma unroll
-  for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
-  spin_project<MU, SF>(psi, h);
-  su3_mul<false>(u, h, w);
-  spin_accumulate<MU, SF, FIRST>(w, acc);
-  // backward: (1 + SB g_mu) U_mu(x - mu)^+ psi(x - mu)
-  ld(n.bwd[MU], psi);
-  LinkIO<L>::load(gauge, 1 - p, MU, n.bwd[MU], g.nb, u0);
-#pragma unroll
-  for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
-  spin_project<MU, SB>(psi, h);
-  su3_mul<true>(u, h, w);
-  spin_accumulate<MU, SB, false>(w, acc);
-}
-
-// acc = (H psi)(s) for output parity p (DAG: H^dagger, which flips the spin signs).
-template <int L, bool DAG, class Ld>
-__device__ __forceinline__ void hop_site(const Geo &g, const void *gauge, const Ld &ld, int s, int p,
-                                         cpx<typename Ld::R> acc[12]) {
-  const Nbr n = neighbours(g, s, p);
-  constexpr int SF = DAG ? 1 : -1;   // forward: 1 - gamma (H), 1 + gamma (H^dagger)
-  constexpr int SB = DAG ? -1 : 1;
-  hop_dir<Ld, L, 0, SF, SB, true>(g, gauge, ld, s, p, n, acc);
-  hop_dir<Ld, L, 1, SF, SB, false>(g, gauge, ld, s, p, n, acc);
-  hop_dir<Ld, L, 2, SF, SB, false>(g, gauge, ld, s, p, n, acc);
-  hop_dir<Ld, L, 3, SF, SB, false>(g, gauge, ld, s, p, n, acc);
-}
-
-// ---------------------------------------------------------------------------
-// Direction-generic variant for splitting one site over T lanes (T = 2 or 4):
-// each lane group takes 4/T directions, chosen at run time from its lane
-// index, so the spin matrices are applied through small phase tables instead of
-// compile-time specialisation (all lanes run the same instructions).
 // Phase codes: 0 -> 1, 1 -> i, 2 -> -1, 3 -> -i.
 template <class R> __device__ __forceinline__ cpx<R> cphase(cpx<R> z, int f) {
   const bool sw = f & 1;
@@ -390,8 +331,7 @@ template <class R> __device__ __forceinline__ cpx<R> cphase(cpx<R> z, int f) {
   return cmake(re, im);
 }
 
-// B_mu (lower -> upper) and B_mu^+ as (source index, phase) per output row:
-// B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1.
+// B_mu (lower spinor -> upper) and B_mu^+, as (source component, phase) per row.
 __device__ __forceinline__ void bmat(int mu, int &j0, int &f0, int &j1, int &f1) {
   j0 = (mu == 0 || mu == 1) ? 1 : 0;
   j1 = 1 - j0;
@@ -405,66 +345,115 @@ __device__ __forceinline__ void bdag(int mu, int &j0, int &f0, int &j1, int &f1)
   f1 = mu == 0 ? 1 : mu == 1 ? 2 : mu == 2 ? 3 : 0;
 }
 
-// Checkerboard index of the neighbour of s (parity p) in direction mu, forward
-// (fwd = true) or backward.
-__device__ __forceinline__ int neighbour(const Geo &g, int s, int p, int mu, bool fwd) {
-  const int xh = s % g.lxh;
-  int r = s / g.lxh;
-  const int y = r % g.ly; r /= g.ly;
-  const int z = r % g.lz;
-  const int t = r / g.lz;
-  if (mu == 0) {
-    const int x = 2 * xh + ((p + y + z + t) & 1);
-    const int xn = fwd ? (x + 1 == g.lx ? 0 : x + 1) : (x == 0 ? g.lx - 1 : x - 1);
-    return s - xh + (xn >> 1);
-  }
-  const int c = mu == 1 ? y : mu == 2 ? z : t;
-  const int L = mu == 1 ? g.ly : mu == 2 ? g.lz : g.lt;
-  const int st = mu == 1 ? g.sy : mu == 2 ? g.sz : g.st;
-  if (fwd) return (c + 1 == L) ? s - (L - 1) * st : s + st;
-  return (c == 0) ? s + (L - 1) * st : s - st;
+// Coordinates of checkerboard site s of parity p.  The divisions by Lx/2, Ly
+// and Lz use (n + 1/2) * (1/d) in FP64, exact for n < 2^30 and d < 2^16.
+struct SiteC { int s, xh, y, z, t, x; };
+
+__device__ __forceinline__ int qdiv(int n, double r) { return (int)(((double)n + 0.5) * r); }
+
+__device__ __forceinline__ SiteC site_c(const Geo &g, int s, int p) {
+  SiteC c;
+  c.s = s;
+  const int q1 = qdiv(s, g.rlxh);
+  c.xh = s - q1 * g.lxh;
+  const int q2 = qdiv(q1, g.rly);
+  c.y = q1 - q2 * g.ly;
+  c.t = qdiv(q2, g.rlz);
+  c.z = q2 - c.t * g.lz;
+  c.x = 2 * c.xh + ((p + c.y + c.z + c.t) & 1);
+  return c;
 }
 
-// One direction with run-time mu; spin signs sf (forward) and sb (backward).
+// Checkerboard index of the neighbour in direction mu, forward or backward.
+__device__ __forceinline__ int nbr(const Geo &g, const SiteC &c, int mu, bool fwd) {
+  if (mu == 0) {
+    const int xn = fwd ? (c.x + 1 == g.lx ? 0 : c.x + 1) : (c.x == 0 ? g.lx - 1 : c.x - 1);
+    return c.s - c.xh + (xn >> 1);
+  }
+  const int co = mu == 1 ? c.y : mu == 2 ? c.z : c.t;
+  const int L = mu == 1 ? g.ly : mu == 2 ? g.lz : g.lt;
+  const int st = mu == 1 ? g.sy : mu == 2 ? g.sz : g.st;
+  if (fwd) return (co + 1 == L) ? c.s - (L - 1) * st : c.s + st;
+  return (co == 0) ? c.s + (L - 1) * st : c.s - st;
+}
+
+// Field loaders: NF packed fields (right-hand sides) read at one site and
+// converted to the compute type R.
+template <int S, int N> struct FieldLd {
+  using R = typename SpinorIO<S>::R;
+  static constexpr int NF = N;
+  const void *base[N];
+  size_t npad;
+  __device__ __forceinline__ void operator()(int r, int s, cpx<R> v[12]) const { SpinorIO<S>::load(base[r], s, npad, v); }
+};
+
+// Sum of an FP64 field and an FP32 field (the solution of a mixed-precision
+// solve: FP64 accumulated part plus the FP32 part not yet folded in).
+struct SumLd {
+  using R = double;
+  static constexpr int NF = 1;
+  const void *a;   // F64
+  const void *b;   // F32, or null
+  size_t npad;
+  __device__ __forceinline__ void operator()(int, int s, cpx<double> v[12]) const {
+    SpinorIO<S_F64>::load(a, s, npad, v);
+    if (b) {
+      cpx<float> w[12];
+      SpinorIO<S_F32>::load(b, s, npad, w);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = cadd(v[k], cmake((double)w[k].re, (double)w[k].im));
+    }
+  }
+};
+
+// Forward and backward terms of one (run-time) direction mu for every field of
+// the loader; each link is loaded and rebuilt once and applied to all fields.
+// Spin signs sf (forward term) and sb (backward term).
 template <class Ld, int L>
-__device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int mu, int sf,
-                                           int sb, bool first, cpx<typename Ld::R> acc[12]) {
+__device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
+                                           int mu, int sf, int sb, bool first,
+                                           cpx<typename Ld::R> acc[Ld::NF][12]) {
   using R = typename Ld::R;
   int j0, f0, j1, f1, k0, e0, k1, e1;
   bmat(mu, j0, f0, j1, f1);
   bdag(mu, k0, e0, k1, e1);
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
-    const int sg = dir == 0 ? sf : sb;
-    const int ph = sg > 0 ? 0 : 2;           // the projection sign as a phase
-    const int nb = neighbour(g, s, p, mu, dir == 0);
-    cpx<R> psi[12], h[6], w[6], u[9];
-    cpx<typename LinkIO<L>::R> u0[9];
-    ld(nb, psi);
-    if (dir == 0) LinkIO<L>::load(gauge, p, mu, s, g.nb, u0);
-    else LinkIO<L>::load(gauge, 1 - p, mu, nb, g.nb, u0);
+    const int ph = (dir == 0 ? sf : sb) > 0 ? 0 : 2;   // the projection sign as a phase
+    const int n = nbr(g, c, mu, dir == 0);
+    cpx<R> u[9];
+    {
+      cpx<typename LinkIO<L>::R> u0[9];
+      if (dir == 0) LinkIO<L>::load(gauge, p, mu, c.s, g.nb, u0);
+      else LinkIO<L>::load(gauge, 1 - p, mu, n, g.nb, u0);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cpx<R> l0 = psi[4 * c + 2], l1 = psi[4 * c + 3];
-      h[2 * c] = cadd(psi[4 * c], cphase(j0 ? l1 : l0, (f0 + ph) & 3));
-      h[2 * c + 1] = cadd(psi[4 * c + 1], cphase(j1 ? l1 : l0, (f1 + ph) & 3));
+      for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
     }
-    if (dir == 0) su3_mul<false>(u, h, w);
-    else su3_mul<true>(u, h, w);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cpx<R> w0 = w[2 * c], w1 = w[2 * c + 1];
-      const cpx<R> lo0 = cphase(k0 ? w1 : w0, (e0 + ph) & 3);
-      const cpx<R> lo1 = cphase(k1 ? w1 : w0, (e1 + ph) & 3);
-      if (first && dir == 0) {
-        acc[4 * c] = w0; acc[4 * c + 1] = w1; acc[4 * c + 2] = lo0; acc[4 * c + 3] = lo1;
-      } else {
-        acc[4 * c] = cadd(acc[4 * c], w0);
-        acc[4 * c + 1] = cadd(acc[4 * c + 1], w1);
-        acc[4 * c + 2] = cadd(acc[4 * c + 2], lo0);
-        acc[4 * c + 3] = cadd(acc[4 * c + 3], lo1);
+    for (int r = 0; r < Ld::NF; ++r) {
+      cpx<R> psi[12], h[6], w[6];
+      ld(r, n, psi);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const cpx<R> l0 = psi[4 * cc + 2], l1 = psi[4 * cc + 3];
+        h[2 * cc] = cadd(psi[4 * cc], cphase(j0 ? l1 : l0, (f0 + ph) & 3));
+        h[2 * cc + 1] = cadd(psi[4 * cc + 1], cphase(j1 ? l1 : l0, (f1 + ph) & 3));
+      }
+      if (dir == 0) su3_mul<false>(u, h, w);
+      else su3_mul<true>(u, h, w);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const cpx<R> w0 = w[2 * cc], w1 = w[2 * cc + 1];
+        const cpx<R> lo0 = cphase(k0 ? w1 : w0, (e0 + ph) & 3);
+        const cpx<R> lo1 = cphase(k1 ? w1 : w0, (e1 + ph) & 3);
+        if (first && dir == 0) {
+          acc[r][4 * cc] = w0; acc[r][4 * cc + 1] = w1; acc[r][4 * cc + 2] = lo0; acc[r][4 * cc + 3] = lo1;
+        } else {
+          acc[r][4 * cc] = cadd(acc[r][4 * cc], w0);
+          acc[r][4 * cc + 1] = cadd(acc[r][4 * cc + 1], w1);
+          acc[r][4 * cc + 2] = cadd(acc[r][4 * cc + 2], lo0);
+          acc[r][4 * cc + 3] = cadd(acc[r][4 * cc + 3], lo1);
+        }
       }
     }
   }
@@ -482,20 +471,18 @@ template <int T, class R> __device__ __forceinline__ void group_sum(cpx<R> acc[1
   }
 }
 
-// Hop on T lanes per site: lane group t (0..T-1) takes directions t, t+T, ...
-// and every group ends with the full sum.  (T = 1, the whole site in one lane,
-// is kept for reference but not launched: it needs ~256 VGPRs.)
+// acc[r] = (H psi_r)(s) (DAG: H^dagger, which flips the spin signs) for output
+// parity p, on T lanes per site; every lane group ends with the full sums.
 template <int L, bool DAG, int T, class Ld>
-__device__ __forceinline__ void hop_part(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int t,
-                                         cpx<typename Ld::R> acc[12]) {
-  if constexpr (T == 1) {
-    hop_site<L, DAG>(g, gauge, ld, s, p, acc);
-  } else {
-    constexpr int SF = DAG ? 1 : -1, SB = DAG ? -1 : 1;
+__device__ __forceinline__ void hop_part(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int grp,
+                                         cpx<typename Ld::R> acc[Ld::NF][12]) {
+  static_assert(T == 2 || T == 4, "2 or 4 lanes per site");
+  constexpr int SF = DAG ? 1 : -1, SB = DAG ? -1 : 1;
+  const SiteC c = site_c(g, s, p);
 #pragma unroll
-    for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L>(g, gauge, ld, s, p, t + k * T, SF, SB, k == 0, acc);
-    group_sum<T>(acc);
-  }
+  for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L>(g, gauge, ld, c, p, grp + k * T, SF, SB, k == 0, acc);
+#pragma unroll
+  for (int r = 0; r < Ld::NF; ++r) group_sum<T>(acc[r]);
 }
 
 // Lane -> (site within a 64-site block, lane group) for T lanes per site; the T
@@ -523,6 +510,9 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)
 // XCDs in turn; this remap gives each XCD one contiguous range of logical
 // blocks, so neighbouring sites share an L2.
 __device__ __forceinline__ int xcd_remap(int hw, int nblocks) {
+#ifdef QIRAL_NO_XCD_REMAP
+  return hw;
+#endif
   const int q = nblocks >> 3, r = nblocks & 7;
   const int xcd = hw & 7, idx = hw >> 3;
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;

@@ -18,6 +18,8 @@ struct qiral_lattice {
   void *ws = nullptr;    // solver workspace, grown on demand
   size_t ws_bytes = 0;
   int device = 0;
+  int tuned_nr[3][5] = {};   // autotuned right-hand sides per lane [prec][min(nrhs,4)], 0 = not tuned
+  int tuned_t[3][5] = {};    // autotuned lanes per site, same index, 0 = not tuned
 };
 
 namespace qiral {
@@ -35,9 +37,19 @@ inline size_t npad_of(const Geo &g) { return (size_t)g.nb * WAVE; }
 size_t half_bytes(const Geo &g, int prec);
 const void *links_for(const qiral_lattice *lat, int prec);
 
-// Lanes per site of a hop launch over `nwork` 64-site work items: enough waves
-// to give every SIMD (256 CUs x 4) a few.  QIRAL_HOP_SPLIT=2|4 overrides.
+// Launch shape of a hop: t lanes per site (2 or 4) and nr right-hand sides per
+// lane (1..4; FP64 1..2).  hop_split picks t for `nwork` 64-site work items
+// (enough waves to give every SIMD, 256 CUs x 4, a few); tuned_nr gives the
+// autotuned nr of a lattice (a heuristic until tuned).  QIRAL_HOP_SPLIT and
+// QIRAL_HOP_NR override.
+struct HopCfg { int t = 4, nr = 1; };
 int hop_split(int prec, long nwork);
+// Blocks per traversal tile of a multi-group hop (see k_hop).
+int hop_tile(const Geo &g, int ngroups);
+int tuned_nr(const qiral_lattice *lat, int prec, int nrhs);
+HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs);
+hipError_t launch_hop_cfg(const HopCfg &c, const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi,
+                          double a, const void *in, void *out, const void *x, int nrhs, hipStream_t s);
 
 // Grid of ceil(nwaves / 4) work-groups (4 waves of 64 lanes each).
 inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }

@@ -100,7 +100,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   if (nwork > (1l << 30)) return fail(QIRAL_ERR_UNSUPPORTED, "too many work items");
   size_t off = 0;
   lay.off_desc = off; off = align_up(off + sizeof(SysDesc) * nsys);
-  lay.off_work = off; off = align_up(off + sizeof(uint32_t) * nwork);
+  lay.off_work = off; off = align_up(off + 2 * sizeof(uint32_t) * nwork);
   lay.off_state = off; off = align_up(off + sizeof(SysState) * nsys);
   lay.off_part = off; off = align_up(off + sizeof(double) * nparts);
   lay.off_sys.resize(nsys);
@@ -133,17 +133,34 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     d.f[F_XE] = p; d.f[F_XH] = p + half_bytes(lat->geo, QIRAL_F64); p += 2 * sz[i].hb64;
     if (!mixed) d.f[F_X] = d.f[F_XH];
   }
-  // ---- work table: right-hand sides of one lattice interleave per block (they share links)
-  std::vector<uint32_t> work;
-  work.reserve(nwork);
+  // ---- work tables.  Plain: one item per (system, block); right-hand sides of
+  // one lattice interleave per block (they share links).  Grouped (the
+  // iterate-precision hop): up to NR systems of one lattice per item.
   bool same_lattice = true;
   for (int i = 1; i < nsys; ++i) same_lattice = same_lattice && sys[i].lat == sys[0].lat;
+  HopCfg hc;
+  if (same_lattice) hc = hop_config(sys[0].lat, prec, nsys);
+  else { hc.nr = 1; hc.t = hop_split(prec, nwork); }
+  std::vector<uint32_t> work, work_hop;
+  work.reserve(nwork);
+  for (int i = 0; i < nsys; ++i)
+    if (sys[i].lat->geo.nb > MAX_BLOCKS) return fail(QIRAL_ERR_UNSUPPORTED, "lattice too large for the work tables");
   if (same_lattice && nsys > 1) {
-    for (int b = 0; b < sys[0].lat->geo.nb; ++b)
-      for (int i = 0; i < nsys; ++i) work.push_back(((uint32_t)i << 24) | (uint32_t)b);
+    // tile by tile (see hop_tile): each system, or group of systems, sweeps the
+    // tile's blocks in turn
+    const int nb = sys[0].lat->geo.nb;
+    const int tile = hop_tile(sys[0].lat->geo, nsys);
+    for (int b0 = 0; b0 < nb; b0 += tile) {
+      const int b1 = std::min(nb, b0 + tile);
+      for (int i = 0; i < nsys; ++i)
+        for (int b = b0; b < b1; ++b) work.push_back(work_item(i, 1, b));
+      for (int i = 0; i < nsys; i += hc.nr)
+        for (int b = b0; b < b1; ++b) work_hop.push_back(work_item(i, std::min(hc.nr, nsys - i), b));
+    }
   } else {
     for (int i = 0; i < nsys; ++i)
-      for (int b = 0; b < sys[i].lat->geo.nb; ++b) work.push_back(((uint32_t)i << 24) | (uint32_t)b);
+      for (int b = 0; b < sys[i].lat->geo.nb; ++b) work.push_back(work_item(i, 1, b));
+    work_hop = work;
   }
   std::vector<SysState> hst(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -158,15 +175,20 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   }
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_work, work.data(), sizeof(uint32_t) * nwork, hipMemcpyHostToDevice, s));
+  QIRAL_HIP(hipMemcpyAsync(ws + lay.off_work + sizeof(uint32_t) * nwork, work_hop.data(),
+                           sizeof(uint32_t) * work_hop.size(), hipMemcpyHostToDevice, s));
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_state, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, s));
 
   Launch L;
   L.desc = (const SysDesc *)(ws + lay.off_desc);
   L.work = (const uint32_t *)(ws + lay.off_work);
   L.nwork = (int)nwork;
+  L.work_hop = (const uint32_t *)(ws + lay.off_work) + nwork;
+  L.nwork_hop = (int)work_hop.size();
   L.nsys = nsys;
-  L.T = hop_split(prec, nwork);
-  L.T64 = hop_split(QIRAL_F64, nwork);
+  L.prec = prec;
+  L.T = hc.t;
+  L.NR = hc.nr;
   L.stream = s;
 
   // ---- inputs

@@ -188,13 +188,20 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
   }
 }
 
-// Per-wave context of a table-driven kernel.  With T lanes per site, T waves
-// share one 64-site work item (sub = 0..T-1 picks the wave's part of it) and a
-// work-group of 4 waves takes 4/T items.
+// Per-wave context of a table-driven kernel.  A work item is one 64-site block
+// of `cnt` consecutive systems that share one lattice (cnt = 1 except for the
+// grouped hop table); it is encoded as (sys0 << 24) | ((cnt - 1) << 22) | block.
+// With T lanes per site, T waves share an item (sub = 0..T-1 picks the wave's
+// part of it) and a work-group of 4 waves takes 4/T items.
 struct Item {
-  int sys, sb, sub, s, grp;
+  int sys, cnt, sb, sub, s, grp;
   bool active;
 };
+
+__host__ __device__ inline uint32_t work_item(int sys0, int cnt, int sb) {
+  return ((uint32_t)sys0 << 24) | ((uint32_t)(cnt - 1) << 22) | (uint32_t)sb;
+}
+constexpr int MAX_BLOCKS = 1 << 22;   // 64-site blocks per parity a work item can address
 
 template <int T>
 __device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
@@ -203,10 +210,11 @@ __device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
   const int idx = wg * (4 / T) + w / T;
   it.sub = w % T;
-  if (idx >= nwork) { it.active = false; it.sys = 0; it.sb = 0; it.s = 0; it.grp = 0; return it; }
+  if (idx >= nwork) { it.active = false; it.sys = 0; it.cnt = 0; it.sb = 0; it.s = 0; it.grp = 0; return it; }
   const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)work[idx]);
   it.sys = (int)(v >> 24);
-  it.sb = (int)(v & 0xffffffu);
+  it.cnt = (int)((v >> 22) & 3u) + 1;
+  it.sb = (int)(v & 0x3fffffu);
   int sib;
   split_lane<T>(it.sub, sib, it.grp);
   it.s = it.sb * WAVE + sib;

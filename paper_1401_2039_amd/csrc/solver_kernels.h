@@ -8,12 +8,15 @@ namespace qiral {
 struct SysDesc;
 
 struct Launch {
-  const SysDesc *desc;   // device system table
-  const uint32_t *work;  // device work table: (system << 24) | 64-site block
+  const SysDesc *desc;       // device system table
+  const uint32_t *work;      // device work table, one item per (system, 64-site block)
   int nwork;
+  const uint32_t *work_hop;  // grouped table for the iterate-precision hop: items cover
+  int nwork_hop;             //   up to NR systems of one lattice
   int nsys;
-  int T;                 // lanes per site of the iterate-precision hop (1, 2 or 4)
-  int T64;               // lanes per site of the FP64 hop
+  int prec;                  // iterate precision (S_F64, S_F32, S_F16S)
+  int T;                     // lanes per site of the iterate-precision hop (2 or 4)
+  int NR;                    // systems per item of the grouped table
   hipStream_t stream;
 };
 

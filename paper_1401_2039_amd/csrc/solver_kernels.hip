@@ -16,45 +16,63 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
   return S == S_F64 ? d.g64 : d.glo;
 }
 
-// out = a H in (EPI 0) or out = x + a H in (EPI 1), parity `par` out.
+// out = a H in (EPI 0) or out = x + a H in (EPI 1), parity `par` out, for the
+// (up to NR) systems of a grouped work item (they share the lattice, so each
+// link is loaded once for all of them).
 // red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
 // T lanes per site (see hop_part); padded lanes compute on site 0 and store nothing.
-template <int S, int L, bool DAG, int EPI, int T>
-__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S)) void k_hop_sys(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
-                                                int nwork, int fin_id, int fout, int fx, int par, int amode, int mask,
-                                                int red, int slot) {
+template <int S, int L, bool DAG, int EPI, int T, int NR>
+__global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const SysDesc *__restrict__ sdesc,
+                                                                 const uint32_t *__restrict__ work, int nwork,
+                                                                 int fin_id, int fout, int fx, int par, int amode,
+                                                                 int mask, int red, int slot) {
   using R = typename SpinorIO<S>::R;
   const Item it = fetch_item<T>(work, nwork);
   if (!it.active) return;
-  const SysDesc &d = sdesc[it.sys];
-  if (!(d.st->status & mask)) return;
-  const bool site_ok = it.s < d.g.vh;
-  const size_t npad = d.npad;
-  double v[NV] = {0.0, 0.0, 0.0};
-  cpx<R> acc[12];
-  FieldLd<S> ld{d.f[fin_id], npad};
-  hop_part<L, DAG, T>(d.g, links_of<S>(d), ld, site_ok ? it.s : 0, par, it.grp, acc);
-  if (site_ok && it.grp == 0) {
-    const R a = (R)coef(amode, d.kappa);
-    if (EPI == 0) {
+  bool act[NR];
+  bool any = false;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] = cscale(a, acc[k]);
-    } else {
-      cpx<R> xv[12];
-      SpinorIO<S>::load(d.f[fx], it.s, npad, xv);
-#pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] = cadd(xv[k], cscale(a, acc[k]));
-      if (red == 3) { dot12(acc, xv, v[0], v[1]); v[2] = norm12(acc); }
-    }
-    SpinorIO<S>::store(d.f[fout], it.s, npad, acc);
-    if (red == 1) v[0] = norm12(acc);
-    if (red == 2) {
-      cpx<R> rt[12];
-      SpinorIO<S>::load(d.f[F_RT], it.s, npad, rt);
-      dot12(rt, acc, v[0], v[1]);
-    }
+  for (int r = 0; r < NR; ++r) {
+    act[r] = r < it.cnt && (sdesc[it.sys + r].st->status & mask);
+    any = any || act[r];
   }
-  if (red) sys_partial<T>(d, slot, it, v);
+  if (!any) return;
+  const SysDesc &d0 = sdesc[it.sys];
+  const bool site_ok = it.s < d0.g.vh;
+  const size_t npad = d0.npad;
+  FieldLd<S, NR> ld;
+  ld.npad = npad;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) ld.base[r] = sdesc[it.sys + min(r, it.cnt - 1)].f[fin_id];
+  cpx<R> acc[NR][12];
+  hop_part<L, DAG, T>(d0.g, links_of<S>(d0), ld, site_ok ? it.s : 0, par, it.grp, acc);
+  const R a = (R)coef(amode, d0.kappa);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (!act[r]) continue;
+    const SysDesc &d = sdesc[it.sys + r];
+    double v[NV] = {0.0, 0.0, 0.0};
+    if (site_ok && it.grp == 0) {
+      if (EPI == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r][k] = cscale(a, acc[r][k]);
+      } else {
+        cpx<R> xv[12];
+        SpinorIO<S>::load(d.f[fx], it.s, npad, xv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(a, acc[r][k]));
+        if (red == 3) { dot12(acc[r], xv, v[0], v[1]); v[2] = norm12(acc[r]); }
+      }
+      SpinorIO<S>::store_fast(d.f[fout], it.s, npad, acc[r]);
+      if (red == 1) v[0] = norm12(acc[r]);
+      if (red == 2) {
+        cpx<R> rt[12];
+        SpinorIO<S>::load(d.f[F_RT], it.s, npad, rt);
+        dot12(rt, acc[r], v[0], v[1]);
+      }
+    }
+    if (red) sys_partial<T>(d, slot, it, v);
+  }
 }
 
 // T64 = H_eo (XH + X): the hop of the current solution for the FP64 residual.
@@ -66,10 +84,10 @@ __global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ s
   const SysDesc &d = sdesc[it.sys];
   if (!(d.st->status & ST_UPDATE)) return;
   const bool site_ok = it.s < d.g.vh;
-  cpx<double> acc[12];
+  cpx<double> acc[1][12];
   SumLd ld{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
   hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
-  if (site_ok && it.grp == 0) SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc);
+  if (site_ok && it.grp == 0) SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc[0]);
 }
 
 // Reliable update on the odd sites: y = XH + X; XH = y; X = 0;
@@ -85,13 +103,14 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
   if (!(d.st->status & ST_UPDATE)) return;
   const bool site_ok = it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
-  cpx<double> acc[12];
-  FieldLd<S_F64> ld{d.f[F_T64], d.npad};
-  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc);
+  cpx<double> acc1[1][12];
+  FieldLd<S_F64, 1> ld{{d.f[F_T64]}, d.npad};
+  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc1);
+  cpx<double> *acc = acc1[0];
   if (site_ok && it.grp == 0) {
     cpx<double> y[12], b[12];
     SumLd yl{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
-    yl(it.s, y);
+    yl(0, it.s, y);
     if (HASLO) {
       SpinorIO<S_F64>::store(d.f[F_XH], it.s, d.npad, y);
       cpx<float> z[12];
@@ -128,9 +147,10 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
   const int fin_id = par ? F_XE : F_XH, fb = par ? F_BO : F_BE, fx = par ? F_XH : F_XE;
   const bool site_ok = it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
-  cpx<double> acc[12];
-  FieldLd<S_F64> ld{d.f[fin_id], d.npad};
-  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, par, it.grp, acc);
+  cpx<double> acc1[1][12];
+  FieldLd<S_F64, 1> ld{{d.f[fin_id]}, d.npad};
+  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, par, it.grp, acc1);
+  cpx<double> *acc = acc1[0];
   if (site_ok && it.grp == 0) {
     cpx<double> x[12], b[12];
     SpinorIO<S_F64>::load(d.f[fx], it.s, d.npad, x);
@@ -358,27 +378,42 @@ __global__ void k_bi_init(const SysDesc *__restrict__ sdesc, int nsys) {
 // launchers
 static inline dim3 grid_of(int nwork, int T = 1) { return dim3(grid_for(nwork, T)); }
 
-template <int S, int L, int T>
+template <int S, int L, int T, int NR>
 static void hop_sys_t(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
                       int slot) {
   const dim3 g = grid_of(l.nwork, T), b(WG);
 #define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot
   if (!dag) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T, NR>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T, NR>), g, b, 0, l.stream, QARGS);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0, T>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1, T>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0, T, NR>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1, T, NR>), g, b, 0, l.stream, QARGS);
   }
 #undef QARGS
+}
+
+template <int S, int L, int T>
+static void hop_sys_n(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
+                      int slot) {
+  if constexpr (S == S_F64) {
+    hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  } else {
+    switch (l.NR) {
+      case 4: hop_sys_t<S, L, T, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
+      case 3: hop_sys_t<S, L, T, 3>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
+      case 2: hop_sys_t<S, L, T, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
+      default: hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
+    }
+  }
 }
 
 template <int S, int L>
 static void hop_sys_p(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
                       int slot) {
-  if constexpr (S == S_F64) hop_sys_t<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  else if (l.T == 4) hop_sys_t<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  else hop_sys_t<S, L, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  if constexpr (S == S_F64) hop_sys_n<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else if (l.T == 4) hop_sys_n<S, L, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else hop_sys_n<S, L, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
 }
 
 void reduce(const Launch &l, int slot, int tmul, int fin, int mask) {
@@ -387,7 +422,12 @@ void reduce(const Launch &l, int slot, int tmul, int fin, int mask) {
 
 void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
              int red, int slot, int fin) {
-  const Launch lp = {l.desc, l.work, l.nwork, l.nsys, prec == S_F64 ? l.T64 : l.T, l.T64, l.stream};
+  // the iterate-precision hop walks the grouped table; an FP64 hop of a mixed
+  // solve (source, reconstruction) walks the plain one
+  const bool grouped = (prec == S_F64) == (l.prec == S_F64);
+  Launch lp = l;
+  if (grouped) { lp.work = l.work_hop; lp.nwork = l.nwork_hop; lp.T = l.T; lp.NR = l.NR; }
+  else { lp.T = 4; lp.NR = 1; }
   if (prec == S_F64) hop_sys_p<S_F64, L_F64R18>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else if (prec == S_F32) hop_sys_p<S_F32, L_F32R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else hop_sys_p<S_F16S, L_F16R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
@@ -412,13 +452,13 @@ template <int T> static void hop_upd_t(const Launch &l, int prec, bool bicg) {
 }
 void hop_upd(const Launch &l, int prec, bool bicg) {
   hop_upd_t<4>(l, prec, bicg);
-  reduce(l, SL_UPD, l.T64, FIN_UPDATE, ST_UPDATE);
+  reduce(l, SL_UPD, 4, FIN_UPDATE, ST_UPDATE);
 }
 
 void hop_res(const Launch &l, int par) {
-  const dim3 g = grid_of(l.nwork, l.T64), b(WG);
+  const dim3 g = grid_of(l.nwork, 4), b(WG);
   hipLaunchKernelGGL(k_hop_res<4>, g, b, 0, l.stream, l.desc, l.work, l.nwork, par);
-  reduce(l, par ? SL_RES_O : SL_RES_E, l.T64, FIN_NONE, ST_ANY);
+  reduce(l, par ? SL_RES_O : SL_RES_E, 4, FIN_NONE, ST_ANY);
 }
 
 void bnorm(const Launch &l) {

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import latgen
-from oracle import storage, wilson as W
+from oracle import solvers as S, storage, wilson as W
 import paper_1401_2039_amd as q
 from gpu_util import say, dev, host, parity_rel, parity_maxabs
 
@@ -155,3 +155,47 @@ def _r12_near(U, x):
             t, z, yy, xx = y[3], y[2], y[1], y[0]
             Ur[t, z, yy, xx] = storage.round_links_r12(U[t, z, yy, xx], np.complex64)
     return Ur
+
+
+@pytest.mark.parametrize("prec", [q.F32, q.F16S], ids=["f32", "f16s"])
+def test_launch_shapes_multi_rhs(prec, monkeypatch):
+    """Every hop launch shape (2 or 4 lanes per site, 1..4 right-hand sides per
+    lane, including a last group with fewer) gives the oracle's result."""
+    dims = (6, 4, 2, 4)
+    say("launch shapes", prec)
+    cfg = latgen.small_config(dims, seed=50, kind="expih", eps=0.4, nrhs=5)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    U, b = cfg["U"], cfg["b"]
+    if prec == q.F32:
+        Ur, br = storage.round_links_r12(U, np.complex64), storage.round_f32(b)
+    else:
+        Ur, br = storage.round_links_r12(U, "f16"), storage.round_f16s(b)
+    src = lat.import_field(dev(b), q.ODD, prec)
+    want = [W.hop_eo(Ur, br[r], 0) for r in range(5)]
+    for t in (2, 4):
+        for nr in (1, 2, 3, 4):
+            monkeypatch.setenv("QIRAL_HOP_SPLIT", str(t))
+            monkeypatch.setenv("QIRAL_HOP_NR", str(nr))
+            out = lat.field(q.EVEN, prec, nrhs=5)
+            lat.dslash_eo(out, src, 0, 0, prec, nrhs=5)
+            got = host(lat.export_field(out, 0, prec, nrhs=5))
+            for r in range(5):
+                assert parity_rel(got[r], want[r], 0) < (2e-6 if prec == q.F32 else 2e-3), (t, nr, r)
+
+
+def test_tune_and_tuned_solve(tmp_path, monkeypatch):
+    dims = (8, 8, 8, 8)
+    say("tune")
+    monkeypatch.setenv("QIRAL_TUNE_CACHE", str(tmp_path / "tune.json"))
+    cfg = latgen.small_config(dims, seed=51, kind="expih", eps=0.3, nrhs=4)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    t, nr, us = lat.tune(q.F32, 4)
+    assert t in (2, 4) and 1 <= nr <= 4 and us > 0
+    assert (tmp_path / "tune.json").exists()
+    lat2 = q.Lattice(dims, 0.12, cfg["U"])
+    t2, nr2, us2 = lat2.tune(q.F32, 4)   # served from the cache
+    assert (t2, nr2, us2) == (t, nr, 0.0)
+    x, st, info = lat2.solve(dev(cfg["b"]), tol=1e-10, inner_prec=q.F32)
+    assert st == 0
+    for r in range(4):
+        assert S.true_rel_residual(cfg["U"], 0.12, 0.0, host(x)[r], cfg["b"][r]) <= 1e-10
