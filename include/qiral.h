@@ -180,6 +180,47 @@ qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_cano
                                int32_t nsys, const qiral_solve_params *params, qiral_solve_info *info,
                                qiral_stream_t stream);
 
+/* ---- Learned preconditioner (an addition to the paper's method) -----------
+ * A 2-layer parallel-transport network 1 -> hidden -> 1 channels:
+ *   psi_out^i(x) = sum_j sum_p W_p^{ij} [T_p psi_in^j](x),
+ * paths p = 0 (identity), 1..4 (+x..+t: U_mu(x) psi(x+mu)), 5..8 (-x..-t:
+ * U_mu(x-mu)^+ psi(x-mu)), W a complex 4x4 spin matrix (Lehner & Wettig, Phys.
+ * Rev. D 108 (2023) 034503).  Weights are FP32 complex (re, im interleaved),
+ * layer 1 [9][hidden][1][4][4] then layer 2 [9][1][hidden][4][4]; the network
+ * runs in FP32 on the lattice's FP32 links, on packed FP32 FULL fields.  It is
+ * created with the weights of 1 + kappa H + kappa^2 H^2 (channel 0 carries psi,
+ * channel 1 carries H psi).  It is used by qiral_solve with solver
+ * QIRAL_FGMRES_NN and params.precond pointing to it. */
+
+/* hidden = 2, 4 or 8; the lattice needs FP32 links.  The handle owns its device
+ * memory (weights, optimiser state, activations, FGMRES workspace). */
+qiral_status qiral_nn_create(qiral_nn **nn, qiral_lattice *lat, int32_t hidden);
+qiral_status qiral_nn_destroy(qiral_nn *nn);
+/* Number of complex weights (host arrays hold 2x as many floats). */
+size_t qiral_nn_num_weights(const qiral_nn *nn);
+qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w_host, size_t count);
+qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w_host, size_t count);
+/* out = N(in) and out = N^dagger(in) on packed FP32 full fields (no aliasing). */
+qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void *in, qiral_stream_t stream);
+qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream);
+/* The Gaussian training vector of (seed, step) as a packed FP32 full field: the
+ * 24 reals of canonical site lex come from Philox4x32-10 (Salmon et al. 2011)
+ * with counter (lex, k, step_lo, step_hi), k = 0..5, key (seed_lo, seed_hi),
+ * uniforms (n + 1/2) 2^-32 and the Box-Muller transform.  norm2 (host, may be
+ * NULL) receives ||v||^2. */
+qiral_status qiral_nn_sample(qiral_nn *nn, void *out, uint64_t seed, uint64_t step, double *norm2,
+                             qiral_stream_t stream);
+/* Loss ||N(src) - target||^2 / ||target||^2 and its gradient with respect to the
+ * real and imaginary parts of every weight (host arrays; grad holds
+ * 2 * qiral_nn_num_weights doubles, re/im interleaved; either may be NULL). */
+qiral_status qiral_nn_grad(qiral_nn *nn, const void *src, const void *target, double *loss, double *grad,
+                           qiral_stream_t stream);
+/* steps Adam updates (lr; beta 0.9, 0.999) on the pairs (D v, v), v the
+ * training vectors of (seed, global step counter); loss_history (host[steps])
+ * may be NULL.  Blocking. */
+qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, uint64_t seed, double *loss_history,
+                            qiral_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

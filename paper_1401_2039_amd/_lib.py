@@ -31,6 +31,8 @@ EXPORTS = [
     "qiral_status_string", "qiral_last_error", "qiral_field_bytes", "qiral_lattice_create",
     "qiral_lattice_destroy", "qiral_lattice_query", "qiral_field_import", "qiral_field_export",
     "qiral_dslash_eo", "qiral_apply_M", "qiral_tune", "qiral_solve", "qiral_solve_batch",
+    "qiral_nn_create", "qiral_nn_destroy", "qiral_nn_num_weights", "qiral_nn_set_weights", "qiral_nn_get_weights",
+    "qiral_nn_apply", "qiral_nn_apply_adjoint", "qiral_nn_sample", "qiral_nn_grad", "qiral_nn_train",
 ]
 
 
@@ -88,6 +90,20 @@ def load():
         "qiral_solve_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I,
                                   ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
     }
+    U64 = ctypes.c_uint64
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig.update({
+        "qiral_nn_create": (I, [ctypes.POINTER(P), P, I]),
+        "qiral_nn_destroy": (I, [P]),
+        "qiral_nn_num_weights": (S, [P]),
+        "qiral_nn_set_weights": (I, [P, P, S]),
+        "qiral_nn_get_weights": (I, [P, P, S]),
+        "qiral_nn_apply": (I, [P, P, P, P]),
+        "qiral_nn_apply_adjoint": (I, [P, P, P, P]),
+        "qiral_nn_sample": (I, [P, P, U64, U64, DP, P]),
+        "qiral_nn_grad": (I, [P, P, P, DP, DP, P]),
+        "qiral_nn_train": (I, [P, I, D, U64, DP, P]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res

@@ -188,3 +188,78 @@ class Lattice:
         x = self.canon(nrhs) if x_canon is None else x_canon
         st, info = qiral_solve(self.handle, self.dims, x, b_canon, nrhs, solve_params(**kw))
         return x, st, info
+
+
+class Network:
+    """The learned preconditioner of a lattice (qiral_nn_*): weights as a complex64
+    numpy array of shape (2, 9, hidden, 4, 4) view of layers [9][H][1] and [9][1][H]."""
+
+    def __init__(self, lattice, hidden=8):
+        import numpy as np
+        self.lat = lattice
+        self.hidden = hidden
+        h = ctypes.c_void_p()
+        L.check(L.load().qiral_nn_create(ctypes.byref(h), ctypes.c_void_p(lattice.handle), int(hidden)),
+                "qiral_nn_create")
+        self.handle = h.value
+        self.nw = int(L.load().qiral_nn_num_weights(ctypes.c_void_p(self.handle)))
+        self._np = np
+
+    def close(self):
+        if self.handle:
+            L.check(L.load().qiral_nn_destroy(ctypes.c_void_p(self.handle)), "qiral_nn_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        """(w1 [9][H][1][4][4], w2 [9][1][H][4][4]) complex64."""
+        np = self._np
+        buf = np.zeros(2 * self.nw, dtype=np.float32)
+        L.check(L.load().qiral_nn_get_weights(ctypes.c_void_p(self.handle), buf.ctypes.data_as(ctypes.c_void_p),
+                                              self.nw), "qiral_nn_get_weights")
+        c = buf.view(np.complex64)
+        H = self.hidden
+        n1 = 9 * H * 16
+        return c[:n1].reshape(9, H, 1, 4, 4).copy(), c[n1:].reshape(9, 1, H, 4, 4).copy()
+
+    def set_weights(self, w1, w2):
+        np = self._np
+        c = np.concatenate([np.asarray(w1, np.complex64).ravel(), np.asarray(w2, np.complex64).ravel()])
+        assert c.size == self.nw
+        buf = np.ascontiguousarray(c).view(np.float32)
+        L.check(L.load().qiral_nn_set_weights(ctypes.c_void_p(self.handle), buf.ctypes.data_as(ctypes.c_void_p),
+                                              self.nw), "qiral_nn_set_weights")
+
+    def apply(self, out, inp, adjoint=False):
+        fn = L.load().qiral_nn_apply_adjoint if adjoint else L.load().qiral_nn_apply
+        L.check(fn(ctypes.c_void_p(self.handle), _need_cuda(out, "out"), _need_cuda(inp, "in"), _stream()),
+                "qiral_nn_apply")
+
+    def sample(self, out, seed, step):
+        n2 = ctypes.c_double()
+        L.check(L.load().qiral_nn_sample(ctypes.c_void_p(self.handle), _need_cuda(out, "out"), int(seed), int(step),
+                                         ctypes.byref(n2), _stream()), "qiral_nn_sample")
+        return n2.value
+
+    def grad(self, src, target):
+        np = self._np
+        loss = ctypes.c_double()
+        g = np.zeros(2 * self.nw, dtype=np.float64)
+        L.check(L.load().qiral_nn_grad(ctypes.c_void_p(self.handle), _need_cuda(src, "src"),
+                                       _need_cuda(target, "target"), ctypes.byref(loss),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+                "qiral_nn_grad")
+        return loss.value, g
+
+    def train(self, steps, lr=1e-3, seed=1):
+        np = self._np
+        hist = np.zeros(max(steps, 1), dtype=np.float64)
+        L.check(L.load().qiral_nn_train(ctypes.c_void_p(self.handle), int(steps), float(lr), int(seed),
+                                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+                "qiral_nn_train")
+        return hist[:steps]

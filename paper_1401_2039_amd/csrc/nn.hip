@@ -1,0 +1,916 @@
+// Learned gauge-covariant preconditioner (an addition to the paper's method):
+// a network of parallel-transport convolution layers (Lehner & Wettig,
+// Phys. Rev. D 108 (2023) 034503)
+//     psi_out^i(x) = sum_j sum_p W_p^{ij} [T_p psi_in^j](x),
+// 9 paths p (0: identity; 1..4: +x..+t, T psi(x) = U_mu(x) psi(x+mu); 5..8:
+// -x..-t, T psi(x) = U_mu(x-mu)^+ psi(x-mu)), W a complex 4x4 spin matrix,
+// trained on pairs (D v, v) of Gaussian v drawn on the device (Philox4x32-10,
+// Salmon et al., SC'11, with the Box-Muller transform) with Adam (Kingma & Ba
+// 2015), and used as the right preconditioner of flexible GMRES(m) (Saad 1993)
+// on the full operator D, with even-odd CGNR as the fallback.
+//
+// Fields are packed FP32 full fields (even half, odd half) per channel; the
+// network runs on the FP32 reconstruct-12 links.  Weights are FP32 complex,
+// layer 1 [9][H][1][4][4] then layer 2 [9][1][H][4][4].
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "qiral_int.h"
+
+using namespace qiral;
+
+struct qiral_nn {
+  qiral_lattice *lat = nullptr;
+  int hidden = 0;
+  int nw1 = 0, nw2 = 0;     // complex weights per layer
+  float2 *w = nullptr;      // [nw1 + nw2]
+  float2 *wadj = nullptr;   // adjoint-layer weights (scratch)
+  float *am = nullptr, *av = nullptr;   // Adam moments, [2 (nw1 + nw2)]
+  double *grad = nullptr;   // dL/dRe, dL/dIm interleaved, [2 (nw1 + nw2)]
+  double *part = nullptr;   // weight-gradient partials
+  double *scal = nullptr;   // small reductions: [0] ||v||^2, [1] loss sum, ... ; plus partial area
+  void *act = nullptr;      // hidden activations (H full F32 fields)
+  void *gact = nullptr;     // gradient w.r.t. the activations (H fields)
+  void *fv = nullptr, *fb = nullptr, *fy = nullptr, *fg = nullptr;   // one full F32 field each
+  double *loss_dev = nullptr;
+  int loss_cap = 0;
+  long adam_step = 0;
+  // FGMRES workspace
+  void *gws = nullptr;
+  size_t gws_bytes = 0;
+};
+
+namespace {
+
+constexpr int NPATH = 9;
+constexpr int WG_CHUNKS = 128;   // site chunks of the weight-gradient reduction
+
+qiral_status fail(qiral_status s, const char *m) {
+  set_error(m);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+__device__ __forceinline__ void path_of(int p, int &mu, bool &fwd) {
+  mu = (p - 1) & 3;
+  fwd = p <= 4;
+}
+
+// t = U psi (adj = false) or U^+ psi (adj = true) on the colour index of a 3x4 block.
+__device__ __forceinline__ void transport(const cpx<float> u[9], const cpx<float> psi[12], cpx<float> t[12], bool adj) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cpx<float> r;
+      if (!adj) {
+        r = cmul(u[3 * a], psi[s]);
+        r = cadd(r, cmul(u[3 * a + 1], psi[4 + s]));
+        r = cadd(r, cmul(u[3 * a + 2], psi[8 + s]));
+      } else {
+        r = cjmul(u[a], psi[s]);
+        r = cadd(r, cjmul(u[3 + a], psi[4 + s]));
+        r = cadd(r, cjmul(u[6 + a], psi[8 + s]));
+      }
+      t[4 * a + s] = r;
+    }
+  }
+}
+
+// (T_p psi)(x) for a full field: x = (par, s), psi read at the neighbour.
+__device__ __forceinline__ void path_apply(const Geo &g, const void *links, const void *field, size_t hb, size_t npad,
+                                           const SiteC &c, int par, int p, cpx<float> t[12]) {
+  if (p == 0) {
+    SpinorIO<S_F32>::load((const char *)field + par * hb, c.s, npad, t);
+    return;
+  }
+  int mu;
+  bool fwd;
+  path_of(p, mu, fwd);
+  const int n = nbr(g, c, mu, fwd);
+  cpx<float> u[9], psi[12];
+  if (fwd) LinkIO<L_F32R12>::load(links, par, mu, c.s, g.nb, u);
+  else LinkIO<L_F32R12>::load(links, 1 - par, mu, n, g.nb, u);
+  SpinorIO<S_F32>::load((const char *)field + (1 - par) * hb, n, npad, psi);
+  transport(u, psi, t, !fwd);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+// One layer, CI output channels per pass of each thread over the paths.
+template <int CIN, int COUT, int CI>
+__global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict__ links,
+                                                   const float2 *__restrict__ w, const void *__restrict__ in,
+                                                   void *__restrict__ out, size_t fstride) {
+  __shared__ float2 sw[NPATH * COUT * CIN * 16];
+  for (int i = threadIdx.x; i < NPATH * COUT * CIN * 16; i += blockDim.x) sw[i] = w[i];
+  __syncthreads();
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * npad) return;
+  const int par = (int)(gid / npad), s = (int)(gid % npad);
+  if (s >= g.vh) return;
+  const SiteC c = site_c(g, s, par);
+#pragma unroll 1
+  for (int i0 = 0; i0 < COUT; i0 += CI) {
+    cpx<float> acc[CI][12];
+#pragma unroll
+    for (int ii = 0; ii < CI; ++ii)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[ii][k] = cmake(0.f, 0.f);
+#pragma unroll 1
+    for (int p = 0; p < NPATH; ++p) {
+#pragma unroll 1
+      for (int j = 0; j < CIN; ++j) {
+        cpx<float> t[12];
+        path_apply(g, links, (const char *)in + j * fstride, hb, npad, c, par, p, t);
+#pragma unroll
+        for (int ii = 0; ii < CI; ++ii) {
+          const float2 *W = sw + ((p * COUT + i0 + ii) * CIN + j) * 16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const cpx<float> wr = cmake(W[4 * r + q].x, W[4 * r + q].y);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) acc[ii][4 * a + r] = cadd(acc[ii][4 * a + r], cmul(wr, t[4 * a + q]));
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < CI; ++ii)
+      SpinorIO<S_F32>::store((char *)out + (i0 + ii) * fstride + par * hb, s, npad, acc[ii]);
+  }
+}
+
+// Adjoint-layer weights: W'[mirror(p)][j][i] = (W[p][i][j])^dagger, so that the
+// forward layer with W' (CIN and COUT swapped) applies the adjoint.
+__global__ void k_adj_weights(const float2 *__restrict__ w, float2 *__restrict__ wa, int cout, int cin) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = NPATH * cout * cin * 16;
+  if (idx >= n) return;
+  const int e = idx & 15, blk = idx >> 4;
+  const int j = blk % cin, i = (blk / cin) % cout, p = blk / (cin * cout);
+  const int pm = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+  const int r = e >> 2, q = e & 3;
+  const float2 v = w[((p * cout + i) * cin + j) * 16 + 4 * q + r];
+  wa[((pm * cin + j) * cout + i) * 16 + 4 * r + q] = make_float2(v.x, -v.y);
+}
+
+// dL/d conj(W_p^{ij}) = sum_{x,c} g^i(x)[c][r] conj((T_p psi^j)(x)[c][s]); one
+// block row per (p, i, j), WG_CHUNKS site chunks, partials in FP64.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_ptc_wgrad(Geo g, const void *__restrict__ links, const void *__restrict__ in,
+                                                   const void *__restrict__ gout, size_t fstride,
+                                                   double *__restrict__ part) {
+  const int combo = blockIdx.y;   // (p * COUT + i) * CIN + j
+  const int j = combo % CIN, i = (combo / CIN) % COUT, p = combo / (CIN * COUT);
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t nsite = 2 * npad;
+  cpx<float> acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = cmake(0.f, 0.f);
+  for (size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x; gid < nsite; gid += (size_t)gridDim.x * blockDim.x) {
+    const int par = (int)(gid / npad), s = (int)(gid % npad);
+    if (s >= g.vh) continue;
+    const SiteC c = site_c(g, s, par);
+    cpx<float> t[12], gg[12];
+    path_apply(g, links, (const char *)in + j * fstride, hb, npad, c, par, p, t);
+    SpinorIO<S_F32>::load((const char *)gout + i * fstride + par * hb, s, npad, gg);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[4 * r + q] = cadd(acc[4 * r + q], cjmul(t[4 * a + q], gg[4 * a + r]));
+  }
+  // fixed-order block reduction
+  __shared__ double red[32][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    double re = wave_sum((double)acc[k].re), im = wave_sum((double)acc[k].im);
+    if (lane == 0) { red[2 * k][wv] = re; red[2 * k + 1][wv] = im; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const double v = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+    part[((size_t)combo * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
+  }
+}
+
+// grad[2 k] = dL/dRe W_k = 2 Re G_k, grad[2 k + 1] = dL/dIm W_k = 2 Im G_k.
+__global__ void k_wgrad_final(const double *__restrict__ part, double *__restrict__ grad, int ncombo, int nchunk) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncombo * 32) return;
+  const int combo = idx >> 5, k = idx & 31;
+  double s = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)combo * nchunk + ch) * 32 + k];
+  grad[(size_t)combo * 32 + k] = 2.0 * s;
+}
+
+// Adam on the real and imaginary parts of every weight.
+__global__ void k_adam(float *__restrict__ theta, const double *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gr = (float)grad[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gr;
+  const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Philox4x32-10 (Salmon et al. 2011): 10 rounds of the multiply-xor round with
+// the published multipliers and Weyl key increments.
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    k.x += 0x9E3779B9u;
+    k.y += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Gaussian training vector: the 24 reals of canonical site `lex` come from six
+// Philox blocks with counter (lex, block, step_lo, step_hi) and key (seed_lo,
+// seed_hi); uniforms u = (n + 1/2) 2^-32 pair into Box-Muller normals
+// sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1).  Also partial sums of ||v||^2.
+__global__ __launch_bounds__(256) void k_gauss(Geo g, void *__restrict__ out, uint2 key, unsigned long long step,
+                                               double *__restrict__ part) {
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double nrm = 0.0;
+  if (gid < 2 * npad) {
+    const int par = (int)(gid / npad), s = (int)(gid % npad);
+    cpx<float> v[12];
+    if (s < g.vh) {
+      const SiteC c = site_c(g, s, par);
+      const unsigned lex = (unsigned)((((size_t)c.t * g.lz + c.z) * g.ly + c.y) * g.lx + c.x);
+      float r[24];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const uint4 u = philox(make_uint4(lex, (unsigned)b, (unsigned)step, (unsigned)(step >> 32)), key);
+        const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float u0 = ((float)w[2 * h] + 0.5f) * 2.3283064365386963e-10f;
+          const float u1 = ((float)w[2 * h + 1] + 0.5f) * 2.3283064365386963e-10f;
+          const float rad = sqrtf(-2.f * logf(u0));
+          r[4 * b + 2 * h] = rad * cosf(6.283185307179586f * u1);
+          r[4 * b + 2 * h + 1] = rad * sinf(6.283185307179586f * u1);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = cmake(r[2 * k], r[2 * k + 1]);
+      nrm = norm12(v);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = cmake(0.f, 0.f);
+    }
+    SpinorIO<S_F32>::store((char *)out + par * hb, s, npad, v);
+  }
+  nrm = wave_sum(nrm);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// g = (y - v) / ||v||^2 and partials of ||y - v||^2.
+__global__ __launch_bounds__(256) void k_loss_grad(Geo g, const void *__restrict__ y, const void *__restrict__ v,
+                                                   void *__restrict__ gout, const double *__restrict__ vnorm,
+                                                   double *__restrict__ part) {
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d2 = 0.0;
+  if (gid < 2 * npad) {
+    const int par = (int)(gid / npad), s = (int)(gid % npad);
+    cpx<float> a[12], b[12];
+    SpinorIO<S_F32>::load((const char *)y + par * hb, s, npad, a);
+    SpinorIO<S_F32>::load((const char *)v + par * hb, s, npad, b);
+    const float inv = (float)(1.0 / vnorm[0]);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = csub(a[k], b[k]);
+    d2 = s < g.vh ? norm12(a) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = cscale(inv, a[k]);
+    SpinorIO<S_F32>::store((char *)gout + par * hb, s, npad, a);
+  }
+  d2 = wave_sum(d2);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[0] = scale * sum(part[0..n)) in index order (one work-group).
+__global__ __launch_bounds__(256) void k_sum(const double *__restrict__ part, int n, double *__restrict__ out,
+                                             const double *__restrict__ divisor) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double s = (red[0] + red[1]) + (red[2] + red[3]);
+    out[0] = divisor ? s / divisor[0] : s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 full-field vector kernels for FGMRES (both halves, padding stays zero)
+__global__ __launch_bounds__(256) void k_cvt64to32(const double2 *__restrict__ a, float2 *__restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+__global__ __launch_bounds__(256) void k_cvt32to64(const float2 *__restrict__ a, double2 *__restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_double2((double)a[i].x, (double)a[i].y);
+}
+
+// Complex dots (V_i | w) for i < k, with partials per work-group.
+__global__ __launch_bounds__(256) void k_mdot(const double2 *__restrict__ V, size_t vstride, int k,
+                                              const double2 *__restrict__ w, size_t n, double *__restrict__ part) {
+  __shared__ double red[2][4];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double2 wv = i < n ? w[i] : make_double2(0.0, 0.0);
+  for (int q = 0; q < k; ++q) {
+    double re = 0.0, im = 0.0;
+    if (i < n) {
+      const double2 v = V[q * vstride + i];
+      re = v.x * wv.x + v.y * wv.y;
+      im = v.x * wv.y - v.y * wv.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
+    __syncthreads();
+    if (threadIdx.x < 2)
+      part[((size_t)q * gridDim.x + blockIdx.x) * 2 + threadIdx.x] =
+          (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+    __syncthreads();
+  }
+}
+
+// coef[q] = sum of the k partial pairs (one thread per coefficient, index order).
+__global__ void k_mdot_final(const double *__restrict__ part, int nblk, int k, double2 *__restrict__ coef) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= k) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    re += part[((size_t)q * nblk + b) * 2];
+    im += part[((size_t)q * nblk + b) * 2 + 1];
+  }
+  coef[q] = make_double2(re, im);
+}
+
+// w += sign * sum_q coef[q] V_q
+__global__ __launch_bounds__(256) void k_maxpy(const double2 *__restrict__ V, size_t vstride, int k,
+                                               const double2 *__restrict__ coef, double sign, double2 *__restrict__ w,
+                                               size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 a = w[i];
+  for (int q = 0; q < k; ++q) {
+    const double2 c = coef[q], v = V[q * vstride + i];
+    a.x += sign * (c.x * v.x - c.y * v.y);
+    a.y += sign * (c.x * v.y + c.y * v.x);
+  }
+  w[i] = a;
+}
+
+// partial sums of |w|^2
+__global__ __launch_bounds__(256) void k_norm(const double2 *__restrict__ w, size_t n, double *__restrict__ part) {
+  __shared__ double red[4];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  if (i < n) a = w[i].x * w[i].x + w[i].y * w[i].y;
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// v = w / sqrt(nrm2[0])  (zero if the norm is zero)
+__global__ __launch_bounds__(256) void k_scale(const double2 *__restrict__ w, const double *__restrict__ nrm2,
+                                               double2 *__restrict__ v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
+  v[i] = make_double2(w[i].x * s, w[i].y * s);
+}
+
+// r = b - r   (r holds D x on entry)
+__global__ __launch_bounds__(256) void k_bminus(const double2 *__restrict__ b, double2 *__restrict__ r, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
+}
+
+// partial sums of ||f||^2 over the sites of a packed F32 full field
+__global__ __launch_bounds__(256) void k_norm32(Geo g, const void *__restrict__ f, double *__restrict__ part) {
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  if (gid < 2 * npad) {
+    const int par = (int)(gid / npad), s = (int)(gid % npad);
+    if (s < g.vh) {
+      cpx<float> v[12];
+      SpinorIO<S_F32>::load((const char *)f + par * hb, s, npad, v);
+      a = norm12(v);
+    }
+  }
+  a = wave_sum(a);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+inline int nblk(size_t n) { return (int)((n + 255) / 256); }
+
+// ---------------------------------------------------------------------------
+// host helpers
+size_t full_bytes32(const Geo &g) { return 2 * half_bytes(g, QIRAL_F32); }
+size_t full_bytes64(const Geo &g) { return 2 * half_bytes(g, QIRAL_F64); }
+
+hipError_t layer_launch(const qiral_nn *nn, const float2 *w, int cin, int cout, const void *in, void *out,
+                        hipStream_t s) {
+  const Geo &g = nn->lat->geo;
+  const size_t fs = full_bytes32(g);
+  const int nb = nblk(2 * npad_of(g));
+  const void *links = nn->lat->g32;
+  if (cin == 1 && cout == 8)
+    hipLaunchKernelGGL((k_ptc_layer<1, 8, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else if (cin == 8 && cout == 1)
+    hipLaunchKernelGGL((k_ptc_layer<8, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else if (cin == 1 && cout == 4)
+    hipLaunchKernelGGL((k_ptc_layer<1, 4, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else if (cin == 4 && cout == 1)
+    hipLaunchKernelGGL((k_ptc_layer<4, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else if (cin == 1 && cout == 2)
+    hipLaunchKernelGGL((k_ptc_layer<1, 2, 2>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else if (cin == 2 && cout == 1)
+    hipLaunchKernelGGL((k_ptc_layer<2, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t wgrad_launch(const qiral_nn *nn, int cin, int cout, const void *in, const void *gout, double *grad,
+                        hipStream_t s) {
+  const Geo &g = nn->lat->geo;
+  const size_t fs = full_bytes32(g);
+  const int ncombo = NPATH * cin * cout;
+  dim3 grid(WG_CHUNKS, ncombo);
+  const void *links = nn->lat->g32;
+  if (cin == 1 && cout == 8) hipLaunchKernelGGL((k_ptc_wgrad<1, 8>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 8 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<8, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 1 && cout == 4) hipLaunchKernelGGL((k_ptc_wgrad<1, 4>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 4 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<4, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 1 && cout == 2) hipLaunchKernelGGL((k_ptc_wgrad<1, 2>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 2 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<2, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_wgrad_final, dim3((ncombo * 32 + 255) / 256), dim3(256), 0, s, nn->part, grad, ncombo, WG_CHUNKS);
+  return hipGetLastError();
+}
+
+// out = N(in), packed F32 full fields
+hipError_t nn_apply_dev(const qiral_nn *nn, void *out, const void *in, hipStream_t s) {
+  hipError_t e = layer_launch(nn, nn->w, 1, nn->hidden, in, nn->act, s);
+  if (e != hipSuccess) return e;
+  return layer_launch(nn, nn->w + nn->nw1, nn->hidden, 1, nn->act, out, s);
+}
+
+// D on a packed full field (out = in - kappa H in), precision prec
+hipError_t apply_D_full(const qiral_lattice *lat, int prec, void *out, const void *in, hipStream_t s) {
+  const size_t hb = half_bytes(lat->geo, prec);
+  const char *ie = (const char *)in, *io = ie + hb;
+  char *oe = (char *)out, *oo = oe + hb;
+  hipError_t e = launch_hop(lat, prec, 0, 0, 1, -lat->kappa, io, oe, ie, 1, s);
+  if (e != hipSuccess) return e;
+  return launch_hop(lat, prec, 0, 1, 1, -lat->kappa, ie, oo, io, 1, s);
+}
+
+void neumann2(int hidden, double kappa, std::vector<float2> &w) {
+  // layer 1: ch0 = psi (identity path), ch1 = H psi; layer 2: psi + kappa ch1 + kappa^2 H ch1.
+  // Spin matrices 1 -+ gamma_mu of the chiral basis gamma_mu = [[0, B],[B^+, 0]],
+  // B_x = -i sigma_x, B_y = -i sigma_y, B_z = -i sigma_z, B_t = 1.
+  const int nw1 = NPATH * hidden * 16, nw2 = NPATH * hidden * 16;
+  w.assign(nw1 + nw2, make_float2(0.f, 0.f));
+  typedef std::complex<double> C;
+  const C I(0, 1);
+  C B[4][2][2] = {{{0, -I}, {-I, 0}}, {{0, -1.0}, {1.0, 0}}, {{-I, 0}, {0, I}}, {{1.0, 0}, {0, 1.0}}};
+  auto gamma = [&](int mu, int r, int c) -> C {
+    if (r < 2 && c >= 2) return B[mu][r][c - 2];
+    if (r >= 2 && c < 2) return std::conj(B[mu][c][r - 2]);
+    return C(0, 0);
+  };
+  auto put = [&](int base, double scale, int mu, int sign) {   // scale (1 + sign gamma_mu); mu < 0: identity
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        C v = (r == c ? C(1, 0) : C(0, 0));
+        if (mu >= 0) v += (double)sign * gamma(mu, r, c);
+        v *= scale;
+        w[base + 4 * r + c] = make_float2((float)v.real(), (float)v.imag());
+      }
+  };
+  auto i1 = [&](int p, int i) { return ((p * hidden + i) * 1 + 0) * 16; };          // layer 1 [p][i][0]
+  auto i2 = [&](int p, int j) { return nw1 + ((p * 1 + 0) * hidden + j) * 16; };   // layer 2 [p][0][j]
+  put(i1(0, 0), 1.0, -1, 0);
+  put(i2(0, 0), 1.0, -1, 0);
+  if (hidden >= 2) {
+    put(i2(0, 1), kappa, -1, 0);
+    for (int mu = 0; mu < 4; ++mu) {
+      put(i1(1 + mu, 1), 1.0, mu, -1);
+      put(i1(5 + mu, 1), 1.0, mu, +1);
+      put(i2(1 + mu, 1), kappa * kappa, mu, -1);
+      put(i2(5 + mu, 1), kappa * kappa, mu, +1);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" qiral_status qiral_nn_create(qiral_nn **out, qiral_lattice *lat, int32_t hidden) {
+  if (!out || !lat) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (hidden != 2 && hidden != 4 && hidden != 8) return fail(QIRAL_ERR_UNSUPPORTED, "hidden channels must be 2, 4 or 8");
+  if (!lat->g32) return fail(QIRAL_ERR_INVALID_ARG, "the network needs the lattice's FP32 links (QIRAL_LINKS_F32)");
+  qiral_nn *nn = new qiral_nn();
+  nn->lat = lat;
+  nn->hidden = hidden;
+  nn->nw1 = NPATH * hidden * 16;
+  nn->nw2 = NPATH * hidden * 16;
+  const int nw = nn->nw1 + nn->nw2;
+  const Geo &g = lat->geo;
+  const size_t f32 = full_bytes32(g);
+  const int nblocks = nblk(2 * npad_of(g));
+  auto cleanup = [&](hipError_t e, const char *what) {
+    (void)qiral_nn_destroy(nn);
+    return hip_fail(e, what);
+  };
+  hipError_t e;
+#define NNALLOC(ptr, bytes)                                   \
+  e = hipMalloc((void **)&(ptr), (bytes));                    \
+  if (e != hipSuccess) return cleanup(e, "hipMalloc(nn)");
+  NNALLOC(nn->w, sizeof(float2) * nw);
+  NNALLOC(nn->wadj, sizeof(float2) * nw);
+  NNALLOC(nn->am, sizeof(float) * 2 * nw);
+  NNALLOC(nn->av, sizeof(float) * 2 * nw);
+  NNALLOC(nn->grad, sizeof(double) * 2 * nw);
+  NNALLOC(nn->part, sizeof(double) * std::max<size_t>((size_t)NPATH * hidden * WG_CHUNKS * 32, (size_t)nblocks + 64));
+  NNALLOC(nn->scal, sizeof(double) * ((size_t)nblocks + 64));
+  NNALLOC(nn->act, f32 * hidden);
+  NNALLOC(nn->gact, f32 * hidden);
+  NNALLOC(nn->fv, f32);
+  NNALLOC(nn->fb, f32);
+  NNALLOC(nn->fy, f32);
+  NNALLOC(nn->fg, f32);
+#undef NNALLOC
+  std::vector<float2> w0;
+  neumann2(hidden, lat->kappa, w0);
+  e = hipMemcpy(nn->w, w0.data(), sizeof(float2) * nw, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(e, "hipMemcpy(nn weights)");
+  (void)hipMemset(nn->am, 0, sizeof(float) * 2 * nw);
+  (void)hipMemset(nn->av, 0, sizeof(float) * 2 * nw);
+  // activations start at zero so that padding sites stay zero
+  (void)hipMemset(nn->act, 0, f32 * hidden);
+  (void)hipMemset(nn->gact, 0, f32 * hidden);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cleanup(e, "nn init");
+  *out = nn;
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_destroy(qiral_nn *nn) {
+  if (!nn) return fail(QIRAL_ERR_INVALID_ARG, "nn is NULL");
+  void *ptrs[] = {nn->w, nn->wadj, nn->am, nn->av, nn->grad, nn->part, nn->scal, nn->act, nn->gact,
+                  nn->fv, nn->fb, nn->fy, nn->fg, nn->loss_dev, nn->gws};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete nn;
+  return QIRAL_OK;
+}
+
+extern "C" size_t qiral_nn_num_weights(const qiral_nn *nn) { return nn ? (size_t)(nn->nw1 + nn->nw2) : 0; }
+
+extern "C" qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w, size_t count) {
+  if (!nn || !w) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  if (count != (size_t)(nn->nw1 + nn->nw2)) return fail(QIRAL_ERR_INVALID_ARG, "count must equal qiral_nn_num_weights");
+  QIRAL_HIP(hipMemcpy(nn->w, w, sizeof(float2) * count, hipMemcpyHostToDevice));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w, size_t count) {
+  if (!nn || !w) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  if (count != (size_t)(nn->nw1 + nn->nw2)) return fail(QIRAL_ERR_INVALID_ARG, "count must equal qiral_nn_num_weights");
+  QIRAL_HIP(hipMemcpy(w, nn->w, sizeof(float2) * count, hipMemcpyDeviceToHost));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
+  if (!nn || !out || !in) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
+  QIRAL_HIP(nn_apply_dev(nn, out, in, (hipStream_t)stream));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
+  if (!nn || !out || !in) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  const int H = nn->hidden;
+  // N^dagger = L1^dagger L2^dagger
+  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
+  QIRAL_HIP(layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s));
+  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w, nn->wadj, H, 1);
+  QIRAL_HIP(layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_sample(qiral_nn *nn, void *out, uint64_t seed, uint64_t step, double *norm2,
+                                        qiral_stream_t stream) {
+  if (!nn || !out) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const Geo &g = nn->lat->geo;
+  const int nb = nblk(2 * npad_of(g));
+  hipLaunchKernelGGL(k_gauss, dim3(nb), dim3(256), 0, s, g, out, make_uint2((unsigned)seed, (unsigned)(seed >> 32)),
+                     (unsigned long long)step, nn->part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, nn->part, nb, nn->scal, (const double *)nullptr);
+  QIRAL_HIP(hipGetLastError());
+  if (norm2) {
+    QIRAL_HIP(hipMemcpyAsync(norm2, nn->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QIRAL_HIP(hipStreamSynchronize(s));
+  }
+  return QIRAL_OK;
+}
+
+namespace {
+
+// Loss L = ||N(src) - target||^2 / ||target||^2 into *loss_dev and its gradient
+// with respect to the real and imaginary parts of every weight into nn->grad.
+hipError_t train_step(qiral_nn *nn, const void *src, const void *target, double *loss_dev, hipStream_t s) {
+  const Geo &g = nn->lat->geo;
+  const int H = nn->hidden;
+  const int nb = nblk(2 * npad_of(g));
+  hipLaunchKernelGGL(k_norm32, dim3(nb), dim3(256), 0, s, g, target, nn->part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, nn->part, nb, nn->scal, (const double *)nullptr);
+  hipError_t e = layer_launch(nn, nn->w, 1, H, src, nn->act, s);
+  if (e != hipSuccess) return e;
+  e = layer_launch(nn, nn->w + nn->nw1, H, 1, nn->act, nn->fy, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, s, g, nn->fy, target, nn->fg, nn->scal, nn->part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, nn->part, nb, loss_dev, nn->scal);
+  // layer 2: weights and the gradient w.r.t. its input (the adjoint layer)
+  e = wgrad_launch(nn, H, 1, nn->act, nn->fg, nn->grad + 2 * nn->nw1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
+  e = layer_launch(nn, nn->wadj, 1, H, nn->fg, nn->gact, s);
+  if (e != hipSuccess) return e;
+  // layer 1 weights
+  e = wgrad_launch(nn, 1, H, src, nn->gact, nn->grad, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" qiral_status qiral_nn_grad(qiral_nn *nn, const void *src, const void *target, double *loss, double *grad,
+                                      qiral_stream_t stream) {
+  if (!nn || !src || !target) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  QIRAL_HIP(train_step(nn, src, target, nn->scal + 1, s));
+  if (loss) QIRAL_HIP(hipMemcpyAsync(loss, nn->scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (grad) QIRAL_HIP(hipMemcpyAsync(grad, nn->grad, sizeof(double) * 2 * (nn->nw1 + nn->nw2), hipMemcpyDeviceToHost, s));
+  QIRAL_HIP(hipStreamSynchronize(s));
+  return QIRAL_OK;
+}
+
+extern "C" qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, uint64_t seed, double *loss_history,
+                                       qiral_stream_t stream) {
+  if (!nn) return fail(QIRAL_ERR_INVALID_ARG, "nn is NULL");
+  if (steps < 0) return fail(QIRAL_ERR_INVALID_ARG, "steps must be >= 0");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(QIRAL_ERR_INVALID_ARG, "lr must be positive");
+  if (steps == 0) return QIRAL_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (nn->loss_cap < steps) {
+    if (nn->loss_dev) (void)hipFree(nn->loss_dev);
+    nn->loss_dev = nullptr;
+    QIRAL_HIP(hipMalloc(&nn->loss_dev, sizeof(double) * steps));
+    nn->loss_cap = steps;
+  }
+  const Geo &g = nn->lat->geo;
+  const int nb = nblk(2 * npad_of(g));
+  const int nreal = 2 * (nn->nw1 + nn->nw2);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int k = 0; k < steps; ++k) {
+    // training pair (D v, v) with v Gaussian; the counter is the global step
+    const unsigned long long ctr = (unsigned long long)nn->adam_step;
+    hipLaunchKernelGGL(k_gauss, dim3(nb), dim3(256), 0, s, g, nn->fv, make_uint2((unsigned)seed, (unsigned)(seed >> 32)),
+                       ctr, nn->part);
+    QIRAL_HIP(apply_D_full(nn->lat, QIRAL_F32, nn->fb, nn->fv, s));
+    QIRAL_HIP(train_step(nn, nn->fb, nn->fv, nn->loss_dev + k, s));
+    nn->adam_step += 1;
+    const float c1 = 1.f - powf(b1, (float)nn->adam_step), c2 = 1.f - powf(b2, (float)nn->adam_step);
+    hipLaunchKernelGGL(k_adam, dim3((nreal + 255) / 256), dim3(256), 0, s, (float *)nn->w, nn->grad, nn->am, nn->av,
+                       nreal, (float)lr, b1, b2, eps, c1, c2);
+    QIRAL_HIP(hipGetLastError());
+  }
+  if (loss_history) QIRAL_HIP(hipMemcpyAsync(loss_history, nn->loss_dev, sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+  QIRAL_HIP(hipStreamSynchronize(s));
+  return QIRAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES(m) on D with the network as right preconditioner.
+namespace qiral {
+qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+                                   qiral_solve_info *info, hipStream_t s);
+void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
+void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
+
+qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
+                        qiral_solve_info *info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  qiral_nn *nn = (qiral_nn *)prm->precond;
+  if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
+  const int m = prm->restart > 0 ? prm->restart : 20;
+  if (m > 64) return fail(QIRAL_ERR_INVALID_ARG, "restart must be <= 64");
+  const Geo &g = lat->geo;
+  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
+  const size_t n2 = f64 / 16;   // complex entries of a full F64 field (padding included, kept zero)
+  const int nbk = nblk(n2);
+  // workspace: V[m+1], Z[m], B, X, W, R (F64 full), two F32 full fields, partials, coefficients
+  const size_t need = (size_t)(2 * m + 5) * f64 + 2 * f32 + sizeof(double) * ((size_t)2 * (m + 1) * nbk + 4 * 64 + nbk);
+  if (nn->gws_bytes < need) {
+    if (nn->gws) (void)hipFree(nn->gws);
+    nn->gws = nullptr;
+    nn->gws_bytes = 0;
+    hipError_t e = hipMalloc(&nn->gws, need);
+    if (e != hipSuccess) return fail(QIRAL_ERR_WORKSPACE, "hipMalloc(FGMRES workspace)");
+    nn->gws_bytes = need;
+  }
+  char *p = (char *)nn->gws;
+  double2 *V = (double2 *)p; p += (size_t)(m + 1) * f64;
+  double2 *Z = (double2 *)p; p += (size_t)m * f64;
+  double2 *B = (double2 *)p; p += f64;
+  double2 *X = (double2 *)p; p += f64;
+  double2 *Wv = (double2 *)p; p += f64;
+  double2 *R = (double2 *)p; p += f64;
+  void *in32 = p; p += f32;
+  void *out32 = p; p += f32;
+  double *part = (double *)p; p += sizeof(double) * 2 * (m + 1) * nbk;
+  double2 *coef = (double2 *)p; p += sizeof(double) * 2 * 64;
+  double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
+  double *npart = (double *)p;
+  const size_t vs = n2;   // stride between vectors of V and Z in complex entries
+  if ((char *)(npart + nbk) > (char *)nn->gws + nn->gws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace layout");
+
+  QIRAL_HIP(hipMemsetAsync(nn->gws, 0, (size_t)(2 * m + 5) * f64 + 2 * f32, s));
+  import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
+  if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
+  auto norm = [&](const double2 *v, double &out) -> qiral_status {
+    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, v, n2, npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    QIRAL_HIP(hipMemcpyAsync(&out, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    QIRAL_HIP(hipStreamSynchronize(s));
+    return QIRAL_OK;
+  };
+  auto residual = [&](double &rn) -> qiral_status {   // R = B - D X
+    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, R, X, s));
+    hipLaunchKernelGGL(k_bminus, dim3(nbk), dim3(256), 0, s, B, R, n2);
+    double r2 = 0;
+    qiral_status st = norm(R, r2);
+    rn = std::sqrt(r2);
+    return st;
+  };
+  double bn2 = 0;
+  qiral_status st = norm(B, bn2);
+  if (st != QIRAL_OK) return st;
+  const double bn = std::sqrt(bn2), target = prm->tol * bn;
+  double rn = 0;
+  if ((st = residual(rn)) != QIRAL_OK) return st;
+  int steps = 0, fell_back = 0;
+  long long hops = 2;
+  double prev_cycle = rn;
+  typedef std::complex<double> C;
+  std::vector<C> H((m + 1) * m), cs(m), sn(m), gv(m + 1);
+  while (rn > target && steps < prm->maxiter) {
+    // V0 = R / |R|
+    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, R, n2, npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, s, R, nrm, V, n2);
+    std::fill(H.begin(), H.end(), C(0));
+    std::fill(gv.begin(), gv.end(), C(0));
+    gv[0] = rn;
+    int k = 0;
+    for (int j = 0; j < m && steps < prm->maxiter; ++j) {
+      // Z_j = N(V_j) in FP32, W = D Z_j in FP64
+      hipLaunchKernelGGL(k_cvt64to32, dim3(nbk), dim3(256), 0, s, V + j * vs, (float2 *)in32, n2);
+      QIRAL_HIP(nn_apply_dev(nn, out32, in32, s));
+      hipLaunchKernelGGL(k_cvt32to64, dim3(nbk), dim3(256), 0, s, (const float2 *)out32, Z + j * vs, n2);
+      QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, Z + j * vs, s));
+      hops += 2;
+      // classical Gram-Schmidt, twice
+      std::vector<C> h(j + 2, C(0));
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, Wv, n2, part);
+        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, s, part, nbk, j + 1, coef);
+        hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, coef, -1.0, Wv, n2);
+        std::vector<double2> c(j + 1);
+        QIRAL_HIP(hipMemcpyAsync(c.data(), coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+        QIRAL_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) h[i] += C(c[i].x, c[i].y);
+      }
+      double w2 = 0;
+      if ((st = norm(Wv, w2)) != QIRAL_OK) return st;
+      h[j + 1] = std::sqrt(w2);
+      hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, s, Wv, nrm, V + (j + 1) * vs, n2);
+      // Givens rotations on the new column
+      for (int i = 0; i < j; ++i) {
+        const C hi = h[i];
+        h[i] = std::conj(cs[i]) * hi + std::conj(sn[i]) * h[i + 1];
+        h[i + 1] = -sn[i] * hi + cs[i] * h[i + 1];
+      }
+      const double den = std::sqrt(std::norm(h[j]) + std::norm(h[j + 1]));
+      cs[j] = den > 0 ? h[j] / den : C(1);
+      sn[j] = den > 0 ? h[j + 1] / den : C(0);
+      h[j] = den;
+      h[j + 1] = 0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = std::conj(cs[j]) * gv[j];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+      k = j + 1;
+      ++steps;
+      if (!std::isfinite(std::abs(gv[j + 1]))) break;
+      if (std::abs(gv[j + 1]) <= 0.5 * target) break;
+    }
+    // y = R^{-1} g, X += Z y
+    std::vector<C> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      C a = gv[i];
+      for (int l = i + 1; l < k; ++l) a -= H[i * m + l] * y[l];
+      // a zero pivot is a breakdown (e.g. a preconditioner returning 0): drop that direction
+      y[i] = std::abs(H[i * m + i]) > 0 ? a / H[i * m + i] : C(0);
+    }
+    std::vector<double2> yc(k);
+    for (int i = 0; i < k; ++i) yc[i] = make_double2(y[i].real(), y[i].imag());
+    QIRAL_HIP(hipMemcpyAsync(coef, yc.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, Z, vs, k, coef, 1.0, X, n2);
+    if ((st = residual(rn)) != QIRAL_OK) return st;
+    hops += 2;
+    if (!std::isfinite(rn)) break;
+    if (rn > target && prm->fallback_cg && rn > 0.5 * prev_cycle) { fell_back = 1; break; }   // stagnation
+    prev_cycle = rn;
+  }
+  // export and, if needed, continue with even-odd CGNR from the current x
+  export_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
+  QIRAL_HIP(hipStreamSynchronize(s));
+  qiral_status result = QIRAL_OK;
+  info->iterations = steps;
+  info->reliable_updates = 0;
+  info->fell_back = 0;
+  info->hop_applications = hops;
+  info->true_rel_resid = bn > 0 ? rn / bn : rn;
+  if (!std::isfinite(rn)) {
+    set_error("a NaN or Inf appeared in FGMRES");
+    result = QIRAL_ERR_NONFINITE;
+  } else if (rn > target && prm->fallback_cg) {
+    qiral_solve_params cg = *prm;
+    cg.solver = QIRAL_CGNR_EO;
+    cg.x0_is_guess = 1;
+    qiral_solve_info ci;
+    memset(&ci, 0, sizeof ci);
+    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, &ci, s);
+    info->iterations = steps + ci.iterations;
+    info->reliable_updates = ci.reliable_updates;
+    info->true_rel_resid = ci.true_rel_resid;
+    info->hop_applications = hops + ci.hop_applications;
+    info->fell_back = 1;
+    (void)fell_back;
+  } else if (rn > target) {
+    set_error("tolerance not reached within maxiter");
+    result = QIRAL_ERR_NOT_CONVERGED;
+  }
+  info->converged = (result == QIRAL_OK);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+}  // namespace qiral

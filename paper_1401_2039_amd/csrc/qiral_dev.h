@@ -506,6 +506,27 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 
+template <class R> __device__ __forceinline__ double norm12(const cpx<R> v[12]) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+  return a;
+}
+
+// (a | b) = sum conj(a) b, accumulated in FP64
+template <class R> __device__ __forceinline__ void dot12(const cpx<R> a[12], const cpx<R> b[12], double &re, double &im) {
+  double r = 0.0, i = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const double ar = a[k].re, ai = a[k].im, br = b[k].re, bi = b[k].im;
+    r += ar * br + ai * bi;
+    i += ar * bi - ai * br;
+  }
+  re = r;
+  im = i;
+}
+
+
 // XCD-aware block order: the hardware hands consecutive work-group ids to the 8
 // XCDs in turn; this remap gives each XCD one contiguous range of logical
 // blocks, so neighbouring sites share an L2.

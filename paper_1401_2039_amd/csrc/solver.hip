@@ -34,6 +34,8 @@
 namespace qiral {
 void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
+qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+                        qiral_solve_info *info, hipStream_t s);
 }  // namespace qiral
 
 using namespace qiral;
@@ -353,11 +355,19 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (p->inner_prec != QIRAL_F64 && !(p->delta > 0.0 && p->delta < 1.0))
     return fail(QIRAL_ERR_INVALID_ARG, "delta must lie in (0, 1) for a mixed-precision solve");
   if (p->check_every < 0) return fail(QIRAL_ERR_INVALID_ARG, "check_every must be >= 0");
-  if (p->solver == QIRAL_FGMRES_NN) return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES needs qiral_solve_nn");
+  if (p->solver == QIRAL_FGMRES_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FGMRES needs a precond network");
   return QIRAL_OK;
 }
 
 }  // namespace
+
+namespace qiral {
+qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+                                   qiral_solve_info *info, hipStream_t s) {
+  std::vector<SysIn> sys{SysIn{lat, x, b}};
+  return run_solve(lat, sys, prm, info, s);
+}
+}  // namespace qiral
 
 extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
                                     const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream) {
@@ -369,8 +379,20 @@ extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const d
   if (st != QIRAL_OK) return st;
   if (!links_for(lat, params->inner_prec))
     return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (see lo_precs)");
-  std::vector<SysIn> sys(nrhs);
   const size_t stride = (size_t)lat->geo.vh * 2 * 24;
+  if (params->solver == QIRAL_FGMRES_NN) {
+    if (params->inner_prec != QIRAL_F64) return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES runs in FP64 (inner_prec F64)");
+    // one right-hand side after the other
+    qiral_status worst = QIRAL_OK;
+    for (int r = 0; r < nrhs; ++r) {
+      qiral_status s = run_fgmres(lat, x_canon + r * stride, b_canon + r * stride, params, info + r,
+                                  (hipStream_t)stream);
+      if (s != QIRAL_OK && s != QIRAL_ERR_NOT_CONVERGED) return s;
+      if (s != QIRAL_OK) worst = s;
+    }
+    return worst;
+  }
+  std::vector<SysIn> sys(nrhs);
   for (int r = 0; r < nrhs; ++r) sys[r] = SysIn{lat, x_canon + r * stride, b_canon + r * stride};
   return run_solve(lat, sys, params, info, (hipStream_t)stream);
 }

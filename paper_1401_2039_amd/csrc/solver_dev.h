@@ -239,24 +239,4 @@ __device__ __forceinline__ void sys_partial(const SysDesc &d, int slot, const It
   }
 }
 
-template <class R> __device__ __forceinline__ double norm12(const cpx<R> v[12]) {
-  double a = 0.0;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) a += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
-  return a;
-}
-
-// (a | b) = sum conj(a) b, accumulated in FP64
-template <class R> __device__ __forceinline__ void dot12(const cpx<R> a[12], const cpx<R> b[12], double &re, double &im) {
-  double r = 0.0, i = 0.0;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const double ar = a[k].re, ai = a[k].im, br = b[k].re, bi = b[k].im;
-    r += ar * br + ai * bi;
-    i += ar * bi - ai * br;
-  }
-  re = r;
-  im = i;
-}
-
 }  // namespace qiral

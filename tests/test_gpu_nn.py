@@ -1,0 +1,139 @@
+"""The learned preconditioner on the GPU against the oracle's PTC network:
+closed-form initial weights, forward and adjoint layers with random weights,
+the weight gradient, the Philox training vectors, training, and FGMRES with its
+CGNR fallback (every solve judged by the oracle's true residual)."""
+import numpy as np
+import pytest
+import torch
+
+import latgen
+from oracle import ptc, solvers as S, storage, wilson as W
+import paper_1401_2039_amd as q
+from gpu_util import say, dev, host
+from philox_ref import site_normals
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4, 4, 2, 4)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    say("nn setup", DIMS)
+    cfg = latgen.small_config(DIMS, seed=60, kind="expih", eps=0.4, nrhs=3)
+    lat = q.Lattice(DIMS, 0.125, cfg["U"])
+    return cfg, lat, storage.round_links_r12(cfg["U"], np.complex64)
+
+
+def _to32(lat, canon):
+    return lat.import_field(dev(canon), q.FULL, q.F32)
+
+
+def _from32(lat, packed):
+    return host(lat.export_field(packed, q.FULL, q.F32))[0]
+
+
+def _rel(a, b):
+    return np.sqrt(W.norm2(a - b) / W.norm2(b))
+
+
+def test_initial_weights_are_neumann(setup):
+    cfg, lat, Ur = setup
+    say("nn neumann")
+    net = q.Network(lat, 8)
+    psi = storage.round_f32(cfg["b"][0])
+    out = lat.field(q.FULL, q.F32)
+    net.apply(out, _to32(lat, psi[None]))
+    h = W.hop(Ur, psi)
+    want = psi + 0.125 * h + 0.125 ** 2 * W.hop(Ur, h)
+    assert _rel(_from32(lat, out), want) < 2e-6
+
+
+def _rand_weights(seed, H):
+    rng = np.random.default_rng(seed)
+    w1 = 0.3 * (rng.standard_normal((9, H, 1, 4, 4)) + 1j * rng.standard_normal((9, H, 1, 4, 4)))
+    w2 = 0.3 * (rng.standard_normal((9, 1, H, 4, 4)) + 1j * rng.standard_normal((9, 1, H, 4, 4)))
+    return w1.astype(np.complex64), w2.astype(np.complex64)
+
+
+@pytest.mark.parametrize("H", [2, 8])
+def test_forward_and_adjoint(setup, H):
+    cfg, lat, Ur = setup
+    say("nn forward/adjoint", H)
+    net = q.Network(lat, H)
+    w1, w2 = _rand_weights(H, H)
+    net.set_weights(w1, w2)
+    g1, g2 = net.get_weights()
+    assert np.array_equal(g1, w1) and np.array_equal(g2, w2)
+    ws = [w1.astype(np.complex128), w2.astype(np.complex128)]
+    x = storage.round_f32(cfg["b"][0])
+    y = storage.round_f32(cfg["b"][1])
+    out = lat.field(q.FULL, q.F32)
+    net.apply(out, _to32(lat, x[None]))
+    assert _rel(_from32(lat, out), ptc.network(Ur, ws, x)) < 1e-5
+    outa = lat.field(q.FULL, q.F32)
+    net.apply(outa, _to32(lat, y[None]), adjoint=True)
+    assert _rel(_from32(lat, outa), ptc.network_adjoint(Ur, ws, y)) < 1e-5
+
+
+def test_weight_gradient(setup):
+    cfg, lat, Ur = setup
+    say("nn gradient")
+    net = q.Network(lat, 8)
+    w1, w2 = _rand_weights(7, 8)
+    net.set_weights(w1, w2)
+    src = storage.round_f32(cfg["b"][0])
+    tgt = storage.round_f32(cfg["b"][1])
+    loss, g = net.grad(_to32(lat, src[None]), _to32(lat, tgt[None]))
+    L, G = ptc.loss_and_grad(Ur, [w1.astype(np.complex128), w2.astype(np.complex128)], src, tgt)
+    assert abs(loss - L) < 1e-5 * L
+    want = np.concatenate([(2 * G[0]).ravel(), (2 * G[1]).ravel()])
+    got = g[0::2] + 1j * g[1::2]
+    assert np.abs(got - want).max() < 1e-4 * np.abs(want).max()
+
+
+def test_training_vectors_match_philox(setup):
+    cfg, lat, _ = setup
+    say("nn philox")
+    net = q.Network(lat, 2)
+    out = lat.field(q.FULL, q.F32)
+    seed, step = 0x1234567890ABCDEF, 77
+    n2 = net.sample(out, seed, step)
+    v = _from32(lat, out)
+    lx, ly, lz, lt = DIMS
+    for (x, y, z, t) in [(0, 0, 0, 0), (3, 2, 1, 3), (1, 0, 1, 2)]:
+        lex = ((t * lz + z) * ly + y) * lx + x
+        want = site_normals(lex, seed, step)
+        got = np.stack([v[t, z, y, x].real, v[t, z, y, x].imag], axis=-1).reshape(-1)
+        assert np.abs(got - want).max() < 2e-5 * max(1.0, np.abs(want).max())
+    assert abs(n2 - W.norm2(v)) < 1e-5 * n2
+
+
+def test_training_lowers_loss(setup):
+    cfg, lat, _ = setup
+    say("nn training")
+    net = q.Network(lat, 8)
+    hist = net.train(300, lr=2e-3, seed=5)
+    assert np.all(np.isfinite(hist))
+    assert hist[-50:].mean() < hist[:50].mean()
+
+
+def test_fgmres_with_network():
+    say("fgmres")
+    cfg = latgen.make_config(0)
+    lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
+    net = q.Network(lat, 8)
+    net.train(100, lr=1e-3, seed=3)
+    params = q.solve_params(solver=q.FGMRES_NN, tol=1e-10, restart=20, maxiter=500)
+    params.precond = net.handle
+    x = lat.canon(1)
+    st, info = q.qiral_solve(lat.handle, lat.dims, x, dev(cfg["b"]), 1, params)
+    assert st == 0 and info[0]["fell_back"] == 0
+    assert S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, host(x)[0], cfg["b"][0]) <= 1e-10
+    # a broken preconditioner (all weights zero) makes FGMRES stall: the CGNR fallback still solves
+    w1, w2 = net.get_weights()
+    net.set_weights(np.zeros_like(w1), np.zeros_like(w2))
+    x2 = lat.canon(1)
+    st, info = q.qiral_solve(lat.handle, lat.dims, x2, dev(cfg["b"]), 1, params)
+    assert st == 0 and info[0]["fell_back"] == 1
+    assert S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, host(x2)[0], cfg["b"][0]) <= 1e-10
