@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads (stderr JSON lines)")
     ap.add_argument("--suite-out", default=None, help="append the suite's JSON lines to this file")
+    ap.add_argument("--parts", default="c1,c0,c2,c3,c99,c4", help="suite parts to run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -160,7 +161,7 @@ def main():
     }
     print(json.dumps(res), flush=True)
     if args.suite:
-        suite(lat, q, latgen, np, torch, args.suite_out)
+        suite(lat, q, latgen, np, torch, args.suite_out, args.parts.split(','))
     lat.close()
 
 
@@ -245,14 +246,15 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None):
     return res
 
 
-def suite(lat1, q, latgen, np, torch, path=None):
+def suite(lat1, q, latgen, np, torch, path=None, parts=()):
     """Extra measurements: hop throughput of every storage class on the workloads'
     lattices (warm and cache-flushed) and time to solution of each solver form."""
     import time as _t
     flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     dims1 = (16, 16, 16, 32)
-    for prec in (q.F64, q.F32, q.F16S):
-        _emit(hop_rates(q, lat1, dims1, torch, prec, flush=flush), path)
+    if "c1" in parts:
+        for prec in (q.F64, q.F32, q.F16S):
+            _emit(hop_rates(q, lat1, dims1, torch, prec, flush=flush), path)
 
     def timed_solve(lat, b, reps=2, **kw):
         x = torch.zeros_like(b)
@@ -265,7 +267,26 @@ def suite(lat1, q, latgen, np, torch, path=None):
             ts.append(_t.perf_counter() - t0)
         return min(ts), st, info, x
 
-    # 16^3x32 solver forms
+    if "c1" in parts:
+        suite_c1(lat1, q, latgen, torch, path, timed_solve)
+    if "c0" in parts:
+        suite_c0(q, latgen, torch, path, timed_solve)
+    if "c2" in parts:
+        suite_c2(q, latgen, torch, path, timed_solve, flush)
+    if "c3" in parts:
+        suite_c3(q, latgen, torch, path, timed_solve)
+    if "c99" in parts:
+        c99 = latgen.make_config(99, with_source=False)
+        lat99 = q.Lattice(c99["dims"], c99["kappa"], c99["U"])
+        del c99
+        for prec in (q.F64, q.F32, q.F16S):
+            _emit(hop_rates(q, lat99, (32, 32, 32, 64), torch, prec, reps=50, flush=flush), path)
+        lat99.close()
+    if "c4" in parts:
+        suite_c4(q, latgen, torch, path, timed_solve)
+
+
+def suite_c1(lat1, q, latgen, torch, path, timed_solve):
     cfg = latgen.make_config(1)
     b1 = torch.from_numpy(cfg["b"]).cuda()
     for name, kw in [("cgnr_f64", dict(inner_prec=q.F64)), ("cgnr_f32", dict(inner_prec=q.F32)),
@@ -279,6 +300,10 @@ def suite(lat1, q, latgen, np, torch, path=None):
                "status": st, "iterations": info[0]["iterations"], "reliable_updates": info[0]["reliable_updates"],
                "true_rel_resid": info[0]["true_rel_resid"], "hops": info[0]["hop_applications"]}, path)
 
+
+
+def suite_c0(q, latgen, torch, path, timed_solve):
+    import time as _t
     # 4^4 Haar (plain method): GPU FP64 eo-CGNR vs the oracle in CPU seconds
     c0 = latgen.make_config(0)
     lat0 = q.Lattice(c0["dims"], c0["kappa"], c0["U"])
@@ -293,6 +318,9 @@ def suite(lat1, q, latgen, np, torch, path=None):
            "oracle_iterations": oinfo["iterations"], "true_rel_resid": info[0]["true_rel_resid"]}, path)
     lat0.close()
 
+
+
+def suite_c2(q, latgen, torch, path, timed_solve, flush):
     # 24^3x48: hop rates (1 RHS all classes, 12 RHS F16S), 12 point sources
     c2 = latgen.make_config(2)
     lat2 = q.Lattice(c2["dims"], c2["kappa"], c2["U"])
@@ -301,6 +329,10 @@ def suite(lat1, q, latgen, np, torch, path=None):
     _emit(hop_rates(q, lat2, c2["dims"], torch, q.F16S, nrhs=12, reps=50, flush=flush), path)
     _emit(hop_rates(q, lat2, c2["dims"], torch, q.F32, nrhs=12, reps=50, flush=flush), path)
     b2 = torch.from_numpy(c2["b"]).cuda()
+    for prec, nm in ((q.F16S, "f16s"), (q.F32, "f32"), (q.F64, "f64")):
+        t_, nr_, us_ = lat2.tune(prec, 12)
+        _emit({"kind": "tune", "dims": list(c2["dims"]), "prec": nm, "nrhs": 12, "lanes_per_site": t_,
+               "rhs_per_lane": nr_, "us": round(us_, 2)}, path)
     for name, kw in [("batched12_f16s", dict(inner_prec=q.F16S)), ("batched12_f32", dict(inner_prec=q.F32)),
                      ("batched12_f64", dict(inner_prec=q.F64))]:
         t, st, info, _ = timed_solve(lat2, b2, reps=1, tol=1e-10, **kw)
@@ -318,6 +350,10 @@ def suite(lat1, q, latgen, np, torch, path=None):
     lat2.close()
     del b2
 
+
+
+def suite_c3(q, latgen, torch, path, timed_solve):
+    import time as _t
     # uneven batch of 32 systems
     cfgs = [latgen.make_config(3, s) for s in range(32)]
     lats = [q.Lattice(c["dims"], c["kappa"], c["U"]) for c in cfgs]
@@ -346,13 +382,63 @@ def suite(lat1, q, latgen, np, torch, path=None):
         l.close()
     del bs, xs
 
-    # 32^3x64: beyond the last-level cache
-    c99 = latgen.make_config(99, with_source=False)
-    lat99 = q.Lattice(c99["dims"], c99["kappa"], c99["U"])
-    del c99
-    for prec in (q.F64, q.F32, q.F16S):
-        _emit(hop_rates(q, lat99, (32, 32, 32, 64), torch, prec, reps=50, flush=flush), path)
-    lat99.close()
+
+
+def suite_c4(q, latgen, torch, path, timed_solve):
+    """24^3x48, exp(0.5 i H), kappa 0.125, 12 Gaussian sources: the 2-layer network
+    (8 hidden channels) trained on 2048 pairs (D v, v), FGMRES(20) with it, against
+    plain even-odd CGNR in FP64 and the mixed batched CGNR."""
+    import time as _t
+    import numpy as np
+    c4 = latgen.make_config(4)
+    lat = q.Lattice(c4["dims"], c4["kappa"], c4["U"])
+    b = torch.from_numpy(c4["b"]).cuda()
+    del c4["U"]
+    lat.tune(q.F16S, 12)
+    net = q.Network(lat, 8)
+    # the untrained network (Neumann series 1 + kH + k^2 H^2) on one source first
+    params = q.solve_params(solver=q.FGMRES_NN, tol=1e-10, restart=20, maxiter=2000)
+    params.precond = net.handle
+    x = torch.zeros_like(b[:1])
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    st, info = q.qiral_solve(lat.handle, lat.dims, x, b[:1].contiguous(), 1, params)
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 1 of 12 gaussian", "form": "fgmres20_neumann2",
+           "seconds": round(_t.perf_counter() - t0, 4), "status": st, "iterations": info[0]["iterations"],
+           "fell_back": info[0]["fell_back"], "true_rel_resid": info[0]["true_rel_resid"]}, path)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    hist = net.train(2048, lr=1e-3, seed=4)
+    t_train = _t.perf_counter() - t0
+    _emit({"kind": "train", "workload": "24^3x48 eps0.5 k0.125", "pairs": 2048, "seconds": round(t_train, 3),
+           "loss_first64": float(np.mean(hist[:64])), "loss_last64": float(np.mean(hist[-64:]))}, path)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    st, info = q.qiral_solve(lat.handle, lat.dims, x, b, 12, params)
+    t_nn = _t.perf_counter() - t0
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "fgmres20_trained",
+           "seconds": round(t_nn, 4), "status": st, "iterations": [i["iterations"] for i in info],
+           "fell_back": [i["fell_back"] for i in info],
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    tseq = 0.0
+    its = []
+    for r in range(12):
+        t, st, info, _ = timed_solve(lat, b[r:r + 1].contiguous(), reps=1, tol=1e-10)
+        tseq += t
+        its.append(info[0]["iterations"])
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "sequential12_cgnr_f64",
+           "seconds": round(tseq, 4), "iterations": its}, path)
+    t, st, info, _ = timed_solve(lat, b, reps=1, tol=1e-10, inner_prec=q.F16S)
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "batched12_cgnr_f16s",
+           "seconds": round(t, 4), "iterations": [i["iterations"] for i in info],
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    gain = tseq - t_nn
+    _emit({"kind": "summary", "workload": "24^3x48 eps0.5 k0.125", "training_s": round(t_train, 3),
+           "fgmres_12rhs_s": round(t_nn, 4), "cgnr_f64_12rhs_s": round(tseq, 4),
+           "break_even_solves_of_12": (round(t_train / gain, 2) if gain > 0 else None)}, path)
+    net.close()
+    lat.close()
 
 
 if __name__ == "__main__":

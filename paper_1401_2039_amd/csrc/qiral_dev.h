@@ -207,13 +207,16 @@ template <> struct SpinorIO<S_F16S> {
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
     uint4 *p = (uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
     const bool zero = !(m > 0.f);
-    const float r = zero ? 0.f : 1.f / m;
+    // 1/m overflows for m below ~3e-39 (FP32 denormals, e.g. far from a point
+    // source); such sites are pre-scaled by 2^64 so the reciprocal stays finite.
+    const float pre = m < 0x1p-64f ? 0x1p64f : 1.f;
+    const float r = zero ? 0.f : 1.f / (m * pre);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       unsigned w[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        w[c] = (unsigned)f2h(v[4 * j + c].re * r) | ((unsigned)f2h(v[4 * j + c].im * r) << 16);
+        w[c] = (unsigned)f2h((v[4 * j + c].re * pre) * r) | ((unsigned)f2h((v[4 * j + c].im * pre) * r) << 16);
       st_nt(p + j * WAVE, make_uint4(w[0], w[1], w[2], w[3]));
     }
     st_nt(scale_ptr(base, npad) + s, m);

@@ -199,3 +199,25 @@ def test_tune_and_tuned_solve(tmp_path, monkeypatch):
     assert st == 0
     for r in range(4):
         assert S.true_rel_residual(cfg["U"], 0.12, 0.0, host(x)[r], cfg["b"][r]) <= 1e-10
+
+
+def test_f16s_tiny_scales():
+    """Sites whose largest component is an FP32 denormal (far from a point source)
+    go through the F16S hop output without overflow."""
+    dims = (4, 4, 2, 4)
+    say("f16s tiny scales")
+    cfg = latgen.small_config(dims, seed=52, kind="expih", eps=0.4)
+    b = cfg["b"].copy()
+    b[0, :2] *= 1e-41    # two t-slices with denormal magnitudes
+    b[0, 2] *= 1e-30
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    br = storage.round_f16s(b)
+    src = lat.import_field(dev(b), q.ODD, q.F16S)
+    out = lat.field(q.EVEN, q.F16S)
+    lat.dslash_eo(out, src, 0, 0, q.F16S)
+    got = host(lat.export_field(out, 0, q.F16S))[0]
+    assert np.all(np.isfinite(got))
+    want = W.hop_eo(storage.round_links_r12(cfg["U"], "f16"), br[0], 0)
+    diff = np.abs(W.project(got, 0) - want).reshape(-1, 12).max(axis=1)
+    scale = np.abs(np.stack([want.real, want.imag])).reshape(2, -1, 12).max(axis=(0, 2))
+    assert np.all(diff <= (2.0 ** -11) * scale * 1.01 + 1e-6 * scale), diff.max()

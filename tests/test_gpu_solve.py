@@ -136,3 +136,22 @@ def test_cgnr_c1_mixed_vs_f64():
         say("C1", prec, info[0])
         assert st == 0
         assert _resid(cfg, host(x)[0]) <= 1e-10
+
+
+@pytest.mark.parametrize("nr", [2, 3])
+def test_batched_point_sources_split2(nr, monkeypatch):
+    """Point sources (values spanning many decades) through the grouped multi-RHS
+    mixed solve with 2 lanes per site and nr right-hand sides per lane."""
+    dims = (8, 8, 8, 8)
+    say("batched point sources", nr)
+    monkeypatch.setenv("QIRAL_HOP_SPLIT", "2")
+    monkeypatch.setenv("QIRAL_HOP_NR", str(nr))
+    U = latgen.gauge_field(1003, 0, dims, "expih", 0.4)
+    b = latgen.point_sources(1003, 0, dims)[:5]
+    lat = q.Lattice(dims, 0.12, U)
+    for prec in (q.F16S, q.F32):
+        x, st, info = lat.solve(dev(b), tol=1e-10, inner_prec=prec)
+        assert st == 0, info
+        xs = host(x)
+        for r in range(5):
+            assert S.true_rel_residual(U, 0.12, 0.0, xs[r], b[r]) <= 1e-10
