@@ -27,6 +27,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f32_16x16x16x32_traffic.md")
+HOP_SOURCES = [os.path.join(ROOT, "paper_1401_2039_amd", "csrc", f) for f in ("qiral_dev.h", "api.hip")]
+
+
+def hop_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in HOP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant hop from the committed counter summary,
+    or None if it is missing or was taken on different kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+        if kv.get("source_sha256") != hop_source_hash():
+            return None
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 FLOP_PER_SITE = 1320           # one even-odd hop, per output site
 # algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output spinor
 HOP_BYTES = {"f64": 8 * 144 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
@@ -123,6 +150,13 @@ def main():
     dslash_gflops = FLOP_PER_SITE * vh / (hop_us * 1e-6) / 1e9
     log(f"[bench] F32 hop 16^3x32: {hop_us:.2f} us/launch, {achieved:.0f} GB/s algorithmic, {dslash_gflops:.0f} GFLOP/s")
 
+    # ---- a plain 1 GiB device copy: the reference a counter run scales FETCH_SIZE / WRITE_SIZE by
+    cx = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cy = torch.empty_like(cx)
+    cy.copy_(cx)
+    torch.cuda.synchronize()
+    del cx, cy
+
     # ---- CPU oracle on a bounded sample: a few CGNR iterations of the same workload
     cpu = None
     if not args.no_cpu:
@@ -154,7 +188,8 @@ def main():
         "dslash_gflops": round(dslash_gflops, 1),
         "roofline": {"bound": "hbm", "kernel": "k_hop<S_F32,L_F32R12,false,0> (qiral_dslash_eo, F32)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "source_sha256": hop_source_hash(),
                      "launch_us": round(hop_us, 3), "bytes_per_launch": hop_bytes,
                      "fits_last_level_cache": True},
         "cpu_baseline": cpu,

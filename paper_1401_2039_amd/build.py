@@ -2,6 +2,7 @@
 shared library libqiral_hip.so (no torch types cross its C ABI)."""
 import concurrent.futures
 import os
+import re
 import shutil
 import subprocess
 
@@ -46,6 +47,27 @@ def build_library(jobs=None):
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def kernel_resources(src):
+    """Per-kernel register, scratch and LDS use of one source, as the compiler
+    reports it for gfx950 (device-only compile, nothing written)."""
+    cmd = [HIPCC, *CFLAGS, "--cuda-device-only", "-c", src, "-o", os.devnull,
+           "-Rpass-analysis=kernel-resource-usage"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    rows, cur = [], None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = {"name": m.group(1)}
+            rows.append(cur)
+            continue
+        m = re.search(r"remark:\s+([A-Za-z][\w /\[\]]*?): (\S+) \[-Rpass", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = m.group(2)
+    return rows
 
 
 def clean():

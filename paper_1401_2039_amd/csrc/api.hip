@@ -187,7 +187,7 @@ __global__ __launch_bounds__(WG) void k_export(Geo g, double *__restrict__ canon
 // so a group's neighbour spinors are re-read while still cached and the tile's
 // links are re-read from cache by the next group.  T lanes share a site
 // (hop_part), so T waves cover an item.
-template <int S, int L, bool DAG, int EPI, int T, int NR>
+template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, const void *__restrict__ gauge,
                                                              const void *__restrict__ in, void *__restrict__ out,
                                                              const void *__restrict__ xin, size_t fstride, int nrhs,
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, cons
 #pragma unroll
   for (int r = 0; r < NR; ++r) ld.base[r] = (const char *)in + (size_t)(r0 + min(r, cnt - 1)) * fstride;
   cpx<R> acc[NR][12];
-  hop_part<L, DAG, T>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
+  hop_part<L, DAG, T, NT>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
   if (!site_ok || grp != 0) return;
   const R ar = (R)a;
 #pragma unroll
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, cons
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(ar, acc[r][k]));
     }
-    SpinorIO<S>::store_fast((char *)out + (size_t)(r0 + r) * fstride, s, npad, acc[r]);
+    SpinorIO<S>::template store_fast<NT>((char *)out + (size_t)(r0 + r) * fstride, s, npad, acc[r]);
   }
 }
 
@@ -246,7 +246,16 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
   c.t = hop_split(prec, nitems);
   const int tt = lat->tuned_t[prec][nrhs < 4 ? nrhs : 4];
   if (tt && !getenv("QIRAL_HOP_SPLIT") && !(prec == QIRAL_F64 && tt != 4)) c.t = tt;
+  if (c.nr > hop_nr_max(prec, c.t)) c.t = 4;
   return c;
+}
+
+bool hop_stream(const Geo &g, int prec, long nrhs) {
+  if (const char *e = getenv("QIRAL_HOP_NT")) return atoi(e) != 0;
+  const double link = prec == QIRAL_F64 ? 144 : prec == QIRAL_F32 ? 48 : 24;
+  const double sp = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
+  const double bytes = (double)g.vh * (8 * link + 2 * sp * nrhs);
+  return bytes > 128e6;   // half the 256 MB last-level cache
 }
 
 int hop_tile(const Geo &g, int ngroups) {
@@ -268,9 +277,9 @@ int hop_split(int prec, long nwork) {
   return 2;
 }
 
-template <int S, int L, int T, int NR>
-static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
-                                void *out, const void *x, int nrhs, hipStream_t st) {
+template <int S, int L, int T, int NR, bool NT>
+static hipError_t launch_hop_ttt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
+                                 void *out, const void *x, int nrhs, hipStream_t st) {
   const Geo &g = lat->geo;
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
@@ -280,28 +289,31 @@ static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int
   const int nwg = (int)((nitems * T + 3) / 4);
   dim3 grid(nwg), block(WG);
   if (!dagger) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
-    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
-    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
   }
   return hipGetLastError();
+}
+
+template <int S, int L, int T, int NR>
+static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
+                                void *out, const void *x, int nrhs, hipStream_t st) {
+  if (hop_stream(lat->geo, S, nrhs)) return launch_hop_ttt<S, L, T, NR, true>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  return launch_hop_ttt<S, L, T, NR, false>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
 }
 
 template <int S, int L, int T>
 static hipError_t launch_hop_n(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
                                const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
-  if constexpr (S == S_F64) {
-    return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  } else {
-    switch (c.nr) {
-      case 4: return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-      case 3: return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-      case 2: return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-      default: return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    }
-  }
+  constexpr int NM = hop_nr_max(S, T);
+  if (c.nr > NM) return hipErrorInvalidValue;   // excluded by hop_config and the tuner
+  if constexpr (NM >= 4) if (c.nr == 4) return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  if constexpr (NM >= 3) if (c.nr == 3) return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  if constexpr (NM >= 2) if (c.nr == 2) return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
 }
 
 template <int S, int L>

@@ -72,7 +72,9 @@ enum { S_F64 = 0, S_F32 = 1, S_F16S = 2 };
 
 // Non-temporal (streaming) 16- and 8-byte accesses: data read or written once
 // per launch (links, hop outputs) is marked so that it does not displace the
-// neighbour spinors that other sites re-read from L2.
+// neighbour spinors that other sites re-read from L2.  Used only when a hop's
+// working set exceeds the last-level cache (otherwise the streaming hint keeps
+// links and outputs from staying cached between launches, which costs more).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -121,7 +123,9 @@ template <> struct SpinorIO<S_F64> {
 #pragma unroll
     for (int k = 0; k < 12; ++k) p[k * WAVE] = make_double2(v[k].re, v[k].im);
   }
+  template <bool NT = false>
   __device__ static void store_fast(void *base, int s, size_t npad, const cpx<double> v[12]) {
+    if (!NT) return store(base, s, npad, v);
     double2 *p = (double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
 #pragma unroll
     for (int k = 0; k < 12; ++k) st_nt(p + k * WAVE, make_double2(v[k].re, v[k].im));
@@ -148,7 +152,9 @@ template <> struct SpinorIO<S_F32> {
 #pragma unroll
     for (int j = 0; j < 6; ++j) p[j * WAVE] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
   }
+  template <bool NT = false>
   __device__ static void store_fast(void *base, int s, size_t npad, const cpx<float> v[12]) {
+    if (!NT) return store(base, s, npad, v);
     float4 *p = (float4 *)base + (size_t)(s >> 6) * (6 * WAVE) + (s & 63);
 #pragma unroll
     for (int j = 0; j < 6; ++j) st_nt(p + j * WAVE, make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im));
@@ -201,6 +207,7 @@ template <> struct SpinorIO<S_F16S> {
   }
   // Same format, quantised with one reciprocal per site (values may differ from
   // store() in the last FP16 bit); used for the outputs of the hot kernels.
+  template <bool NT = false>
   __device__ static void store_fast(void *base, int s, size_t npad, const cpx<float> v[12]) {
     float m = 0.f;
 #pragma unroll
@@ -217,9 +224,11 @@ template <> struct SpinorIO<S_F16S> {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         w[c] = (unsigned)f2h((v[4 * j + c].re * pre) * r) | ((unsigned)f2h((v[4 * j + c].im * pre) * r) << 16);
-      st_nt(p + j * WAVE, make_uint4(w[0], w[1], w[2], w[3]));
+      if (NT) st_nt(p + j * WAVE, make_uint4(w[0], w[1], w[2], w[3]));
+      else p[j * WAVE] = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    st_nt(scale_ptr(base, npad) + s, m);
+    if (NT) st_nt(scale_ptr(base, npad) + s, m);
+    else scale_ptr(base, npad)[s] = m;
   }
 };
 
@@ -248,21 +257,23 @@ template <int L> struct LinkIO;
 template <> struct LinkIO<L_F64R18> {
   using R = double;
   static constexpr size_t LINK_BYTES = 144;
+  template <bool NT = false>
   __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {
     const double2 *p = (const double2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 9) * WAVE + (s & 63);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) { double2 q = ld_nt(p + j * WAVE); u[j] = cmake(q.x, q.y); }
+    for (int j = 0; j < 9; ++j) { double2 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE]; u[j] = cmake(q.x, q.y); }
   }
 };
 
 template <> struct LinkIO<L_F32R12> {
   using R = float;
   static constexpr size_t LINK_BYTES = 48;
+  template <bool NT = false>
   __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
     const float4 *p = (const float4 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float4 q = ld_nt(p + j * WAVE);
+      float4 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
       u[2 * j] = cmake(q.x, q.y);
       u[2 * j + 1] = cmake(q.z, q.w);
     }
@@ -273,11 +284,12 @@ template <> struct LinkIO<L_F32R12> {
 template <> struct LinkIO<L_F16R12> {
   using R = float;
   static constexpr size_t LINK_BYTES = 24;
+  template <bool NT = false>
   __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
     const uint2 *p = (const uint2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint2 q = ld_nt(p + j * WAVE);
+      uint2 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
       u[2 * j] = cmake(h2f((unsigned short)(q.x & 0xffffu)), h2f((unsigned short)(q.x >> 16)));
       u[2 * j + 1] = cmake(h2f((unsigned short)(q.y & 0xffffu)), h2f((unsigned short)(q.y >> 16)));
     }
@@ -373,9 +385,13 @@ __device__ __forceinline__ int nbr(const Geo &g, const SiteC &c, int mu, bool fw
     const int xn = fwd ? (c.x + 1 == g.lx ? 0 : c.x + 1) : (c.x == 0 ? g.lx - 1 : c.x - 1);
     return c.s - c.xh + (xn >> 1);
   }
-  const int co = mu == 1 ? c.y : mu == 2 ? c.z : c.t;
-  const int L = mu == 1 ? g.ly : mu == 2 ? g.lz : g.lt;
-  const int st = mu == 1 ? g.sy : mu == 2 ? g.sz : g.st;
+  // Selected arithmetically: a conditional over the struct members lets the
+  // compiler index the coordinate struct at run time (per lane), which moves it
+  // out of registers into LDS or scratch.
+  const int m1 = mu == 1, m2 = mu == 2, m3 = mu == 3;
+  const int co = m1 * c.y + m2 * c.z + m3 * c.t;
+  const int L = m1 * g.ly + m2 * g.lz + m3 * g.lt;
+  const int st = m1 * g.sy + m2 * g.sz + m3 * g.st;
   if (fwd) return (co + 1 == L) ? c.s - (L - 1) * st : c.s + st;
   return (co == 0) ? c.s + (L - 1) * st : c.s - st;
 }
@@ -412,7 +428,7 @@ struct SumLd {
 // Forward and backward terms of one (run-time) direction mu for every field of
 // the loader; each link is loaded and rebuilt once and applied to all fields.
 // Spin signs sf (forward term) and sb (backward term).
-template <class Ld, int L>
+template <class Ld, int L, bool NT = false>
 __device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
                                            int mu, int sf, int sb, bool first,
                                            cpx<typename Ld::R> acc[Ld::NF][12]) {
@@ -427,8 +443,8 @@ __device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, cons
     cpx<R> u[9];
     {
       cpx<typename LinkIO<L>::R> u0[9];
-      if (dir == 0) LinkIO<L>::load(gauge, p, mu, c.s, g.nb, u0);
-      else LinkIO<L>::load(gauge, 1 - p, mu, n, g.nb, u0);
+      if (dir == 0) LinkIO<L>::template load<NT>(gauge, p, mu, c.s, g.nb, u0);
+      else LinkIO<L>::template load<NT>(gauge, 1 - p, mu, n, g.nb, u0);
 #pragma unroll
       for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
     }
@@ -476,14 +492,14 @@ template <int T, class R> __device__ __forceinline__ void group_sum(cpx<R> acc[1
 
 // acc[r] = (H psi_r)(s) (DAG: H^dagger, which flips the spin signs) for output
 // parity p, on T lanes per site; every lane group ends with the full sums.
-template <int L, bool DAG, int T, class Ld>
+template <int L, bool DAG, int T, bool NT = false, class Ld>
 __device__ __forceinline__ void hop_part(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int grp,
                                          cpx<typename Ld::R> acc[Ld::NF][12]) {
   static_assert(T == 2 || T == 4, "2 or 4 lanes per site");
   constexpr int SF = DAG ? 1 : -1, SB = DAG ? -1 : 1;
   const SiteC c = site_c(g, s, p);
 #pragma unroll
-  for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L>(g, gauge, ld, c, p, grp + k * T, SF, SB, k == 0, acc);
+  for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L, NT>(g, gauge, ld, c, p, grp + k * T, SF, SB, k == 0, acc);
 #pragma unroll
   for (int r = 0; r < Ld::NF; ++r) group_sum<T>(acc[r]);
 }

@@ -43,7 +43,14 @@ const void *links_for(const qiral_lattice *lat, int prec);
 // autotuned nr of a lattice (a heuristic until tuned).  QIRAL_HOP_SPLIT and
 // QIRAL_HOP_NR override.
 struct HopCfg { int t = 4, nr = 1; };
+// Largest number of right-hand sides per lane that a hop of storage precision
+// S with T lanes per site keeps in registers (FP64 spills at 2, FP32 on 2 lanes
+// per site at 3).
+constexpr int hop_nr_max(int S, int T) { return S == 0 ? 1 : (S == 1 && T == 2) ? 2 : 4; }
 int hop_split(int prec, long nwork);
+// Streaming (non-temporal) link loads and output stores for hops whose working
+// set exceeds half the last-level cache.  QIRAL_HOP_NT=0|1 overrides.
+bool hop_stream(const Geo &g, int prec, long nrhs);
 // Blocks per traversal tile of a multi-group hop (see k_hop).
 int hop_tile(const Geo &g, int ngroups);
 int tuned_nr(const qiral_lattice *lat, int prec, int nrhs);

@@ -191,6 +191,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   L.prec = prec;
   L.T = hc.t;
   L.NR = hc.nr;
+  L.NT = hop_stream(sys[0].lat->geo, prec, same_lattice ? nsys : 1);
+  L.NT64 = hop_stream(sys[0].lat->geo, QIRAL_F64, 1);
   L.stream = s;
 
   // ---- inputs

@@ -17,6 +17,8 @@ struct Launch {
   int prec;                  // iterate precision (S_F64, S_F32, S_F16S)
   int T;                     // lanes per site of the iterate-precision hop (2 or 4)
   int NR;                    // systems per item of the grouped table
+  int NT;                    // streaming accesses in the iterate-precision hop (see hop_stream)
+  int NT64;                  // ... and in the FP64 hops of a mixed solve
   hipStream_t stream;
 };
 

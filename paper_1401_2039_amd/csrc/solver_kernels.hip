@@ -21,7 +21,7 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
 // link is loaded once for all of them).
 // red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
 // T lanes per site (see hop_part); padded lanes compute on site 0 and store nothing.
-template <int S, int L, bool DAG, int EPI, int T, int NR>
+template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const SysDesc *__restrict__ sdesc,
                                                                  const uint32_t *__restrict__ work, int nwork,
                                                                  int fin_id, int fout, int fx, int par, int amode,
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
 #pragma unroll
   for (int r = 0; r < NR; ++r) ld.base[r] = sdesc[it.sys + min(r, it.cnt - 1)].f[fin_id];
   cpx<R> acc[NR][12];
-  hop_part<L, DAG, T>(d0.g, links_of<S>(d0), ld, site_ok ? it.s : 0, par, it.grp, acc);
+  hop_part<L, DAG, T, NT>(d0.g, links_of<S>(d0), ld, site_ok ? it.s : 0, par, it.grp, acc);
   const R a = (R)coef(amode, d0.kappa);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
         for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(a, acc[r][k]));
         if (red == 3) { dot12(acc[r], xv, v[0], v[1]); v[2] = norm12(acc[r]); }
       }
-      SpinorIO<S>::store_fast(d.f[fout], it.s, npad, acc[r]);
+      SpinorIO<S>::template store_fast<NT>(d.f[fout], it.s, npad, acc[r]);
       if (red == 1) v[0] = norm12(acc[r]);
       if (red == 2) {
         cpx<R> rt[12];
@@ -378,34 +378,37 @@ __global__ void k_bi_init(const SysDesc *__restrict__ sdesc, int nsys) {
 // launchers
 static inline dim3 grid_of(int nwork, int T = 1) { return dim3(grid_for(nwork, T)); }
 
-template <int S, int L, int T, int NR>
-static void hop_sys_t(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
-                      int slot) {
+template <int S, int L, int T, int NR, bool NT>
+static void hop_sys_tt(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
+                       int red, int slot) {
   const dim3 g = grid_of(l.nwork, T), b(WG);
 #define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot
   if (!dag) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T, NR>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T, NR>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T, NR, NT>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T, NR, NT>), g, b, 0, l.stream, QARGS);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0, T, NR>), g, b, 0, l.stream, QARGS);
-    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1, T, NR>), g, b, 0, l.stream, QARGS);
+    if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, true, 0, T, NR, NT>), g, b, 0, l.stream, QARGS);
+    else hipLaunchKernelGGL((k_hop_sys<S, L, true, 1, T, NR, NT>), g, b, 0, l.stream, QARGS);
   }
 #undef QARGS
+}
+
+template <int S, int L, int T, int NR>
+static void hop_sys_t(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
+                      int slot) {
+  if (l.NT) hop_sys_tt<S, L, T, NR, true>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  else hop_sys_tt<S, L, T, NR, false>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
 }
 
 template <int S, int L, int T>
 static void hop_sys_n(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask, int red,
                       int slot) {
-  if constexpr (S == S_F64) {
-    hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  } else {
-    switch (l.NR) {
-      case 4: hop_sys_t<S, L, T, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
-      case 3: hop_sys_t<S, L, T, 3>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
-      case 2: hop_sys_t<S, L, T, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
-      default: hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot); break;
-    }
-  }
+  // l.NR never exceeds hop_nr_max(S, T): the solver takes (T, NR) from hop_config.
+  constexpr int NM = hop_nr_max(S, T);
+  if constexpr (NM >= 4) if (l.NR == 4) return hop_sys_t<S, L, T, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  if constexpr (NM >= 3) if (l.NR == 3) return hop_sys_t<S, L, T, 3>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  if constexpr (NM >= 2) if (l.NR == 2) return hop_sys_t<S, L, T, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
 }
 
 template <int S, int L>
@@ -426,8 +429,8 @@ void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int f
   // solve (source, reconstruction) walks the plain one
   const bool grouped = (prec == S_F64) == (l.prec == S_F64);
   Launch lp = l;
-  if (grouped) { lp.work = l.work_hop; lp.nwork = l.nwork_hop; lp.T = l.T; lp.NR = l.NR; }
-  else { lp.T = 4; lp.NR = 1; }
+  if (grouped) { lp.work = l.work_hop; lp.nwork = l.nwork_hop; lp.T = l.T; lp.NR = l.NR; lp.NT = l.NT; }
+  else { lp.T = 4; lp.NR = 1; lp.NT = l.NT64; }
   if (prec == S_F64) hop_sys_p<S_F64, L_F64R18>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else if (prec == S_F32) hop_sys_p<S_F32, L_F32R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else hop_sys_p<S_F16S, L_F16R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
