@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads (stderr JSON lines)")
     ap.add_argument("--suite-out", default=None, help="append the suite's JSON lines to this file")
     ap.add_argument("--parts", default="c1,c0,c2,c3,c99,c4", help="suite parts to run")
+    ap.add_argument("--suite-hop-reps", type=int, default=None,
+                    help="timed launches per hop measurement in the suite (default 100, 50 on 32^3x64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -196,7 +198,7 @@ def main():
     }
     print(json.dumps(res), flush=True)
     if args.suite:
-        suite(lat, q, latgen, np, torch, args.suite_out, args.parts.split(','))
+        suite(lat, q, latgen, np, torch, args.suite_out, args.parts.split(','), args.suite_hop_reps)
     lat.close()
 
 
@@ -281,7 +283,7 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None):
     return res
 
 
-def suite(lat1, q, latgen, np, torch, path=None, parts=()):
+def suite(lat1, q, latgen, np, torch, path=None, parts=(), hop_reps=None):
     """Extra measurements: hop throughput of every storage class on the workloads'
     lattices (warm and cache-flushed) and time to solution of each solver form."""
     import time as _t
@@ -289,7 +291,7 @@ def suite(lat1, q, latgen, np, torch, path=None, parts=()):
     dims1 = (16, 16, 16, 32)
     if "c1" in parts:
         for prec in (q.F64, q.F32, q.F16S):
-            _emit(hop_rates(q, lat1, dims1, torch, prec, flush=flush), path)
+            _emit(hop_rates(q, lat1, dims1, torch, prec, reps=hop_reps or 100, flush=flush), path)
 
     def timed_solve(lat, b, reps=2, **kw):
         x = torch.zeros_like(b)
@@ -315,7 +317,7 @@ def suite(lat1, q, latgen, np, torch, path=None, parts=()):
         lat99 = q.Lattice(c99["dims"], c99["kappa"], c99["U"])
         del c99
         for prec in (q.F64, q.F32, q.F16S):
-            _emit(hop_rates(q, lat99, (32, 32, 32, 64), torch, prec, reps=50, flush=flush), path)
+            _emit(hop_rates(q, lat99, (32, 32, 32, 64), torch, prec, reps=hop_reps or 50, flush=flush), path)
         lat99.close()
     if "c4" in parts:
         suite_c4(q, latgen, torch, path, timed_solve)
