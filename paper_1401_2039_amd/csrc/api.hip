@@ -185,42 +185,47 @@ __global__ __launch_bounds__(WG) void k_export(Geo g, double *__restrict__ canon
 // every link it loads to all NR of them).  Items run tile by tile: within a
 // tile of at least two t-slices, every group sweeps the tile's blocks in turn,
 // so a group's neighbour spinors are re-read while still cached and the tile's
-// links are re-read from cache by the next group.  T lanes share a site
-// (hop_part), so T waves cover an item.
+// links are re-read from cache by the next group.  T waves cover an item, each
+// taking 4/T directions for all 64 sites (hop_wave), and their sums are added
+// in LDS (wave_combine).
 template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, const void *__restrict__ gauge,
                                                              const void *__restrict__ in, void *__restrict__ out,
                                                              const void *__restrict__ xin, size_t fstride, int nrhs,
-                                                             int p, double a, int tile) {
+                                                             int p, double a, int tile, int zb) {
   using R = typename SpinorIO<S>::R;
+  using LDS = HopLds<T, NR, R>;
+  __shared__ typename LDS::V lds[LDS::VECS];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
-  const int item = wg * (4 / T) + w / T;
+  const int slot = w / T, grp = w % T;
+  const int item = wg * (4 / T) + slot;
   // item order: (tile of `tile` blocks, right-hand-side group, block in tile)
   const int ngr = (nrhs + NR - 1) / NR;
   const int per_tile = ngr * tile;
   const int ti = item / per_tile, rem = item - ti * per_tile;
   const int rg = rem / tile;
-  const int sb = ti * tile + (rem - rg * tile);
-  if (sb >= g.nb) return;
+  const int sbl = ti * tile + (rem - rg * tile);
+  const bool item_ok = sbl < g.nb;   // uniform over the item's waves
+  const int sb = item_ok ? block_order(g, sbl, zb) : 0;
   const int r0 = rg * NR;
-  const int cnt = min(NR, nrhs - r0);
-  int sib, grp;
-  split_lane<T>(w % T, sib, grp);
-  const int s = sb * WAVE + sib;
-  const bool site_ok = s < g.vh;
+  const int cnt = item_ok ? min(NR, nrhs - r0) : 1;
+  const int s = sb * WAVE + (int)(threadIdx.x & (WAVE - 1));
+  const bool site_ok = item_ok && s < g.vh;
   const size_t npad = (size_t)g.nb * WAVE;
   FieldLd<S, NR> ld;
   ld.npad = npad;
 #pragma unroll
   for (int r = 0; r < NR; ++r) ld.base[r] = (const char *)in + (size_t)(r0 + min(r, cnt - 1)) * fstride;
   cpx<R> acc[NR][12];
-  hop_part<L, DAG, T, NT>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
+  if (item_ok) hop_wave<L, DAG, T, NT>(g, gauge, ld, site_ok ? s : 0, p, grp, acc);
+  else zero_acc<NR>(acc);
+  wave_combine<T, NR>(acc, slot, grp, lds);
   if (!site_ok || grp != 0) return;
   const R ar = (R)a;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    if (r >= cnt) break;
+    if (r >= cnt) continue;
     if (EPI == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r][k] = cscale(ar, acc[r][k]);
@@ -258,6 +263,21 @@ bool hop_stream(const Geo &g, int prec, long nrhs) {
   return bytes > 128e6;   // half the 256 MB last-level cache
 }
 
+int hop_zb(const Geo &g, int prec) {
+  if (g.sz % WAVE != 0 || (long)g.nb * WAVE != g.vh) return 0;
+  if (const char *e = getenv("QIRAL_HOP_ORDER")) {   // 0: plain order; n > 0: tiles of n planes
+    const int n = atoi(e);
+    return (n > 0 && n < g.lz && g.lz % n == 0) ? n : 0;
+  }
+  // keep zb planes of input spinors (the reuse distance of a t-neighbour) to
+  // about 0.5 MB per XCD
+  const long site_b = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
+  int zb = 0;
+  for (int z = 1; z <= g.lz; ++z)
+    if (g.lz % z == 0 && (long)z * g.sz * site_b <= (512l << 10)) zb = z;
+  return zb >= g.lz ? 0 : zb;   // a tile of every plane is the plain order
+}
+
 int hop_tile(const Geo &g, int ngroups) {
   if (ngroups <= 1) return g.nb;   // one group: plain block order
   const int slice = (g.st + WAVE - 1) / WAVE;   // blocks per t-slice
@@ -284,16 +304,17 @@ static hipError_t launch_hop_ttt(const qiral_lattice *lat, int dagger, int p, in
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
   const int tile = hop_tile(g, (nrhs + NR - 1) / NR);
+  const int zb = hop_zb(g, S);
   const long ntile = (g.nb + tile - 1) / tile;
   const long nitems = ntile * tile * ((nrhs + NR - 1) / NR);
   const int nwg = (int)((nitems * T + 3) / 4);
   dim3 grid(nwg), block(WG);
   if (!dagger) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
-    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
-    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
   }
   return hipGetLastError();
 }

@@ -304,11 +304,11 @@ template <> struct LinkIO<L_F16R12> {
 // S B^+ h, so each of the 8 terms is one spin projection to a half spinor (6
 // complex), two SU(3) x colour-vector products, and a reconstruction.
 //
-// A site's 8 terms are shared by T lanes (T = 2 or 4): lane group g takes the
-// directions g, g + T, ...; the groups' sums are combined with cross-lane
-// shuffles.  Because lanes of one wave take different directions, the spin
-// matrices are applied through small (source, phase) tables rather than
-// compile-time specialisation, so all lanes run the same instructions.
+// A site's directions are shared by the T waves of its work item (T = 1, 2 or
+// 4): wave group g takes directions g, g + T, ...  The direction is uniform
+// over a wave, so each is compiled on its own with the spin matrices as
+// constants (the projections are additions with swapped or negated parts), and
+// the groups' partial sums are added in LDS in a fixed order.
 
 // w = U h (ADJ = false) or U^+ h (ADJ = true) for both spin components of h.
 template <bool ADJ, class R>
@@ -335,29 +335,6 @@ __device__ __forceinline__ void su3_mul(const cpx<R> u[9], const cpx<R> h[6], cp
 template <class Rd, class Rs> __device__ __forceinline__ void cvt12(const cpx<Rs> a[12], cpx<Rd> b[12]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) b[k] = cmake((Rd)a[k].re, (Rd)a[k].im);
-}
-
-// Phase codes: 0 -> 1, 1 -> i, 2 -> -1, 3 -> -i.
-template <class R> __device__ __forceinline__ cpx<R> cphase(cpx<R> z, int f) {
-  const bool sw = f & 1;
-  R re = sw ? z.im : z.re, im = sw ? z.re : z.im;
-  re = (f == 1 || f == 2) ? -re : re;
-  im = (f >= 2) ? -im : im;
-  return cmake(re, im);
-}
-
-// B_mu (lower spinor -> upper) and B_mu^+, as (source component, phase) per row.
-__device__ __forceinline__ void bmat(int mu, int &j0, int &f0, int &j1, int &f1) {
-  j0 = (mu == 0 || mu == 1) ? 1 : 0;
-  j1 = 1 - j0;
-  f0 = mu == 0 ? 3 : mu == 1 ? 2 : mu == 2 ? 3 : 0;
-  f1 = mu == 0 ? 3 : mu == 1 ? 0 : mu == 2 ? 1 : 0;
-}
-__device__ __forceinline__ void bdag(int mu, int &j0, int &f0, int &j1, int &f1) {
-  j0 = (mu == 0 || mu == 1) ? 1 : 0;
-  j1 = 1 - j0;
-  f0 = mu == 0 ? 1 : mu == 1 ? 0 : mu == 2 ? 1 : 0;
-  f1 = mu == 0 ? 1 : mu == 1 ? 2 : mu == 2 ? 3 : 0;
 }
 
 // Coordinates of checkerboard site s of parity p.  The divisions by Lx/2, Ly
@@ -425,91 +402,171 @@ struct SumLd {
   }
 };
 
-// Forward and backward terms of one (run-time) direction mu for every field of
-// the loader; each link is loaded and rebuilt once and applied to all fields.
-// Spin signs sf (forward term) and sb (backward term).
-template <class Ld, int L, bool NT = false>
-__device__ __forceinline__ void hop_dir_rt(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
-                                           int mu, int sf, int sb, bool first,
-                                           cpx<typename Ld::R> acc[Ld::NF][12]) {
-  using R = typename Ld::R;
-  int j0, f0, j1, f1, k0, e0, k1, e1;
-  bmat(mu, j0, f0, j1, f1);
-  bdag(mu, k0, e0, k1, e1);
-#pragma unroll
-  for (int dir = 0; dir < 2; ++dir) {
-    const int ph = (dir == 0 ? sf : sb) > 0 ? 0 : 2;   // the projection sign as a phase
-    const int n = nbr(g, c, mu, dir == 0);
-    cpx<R> u[9];
-    {
-      cpx<typename LinkIO<L>::R> u0[9];
-      if (dir == 0) LinkIO<L>::template load<NT>(gauge, p, mu, c.s, g.nb, u0);
-      else LinkIO<L>::template load<NT>(gauge, 1 - p, mu, n, g.nb, u0);
-#pragma unroll
-      for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
-    }
-#pragma unroll
-    for (int r = 0; r < Ld::NF; ++r) {
-      cpx<R> psi[12], h[6], w[6];
-      ld(r, n, psi);
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        const cpx<R> l0 = psi[4 * cc + 2], l1 = psi[4 * cc + 3];
-        h[2 * cc] = cadd(psi[4 * cc], cphase(j0 ? l1 : l0, (f0 + ph) & 3));
-        h[2 * cc + 1] = cadd(psi[4 * cc + 1], cphase(j1 ? l1 : l0, (f1 + ph) & 3));
-      }
-      if (dir == 0) su3_mul<false>(u, h, w);
-      else su3_mul<true>(u, h, w);
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        const cpx<R> w0 = w[2 * cc], w1 = w[2 * cc + 1];
-        const cpx<R> lo0 = cphase(k0 ? w1 : w0, (e0 + ph) & 3);
-        const cpx<R> lo1 = cphase(k1 ? w1 : w0, (e1 + ph) & 3);
-        if (first && dir == 0) {
-          acc[r][4 * cc] = w0; acc[r][4 * cc + 1] = w1; acc[r][4 * cc + 2] = lo0; acc[r][4 * cc + 3] = lo1;
-        } else {
-          acc[r][4 * cc] = cadd(acc[r][4 * cc], w0);
-          acc[r][4 * cc + 1] = cadd(acc[r][4 * cc + 1], w1);
-          acc[r][4 * cc + 2] = cadd(acc[r][4 * cc + 2], lo0);
-          acc[r][4 * cc + 3] = cadd(acc[r][4 * cc + 3], lo1);
-        }
-      }
-    }
-  }
+// B_mu and B_mu^+ as (source component, phase) per row: row i of B psi_lo is
+// phase f_i times component j_i of psi_lo; row i of B^+ h is phase e_i times
+// component j_i of h.  Phase codes: 0 -> 1, 1 -> i, 2 -> -1, 3 -> -i.
+template <int MU> struct SpinB {
+  static constexpr int j0 = (MU == 0 || MU == 1) ? 1 : 0, j1 = 1 - j0;
+  static constexpr int f0 = MU == 0 ? 3 : MU == 1 ? 2 : MU == 2 ? 3 : 0;
+  static constexpr int f1 = MU == 0 ? 3 : MU == 1 ? 0 : MU == 2 ? 1 : 0;
+  static constexpr int e0 = MU == 0 ? 1 : MU == 1 ? 0 : MU == 2 ? 1 : 0;
+  static constexpr int e1 = MU == 0 ? 1 : MU == 1 ? 2 : MU == 2 ? 3 : 0;
+};
+
+template <int F, class R> __device__ __forceinline__ cpx<R> cph(cpx<R> z) {
+  constexpr int f = F & 3;
+  if constexpr (f == 0) return z;
+  else if constexpr (f == 1) return cmake(-z.im, z.re);
+  else if constexpr (f == 2) return cmake(-z.re, -z.im);
+  else return cmake(z.im, -z.re);
 }
 
-// Sum the accumulators of the T lane groups of a site (groups are 64/T lanes apart).
-template <int T, class R> __device__ __forceinline__ void group_sum(cpx<R> acc[12]) {
-#pragma unroll
-  for (int m = 32; m >= 64 / T; m >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      acc[k].re += __shfl_xor(acc[k].re, m, WAVE);
-      acc[k].im += __shfl_xor(acc[k].im, m, WAVE);
-    }
-  }
-}
-
-// acc[r] = (H psi_r)(s) (DAG: H^dagger, which flips the spin signs) for output
-// parity p, on T lanes per site; every lane group ends with the full sums.
-template <int L, bool DAG, int T, bool NT = false, class Ld>
-__device__ __forceinline__ void hop_part(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int grp,
+// One term of the hop for every field of the loader: DIR 0 is the forward
+// neighbour with U_mu(x) and (1 - gamma_mu) (DAG: 1 + gamma_mu), DIR 1 the
+// backward neighbour with U_mu(x - mu)^+ and (1 + gamma_mu) (DAG: 1 - gamma_mu).
+// Each link is loaded and rebuilt once for all fields.  FIRST: the term
+// initialises the accumulators.
+template <int MU, int DIR, bool DAG, bool FIRST, int L, bool NT, class Ld>
+__device__ __forceinline__ void hop_term(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
                                          cpx<typename Ld::R> acc[Ld::NF][12]) {
-  static_assert(T == 2 || T == 4, "2 or 4 lanes per site");
-  constexpr int SF = DAG ? 1 : -1, SB = DAG ? -1 : 1;
-  const SiteC c = site_c(g, s, p);
+  using R = typename Ld::R;
+  using B = SpinB<MU>;
+  constexpr int ph = ((DIR == 0) == DAG) ? 0 : 2;   // the projection sign as a phase
+  const int n = nbr(g, c, MU, DIR == 0);
+  cpx<R> u[9];
+  {
+    cpx<typename LinkIO<L>::R> u0[9];
+    if (DIR == 0) LinkIO<L>::template load<NT>(gauge, p, MU, c.s, g.nb, u0);
+    else LinkIO<L>::template load<NT>(gauge, 1 - p, MU, n, g.nb, u0);
 #pragma unroll
-  for (int k = 0; k < 4 / T; ++k) hop_dir_rt<Ld, L, NT>(g, gauge, ld, c, p, grp + k * T, SF, SB, k == 0, acc);
+    for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+  }
 #pragma unroll
-  for (int r = 0; r < Ld::NF; ++r) group_sum<T>(acc[r]);
+  for (int r = 0; r < Ld::NF; ++r) {
+    cpx<R> psi[12], h[6], w[6];
+    ld(r, n, psi);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      h[2 * cc] = cadd(psi[4 * cc], cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]));
+      h[2 * cc + 1] = cadd(psi[4 * cc + 1], cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]));
+    }
+    su3_mul<DIR == 1>(u, h, w);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const cpx<R> w0 = w[2 * cc], w1 = w[2 * cc + 1];
+      const cpx<R> lo0 = cph<B::e0 + ph>(w[2 * cc + B::j0]);
+      const cpx<R> lo1 = cph<B::e1 + ph>(w[2 * cc + B::j1]);
+      if (FIRST && DIR == 0) {
+        acc[r][4 * cc] = w0; acc[r][4 * cc + 1] = w1; acc[r][4 * cc + 2] = lo0; acc[r][4 * cc + 3] = lo1;
+      } else {
+        acc[r][4 * cc] = cadd(acc[r][4 * cc], w0);
+        acc[r][4 * cc + 1] = cadd(acc[r][4 * cc + 1], w1);
+        acc[r][4 * cc + 2] = cadd(acc[r][4 * cc + 2], lo0);
+        acc[r][4 * cc + 3] = cadd(acc[r][4 * cc + 3], lo1);
+      }
+    }
+  }
 }
 
-// Lane -> (site within a 64-site block, lane group) for T lanes per site; the T
-// waves of a block take sub-blocks sub = 0..T-1.
-template <int T> __device__ __forceinline__ void split_lane(int sub, int &site_in_block, int &grp) {
-  const int lane = (int)(threadIdx.x & (WAVE - 1));
-  site_in_block = sub * (WAVE / T) + lane % (WAVE / T);
-  grp = lane / (WAVE / T);
+template <int MU, bool DAG, bool FIRST, int L, bool NT, class Ld>
+__device__ __forceinline__ void hop_mu(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
+                                       cpx<typename Ld::R> acc[Ld::NF][12]) {
+  hop_term<MU, 0, DAG, FIRST, L, NT>(g, gauge, ld, c, p, acc);
+  hop_term<MU, 1, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+}
+
+// acc[r] = this wave group's part of (H psi_r)(s) (DAG: H^dagger) for output
+// parity p: the directions grp, grp + T, ...  grp must be wave-uniform.
+template <int L, bool DAG, int T, bool NT, class Ld>
+__device__ __forceinline__ void hop_wave(const Geo &g, const void *gauge, const Ld &ld, int s, int p, int grp,
+                                         cpx<typename Ld::R> acc[Ld::NF][12]) {
+  static_assert(T == 1 || T == 2 || T == 4, "1, 2 or 4 waves per site block");
+  const SiteC c = site_c(g, s, p);
+  if constexpr (T == 1) {
+    hop_mu<0, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+    hop_mu<1, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+    hop_mu<2, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+    hop_mu<3, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+  } else if constexpr (T == 2) {
+    if (grp == 0) {
+      hop_mu<0, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+      hop_mu<2, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+    } else {
+      hop_mu<1, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+      hop_mu<3, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+    }
+  } else {
+    if (grp == 0) hop_mu<0, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+    else if (grp == 1) hop_mu<1, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+    else if (grp == 2) hop_mu<2, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+    else hop_mu<3, DAG, true, L, NT>(g, gauge, ld, c, p, acc);
+  }
+}
+
+// LDS for wave_combine: (4/T items) x (T-1 groups) x NF fields x 24 reals x 64
+// lanes, in 16-byte vectors.
+template <class R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int N = 4; };
+template <> struct Vec16<double> { using T = double2; static constexpr int N = 2; };
+template <int T, int NF, class R> struct HopLds {
+  static constexpr int PER = 24 / Vec16<R>::N;   // vectors per field
+  static constexpr int VECS = T == 1 ? 1 : (4 / T) * (T - 1) * NF * PER * WAVE;
+  using V = typename Vec16<R>::T;
+};
+
+template <class R> __device__ __forceinline__ void v16_put(typename Vec16<R>::T *p, const cpx<R> a[12], int j);
+template <> __device__ __forceinline__ void v16_put<float>(float4 *p, const cpx<float> a[12], int j) {
+  *p = make_float4(a[2 * j].re, a[2 * j].im, a[2 * j + 1].re, a[2 * j + 1].im);
+}
+template <> __device__ __forceinline__ void v16_put<double>(double2 *p, const cpx<double> a[12], int j) {
+  *p = make_double2(a[j].re, a[j].im);
+}
+template <class R> __device__ __forceinline__ void v16_add(const typename Vec16<R>::T *p, cpx<R> a[12], int j);
+template <> __device__ __forceinline__ void v16_add<float>(const float4 *p, cpx<float> a[12], int j) {
+  const float4 v = *p;
+  a[2 * j] = cadd(a[2 * j], cmake(v.x, v.y));
+  a[2 * j + 1] = cadd(a[2 * j + 1], cmake(v.z, v.w));
+}
+template <> __device__ __forceinline__ void v16_add<double>(const double2 *p, cpx<double> a[12], int j) {
+  const double2 v = *p;
+  a[j] = cadd(a[j], cmake(v.x, v.y));
+}
+
+// Add the partial sums of the T wave groups of each item (in the order
+// 0, 1, .., T-1, so the result does not depend on scheduling); afterwards group
+// 0 holds the full sums.  Every wave of the work-group must call it (barrier).
+template <int T, int NF, class R>
+__device__ __forceinline__ void wave_combine(cpx<R> acc[NF][12], int slot, int grp,
+                                             typename HopLds<T, NF, R>::V *lds) {
+  if constexpr (T > 1) {
+    constexpr int PER = HopLds<T, NF, R>::PER;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    if (grp != 0) {
+      typename HopLds<T, NF, R>::V *q = lds + (size_t)(slot * (T - 1) + grp - 1) * NF * PER * WAVE + lane;
+#pragma unroll
+      for (int r = 0; r < NF; ++r)
+#pragma unroll
+        for (int j = 0; j < PER; ++j) v16_put<R>(q + (r * PER + j) * WAVE, acc[r], j);
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int g2 = 1; g2 < T; ++g2) {
+        const typename HopLds<T, NF, R>::V *q = lds + (size_t)(slot * (T - 1) + g2 - 1) * NF * PER * WAVE + lane;
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+          for (int j = 0; j < PER; ++j) v16_add<R>(q + (r * PER + j) * WAVE, acc[r], j);
+      }
+    }
+  }
+}
+
+template <int NF, class R> __device__ __forceinline__ void zero_acc(cpx<R> acc[NF][12]) {
+#pragma unroll
+  for (int r = 0; r < NF; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[r][k] = cmake((R)0, (R)0);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,6 +613,21 @@ __device__ __forceinline__ int xcd_remap(int hw, int nblocks) {
   const int q = nblocks >> 3, r = nblocks & 7;
   const int xcd = hw & 7, idx = hw >> 3;
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Traversal order of the 64-site blocks of a hop.  With zb > 0 (a z-plane holds
+// a whole number of blocks and zb divides Lz) logical block L runs over
+// (z-tile of zb planes, t, z within the tile, block within the plane), so the
+// t-neighbours of a block were read zb planes earlier, not a whole t-slice
+// earlier, and are still in the L2 of the XCD that takes the range.  zb = 0 is
+// the plain lexicographic order.
+__host__ __device__ inline int block_order(const Geo &g, int L, int zb) {
+  if (zb <= 0) return L;
+  const int B = g.sz / WAVE;   // blocks per z-plane
+  const int yb = L % B, L1 = L / B;
+  const int zi = L1 % zb, L2 = L1 / zb;
+  const int t = L2 % g.lt, zt = L2 / g.lt;
+  return (t * g.lz + zt * zb + zi) * B + yb;
 }
 
 }  // namespace qiral

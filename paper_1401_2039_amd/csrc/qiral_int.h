@@ -51,6 +51,10 @@ int hop_split(int prec, long nwork);
 // Streaming (non-temporal) link loads and output stores for hops whose working
 // set exceeds half the last-level cache.  QIRAL_HOP_NT=0|1 overrides.
 bool hop_stream(const Geo &g, int prec, long nrhs);
+// Planes per z-tile of the hop's block order (block_order), 0 for the plain
+// order.  QIRAL_HOP_ORDER=0 forces the plain order, QIRAL_HOP_ORDER=n tiles of
+// n planes where the lattice allows them.
+int hop_zb(const Geo &g, int prec);
 // Blocks per traversal tile of a multi-group hop (see k_hop).
 int hop_tile(const Geo &g, int ngroups);
 int tuned_nr(const qiral_lattice *lat, int prec, int nrhs);

@@ -150,19 +150,33 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   if (same_lattice && nsys > 1) {
     // tile by tile (see hop_tile): each system, or group of systems, sweeps the
     // tile's blocks in turn
-    const int nb = sys[0].lat->geo.nb;
-    const int tile = hop_tile(sys[0].lat->geo, nsys);
+    const Geo &g = sys[0].lat->geo;
+    const int nb = g.nb;
+    const int tile = hop_tile(g, nsys);
+    const int zb = hop_zb(g, prec), zb64 = hop_zb(g, QIRAL_F64);
     for (int b0 = 0; b0 < nb; b0 += tile) {
       const int b1 = std::min(nb, b0 + tile);
       for (int i = 0; i < nsys; ++i)
-        for (int b = b0; b < b1; ++b) work.push_back(work_item(i, 1, b));
+        for (int b = b0; b < b1; ++b) work.push_back(work_item(i, 1, block_order(g, b, zb64)));
       for (int i = 0; i < nsys; i += hc.nr)
-        for (int b = b0; b < b1; ++b) work_hop.push_back(work_item(i, std::min(hc.nr, nsys - i), b));
+        for (int b = b0; b < b1; ++b) work_hop.push_back(work_item(i, std::min(hc.nr, nsys - i), block_order(g, b, zb)));
     }
   } else {
-    for (int i = 0; i < nsys; ++i)
-      for (int b = 0; b < sys[i].lat->geo.nb; ++b) work.push_back(work_item(i, 1, b));
-    work_hop = work;
+    // plain table: the block order of the FP64 hops; grouped: of the iterate's
+    for (int i = 0; i < nsys; ++i) {
+      const Geo &g = sys[i].lat->geo;
+      const int zb = hop_zb(g, QIRAL_F64);
+      for (int b = 0; b < g.nb; ++b) work.push_back(work_item(i, 1, block_order(g, b, zb)));
+    }
+    if (prec == QIRAL_F64) {
+      work_hop = work;
+    } else {
+      for (int i = 0; i < nsys; ++i) {
+        const Geo &g = sys[i].lat->geo;
+        const int zb = hop_zb(g, prec);
+        for (int b = 0; b < g.nb; ++b) work_hop.push_back(work_item(i, 1, block_order(g, b, zb)));
+      }
+    }
   }
   std::vector<SysState> hst(nsys);
   for (int i = 0; i < nsys; ++i) {

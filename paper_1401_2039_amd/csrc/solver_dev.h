@@ -193,8 +193,10 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
 // grouped hop table); it is encoded as (sys0 << 24) | ((cnt - 1) << 22) | block.
 // With T lanes per site, T waves share an item (sub = 0..T-1 picks the wave's
 // part of it) and a work-group of 4 waves takes 4/T items.
+// A work item as one wave sees it: T waves share an item (wave group grp of
+// the item in work-group slot `slot`); each lane takes site s of the block.
 struct Item {
-  int sys, cnt, sb, sub, s, grp;
+  int sys, cnt, sb, sub, s, grp, slot;
   bool active;
 };
 
@@ -209,15 +211,14 @@ __device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
   const int idx = wg * (4 / T) + w / T;
-  it.sub = w % T;
-  if (idx >= nwork) { it.active = false; it.sys = 0; it.cnt = 0; it.sb = 0; it.s = 0; it.grp = 0; return it; }
+  it.sub = it.grp = w % T;
+  it.slot = w / T;
+  if (idx >= nwork) { it.active = false; it.sys = 0; it.cnt = 1; it.sb = 0; it.s = 0; return it; }
   const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)work[idx]);
   it.sys = (int)(v >> 24);
   it.cnt = (int)((v >> 22) & 3u) + 1;
   it.sb = (int)(v & 0x3fffffu);
-  int sib;
-  split_lane<T>(it.sub, sib, it.grp);
-  it.s = it.sb * WAVE + sib;
+  it.s = it.sb * WAVE + lane_id();
   it.active = true;
   return it;
 }

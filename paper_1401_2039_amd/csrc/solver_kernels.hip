@@ -20,32 +20,36 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
 // (up to NR) systems of a grouped work item (they share the lattice, so each
 // link is loaded once for all of them).
 // red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
-// T lanes per site (see hop_part); padded lanes compute on site 0 and store nothing.
+// T waves per item (see hop_wave); padded lanes compute on site 0 and store
+// nothing.  Every wave reaches wave_combine's barrier.
 template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const SysDesc *__restrict__ sdesc,
                                                                  const uint32_t *__restrict__ work, int nwork,
                                                                  int fin_id, int fout, int fx, int par, int amode,
                                                                  int mask, int red, int slot) {
   using R = typename SpinorIO<S>::R;
+  using LDS = HopLds<T, NR, R>;
+  __shared__ typename LDS::V lds[LDS::VECS];
   const Item it = fetch_item<T>(work, nwork);
-  if (!it.active) return;
   bool act[NR];
   bool any = false;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    act[r] = r < it.cnt && (sdesc[it.sys + r].st->status & mask);
+    act[r] = it.active && r < it.cnt && (sdesc[it.sys + r].st->status & mask);
     any = any || act[r];
   }
-  if (!any) return;
   const SysDesc &d0 = sdesc[it.sys];
-  const bool site_ok = it.s < d0.g.vh;
+  const bool site_ok = it.active && it.s < d0.g.vh;
   const size_t npad = d0.npad;
   FieldLd<S, NR> ld;
   ld.npad = npad;
 #pragma unroll
   for (int r = 0; r < NR; ++r) ld.base[r] = sdesc[it.sys + min(r, it.cnt - 1)].f[fin_id];
   cpx<R> acc[NR][12];
-  hop_part<L, DAG, T, NT>(d0.g, links_of<S>(d0), ld, site_ok ? it.s : 0, par, it.grp, acc);
+  if (any) hop_wave<L, DAG, T, NT>(d0.g, links_of<S>(d0), ld, site_ok ? it.s : 0, par, it.grp, acc);
+  else zero_acc<NR>(acc);
+  wave_combine<T, NR>(acc, it.slot, it.grp, lds);
+  if (!any) return;
   const R a = (R)coef(amode, d0.kappa);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -75,37 +79,47 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
   }
 }
 
+// The FP64 hops of the reliable update and the true residual: 4 waves per
+// item, directions summed in LDS.
+constexpr int T64 = 4;
+using Lds64 = HopLds<T64, 1, double>;
+
 // T64 = H_eo (XH + X): the hop of the current solution for the FP64 residual.
-template <bool HASLO, int T>
+template <bool HASLO>
 __global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork) {
-  const Item it = fetch_item<T>(work, nwork);
-  if (!it.active) return;
+  __shared__ Lds64::V lds[Lds64::VECS];
+  const Item it = fetch_item<T64>(work, nwork);
   const SysDesc &d = sdesc[it.sys];
-  if (!(d.st->status & ST_UPDATE)) return;
-  const bool site_ok = it.s < d.g.vh;
+  const bool on = it.active && (d.st->status & ST_UPDATE);
+  const bool site_ok = on && it.s < d.g.vh;
   cpx<double> acc[1][12];
   SumLd ld{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
-  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
+  if (on) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
+  else zero_acc<1>(acc);
+  wave_combine<T64, 1>(acc, it.slot, it.grp, lds);
   if (site_ok && it.grp == 0) SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc[0]);
 }
 
 // Reliable update on the odd sites: y = XH + X; XH = y; X = 0;
 // r_hat = BH - (y - kappa^2 H_oe T64) in FP64; R = r_hat rounded to the iterate
 // precision; reduces ||r_hat||^2 (and (rt | r_hat) for BiCGStab).
-template <int SO, bool HASLO, bool BICG, int T>
+template <int SO, bool HASLO, bool BICG>
 __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork) {
   using RO = typename SpinorIO<SO>::R;
-  const Item it = fetch_item<T>(work, nwork);
-  if (!it.active) return;
+  __shared__ Lds64::V lds[Lds64::VECS];
+  const Item it = fetch_item<T64>(work, nwork);
   const SysDesc &d = sdesc[it.sys];
-  if (!(d.st->status & ST_UPDATE)) return;
-  const bool site_ok = it.s < d.g.vh;
+  const bool on = it.active && (d.st->status & ST_UPDATE);
+  const bool site_ok = on && it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
   cpx<double> acc1[1][12];
   FieldLd<S_F64, 1> ld{{d.f[F_T64]}, d.npad};
-  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc1);
+  if (on) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc1);
+  else zero_acc<1>(acc1);
+  wave_combine<T64, 1>(acc1, it.slot, it.grp, lds);
+  if (!on) return;
   cpx<double> *acc = acc1[0];
   if (site_ok && it.grp == 0) {
     cpx<double> y[12], b[12];
@@ -134,22 +148,24 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
       dot12(rtd, acc, v[1], v[2]);
     }
   }
-  sys_partial<T>(d, SL_UPD, it, v);
+  sys_partial<T64>(d, SL_UPD, it, v);
 }
 
 // ||b - D x||^2 on the sites of parity p: B_p - X_p + kappa H X_{1-p}.
-template <int T>
 __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork, int par) {
-  const Item it = fetch_item<T>(work, nwork);
-  if (!it.active) return;
+  __shared__ Lds64::V lds[Lds64::VECS];
+  const Item it = fetch_item<T64>(work, nwork);
   const SysDesc &d = sdesc[it.sys];
   const int fin_id = par ? F_XE : F_XH, fb = par ? F_BO : F_BE, fx = par ? F_XH : F_XE;
-  const bool site_ok = it.s < d.g.vh;
+  const bool site_ok = it.active && it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
   cpx<double> acc1[1][12];
   FieldLd<S_F64, 1> ld{{d.f[fin_id]}, d.npad};
-  hop_part<L_F64R18, false, T>(d.g, d.g64, ld, site_ok ? it.s : 0, par, it.grp, acc1);
+  if (it.active) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, par, it.grp, acc1);
+  else zero_acc<1>(acc1);
+  wave_combine<T64, 1>(acc1, it.slot, it.grp, lds);
+  if (!it.active) return;
   cpx<double> *acc = acc1[0];
   if (site_ok && it.grp == 0) {
     cpx<double> x[12], b[12];
@@ -159,7 +175,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
     for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], x[k]), cscale(d.kappa, acc[k]));
     v[0] = norm12(acc);
   }
-  sys_partial<T>(d, par ? SL_RES_O : SL_RES_E, it, v);
+  sys_partial<T64>(d, par ? SL_RES_O : SL_RES_E, it, v);
 }
 
 // Sum a system's partials of one reduction slot and run the solver's scalar
@@ -170,29 +186,43 @@ constexpr int RED_WG = 1024;
 __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int tmul, int fin,
                                                    int mask) {
   const SysDesc &d = sdesc[blockIdx.x];
-  if (!(d.st->status & mask)) return;
+  const int status = d.st->status;   // tested after the partials' loads are issued
   const int np = d.g.nb * tmul;
   const double *p = d.part + (size_t)slot * NV * (d.g.nb * 4);
   __shared__ double red[NV][RED_WG / WAVE];
   const int tid = threadIdx.x, w = tid >> 6;
   const int npair = np >> 1;
+  const double2 *q[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) q[i] = (const double2 *)(p + (size_t)i * d.g.nb * 4);   // 32-byte aligned rows
+  // Pairs k, k + RED_WG, ... of every row.  The loads of a step (4 pairs of all
+  // rows) are issued together: the partials were just written by other compute
+  // units, so each round trip costs a full memory latency.
+  double a[NV][4];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[i][j] = 0.0;
+  for (int k0 = tid; k0 < npair; k0 += 4 * RED_WG) {
+    double2 x[NV][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + j * RED_WG;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) x[i][j] = k < npair ? q[i][k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[i][j] += x[i][j].x + x[i][j].y;
+  }
+  if (!(status & mask)) return;   // uniform over the work-group
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    const double *q = p + (size_t)i * d.g.nb * 4;   // 32-byte aligned rows
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = tid;
-    // pairs k, k + RED_WG, ... ; four independent loads in flight per step
-    for (; k + 3 * RED_WG < npair; k += 4 * RED_WG) {
-      const double2 x0 = ((const double2 *)q)[k];
-      const double2 x1 = ((const double2 *)q)[k + RED_WG];
-      const double2 x2 = ((const double2 *)q)[k + 2 * RED_WG];
-      const double2 x3 = ((const double2 *)q)[k + 3 * RED_WG];
-      a0 += x0.x + x0.y; a1 += x1.x + x1.y; a2 += x2.x + x2.y; a3 += x3.x + x3.y;
-    }
-    for (; k < npair; k += RED_WG) { const double2 x0 = ((const double2 *)q)[k]; a0 += x0.x + x0.y; }
-    if (tid == 0 && (np & 1)) a0 += q[np - 1];
-    double a = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane_id() == 0) red[i][w] = a;
+    double s = (a[i][0] + a[i][1]) + (a[i][2] + a[i][3]);
+    if (tid == 0 && (np & 1)) s += ((const double *)q[i])[np - 1];
+    s = wave_sum(s);
+    if (lane_id() == 0) red[i][w] = s;
   }
   __syncthreads();
   if (tid == 0) {
@@ -437,31 +467,26 @@ void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int f
   if (red) reduce(l, slot, lp.T, fin, mask);
 }
 
-template <int T> static void hop_sum_t(const Launch &l, bool haslo) {
-  if (haslo) hipLaunchKernelGGL((k_hop_sum<true, T>), grid_of(l.nwork, T), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
-  else hipLaunchKernelGGL((k_hop_sum<false, T>), grid_of(l.nwork, T), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
-}
 void hop_sum(const Launch &l, bool haslo) {
-  hop_sum_t<4>(l, haslo);
+  const dim3 g = grid_of(l.nwork, T64), b(WG);
+  if (haslo) hipLaunchKernelGGL((k_hop_sum<true>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_hop_sum<false>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
 }
 
-template <int T> static void hop_upd_t(const Launch &l, int prec, bool bicg) {
-  const dim3 g = grid_of(l.nwork, T), b(WG);
-#define QU(SO, LO, BI) hipLaunchKernelGGL((k_hop_upd<SO, LO, BI, T>), g, b, 0, l.stream, l.desc, l.work, l.nwork)
+void hop_upd(const Launch &l, int prec, bool bicg) {
+  const dim3 g = grid_of(l.nwork, T64), b(WG);
+#define QU(SO, LO, BI) hipLaunchKernelGGL((k_hop_upd<SO, LO, BI>), g, b, 0, l.stream, l.desc, l.work, l.nwork)
   if (prec == S_F64) { if (bicg) QU(S_F64, false, true); else QU(S_F64, false, false); }
   else if (prec == S_F32) { if (bicg) QU(S_F32, true, true); else QU(S_F32, true, false); }
   else { if (bicg) QU(S_F16S, true, true); else QU(S_F16S, true, false); }
 #undef QU
-}
-void hop_upd(const Launch &l, int prec, bool bicg) {
-  hop_upd_t<4>(l, prec, bicg);
-  reduce(l, SL_UPD, 4, FIN_UPDATE, ST_UPDATE);
+  reduce(l, SL_UPD, T64, FIN_UPDATE, ST_UPDATE);
 }
 
 void hop_res(const Launch &l, int par) {
-  const dim3 g = grid_of(l.nwork, 4), b(WG);
-  hipLaunchKernelGGL(k_hop_res<4>, g, b, 0, l.stream, l.desc, l.work, l.nwork, par);
-  reduce(l, par ? SL_RES_O : SL_RES_E, 4, FIN_NONE, ST_ANY);
+  const dim3 g = grid_of(l.nwork, T64), b(WG);
+  hipLaunchKernelGGL(k_hop_res, g, b, 0, l.stream, l.desc, l.work, l.nwork, par);
+  reduce(l, par ? SL_RES_O : SL_RES_E, T64, FIN_NONE, ST_ANY);
 }
 
 void bnorm(const Launch &l) {

@@ -155,3 +155,22 @@ def test_batched_point_sources_split2(nr, monkeypatch):
         xs = host(x)
         for r in range(5):
             assert S.true_rel_residual(U, 0.12, 0.0, xs[r], b[r]) <= 1e-10
+
+
+def test_block_order_solve_bitwise(monkeypatch):
+    """Solves whose hops run in the z-tiled block order equal those in the plain
+    order bit for bit (partials are indexed by block, not by visit order)."""
+    dims = (8, 16, 8, 8)
+    say("block order solve")
+    cfg = latgen.small_config(dims, seed=54, kind="expih", eps=0.3, nrhs=3)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    for prec, nrhs in ((q.F64, 1), (q.F32, 1), (q.F32, 3), (q.F16S, 3)):
+        res = []
+        for order in ("0", "2"):
+            monkeypatch.setenv("QIRAL_HOP_ORDER", order)
+            x, st, info = lat.solve(dev(cfg["b"][:nrhs]), tol=1e-10, inner_prec=prec)
+            assert st == 0, info
+            res.append((x, [i["iterations"] for i in info]))
+        assert torch.equal(res[0][0], res[1][0]) and res[0][1] == res[1][1], (prec, nrhs)
+    for r in range(3):
+        assert S.true_rel_residual(cfg["U"], 0.12, 0.0, host(res[1][0])[r], cfg["b"][r]) <= 1e-10
