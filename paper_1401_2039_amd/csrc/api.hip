@@ -250,8 +250,8 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
   const long nitems = nb * ((nrhs + c.nr - 1) / c.nr);
   c.t = hop_split(prec, nitems);
   const int tt = lat->tuned_t[prec][nrhs < 4 ? nrhs : 4];
-  if (tt && !getenv("QIRAL_HOP_SPLIT") && !(prec == QIRAL_F64 && tt != 4)) c.t = tt;
-  if (c.nr > hop_nr_max(prec, c.t)) c.t = 4;
+  if (tt && !getenv("QIRAL_HOP_SPLIT") && hop_nr_max(prec, tt) >= 1) c.t = tt;
+  if (c.nr > hop_nr_max(prec, c.t)) c.t = (c.t == 1 && c.nr <= hop_nr_max(prec, 2)) ? 2 : 4;
   return c;
 }
 
@@ -287,7 +287,7 @@ int hop_tile(const Geo &g, int ngroups) {
 int hop_split(int prec, long nwork) {
   if (const char *e = getenv("QIRAL_HOP_SPLIT")) {
     const int t = atoi(e);
-    if (t == 4 || (t == 2 && prec != QIRAL_F64)) return t;
+    if (t == 4 || (t == 2 && prec != QIRAL_F64) || (t == 1 && prec == QIRAL_F16S)) return t;
   }
   // A whole site per lane needs ~256 VGPRs (one wave per SIMD) and the FP64
   // hop spills below 4 lanes per site, so the split is 4 (FP64, and lattices
@@ -329,12 +329,16 @@ static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int
 template <int S, int L, int T>
 static hipError_t launch_hop_n(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
                                const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
-  constexpr int NM = hop_nr_max(S, T);
-  if (c.nr > NM) return hipErrorInvalidValue;   // excluded by hop_config and the tuner
-  if constexpr (NM >= 4) if (c.nr == 4) return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  if constexpr (NM >= 3) if (c.nr == 3) return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  if constexpr (NM >= 2) if (c.nr == 2) return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  constexpr int NM = hop_nr_max(S, T);   // shapes beyond it are excluded by hop_config and the tuner
+  if constexpr (NM == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (c.nr > NM) return hipErrorInvalidValue;
+    if constexpr (NM >= 4) if (c.nr == 4) return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    if constexpr (NM >= 3) if (c.nr == 3) return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    if constexpr (NM >= 2) if (c.nr == 2) return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+  }
 }
 
 template <int S, int L>
@@ -343,6 +347,7 @@ static hipError_t launch_hop_t(const HopCfg &c, const qiral_lattice *lat, int da
   if constexpr (S == S_F64) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
   else {
     if (c.t == 4) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    if (c.t == 1) return launch_hop_n<S, L, 1>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
     return launch_hop_n<S, L, 2>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
   }
 }

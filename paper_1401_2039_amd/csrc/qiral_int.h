@@ -44,9 +44,12 @@ const void *links_for(const qiral_lattice *lat, int prec);
 // QIRAL_HOP_NR override.
 struct HopCfg { int t = 4, nr = 1; };
 // Largest number of right-hand sides per lane that a hop of storage precision
-// S with T lanes per site keeps in registers (FP64 spills at 2, FP32 on 2 lanes
-// per site at 3).
-constexpr int hop_nr_max(int S, int T) { return S == 0 ? 1 : (S == 1 && T == 2) ? 2 : 4; }
+// S with T waves per site block keeps in registers; 0: the split is not built
+// (FP64 needs T = 4; one wave per block fits only the F16S hop with one RHS;
+// FP32 on 2 waves per block spills at 3 RHS).
+constexpr int hop_nr_max(int S, int T) {
+  return S == 0 ? (T == 4 ? 1 : 0) : T == 1 ? (S == 2 ? 1 : 0) : (S == 1 && T == 2) ? 2 : 4;
+}
 int hop_split(int prec, long nwork);
 // Streaming (non-temporal) link loads and output stores for hops whose working
 // set exceeds half the last-level cache.  QIRAL_HOP_NT=0|1 overrides.

@@ -143,6 +143,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   HopCfg hc;
   if (same_lattice) hc = hop_config(sys[0].lat, prec, nsys);
   else { hc.nr = 1; hc.t = hop_split(prec, nwork); }
+  if (hc.t == 1) hc.t = 2;   // the solver's hop kernel carries more state: one wave per block spills
   std::vector<uint32_t> work, work_hop;
   work.reserve(nwork);
   for (int i = 0; i < nsys; ++i)

@@ -435,10 +435,12 @@ static void hop_sys_n(const Launch &l, bool dag, int epi, int fi, int fo, int fx
                       int slot) {
   // l.NR never exceeds hop_nr_max(S, T): the solver takes (T, NR) from hop_config.
   constexpr int NM = hop_nr_max(S, T);
-  if constexpr (NM >= 4) if (l.NR == 4) return hop_sys_t<S, L, T, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  if constexpr (NM >= 3) if (l.NR == 3) return hop_sys_t<S, L, T, 3>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  if constexpr (NM >= 2) if (l.NR == 2) return hop_sys_t<S, L, T, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  if constexpr (NM > 0) {
+    if constexpr (NM >= 4) if (l.NR == 4) return hop_sys_t<S, L, T, 4>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+    if constexpr (NM >= 3) if (l.NR == 3) return hop_sys_t<S, L, T, 3>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+    if constexpr (NM >= 2) if (l.NR == 2) return hop_sys_t<S, L, T, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+    hop_sys_t<S, L, T, 1>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
+  }
 }
 
 template <int S, int L>

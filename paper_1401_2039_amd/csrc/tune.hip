@@ -90,8 +90,7 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
   const std::string key = cache_key(lat, prec, nrhs);
   int t = 0, nr = 0;
   double us = 0.0;
-  if (cache_lookup(key, t, nr) && (t == 2 || t == 4) && nr >= 1 && nr <= hop_nr_max(prec, t) &&
-      !(prec == QIRAL_F64 && t != 4)) {
+  if (cache_lookup(key, t, nr) && (t == 1 || t == 2 || t == 4) && nr >= 1 && nr <= hop_nr_max(prec, t)) {
     lat->tuned_t[prec][idx] = t;
     lat->tuned_nr[prec][idx] = nr;
   } else {
@@ -108,8 +107,7 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
     (void)hipEventCreate(&e1);
     double best = 1e30;
     const int nrmax = prec == QIRAL_F64 ? 1 : 4;
-    for (int tt : {2, 4}) {
-      if (prec == QIRAL_F64 && tt != 4) continue;
+    for (int tt : {1, 2, 4}) {
       for (int n = 1; n <= std::min(std::min(nrmax, hop_nr_max(prec, tt)), (int)nrhs); ++n) {
         HopCfg c;
         c.t = tt;

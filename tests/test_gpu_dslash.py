@@ -159,8 +159,9 @@ def _r12_near(U, x):
 
 @pytest.mark.parametrize("prec", [q.F32, q.F16S], ids=["f32", "f16s"])
 def test_launch_shapes_multi_rhs(prec, monkeypatch):
-    """Every hop launch shape (2 or 4 lanes per site, 1..4 right-hand sides per
-    lane, including a last group with fewer) gives the oracle's result."""
+    """Every hop launch shape (1 (F16S), 2 or 4 waves per site block, 1..4
+    right-hand sides per lane, including a last group with fewer) gives the
+    oracle's result; shapes a precision does not build fall back to a built one."""
     dims = (6, 4, 2, 4)
     say("launch shapes", prec)
     cfg = latgen.small_config(dims, seed=50, kind="expih", eps=0.4, nrhs=5)
@@ -172,7 +173,7 @@ def test_launch_shapes_multi_rhs(prec, monkeypatch):
         Ur, br = storage.round_links_r12(U, "f16"), storage.round_f16s(b)
     src = lat.import_field(dev(b), q.ODD, prec)
     want = [W.hop_eo(Ur, br[r], 0) for r in range(5)]
-    for t in (2, 4):
+    for t in (1, 2, 4):
         for nr in (1, 2, 3, 4):
             monkeypatch.setenv("QIRAL_HOP_SPLIT", str(t))
             monkeypatch.setenv("QIRAL_HOP_NR", str(nr))
