@@ -118,6 +118,53 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
   const int par = (int)(gid / npad), s = (int)(gid % npad);
   if (s >= g.vh) return;
   const SiteC c = site_c(g, s, par);
+  if constexpr (COUT == 1 && CIN > 1) {
+    // Spin weights commute with the colour transport: per path, mix the CIN
+    // input channels at the neighbour, then transport once.
+    cpx<float> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cmake(0.f, 0.f);
+#pragma unroll 1
+    for (int p = 0; p < NPATH; ++p) {
+      int mu = 0, n = s, lp = par;
+      bool fwd = true;
+      if (p > 0) {
+        path_of(p, mu, fwd);
+        n = nbr(g, c, mu, fwd);
+        lp = 1 - par;
+      }
+      cpx<float> m[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) m[k] = cmake(0.f, 0.f);
+#pragma unroll 1
+      for (int j = 0; j < CIN; ++j) {
+        cpx<float> psi[12];
+        SpinorIO<S_F32>::load((const char *)in + j * fstride + lp * hb, n, npad, psi);
+        const float2 *W = sw + (p * CIN + j) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const cpx<float> wr = cmake(W[4 * r + q].x, W[4 * r + q].y);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) m[4 * a + r] = cadd(m[4 * a + r], cmul(wr, psi[4 * a + q]));
+          }
+      }
+      if (p == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cadd(acc[k], m[k]);
+      } else {
+        cpx<float> u[9], t[12];
+        if (fwd) LinkIO<L_F32R12>::load(links, par, mu, c.s, g.nb, u);
+        else LinkIO<L_F32R12>::load(links, 1 - par, mu, n, g.nb, u);
+        transport(u, m, t, !fwd);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cadd(acc[k], t[k]);
+      }
+    }
+    SpinorIO<S_F32>::store((char *)out + par * hb, s, npad, acc);
+    return;
+  }
 #pragma unroll 1
   for (int i0 = 0; i0 < COUT; i0 += CI) {
     cpx<float> acc[CI][12];
@@ -367,16 +414,26 @@ __global__ __launch_bounds__(256) void k_mdot(const double2 *__restrict__ V, siz
   }
 }
 
-// coef[q] = sum of the k partial pairs (one thread per coefficient, index order).
-__global__ void k_mdot_final(const double *__restrict__ part, int nblk, int k, double2 *__restrict__ coef) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= k) return;
+// coef[q] = sum of the partial pairs of coefficient q, one work-group per q
+// (grid = k): strided sums, then a fixed-order wave and work-group reduction.
+__global__ __launch_bounds__(256) void k_mdot_final(const double *__restrict__ part, int nblk,
+                                                    double2 *__restrict__ coef) {
+  __shared__ double red[2][4];
+  const int q = blockIdx.x;
+  const double *pq = part + (size_t)q * nblk * 2;
   double re = 0.0, im = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    re += part[((size_t)q * nblk + b) * 2];
-    im += part[((size_t)q * nblk + b) * 2 + 1];
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const double2 v = ((const double2 *)pq)[b];
+    re += v.x;
+    im += v.y;
   }
-  coef[q] = make_double2(re, im);
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    coef[q] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                           (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
 }
 
 // w += sign * sum_q coef[q] V_q
@@ -832,7 +889,7 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
       std::vector<C> h(j + 2, C(0));
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, Wv, n2, part);
-        hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, s, part, nbk, j + 1, coef);
+        hipLaunchKernelGGL(k_mdot_final, dim3(j + 1), dim3(256), 0, s, part, nbk, coef);
         hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, coef, -1.0, Wv, n2);
         std::vector<double2> c(j + 1);
         QIRAL_HIP(hipMemcpyAsync(c.data(), coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
