@@ -100,8 +100,10 @@ size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec 
  * into an FP64 reconstruct-18 store and, for each bit of lo_precs, a
  * reduced-precision store (FP32 or FP16 links, lo_recon = 12 keeps rows 0 and 1
  * and rebuilds row 2 = conj(row0 x row1), exact for SU(3)).  gauge_canon may be
- * freed once the call returns.  kappa is the hopping parameter of Fig. "dirac";
- * mu is its twisted-mass parameter: mu != 0 returns QIRAL_ERR_UNSUPPORTED. */
+ * freed once the call returns.  kappa is the hopping parameter and mu the
+ * twisted-mass parameter of the operator of Fig. "dirac",
+ *   D = A - kappa H,   A = 1 + 2 i kappa mu g5   (A = 1 for mu = 0);
+ * every operator, solve and true residual on the handle uses this D. */
 qiral_status qiral_lattice_create(qiral_lattice **lat, const int32_t dims[4], double kappa, double mu,
                                   const double *gauge_canon, uint32_t lo_precs, qiral_recon lo_recon,
                                   qiral_stream_t stream);
@@ -129,12 +131,16 @@ qiral_status qiral_dslash_eo(const qiral_lattice *lat, void *out, const void *in
 
 /* out = op(in) for packed fields of precision prec: FULL fields for OP_D/OP_DDAG,
  * ODD half-fields for OP_SCHUR/OP_SCHUR_DAG.  tmp is an EVEN half-field of the
- * same precision and nrhs (used by the Schur ops; may be NULL for D/D^dagger). */
+ * same precision and nrhs (used by the Schur ops; may be NULL for D/D^dagger).
+ * The Schur complement on the odd sites (template "schur") is
+ *   S = A - kappa^2 H_oe A^-1 H_eo,   A^-1 = (1 - 2 i kappa mu g5) / (1 + 4 kappa^2 mu^2),
+ * and S^dagger = A^dagger - kappa^2 H_oe^dagger A^-dagger H_eo^dagger. */
 qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, void *tmp, qiral_op op,
                            qiral_prec prec, int32_t nrhs, qiral_stream_t stream);
 
 /* Autotune the hop's launch shape for this lattice, precision and number of
- * right-hand sides (lanes per site 2 or 4, right-hand sides per lane 1..4) by
+ * right-hand sides (waves per 64-site block 1 (F16S only), 2 or 4 (FP64: 4 only);
+ * right-hand sides per lane 1..4, FP64 1, FP32 on 2 waves 1..2, 1 wave 1) by
  * timing each candidate on the stream; later hops and solves on this handle use
  * the fastest.  If the environment variable QIRAL_TUNE_CACHE names a file, the
  * result is looked up there first and stored there (JSON).  Allocates and frees
@@ -167,8 +173,11 @@ typedef struct {
   int64_t hop_applications;  /* H_eo / H_oe applications (units of V/2 sites)       */
 } qiral_solve_info;
 
-/* Solve D x = b for nrhs right-hand sides on one lattice.  x_canon and b_canon are
- * canonical full fields (device); info points to nrhs host structs.  Blocking:
+/* Solve D x = b for nrhs right-hand sides on one lattice.  The Krylov solvers run
+ * on the Schur system S x_o = b_hat of the odd sites, b_hat = b_o + kappa H_oe
+ * A^-1 b_e, and rebuild x_e = A^-1 (b_e + kappa H_eo x_o) (template "schur").
+ * x_canon and b_canon are canonical full fields (device); info points to nrhs
+ * host structs.  Blocking:
  * returns after the stream has drained.  Returns QIRAL_ERR_NOT_CONVERGED if any
  * right-hand side missed the tolerance. */
 qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,

@@ -133,14 +133,16 @@ def qiral_solve_batch(handles, dims_list, xs, bs, params, stream=None):
 
 
 class Lattice:
-    """A lattice handle: dims, kappa and packed links on the current CUDA device."""
+    """A lattice handle: dims, kappa, twisted mass mu and packed links on the
+    current CUDA device."""
 
-    def __init__(self, dims, kappa, gauge, lo_precs=L.LINKS_F32 | L.LINKS_F16, device="cuda"):
+    def __init__(self, dims, kappa, gauge, lo_precs=L.LINKS_F32 | L.LINKS_F16, device="cuda", mu=0.0):
         self.dims = tuple(int(d) for d in dims)
         self.kappa = float(kappa)
+        self.mu = float(mu)
         g = gauge if isinstance(gauge, torch.Tensor) else torch.from_numpy(gauge)
         g = g.to(device=device, dtype=torch.complex128).contiguous()
-        self.handle = qiral_lattice_create(self.dims, self.kappa, g, lo_precs)
+        self.handle = qiral_lattice_create(self.dims, self.kappa, g, lo_precs, mu=self.mu)
 
     def close(self):
         if self.handle:

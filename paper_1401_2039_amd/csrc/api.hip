@@ -192,7 +192,8 @@ template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, const void *__restrict__ gauge,
                                                              const void *__restrict__ in, void *__restrict__ out,
                                                              const void *__restrict__ xin, size_t fstride, int nrhs,
-                                                             int p, double a, int tile, int zb) {
+                                                             int p, double a, int tile, int zb, int chio, int chix,
+                                                             double tmu) {
   using R = typename SpinorIO<S>::R;
   using LDS = HopLds<T, NR, R>;
   __shared__ typename LDS::V lds[LDS::VECS];
@@ -232,9 +233,11 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop(Geo g, cons
     } else {
       cpx<R> xv[12];
       SpinorIO<S>::load((const char *)xin + (size_t)(r0 + r) * fstride, s, npad, xv);
+      apply_chi(xv, chix, tmu);
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(ar, acc[r][k]));
     }
+    apply_chi(acc[r], chio, tmu);
     SpinorIO<S>::template store_fast<NT>((char *)out + (size_t)(r0 + r) * fstride, s, npad, acc[r]);
   }
 }
@@ -299,8 +302,9 @@ int hop_split(int prec, long nwork) {
 
 template <int S, int L, int T, int NR, bool NT>
 static hipError_t launch_hop_ttt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
-                                 void *out, const void *x, int nrhs, hipStream_t st) {
+                                 void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
   const Geo &g = lat->geo;
+  const double tmu = 2.0 * lat->kappa * lat->mu;
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
   const int tile = hop_tile(g, (nrhs + NR - 1) / NR);
@@ -310,58 +314,58 @@ static hipError_t launch_hop_ttt(const qiral_lattice *lat, int dagger, int p, in
   const int nwg = (int)((nitems * T + 3) / 4);
   dim3 grid(nwg), block(WG);
   if (!dagger) {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
-    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, false, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb, chio, chix, tmu);
+    else hipLaunchKernelGGL((k_hop<S, L, false, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb, chio, chix, tmu);
   } else {
-    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
-    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb);
+    if (epi == 0) hipLaunchKernelGGL((k_hop<S, L, true, 0, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb, chio, chix, tmu);
+    else hipLaunchKernelGGL((k_hop<S, L, true, 1, T, NR, NT>), grid, block, 0, st, g, gauge, in, out, x, fstride, nrhs, p, a, tile, zb, chio, chix, tmu);
   }
   return hipGetLastError();
 }
 
 template <int S, int L, int T, int NR>
 static hipError_t launch_hop_tt(const qiral_lattice *lat, int dagger, int p, int epi, double a, const void *in,
-                                void *out, const void *x, int nrhs, hipStream_t st) {
-  if (hop_stream(lat->geo, S, nrhs)) return launch_hop_ttt<S, L, T, NR, true>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  return launch_hop_ttt<S, L, T, NR, false>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+                                void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
+  if (hop_stream(lat->geo, S, nrhs)) return launch_hop_ttt<S, L, T, NR, true>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+  return launch_hop_ttt<S, L, T, NR, false>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
 }
 
 template <int S, int L, int T>
 static hipError_t launch_hop_n(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
-                               const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
+                               const void *in, void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
   constexpr int NM = hop_nr_max(S, T);   // shapes beyond it are excluded by hop_config and the tuner
   if constexpr (NM == 0) {
     return hipErrorInvalidValue;
   } else {
     if (c.nr > NM) return hipErrorInvalidValue;
-    if constexpr (NM >= 4) if (c.nr == 4) return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    if constexpr (NM >= 3) if (c.nr == 3) return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    if constexpr (NM >= 2) if (c.nr == 2) return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    if constexpr (NM >= 4) if (c.nr == 4) return launch_hop_tt<S, L, T, 4>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+    if constexpr (NM >= 3) if (c.nr == 3) return launch_hop_tt<S, L, T, 3>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+    if constexpr (NM >= 2) if (c.nr == 2) return launch_hop_tt<S, L, T, 2>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+    return launch_hop_tt<S, L, T, 1>(lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
   }
 }
 
 template <int S, int L>
 static hipError_t launch_hop_t(const HopCfg &c, const qiral_lattice *lat, int dagger, int p, int epi, double a,
-                               const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
-  if constexpr (S == S_F64) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+                               const void *in, void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
+  if constexpr (S == S_F64) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
   else {
-    if (c.t == 4) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    if (c.t == 1) return launch_hop_n<S, L, 1>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
-    return launch_hop_n<S, L, 2>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+    if (c.t == 4) return launch_hop_n<S, L, 4>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+    if (c.t == 1) return launch_hop_n<S, L, 1>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+    return launch_hop_n<S, L, 2>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
   }
 }
 
 hipError_t launch_hop_cfg(const HopCfg &c, const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a,
-                          const void *in, void *out, const void *x, int nrhs, hipStream_t st) {
-  if (prec == QIRAL_F64) return launch_hop_t<S_F64, L_F64R18>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  if (prec == QIRAL_F32) return launch_hop_t<S_F32, L_F32R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
-  return launch_hop_t<S_F16S, L_F16R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st);
+                          const void *in, void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
+  if (prec == QIRAL_F64) return launch_hop_t<S_F64, L_F64R18>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+  if (prec == QIRAL_F32) return launch_hop_t<S_F32, L_F32R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
+  return launch_hop_t<S_F16S, L_F16R12>(c, lat, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
 }
 
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int p, int epi, double a, const void *in,
-                      void *out, const void *x, int nrhs, hipStream_t st) {
-  return launch_hop_cfg(hop_config(lat, prec, nrhs), lat, prec, dagger, p, epi, a, in, out, x, nrhs, st);
+                      void *out, const void *x, int nrhs, hipStream_t st, int chio, int chix) {
+  return launch_hop_cfg(hop_config(lat, prec, nrhs), lat, prec, dagger, p, epi, a, in, out, x, nrhs, st, chio, chix);
 }
 }  // namespace qiral
 
@@ -380,7 +384,6 @@ extern "C" qiral_status qiral_lattice_create(qiral_lattice **out, const int32_t 
     return fail(QIRAL_ERR_INVALID_ARG, "lo_precs may only hold QIRAL_LINKS_F32 and QIRAL_LINKS_F16");
   if (lo_recon != QIRAL_RECON12 && lo_recon != QIRAL_RECON18)
     return fail(QIRAL_ERR_INVALID_ARG, "lo_recon must be QIRAL_RECON12 or QIRAL_RECON18");
-  if (mu != 0.0) return fail(QIRAL_ERR_UNSUPPORTED, "twisted mass (mu != 0) is not implemented on the GPU");
   if (lo_precs && lo_recon != QIRAL_RECON12)
     return fail(QIRAL_ERR_UNSUPPORTED, "reduced-precision links are stored reconstruct-12 only");
 
@@ -559,15 +562,18 @@ extern "C" qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const
   if (op == QIRAL_OP_D || op == QIRAL_OP_DDAG) {
     // full fields: [rhs][even | odd]; handle one right-hand side per pair of launches
     const size_t hb = half_bytes(lat->geo, prec);
+    // D = A - kappa H (D^dagger = A^dagger - kappa H^dagger), A = 1 + 2 i kappa mu gamma_5
     for (int r = 0; r < nrhs; ++r) {
       const char *ie = (const char *)in + 2 * hb * r, *io = ie + hb;
       char *oe = (char *)out + 2 * hb * r, *oo = oe + hb;
-      QIRAL_HIP(launch_hop(lat, prec, dag, 0, 1, -k, io, oe, ie, 1, s));
-      QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k, ie, oo, io, 1, s));
+      const int ca = dag ? CHI_ADAG : CHI_A;
+      QIRAL_HIP(launch_hop(lat, prec, dag, 0, 1, -k, io, oe, ie, 1, s, CHI_ONE, ca));
+      QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k, ie, oo, io, 1, s, CHI_ONE, ca));
     }
   } else {
-    QIRAL_HIP(launch_hop(lat, prec, dag, 0, 0, 1.0, in, tmp, nullptr, nrhs, s));
-    QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k * k, tmp, out, in, nrhs, s));
+    // S = A - kappa^2 H_oe A^-1 H_eo (S^dagger: daggered hops and site factors)
+    QIRAL_HIP(launch_hop(lat, prec, dag, 0, 0, 1.0, in, tmp, nullptr, nrhs, s, dag ? CHI_AINVDAG : CHI_AINV, CHI_ONE));
+    QIRAL_HIP(launch_hop(lat, prec, dag, 1, 1, -k * k, tmp, out, in, nrhs, s, CHI_ONE, dag ? CHI_ADAG : CHI_A));
   }
   return QIRAL_OK;
 }

@@ -553,14 +553,14 @@ hipError_t nn_apply_dev(const qiral_nn *nn, void *out, const void *in, hipStream
   return layer_launch(nn, nn->w + nn->nw1, nn->hidden, 1, nn->act, out, s);
 }
 
-// D on a packed full field (out = in - kappa H in), precision prec
+// D on a packed full field (out = A in - kappa H in, A = 1 + 2 i kappa mu gamma_5), precision prec
 hipError_t apply_D_full(const qiral_lattice *lat, int prec, void *out, const void *in, hipStream_t s) {
   const size_t hb = half_bytes(lat->geo, prec);
   const char *ie = (const char *)in, *io = ie + hb;
   char *oe = (char *)out, *oo = oe + hb;
-  hipError_t e = launch_hop(lat, prec, 0, 0, 1, -lat->kappa, io, oe, ie, 1, s);
+  hipError_t e = launch_hop(lat, prec, 0, 0, 1, -lat->kappa, io, oe, ie, 1, s, CHI_ONE, CHI_A);
   if (e != hipSuccess) return e;
-  return launch_hop(lat, prec, 0, 1, 1, -lat->kappa, ie, oo, io, 1, s);
+  return launch_hop(lat, prec, 0, 1, 1, -lat->kappa, ie, oo, io, 1, s, CHI_ONE, CHI_A);
 }
 
 void neumann2(int hidden, double kappa, std::vector<float2> &w) {

@@ -562,6 +562,21 @@ __device__ __forceinline__ void wave_combine(cpx<R> acc[NF][12], int slot, int g
   }
 }
 
+// The site-diagonal part of the twisted-mass operator, A = 1 + i t gamma_5
+// with t = 2 kappa mu (gamma_5 = diag(1, 1, -1, -1) in the chiral basis), and
+// its dagger, inverse and inverse dagger act on a spinor as one complex factor
+// on the upper spins and its conjugate-sign partner on the lower ones.
+enum { CHI_ONE = 0, CHI_A = 1, CHI_ADAG = 2, CHI_AINV = 3, CHI_AINVDAG = 4 };
+
+template <class R> __device__ __forceinline__ void apply_chi(cpx<R> v[12], int mode, double t) {
+  if (mode == CHI_ONE || t == 0.0) return;
+  const double n = (mode == CHI_AINV || mode == CHI_AINVDAG) ? 1.0 / (1.0 + t * t) : 1.0;
+  const double sg = (mode == CHI_A || mode == CHI_AINVDAG) ? 1.0 : -1.0;
+  const cpx<R> cu = cmake((R)n, (R)(n * sg * t)), cl = cmake((R)n, (R)(-n * sg * t));
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = cmul((k & 3) < 2 ? cu : cl, v[k]);
+}
+
 template <int NF, class R> __device__ __forceinline__ void zero_acc(cpx<R> acc[NF][12]) {
 #pragma unroll
   for (int r = 0; r < NF; ++r)

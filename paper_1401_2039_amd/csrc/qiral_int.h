@@ -63,15 +63,18 @@ int hop_tile(const Geo &g, int ngroups);
 int tuned_nr(const qiral_lattice *lat, int prec, int nrhs);
 HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs);
 hipError_t launch_hop_cfg(const HopCfg &c, const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi,
-                          double a, const void *in, void *out, const void *x, int nrhs, hipStream_t s);
+                          double a, const void *in, void *out, const void *x, int nrhs, hipStream_t s,
+                          int chio = 0, int chix = 0);
 
 // Grid of ceil(nwaves / 4) work-groups (4 waves of 64 lanes each).
 inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }
 
 // Launchers implemented in api.hip (single lattice, nrhs consecutive fields).
-// epi = 0: out = a * H in;  epi = 1: out = x + a * H in.
+// epi = 0: out = C_o (a * H in);  epi = 1: out = C_o (C_x x + a * H in), where
+// C_o, C_x are the twisted-mass site factors selected by chio, chix (CHI_*;
+// the identity for CHI_ONE or mu = 0).
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi, double a,
-                      const void *in, void *out, const void *x, int nrhs, hipStream_t s);
+                      const void *in, void *out, const void *x, int nrhs, hipStream_t s, int chio = 0, int chix = 0);
 
 // Ensure the handle's workspace holds at least `bytes`.
 qiral_status ensure_workspace(qiral_lattice *lat, size_t bytes);

@@ -120,6 +120,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     memset(&d, 0, sizeof(d));
     d.g = lat->geo;
     d.kappa = lat->kappa;
+    d.tmu = 2.0 * lat->kappa * lat->mu;
     d.g64 = lat->g64;
     d.glo = links_for(lat, prec);
     d.npad = npad_of(lat->geo);
@@ -222,7 +223,15 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     QIRAL_HIP(hipMemsetAsync(d.f[F_AP], 0, half_bytes(g, prec), s));
   }
   bnorm(L);
-  hop_sys(L, S_F64, false, 1, F_BE, F_BH, F_BO, 1, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);   // b_hat
+  // b_hat = b_o + kappa H_oe A^-1 b_e (A = 1 without twisted mass)
+  bool twisted = false;
+  for (int i = 0; i < nsys; ++i) twisted = twisted || sys[i].lat->mu != 0.0;
+  if (twisted) {
+    copy_field(L, S_F64, F_BE, F_T64, ST_ANY, CHI_AINV);
+    hop_sys(L, S_F64, false, 1, F_T64, F_BH, F_BO, 1, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);
+  } else {
+    hop_sys(L, S_F64, false, 1, F_BE, F_BH, F_BO, 1, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);
+  }
   QIRAL_HIP(hipGetLastError());
 
   auto start_krylov = [&]() {
@@ -230,8 +239,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     hop_sum(L, mixed);
     hop_upd(L, prec, bicg);
     if (!bicg) {
-      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
-      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_NZ_INIT);
+      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
+      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_NZ_INIT, CHI_ONE, CHI_ADAG);
       cg2(L, prec);   // p = z (beta = 0, p = 0)
     } else {
       copy_field(L, prec, F_R, F_RT, ST_RUN);
@@ -240,20 +249,20 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   };
   auto iteration = [&]() {
     if (!bicg) {
-      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
-      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 1, SL_AP, FIN_ALPHA);
+      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
+      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 1, SL_AP, FIN_ALPHA, CHI_ONE, CHI_A);
       cg1(L, prec);
       if (mixed) { hop_sum(L, true); hop_upd(L, prec, false); }
-      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
-      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_BETA);
+      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
+      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_BETA, CHI_ONE, CHI_ADAG);
       cg2(L, prec);
     } else {
       bi_p(L, prec);
-      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
-      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 2, SL_BI1, FIN_BI_ALPHA);
+      hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
+      hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 2, SL_BI1, FIN_BI_ALPHA, CHI_ONE, CHI_A);
       bi_s(L, prec);
-      hop_sys(L, prec, false, 0, F_Z, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE);
-      hop_sys(L, prec, false, 1, F_TMP, F_T, F_Z, 1, A_MKAPPA2, ST_RUN, 3, SL_BI2, FIN_BI_OMEGA);
+      hop_sys(L, prec, false, 0, F_Z, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
+      hop_sys(L, prec, false, 1, F_TMP, F_T, F_Z, 1, A_MKAPPA2, ST_RUN, 3, SL_BI2, FIN_BI_OMEGA, CHI_ONE, CHI_A);
       bi_xr(L, prec);
       if (mixed) { hop_sum(L, true); hop_upd(L, prec, true); }
     }
@@ -310,7 +319,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
       if (enqueued > (long)prm->maxiter + 4l * chunk) break;   // device stops at maxiter; safety net
     }
     // reconstruct x_e, export, FP64 true residual
-    hop_sys(L, S_F64, false, 1, F_XH, F_XE, F_BE, 0, A_KAPPA, ST_ANY, 0, 0, FIN_NONE);
+    hop_sys(L, S_F64, false, 1, F_XH, F_XE, F_BE, 0, A_KAPPA, ST_ANY, 0, 0, FIN_NONE, CHI_AINV);   // x_e
     hop_res(L, 0);
     hop_res(L, 1);
     QIRAL_HIP(hipGetLastError());

@@ -52,6 +52,7 @@ struct SysState {
 struct SysDesc {
   Geo g;
   double kappa;
+  double tmu;         // 2 kappa mu: the twisted-mass site factor A = 1 + i tmu gamma_5
   const void *g64;    // FP64 links
   const void *glo;    // links in the iterate precision (== g64 for a plain solve)
   void *f[NF];

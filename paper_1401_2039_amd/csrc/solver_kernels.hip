@@ -16,9 +16,10 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
   return S == S_F64 ? d.g64 : d.glo;
 }
 
-// out = a H in (EPI 0) or out = x + a H in (EPI 1), parity `par` out, for the
-// (up to NR) systems of a grouped work item (they share the lattice, so each
-// link is loaded once for all of them).
+// out = C_o (a H in) (EPI 0) or out = C_o (C_x x + a H in) (EPI 1), parity
+// `par` out, for the (up to NR) systems of a grouped work item (they share the
+// lattice, so each link is loaded once for all of them).  C_o and C_x are the
+// twisted-mass site factors chio and chix (CHI_*).
 // red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
 // T waves per item (see hop_wave); padded lanes compute on site 0 and store
 // nothing.  Every wave reaches wave_combine's barrier.
@@ -26,7 +27,7 @@ template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
 __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const SysDesc *__restrict__ sdesc,
                                                                  const uint32_t *__restrict__ work, int nwork,
                                                                  int fin_id, int fout, int fx, int par, int amode,
-                                                                 int mask, int red, int slot) {
+                                                                 int mask, int red, int slot, int chio, int chix) {
   using R = typename SpinorIO<S>::R;
   using LDS = HopLds<T, NR, R>;
   __shared__ typename LDS::V lds[LDS::VECS];
@@ -60,11 +61,17 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
       if (EPI == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[r][k] = cscale(a, acc[r][k]);
+        apply_chi(acc[r], chio, d0.tmu);
       } else {
         cpx<R> xv[12];
         SpinorIO<S>::load(d.f[fx], it.s, npad, xv);
+        cpx<R> ax[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[r][k] = cadd(xv[k], cscale(a, acc[r][k]));
+        for (int k = 0; k < 12; ++k) ax[k] = xv[k];
+        apply_chi(ax, chix, d0.tmu);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r][k] = cadd(ax[k], cscale(a, acc[r][k]));
+        apply_chi(acc[r], chio, d0.tmu);
         if (red == 3) { dot12(acc[r], xv, v[0], v[1]); v[2] = norm12(acc[r]); }
       }
       SpinorIO<S>::template store_fast<NT>(d.f[fout], it.s, npad, acc[r]);
@@ -84,7 +91,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
 constexpr int T64 = 4;
 using Lds64 = HopLds<T64, 1, double>;
 
-// T64 = H_eo (XH + X): the hop of the current solution for the FP64 residual.
+// T64 = A^-1 H_eo (XH + X): the hop of the current solution for the FP64 residual.
 template <bool HASLO>
 __global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork) {
@@ -98,11 +105,14 @@ __global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ s
   if (on) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
   else zero_acc<1>(acc);
   wave_combine<T64, 1>(acc, it.slot, it.grp, lds);
-  if (site_ok && it.grp == 0) SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc[0]);
+  if (site_ok && it.grp == 0) {
+    apply_chi(acc[0], CHI_AINV, d.tmu);
+    SpinorIO<S_F64>::store(d.f[F_T64], it.s, d.npad, acc[0]);
+  }
 }
 
 // Reliable update on the odd sites: y = XH + X; XH = y; X = 0;
-// r_hat = BH - (y - kappa^2 H_oe T64) in FP64; R = r_hat rounded to the iterate
+// r_hat = BH - (A y - kappa^2 H_oe T64) in FP64; R = r_hat rounded to the iterate
 // precision; reduces ||r_hat||^2 (and (rt | r_hat) for BiCGStab).
 template <int SO, bool HASLO, bool BICG>
 __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
@@ -133,6 +143,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
       SpinorIO<S_F32>::store(d.f[F_X], it.s, d.npad, z);
     }
     SpinorIO<S_F64>::load(d.f[F_BH], it.s, d.npad, b);
+    apply_chi(y, CHI_A, d.tmu);
     const double k2 = d.kappa * d.kappa;
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], y[k]), cscale(k2, acc[k]));
@@ -151,7 +162,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
   sys_partial<T64>(d, SL_UPD, it, v);
 }
 
-// ||b - D x||^2 on the sites of parity p: B_p - X_p + kappa H X_{1-p}.
+// ||b - D x||^2 on the sites of parity p: B_p - A X_p + kappa H X_{1-p}.
 __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                                 int nwork, int par) {
   __shared__ Lds64::V lds[Lds64::VECS];
@@ -171,6 +182,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
     cpx<double> x[12], b[12];
     SpinorIO<S_F64>::load(d.f[fx], it.s, d.npad, x);
     SpinorIO<S_F64>::load(d.f[fb], it.s, d.npad, b);
+    apply_chi(x, CHI_A, d.tmu);
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], x[k]), cscale(d.kappa, acc[k]));
     v[0] = norm12(acc);
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(WG) void k_bi_xr(const SysDesc *__restrict__ sdesc,
 // copy a half-field of the iterate precision: dst = src
 template <int S>
 __global__ __launch_bounds__(WG) void k_copy(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
-                                             int nwork, int fsrc, int fdst, int mask) {
+                                             int nwork, int fsrc, int fdst, int mask, int chi) {
   using R = typename SpinorIO<S>::R;
   const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
@@ -388,6 +400,7 @@ __global__ __launch_bounds__(WG) void k_copy(const SysDesc *__restrict__ sdesc, 
   if (it.s >= d.g.vh) return;
   cpx<R> a[12];
   SpinorIO<S>::load(d.f[fsrc], it.s, d.npad, a);
+  apply_chi(a, chi, d.tmu);
   SpinorIO<S>::store(d.f[fdst], it.s, d.npad, a);
 }
 
@@ -412,7 +425,7 @@ template <int S, int L, int T, int NR, bool NT>
 static void hop_sys_tt(const Launch &l, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
                        int red, int slot) {
   const dim3 g = grid_of(l.nwork, T), b(WG);
-#define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot
+#define QARGS l.desc, l.work, l.nwork, fi, fo, fx, par, amode, mask, red, slot, l.chio, l.chix
   if (!dag) {
     if (epi == 0) hipLaunchKernelGGL((k_hop_sys<S, L, false, 0, T, NR, NT>), g, b, 0, l.stream, QARGS);
     else hipLaunchKernelGGL((k_hop_sys<S, L, false, 1, T, NR, NT>), g, b, 0, l.stream, QARGS);
@@ -456,11 +469,13 @@ void reduce(const Launch &l, int slot, int tmul, int fin, int mask) {
 }
 
 void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
-             int red, int slot, int fin) {
+             int red, int slot, int fin, int chio, int chix) {
   // the iterate-precision hop walks the grouped table; an FP64 hop of a mixed
   // solve (source, reconstruction) walks the plain one
   const bool grouped = (prec == S_F64) == (l.prec == S_F64);
   Launch lp = l;
+  lp.chio = chio;
+  lp.chix = chix;
   if (grouped) { lp.work = l.work_hop; lp.nwork = l.nwork_hop; lp.T = l.T; lp.NR = l.NR; lp.NT = l.NT; }
   else { lp.T = 4; lp.NR = 1; lp.NT = l.NT64; }
   if (prec == S_F64) hop_sys_p<S_F64, L_F64R18>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
@@ -533,11 +548,11 @@ void bi_xr(const Launch &l, int prec) {
   reduce(l, SL_BI3, 1, FIN_BI_RHO, ST_RUN);
 }
 
-void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask) {
+void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask, int chi) {
   const dim3 g = grid_of(l.nwork), b(WG);
-  if (prec == S_F64) hipLaunchKernelGGL(k_copy<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
-  else if (prec == S_F32) hipLaunchKernelGGL(k_copy<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
-  else hipLaunchKernelGGL(k_copy<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask);
+  if (prec == S_F64) hipLaunchKernelGGL(k_copy<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask, chi);
+  else if (prec == S_F32) hipLaunchKernelGGL(k_copy<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask, chi);
+  else hipLaunchKernelGGL(k_copy<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork, fsrc, fdst, mask, chi);
 }
 
 void bi_init(const Launch &l, int nsys) {
