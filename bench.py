@@ -233,14 +233,15 @@ def _emit(rec, path):
             f.write(json.dumps(rec) + "\n")
 
 
-def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None):
+def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None, psi=None):
     """Average duration of one even-odd hop launch (HIP events on the launch stream):
-    warm (back to back) and, with a flush buffer, cold (the 256 MB last-level
-    cache overwritten before every launch)."""
+    warm (back to back) and, with a flush buffer, cold (median of single launches,
+    each after a 1 GiB read that replaces the 256 MB last-level cache's contents)."""
     import numpy as np
     import latgen
     vh = int(np.prod(dims)) // 2
-    psi = torch.from_numpy(latgen.gaussian_source(5, 0, dims, nrhs)).cuda()
+    if psi is None:
+        psi = torch.from_numpy(latgen.gaussian_source(5, 0, dims, nrhs)).cuda()
     src = lat.import_field(psi, q.ODD, prec)
     out = lat.field(q.EVEN, prec, nrhs)
     del psi
@@ -256,17 +257,18 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None):
     warm = e0.elapsed_time(e1) * 1e3 / reps
     cold = None
     if flush is not None:
-        tot = 0.0
-        n = max(5, reps // 10)
-        for _ in range(n):
-            flush.add_(1)
+        ts = []
+        for _ in range(max(11, reps // 5)):
+            # read 1 GiB: the caches then hold clean unrelated lines (a write
+            # would also leave 256 MB of dirty lines for the hop to write back)
+            flush.sum()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
             lat.dslash_eo(out, src, 0, 0, prec, nrhs)
             b.record(stream)
             b.synchronize()
-            tot += a.elapsed_time(b) * 1e3
-        cold = tot / n
+            ts.append(a.elapsed_time(b) * 1e3)
+        cold = float(np.median(ts))
     key = {q.F64: "f64", q.F32: "f32", q.F16S: "f16s"}[prec]
     link_b = {"f64": 144, "f32": 48, "f16s": 24}[key] * 8
     sp_b = {"f64": 192, "f32": 96, "f16s": 52}[key]
@@ -321,6 +323,8 @@ def suite(lat1, q, latgen, np, torch, path=None, parts=(), hop_reps=None):
         lat99.close()
     if "c4" in parts:
         suite_c4(q, latgen, torch, path, timed_solve)
+    if "c64" in parts:
+        suite_c64(q, latgen, torch, path, timed_solve, flush, hop_reps)
 
 
 def suite_c1(lat1, q, latgen, torch, path, timed_solve):
@@ -475,6 +479,69 @@ def suite_c4(q, latgen, torch, path, timed_solve):
            "fgmres_12rhs_s": round(t_nn, 4), "cgnr_f64_12rhs_s": round(tseq, 4),
            "break_even_solves_of_12": (round(t_train / gain, 2) if gain > 0 else None)}, path)
     net.close()
+    lat.close()
+
+
+def suite_c64(q, latgen, torch, path, timed_solve, flush, hop_reps=None):
+    """The paper's largest lattice, 64^3x128 (the 32^3x64 exp(0.3 i H) links tiled
+    2x2x2x2), on one GPU: hop throughput of each storage class, the FP64 hop
+    checked on sampled sites against the oracle's single-site hop, and time to a
+    1e-10 true residual for plain FP64 eo-CGNR and the mixed forms."""
+    import time as _t
+    import numpy as np
+    from oracle import wilson as W
+    t0 = _t.perf_counter()
+    cfg = latgen.tiled_config()
+    dims, reps = cfg["dims"], cfg["reps"]
+    cell = torch.from_numpy(cfg["U_cell"]).cuda()
+    U = cell.repeat(reps[3], reps[2], reps[1], reps[0], 1, 1, 1)   # [t][z][y][x][mu][3][3]
+    del cell
+    lat = q.Lattice(dims, cfg["kappa"], U)
+    del U
+    b = latgen.device_gaussian_source(100, 0, dims, 1)
+    torch.cuda.synchronize()
+    log(f"[suite] 64^3x128 inputs and lattice in {_t.perf_counter() - t0:.1f}s")
+    for prec in (q.F64, q.F32, q.F16S):
+        _emit(hop_rates(q, lat, dims, torch, prec, reps=hop_reps or 20, flush=flush, psi=b), path)
+    # sampled-site parity of the FP64 hop (links read through the tiling)
+    class Tiled:
+        def __init__(self, u, cdims):
+            self.u, self.c = u, cdims
+
+        def __getitem__(self, i):
+            t, z, y, x = i[0] % self.c[3], i[1] % self.c[2], i[2] % self.c[1], i[3] % self.c[0]
+            return self.u[(t, z, y, x) + tuple(i[4:])]
+    class DevField:   # reads the device source one site at a time
+        def __init__(self, f):
+            self.f, self.shape = f, tuple(f.shape)
+
+        def __getitem__(self, i):
+            return self.f[i].cpu().numpy()
+    Ut = Tiled(cfg["U_cell"], cfg["cell_dims"])
+    bsrc = DevField(b[0])
+    src = lat.import_field(b, q.ODD, q.F64)
+    out = lat.field(q.EVEN, q.F64)
+    lat.dslash_eo(out, src, 0, 0, q.F64)
+    got = lat.export_field(out, q.EVEN, q.F64)
+    rng = np.random.default_rng(64)
+    worst = 0.0
+    for _ in range(24):
+        x = [int(rng.integers(0, L)) for L in dims]
+        x[0] = (x[0] & ~1) | ((x[1] + x[2] + x[3]) & 1)   # an even site
+        # the 8 neighbours of an even site are odd: the full source stands for its odd half
+        want = W.hop_site(Ut, bsrc, tuple(x))
+        g = got[0, x[3], x[2], x[1], x[0]].cpu().numpy()
+        worst = max(worst, float(np.abs(g - want).max() / np.abs(want).max()))
+    del src, out, got
+    _emit({"kind": "parity", "workload": "64^3x128 tiled exp(0.3iH)", "what": "FP64 hop on 24 sampled even sites",
+           "max_rel_err": worst}, path)
+    for name, kw in [("cgnr_f64", dict(inner_prec=q.F64)), ("cgnr_f32", dict(inner_prec=q.F32)),
+                     ("cgnr_f16s", dict(inner_prec=q.F16S))]:
+        t, st, info, _ = timed_solve(lat, b, reps=1, tol=1e-10, **kw)
+        _emit({"kind": "solve", "workload": "64^3x128 tiled exp(0.3iH) k0.12 1rhs", "form": name, "seconds": round(t, 4),
+               "status": st, "iterations": info[0]["iterations"], "reliable_updates": info[0]["reliable_updates"],
+               "true_rel_resid": info[0]["true_rel_resid"],
+               "device_gb": round(torch.cuda.max_memory_allocated() / 1e9, 1)}, path)
     lat.close()
 
 

@@ -34,6 +34,7 @@ CONFIG_DIMS = {
     3: [(8, 8, 8, 8)] * 8 + [(12, 12, 12, 24)] * 8 + [(16, 16, 16, 32)] * 8 + [(20, 20, 20, 40)] * 8,
     4: [(24, 24, 24, 48)],
     99: [(32, 32, 32, 64)],
+    100: [(64, 64, 64, 128)],
 }
 
 
@@ -173,6 +174,35 @@ def make_config(cid: int, sys: int = 0, with_source: bool = True) -> dict:
     if with_source:
         cfg["b"] = point_sources(cid, sys, dims) if cid == 2 else gaussian_source(cid, sys, dims, nrhs)
     return cfg
+
+
+def tiled_config() -> dict:
+    """Config 100 (measurement only): the 64^3x128 lattice of the paper's largest
+    run.  Its links repeat the 32^3x64 links of config 99 twice along every axis
+    (a periodic tiling of that cell, so every link is the same exp(0.3 i H) draw
+    as there); kappa 0.12; one Gaussian source drawn on the whole lattice.
+    Returns the cell links, the tiling and the source; the caller tiles the links
+    where they are needed (19.3 GB in complex128)."""
+    cell = make_config(99, with_source=False)
+    dims = CONFIG_DIMS[100][0]
+    reps = tuple(d // c for d, c in zip(dims, cell["dims"]))
+    return dict(cid=100, sys=0, dims=dims, kappa=cell["kappa"], mu=0.0, eps=cell["eps"], kind="tiled " + cell["kind"],
+                nrhs=1, U_cell=cell["U"], cell_dims=cell["dims"], reps=reps)
+
+
+def device_gaussian_source(cid: int, sys: int, dims, nrhs: int = 1, device: str = "cuda"):
+    """A complex Gaussian source (Re, Im ~ N(0, 1)) drawn directly in device
+    memory by torch's counter-based generator, seeded from the same seed
+    sequence as gaussian_source (stream 1).  For lattices whose host-side draw
+    would take minutes; the values differ from gaussian_source's."""
+    import torch
+    seed = int(np.random.SeedSequence([*SEED_BASE, cid, sys, STREAM_SOURCE]).generate_state(1, dtype=np.uint64)[0])
+    g = torch.Generator(device=device)
+    g.manual_seed(seed & ((1 << 63) - 1))
+    shape = (nrhs,) + site_shape(dims) + (3, 4)
+    re = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    im = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    return torch.complex(re, im)
 
 
 def small_config(dims, seed: int = 0, kind: str = "haar", eps: float = 0.3, kappa: float = 0.12,
