@@ -226,18 +226,19 @@ __device__ __forceinline__ Item fetch_item(const uint32_t *work, int nwork) {
 
 inline int grid_for(int nwork, int T) { return (nwork * T + 3) / 4; }
 
-// Store a wave's partial sums (partial index sb * T + sub of nb * T, each of
-// the NV values in its own row of 4 nb); the
-// reduce kernel sums them.  Lanes of groups other than 0 must pass zeros.
-template <int T>
+// Store a work item's partial sums: one per 64-site block (index sb), each of
+// the NV values in its own row; the reduce kernel sums them in index order.
+// Only wave group 0 of an item writes: after wave_combine it holds the item's
+// full sums.
 __device__ __forceinline__ void sys_partial(const SysDesc &d, int slot, const Item &it, double v[NV]) {
+  if (it.grp != 0) return;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if (lane_id() == 0) {
-    const size_t stride = (size_t)d.g.nb * 4;   // room for 4 partials per block (T <= 4)
+    const size_t stride = (size_t)d.g.nb * 4;   // row length (room kept for 4 per block)
     double *p = d.part + (size_t)slot * NV * stride;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) p[i * stride + it.sb * T + it.sub] = v[i];
+    for (int i = 0; i < NV; ++i) p[i * stride + it.sb] = v[i];
   }
 }
 

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
         dot12(rt, acc[r], v[0], v[1]);
       }
     }
-    if (red) sys_partial<T>(d, slot, it, v);
+    if (red) sys_partial(d, slot, it, v);
   }
 }
 
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
       dot12(rtd, acc, v[1], v[2]);
     }
   }
-  sys_partial<T64>(d, SL_UPD, it, v);
+  sys_partial(d, SL_UPD, it, v);
 }
 
 // ||b - D x||^2 on the sites of parity p: B_p - A X_p + kappa H X_{1-p}.
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
     for (int k = 0; k < 12; ++k) acc[k] = cadd(csub(b[k], x[k]), cscale(d.kappa, acc[k]));
     v[0] = norm12(acc);
   }
-  sys_partial<T64>(d, par ? SL_RES_O : SL_RES_E, it, v);
+  sys_partial(d, par ? SL_RES_O : SL_RES_E, it, v);
 }
 
 // Sum a system's partials of one reduction slot and run the solver's scalar
@@ -195,11 +195,11 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
 // strided subset with independent 16-byte loads, then waves and the work-group
 // combine in a fixed order: the result does not depend on scheduling.
 constexpr int RED_WG = 1024;
-__global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int tmul, int fin,
+__global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int fin,
                                                    int mask) {
   const SysDesc &d = sdesc[blockIdx.x];
   const int status = d.st->status;   // tested after the partials' loads are issued
-  const int np = d.g.nb * tmul;
+  const int np = d.g.nb;   // one partial per block
   const double *p = d.part + (size_t)slot * NV * (d.g.nb * 4);
   __shared__ double red[NV][RED_WG / WAVE];
   const int tid = threadIdx.x, w = tid >> 6;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(WG) void k_bnorm(const SysDesc *__restrict__ sdesc,
     SpinorIO<S_F64>::load(d.f[F_BO], it.s, d.npad, a);
     v[0] += norm12(a);
   }
-  sys_partial<1>(d, SL_B, it, v);
+  sys_partial(d, SL_B, it, v);
 }
 
 // CGNR: X += alpha P; R -= alpha AP; ||R||^2
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
     SpinorIO<S>::store(d.f[F_R], it.s, d.npad, r);
     v[0] = norm12(r);
   }
-  sys_partial<1>(d, SL_R, it, v);
+  sys_partial(d, SL_R, it, v);
 }
 
 // CGNR: P = Z + beta P
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(WG) void k_bi_xr(const SysDesc *__restrict__ sdesc,
     dot12(rt, s, v[0], v[1]);
     v[2] = norm12(s);
   }
-  sys_partial<1>(d, SL_BI3, it, v);
+  sys_partial(d, SL_BI3, it, v);
 }
 
 // copy a half-field of the iterate precision: dst = src
@@ -464,8 +464,8 @@ static void hop_sys_p(const Launch &l, bool dag, int epi, int fi, int fo, int fx
   else hop_sys_n<S, L, 2>(l, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
 }
 
-void reduce(const Launch &l, int slot, int tmul, int fin, int mask) {
-  hipLaunchKernelGGL(k_reduce, dim3(l.nsys), dim3(RED_WG), 0, l.stream, l.desc, slot, tmul, fin, mask);
+void reduce(const Launch &l, int slot, int fin, int mask) {
+  hipLaunchKernelGGL(k_reduce, dim3(l.nsys), dim3(RED_WG), 0, l.stream, l.desc, slot, fin, mask);
 }
 
 void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int fx, int par, int amode, int mask,
@@ -481,7 +481,7 @@ void hop_sys(const Launch &l, int prec, bool dag, int epi, int fi, int fo, int f
   if (prec == S_F64) hop_sys_p<S_F64, L_F64R18>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else if (prec == S_F32) hop_sys_p<S_F32, L_F32R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
   else hop_sys_p<S_F16S, L_F16R12>(lp, dag, epi, fi, fo, fx, par, amode, mask, red, slot);
-  if (red) reduce(l, slot, lp.T, fin, mask);
+  if (red) reduce(l, slot, fin, mask);
 }
 
 void hop_sum(const Launch &l, bool haslo) {
@@ -497,18 +497,18 @@ void hop_upd(const Launch &l, int prec, bool bicg) {
   else if (prec == S_F32) { if (bicg) QU(S_F32, true, true); else QU(S_F32, true, false); }
   else { if (bicg) QU(S_F16S, true, true); else QU(S_F16S, true, false); }
 #undef QU
-  reduce(l, SL_UPD, T64, FIN_UPDATE, ST_UPDATE);
+  reduce(l, SL_UPD, FIN_UPDATE, ST_UPDATE);
 }
 
 void hop_res(const Launch &l, int par) {
   const dim3 g = grid_of(l.nwork, T64), b(WG);
   hipLaunchKernelGGL(k_hop_res, g, b, 0, l.stream, l.desc, l.work, l.nwork, par);
-  reduce(l, par ? SL_RES_O : SL_RES_E, T64, FIN_NONE, ST_ANY);
+  reduce(l, par ? SL_RES_O : SL_RES_E, FIN_NONE, ST_ANY);
 }
 
 void bnorm(const Launch &l) {
   hipLaunchKernelGGL(k_bnorm, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
-  reduce(l, SL_B, 1, FIN_BNORM, ST_ANY);
+  reduce(l, SL_B, FIN_BNORM, ST_ANY);
 }
 
 void cg1(const Launch &l, int prec) {
@@ -516,7 +516,7 @@ void cg1(const Launch &l, int prec) {
   if (prec == S_F64) hipLaunchKernelGGL((k_cg1<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else if (prec == S_F32) hipLaunchKernelGGL((k_cg1<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else hipLaunchKernelGGL((k_cg1<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
-  reduce(l, SL_R, 1, FIN_NR, ST_RUN);
+  reduce(l, SL_R, FIN_NR, ST_RUN);
 }
 
 void cg2(const Launch &l, int prec) {
@@ -545,7 +545,7 @@ void bi_xr(const Launch &l, int prec) {
   if (prec == S_F64) hipLaunchKernelGGL((k_bi_xr<S_F64, S_F64>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else if (prec == S_F32) hipLaunchKernelGGL((k_bi_xr<S_F32, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else hipLaunchKernelGGL((k_bi_xr<S_F16S, S_F32>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
-  reduce(l, SL_BI3, 1, FIN_BI_RHO, ST_RUN);
+  reduce(l, SL_BI3, FIN_BI_RHO, ST_RUN);
 }
 
 void copy_field(const Launch &l, int prec, int fsrc, int fdst, int mask, int chi) {
