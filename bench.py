@@ -372,7 +372,7 @@ def suite_c2(q, latgen, torch, path, timed_solve, flush):
     b2 = torch.from_numpy(c2["b"]).cuda()
     for prec, nm in ((q.F16S, "f16s"), (q.F32, "f32"), (q.F64, "f64")):
         t_, nr_, us_ = lat2.tune(prec, 12)
-        _emit({"kind": "tune", "dims": list(c2["dims"]), "prec": nm, "nrhs": 12, "lanes_per_site": t_,
+        _emit({"kind": "tune", "dims": list(c2["dims"]), "prec": nm, "nrhs": 12, "waves_per_block": t_,
                "rhs_per_lane": nr_, "us": round(us_, 2)}, path)
     for name, kw in [("batched12_f16s", dict(inner_prec=q.F16S)), ("batched12_f32", dict(inner_prec=q.F32)),
                      ("batched12_f64", dict(inner_prec=q.F64))]:

@@ -94,7 +94,7 @@ def qiral_apply_M(handle, dims, out, inp, tmp, op, prec, nrhs=1, stream=None):
 
 
 def qiral_tune(handle, prec, nrhs=1, stream=None):
-    """Autotune the hop launch shape; returns (lanes per site, rhs per lane, microseconds)."""
+    """Autotune the hop launch shape; returns (waves per site block, rhs per lane, microseconds)."""
     t, nr, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     L.check(L.load().qiral_tune(ctypes.c_void_p(handle), int(prec), int(nrhs), ctypes.byref(t), ctypes.byref(nr),
                                 ctypes.byref(us), _stream(stream)), "qiral_tune")

@@ -248,7 +248,7 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
   const long nb = lat->geo.nb;
   if (const char *e = getenv("QIRAL_HOP_NR")) c.nr = atoi(e);
   else c.nr = tuned_nr(lat, prec, (int)nrhs);
-  c.nr = std::max(1, std::min(c.nr, prec == QIRAL_F64 ? 1 : 4));   // FP64 with 2 per lane spills
+  c.nr = std::max(1, std::min(c.nr, prec == QIRAL_F64 ? 1 : 4));   // FP64 with 2 RHS per lane spills
   if (c.nr > nrhs) c.nr = (int)nrhs;
   const long nitems = nb * ((nrhs + c.nr - 1) / c.nr);
   c.t = hop_split(prec, nitems);
@@ -292,9 +292,10 @@ int hop_split(int prec, long nwork) {
     const int t = atoi(e);
     if (t == 4 || (t == 2 && prec != QIRAL_F64) || (t == 1 && prec == QIRAL_F16S)) return t;
   }
-  // A whole site per lane needs ~256 VGPRs (one wave per SIMD) and the FP64
-  // hop spills below 4 lanes per site, so the split is 4 (FP64, and lattices
-  // with at most one 64-site block per SIMD) or 2.
+  // FP64 needs 4 waves per site block (fewer spill); otherwise 4 while the
+  // blocks do not fill the SIMDs (more waves hide more latency), else 2 (less
+  // LDS traffic and fewer redundant coordinate computations per site).  One
+  // wave per block (F16S only) is left to the tuner.
   const long simds = 1024;   // 256 compute units x 4 SIMDs
   if (prec == QIRAL_F64 || nwork <= simds) return 4;
   return 2;

@@ -11,7 +11,7 @@ namespace qiral {
 constexpr int WAVE = 64;   // CDNA wavefront; also the site-block of the packed layouts
 constexpr int WG = 256;    // work-group: 4 waves
 // Minimum waves per SIMD asked of the compiler for a hop kernel (storage S, T
-// lanes per site, NR right-hand sides per lane): caps the VGPR budget at
+// waves per site block, NR right-hand sides per lane): caps the VGPR budget at
 // 512 / waves so enough waves stay resident to cover memory latency, while
 // leaving the larger NR / smaller T variants room to avoid spilling.
 #define HOP_MIN_WAVES(S, T, NR) ((S) == 0 ? 2 : (NR) == 1 ? ((T) == 4 ? 4 : 3) : (NR) == 2 ? ((T) == 4 ? 3 : 2) : 2)

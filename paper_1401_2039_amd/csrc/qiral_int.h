@@ -19,7 +19,7 @@ struct qiral_lattice {
   size_t ws_bytes = 0;
   int device = 0;
   int tuned_nr[3][5] = {};   // autotuned right-hand sides per lane [prec][min(nrhs,4)], 0 = not tuned
-  int tuned_t[3][5] = {};    // autotuned lanes per site, same index, 0 = not tuned
+  int tuned_t[3][5] = {};    // autotuned waves per site block, same index, 0 = not tuned
 };
 
 namespace qiral {
@@ -37,8 +37,8 @@ inline size_t npad_of(const Geo &g) { return (size_t)g.nb * WAVE; }
 size_t half_bytes(const Geo &g, int prec);
 const void *links_for(const qiral_lattice *lat, int prec);
 
-// Launch shape of a hop: t lanes per site (2 or 4) and nr right-hand sides per
-// lane (1..4; FP64 1..2).  hop_split picks t for `nwork` 64-site work items
+// Launch shape of a hop: t waves per 64-site block (1, 2 or 4) and nr
+// right-hand sides per lane (1..4; see hop_nr_max).  hop_split picks t for `nwork` 64-site work items
 // (enough waves to give every SIMD, 256 CUs x 4, a few); tuned_nr gives the
 // autotuned nr of a lattice (a heuristic until tuned).  QIRAL_HOP_SPLIT and
 // QIRAL_HOP_NR override.

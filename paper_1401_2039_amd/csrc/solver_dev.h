@@ -192,8 +192,8 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
 // Per-wave context of a table-driven kernel.  A work item is one 64-site block
 // of `cnt` consecutive systems that share one lattice (cnt = 1 except for the
 // grouped hop table); it is encoded as (sys0 << 24) | ((cnt - 1) << 22) | block.
-// With T lanes per site, T waves share an item (sub = 0..T-1 picks the wave's
-// part of it) and a work-group of 4 waves takes 4/T items.
+// T waves share an item (sub = grp = 0..T-1 picks the wave's directions) and
+// a work-group of 4 waves takes 4/T items.
 // A work item as one wave sees it: T waves share an item (wave group grp of
 // the item in work-group slot `slot`); each lane takes site s of the block.
 struct Item {

@@ -1,5 +1,5 @@
-// Autotuner of the hop's launch shape: lanes per site (2 or 4) and right-hand
-// sides per lane (1..4), timed with HIP events on the caller's stream for one
+// Autotuner of the hop's launch shape: waves per 64-site block (1 (F16S), 2 or
+// 4) and right-hand sides per lane (1..4), timed with HIP events on the caller's stream for one
 // lattice, precision and right-hand-side count.  Results live in the lattice
 // handle and, if QIRAL_TUNE_CACHE names a file, in a JSON cache keyed by
 // (architecture, precision, dims, nrhs) that later handles read.

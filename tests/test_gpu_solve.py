@@ -141,7 +141,7 @@ def test_cgnr_c1_mixed_vs_f64():
 @pytest.mark.parametrize("nr", [2, 3])
 def test_batched_point_sources_split2(nr, monkeypatch):
     """Point sources (values spanning many decades) through the grouped multi-RHS
-    mixed solve with 2 lanes per site and nr right-hand sides per lane."""
+    mixed solve with 2 waves per site block and nr right-hand sides per lane."""
     dims = (8, 8, 8, 8)
     say("batched point sources", nr)
     monkeypatch.setenv("QIRAL_HOP_SPLIT", "2")
