@@ -9,6 +9,10 @@
   an addition to the paper's solvers, on the same Schur system.
 * ``fgmres``: flexible GMRES(m) with a right preconditioner that may change
   between iterations (Saad, SIAM J. Sci. Comput. 14, 1993).
+* ``crnr``: the conjugate residual method (Saad, Iterative Methods for Sparse
+  Linear Systems, 2nd ed., Alg. 6.20) on the normal equations A^dag A x =
+  A^dag b, a residual-minimising counterpart of CGNR (Sec. 5 compares CGNR with
+  conjugate-residual variants it does not define).
 
 Stopping rule.  The paper's loop runs while (r|r) > epsilon.  Here epsilon is
 (tol * ||b||)^2 with b the full-lattice source, so that the loop stops when
@@ -73,6 +77,65 @@ def solve_eo_cgnr(U, kappa, mu, b, tol=1e-10, maxiter=100000, max_restarts=5):
         if res <= tol or restarts >= max_restarts:
             break
         xo, more, _ = cgnr(A, Ad, bhat, eps, maxiter, x0=xo)
+        its += more
+        restarts += 1
+    return x, dict(iterations=its, restarts=restarts, true_rel_resid=res, history=hist)
+
+
+def crnr(apply_A, apply_Adag, b, eps, maxiter=100000, x0=None):
+    """Conjugate residual for the Hermitian system M x = A^dag b, M = A^dag A:
+    z is its residual, p the search direction, q = M p, and M-conjugacy of the
+    residuals replaces the A-conjugacy of CG.  The residual r = b - A x of the
+    original system and u = A p are carried along so that the loop stops on
+    (r|r) <= eps, as cgnr does.  Returns (x, iterations, history of n_r)."""
+    if x0 is None:
+        r = b.copy()
+        x = np.zeros_like(b)
+    else:
+        r = b - apply_A(x0)
+        x = x0.copy()
+    z = apply_Adag(r)
+    v = apply_A(z)
+    w = apply_Adag(v)          # M z
+    p, q, u = z.copy(), w.copy(), v.copy()
+    n_zw = W.inner(z, w).real  # (z | M z), real for Hermitian M
+    n_r = W.norm2(r)
+    hist = [n_r]
+    it = 0
+    while n_r > eps and it < maxiter:
+        alpha = n_zw / W.norm2(q)
+        x = x + alpha * p
+        r = r - alpha * u
+        z = z - alpha * q
+        v = apply_A(z)
+        w = apply_Adag(v)
+        n_zw1 = W.inner(z, w).real
+        beta = n_zw1 / n_zw
+        p = z + beta * p
+        q = w + beta * q
+        u = v + beta * u
+        n_zw = n_zw1
+        n_r = W.norm2(r)
+        hist.append(n_r)
+        it += 1
+    return x, it, hist
+
+
+def solve_eo_crnr(U, kappa, mu, b, tol=1e-10, maxiter=100000, max_restarts=5):
+    """As solve_eo_cgnr with the conjugate residual method on the Schur system."""
+    bnorm = np.sqrt(W.norm2(b))
+    eps = (tol * bnorm) ** 2
+    bhat = W.schur_source(U, kappa, mu, b)
+    A = lambda v: W.schur(U, kappa, mu, v)
+    Ad = lambda v: W.schur(U, kappa, mu, v, dagger=True)
+    xo, its, hist = crnr(A, Ad, bhat, eps, maxiter)
+    restarts = 0
+    while True:
+        x = W.reconstruct_even(U, kappa, mu, b, xo) + xo
+        res = true_rel_residual(U, kappa, mu, x, b)
+        if res <= tol or restarts >= max_restarts:
+            break
+        xo, more, _ = crnr(A, Ad, bhat, eps, maxiter, x0=xo)
         its += more
         restarts += 1
     return x, dict(iterations=its, restarts=restarts, true_rel_resid=res, history=hist)

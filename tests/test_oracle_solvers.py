@@ -57,6 +57,47 @@ def test_fgmres_c0(c0):
     assert stepsn < steps
 
 
+def test_eo_crnr_c0(c0):
+    cfg, xd = c0
+    x, info = S.solve_eo_crnr(cfg["U"], cfg["kappa"], 0.0, cfg["b"][0], tol=1e-10)
+    assert info["true_rel_resid"] <= 1e-10
+    assert _rel(x, xd) < 1e-9
+
+
+def test_crnr_minimises_normal_residual_over_krylov_space():
+    """Conjugate residual on M = S^dag S: after k steps from x = 0, the normal
+    residual z_k = S^dag (b - S x_k) is the smallest over x in the Krylov space
+    span{z0, M z0, .., M^(k-1) z0} (checked by a least-squares solve on that
+    basis), and ||z_k|| never increases.  CG's iterate minimises a different
+    norm and fails the first check."""
+    cfg = latgen.small_config((4, 2, 2, 4), seed=12, kind="haar")
+    U, k, b = cfg["U"], 0.12, cfg["b"][0]
+    bh = W.schur_source(U, k, 0.0, b)
+    A = lambda v: W.schur(U, k, 0.0, v)
+    Ad = lambda v: W.schur(U, k, 0.0, v, dagger=True)
+    M = lambda v: Ad(A(v))
+    odd = W.parity_field(W.dims_of(b)) == 1
+    flat = lambda f: f[odd].reshape(-1)
+    z0 = Ad(bh)
+    basis = [z0]
+    for _ in range(5):
+        basis.append(M(basis[-1]))
+    prev = np.inf
+    for steps in range(1, 6):
+        x, _, _ = S.crnr(A, Ad, bh, 0.0, maxiter=steps)
+        zk = np.sqrt(W.norm2(Ad(bh - A(x))))
+        K = np.stack([flat(v) for v in basis[:steps]], axis=1)
+        MK = np.stack([flat(M(v)) for v in basis[:steps]], axis=1)
+        y, *_ = np.linalg.lstsq(MK, flat(z0), rcond=None)
+        best = np.linalg.norm(flat(z0) - MK @ y)
+        assert zk <= best * (1 + 1e-8) + 1e-12, (steps, zk, best)
+        assert zk <= prev * (1 + 1e-12)
+        prev = zk
+        xcg, _, _ = S.cgnr(A, Ad, bh, 0.0, maxiter=steps)
+        if steps >= 2:
+            assert np.sqrt(W.norm2(Ad(bh - A(xcg)))) > best * (1 + 1e-6)
+
+
 def test_twisted_mass_schur():
     cfg = latgen.small_config((4, 2, 2, 4), seed=11)
     U, b = cfg["U"], cfg["b"][0]
