@@ -333,6 +333,7 @@ def suite_c1(lat1, q, latgen, torch, path, timed_solve):
     for name, kw in [("cgnr_f64", dict(inner_prec=q.F64)), ("cgnr_f32", dict(inner_prec=q.F32)),
                      ("cgnr_f16s", dict(inner_prec=q.F16S)), ("bicgstab_f64", dict(solver=q.BICGSTAB_EO)),
                      ("bicgstab_f32", dict(solver=q.BICGSTAB_EO, inner_prec=q.F32)),
+                     ("crnr_f64", dict(solver=q.CRNR_EO)),
                      ("cgnr_f32_graph", dict(inner_prec=q.F32, use_graph=1))]:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):

@@ -73,13 +73,17 @@ typedef enum { QIRAL_EVEN = 0, QIRAL_ODD = 1, QIRAL_FULL = 2 } qiral_subset;
 typedef enum {
   QIRAL_OP_D = 0,        /* full-lattice D = 1 - kappa H                           */
   QIRAL_OP_DDAG = 1,     /* D^dagger = 1 - kappa H^dagger                          */
-  QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = 1 - kappa^2 H_oe H_eo    */
-  QIRAL_OP_SCHUR_DAG = 3 /* S^dagger = 1 - kappa^2 H^dagger_oe H^dagger_eo         */
+  QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = A - kappa^2 H_oe A^-1 H_eo */
+  QIRAL_OP_SCHUR_DAG = 3 /* S^dagger (see qiral_apply_M)                             */
 } qiral_op;
 typedef enum {
   QIRAL_CGNR_EO = 0,     /* CGNR (Fig. "CG") on the Schur system ("schur" template) */
   QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system      */
-  QIRAL_FGMRES_NN = 2    /* FGMRES(m) on D with the learned preconditioner          */
+  QIRAL_FGMRES_NN = 2,   /* FGMRES(m) on D with the learned preconditioner          */
+  QIRAL_CRNR_EO = 3      /* conjugate residual (Saad, Alg. 6.20) on the Schur normal
+                            equations S^dagger S x_o = S^dagger b_hat, stopping on the
+                            Schur residual like CGNR; FP64 only (inner_prec F64,
+                            otherwise QIRAL_ERR_UNSUPPORTED)                          */
 } qiral_solver;
 
 /* Bit i of lo_precs asks lattice_create for a packed link store of precision i. */
@@ -149,7 +153,7 @@ qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, int32
                         double *best_us, qiral_stream_t stream);
 
 typedef struct {
-  qiral_solver solver; /* QIRAL_CGNR_EO (default) or QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN        */
+  qiral_solver solver; /* QIRAL_CGNR_EO (default), QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN, QIRAL_CRNR_EO */
   double tol;          /* relative FP64 residual ||b - D x|| / ||b|| to reach (e.g. 1e-10)   */
   int32_t maxiter;     /* iteration limit (outer iterations of the solver)                    */
   qiral_prec inner_prec; /* F64: plain solve.  F32/F16S: reduced-precision iterations with

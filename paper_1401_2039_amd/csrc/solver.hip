@@ -67,13 +67,13 @@ struct SysSizes {
   size_t bytes;
 };
 
-SysSizes sys_sizes(const Geo &g, int prec, bool bicg) {
+SysSizes sys_sizes(const Geo &g, int prec, int nit) {
   SysSizes z;
   z.hb_it = align_up(half_bytes(g, prec));
   z.hb64 = align_up(half_bytes(g, QIRAL_F64));
   const bool mixed = prec != QIRAL_F64;
   z.hb_x = mixed ? align_up(half_bytes(g, QIRAL_F32)) : 0;
-  const int nit = bicg ? 7 : 5;   // R P Z AP TMP (+ RT T)
+  // nit iterate-precision half-fields: R P Z AP TMP (+ RT T for BiCGStab, + RT T W for CR)
   // F64: BH T64, [BE|BO] full, [XE|XH] full
   z.bytes = nit * z.hb_it + z.hb_x + 2 * z.hb64 + 2 * (2 * z.hb64);
   return z;
@@ -86,6 +86,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   const int prec = prm->inner_prec;
   const bool mixed = prec != QIRAL_F64;
   const bool bicg = prm->solver == QIRAL_BICGSTAB_EO;
+  const bool cr = prm->solver == QIRAL_CRNR_EO;
+  const int nit = bicg ? 7 : cr ? 8 : 5;
 
   // ---- layout
   Layout lay;
@@ -94,7 +96,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   size_t nparts = 0;
   lay.part_off.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
-    sz[i] = sys_sizes(sys[i].lat->geo, prec, bicg);
+    sz[i] = sys_sizes(sys[i].lat->geo, prec, nit);
     nwork += sys[i].lat->geo.nb;
     lay.part_off[i] = nparts;
     nparts += (size_t)NSLOT * NV * 4 * sys[i].lat->geo.nb;
@@ -127,8 +129,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     d.st = (SysState *)(ws + lay.off_state) + i;
     d.part = (double *)(ws + lay.off_part) + lay.part_off[i];
     char *p = ws + lay.off_sys[i];
-    const int it_fields[] = {F_R, F_P, F_Z, F_AP, F_TMP, F_RT, F_T};
-    for (int k = 0; k < (bicg ? 7 : 5); ++k) { d.f[it_fields[k]] = p; p += sz[i].hb_it; }
+    const int it_fields[] = {F_R, F_P, F_Z, F_AP, F_TMP, F_RT, F_T, F_W};
+    for (int k = 0; k < nit; ++k) { d.f[it_fields[k]] = p; p += sz[i].hb_it; }
     if (mixed) { d.f[F_X] = p; p += sz[i].hb_x; }
     d.f[F_BH] = p; p += sz[i].hb64;
     d.f[F_T64] = p; p += sz[i].hb64;
@@ -188,7 +190,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     x.delta2 = prm->delta * prm->delta;
     x.maxiter = prm->maxiter;
     x.mixed = mixed;
-    x.solver = bicg ? SOLVER_BICG : SOLVER_CG;
+    x.solver = bicg ? SOLVER_BICG : cr ? SOLVER_CR : SOLVER_CG;
     x.status = ST_UPDATE;
   }
   QIRAL_HIP(hipMemcpyAsync(ws + lay.off_desc, desc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, s));
@@ -234,11 +236,24 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   }
   QIRAL_HIP(hipGetLastError());
 
+  // CR: v = S z (F_RT), w = S^dagger v (F_W) with (z | w) reduced into `fin`
+  auto cr_apply = [&](int fin) {
+    hop_sys(L, prec, false, 0, F_Z, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
+    hop_sys(L, prec, false, 1, F_TMP, F_RT, F_Z, 1, A_MKAPPA2, ST_RUN, 0, 0, FIN_NONE, CHI_ONE, CHI_A);
+    hop_sys(L, prec, true, 0, F_RT, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
+    hop_sys(L, prec, true, 1, F_TMP, F_W, F_RT, 1, A_MKAPPA2, ST_RUN, 4, SL_Z, fin, CHI_ONE, CHI_ADAG);
+  };
   auto start_krylov = [&]() {
     // r = b_hat - S x (FP64), then the solver's own start
     hop_sum(L, mixed);
     hop_upd(L, prec, bicg);
-    if (!bicg) {
+    if (cr) {
+      // z = S^dagger r, v = S z, w = S^dagger v, (z | w); then p = z, q = w, u = v, alpha
+      hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
+      hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 0, 0, FIN_NONE, CHI_ONE, CHI_ADAG);
+      cr_apply(FIN_CR_ZW);
+      cr2(L, true);
+    } else if (!bicg) {
       hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
       hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_NZ_INIT, CHI_ONE, CHI_ADAG);
       cg2(L, prec);   // p = z (beta = 0, p = 0)
@@ -248,7 +263,11 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     }
   };
   auto iteration = [&]() {
-    if (!bicg) {
+    if (cr) {
+      cr1(L);
+      cr_apply(FIN_CR_BETA);
+      cr2(L, false);
+    } else if (!bicg) {
       hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
       hop_sys(L, prec, false, 1, F_TMP, F_AP, F_P, 1, A_MKAPPA2, ST_RUN, 1, SL_AP, FIN_ALPHA, CHI_ONE, CHI_A);
       cg1(L, prec);
@@ -374,13 +393,16 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (!p) return fail(QIRAL_ERR_INVALID_ARG, "params is NULL");
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(QIRAL_ERR_INVALID_ARG, "tol must be positive");
   if (p->maxiter < 1) return fail(QIRAL_ERR_INVALID_ARG, "maxiter must be >= 1");
-  if (p->solver != QIRAL_CGNR_EO && p->solver != QIRAL_BICGSTAB_EO && p->solver != QIRAL_FGMRES_NN)
+  if (p->solver != QIRAL_CGNR_EO && p->solver != QIRAL_BICGSTAB_EO && p->solver != QIRAL_FGMRES_NN &&
+      p->solver != QIRAL_CRNR_EO)
     return fail(QIRAL_ERR_INVALID_ARG, "bad solver");
   if (p->inner_prec != QIRAL_F64 && p->inner_prec != QIRAL_F32 && p->inner_prec != QIRAL_F16S)
     return fail(QIRAL_ERR_INVALID_ARG, "bad inner precision");
   if (p->inner_prec != QIRAL_F64 && !(p->delta > 0.0 && p->delta < 1.0))
     return fail(QIRAL_ERR_INVALID_ARG, "delta must lie in (0, 1) for a mixed-precision solve");
   if (p->check_every < 0) return fail(QIRAL_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (p->solver == QIRAL_CRNR_EO && p->inner_prec != QIRAL_F64)
+    return fail(QIRAL_ERR_UNSUPPORTED, "the conjugate residual solver runs in FP64 (inner_prec F64)");
   if (p->solver == QIRAL_FGMRES_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FGMRES needs a precond network");
   return QIRAL_OK;
 }

@@ -15,10 +15,10 @@ constexpr int NV = 3;   // values per reduction
 
 enum : int {
   FIN_NONE = 0, FIN_BNORM, FIN_NZ_INIT, FIN_ALPHA, FIN_NR, FIN_BETA, FIN_UPDATE,
-  FIN_BI_ALPHA, FIN_BI_OMEGA, FIN_BI_RHO
+  FIN_BI_ALPHA, FIN_BI_OMEGA, FIN_BI_RHO, FIN_CR_ZW, FIN_CR_BETA, FIN_CR_ALPHA
 };
 
-enum : int { SOLVER_CG = 0, SOLVER_BICG = 1 };
+enum : int { SOLVER_CG = 0, SOLVER_BICG = 1, SOLVER_CR = 2 };
 
 // Vectors of one system.  Odd half-fields unless noted.  "it" = iterate
 // precision (FP64 for a plain solve, FP32 or F16S for a mixed one).
@@ -26,8 +26,8 @@ enum : int {
   F_X = 0,   // iterated solution: FP64 (plain) or FP32 (mixed, not yet folded into XH)
   F_R,       // residual (it)
   F_P,       // search direction (it)
-  F_Z,       // S^dagger r (CG) / s (BiCGStab) (it)
-  F_AP,      // S p (CG) / v (BiCGStab) (it)
+  F_Z,       // S^dagger r (CG, CR) / s (BiCGStab) (it)
+  F_AP,      // S p (CG) / v (BiCGStab) / q = S^dagger S p (CR) (it)
   F_TMP,     // even half-field temporary (it)
   F_XH,      // FP64 solution (mixed: accumulated; plain: unused)
   F_BH,      // FP64 Schur source b_hat
@@ -35,8 +35,9 @@ enum : int {
   F_BE,      // FP64 even half of b
   F_BO,      // FP64 odd half of b
   F_XE,      // FP64 even half of x
-  F_RT,      // BiCGStab shadow residual (it)
-  F_T,       // BiCGStab t = S s (it)
+  F_RT,      // BiCGStab shadow residual / CR v = S z (it)
+  F_T,       // BiCGStab t = S s / CR u = S p (it)
+  F_W,       // CR w = S^dagger S z (it)
   NF
 };
 
@@ -135,6 +136,27 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
       if (!cfinite(nr)) { st->nonfinite = 1; st->status = ST_DONE; }
       else if (nr <= st->thr2 || st->final_update || st->iter >= st->maxiter) st->status = ST_DONE;
       else st->status = ST_RUN;
+      break;
+    }
+    case FIN_CR_ZW:   // (z | S^dagger S z) of the conjugate residual start; z, v, w took 3 S
+      st->nz = t[0];
+      st->beta = 0.0;
+      st->hops += 6;
+      if (!cfinite(t[0])) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    case FIN_CR_BETA: {   // beta = (z|Mz)_new / (z|Mz)_old
+      const double b = t[0] / st->nz;
+      st->beta = b;
+      st->nz = t[0];
+      st->hops += 4;
+      if (!cfinite(b)) { st->nonfinite = 1; st->status = ST_DONE; }
+      break;
+    }
+    case FIN_CR_ALPHA: {   // alpha = (z|Mz) / (q|q), q = M p
+      st->nAp = t[0];
+      const double a = st->nz / t[0];
+      st->alpha = a;
+      if (!cfinite(a)) { st->nonfinite = 1; st->status = ST_DONE; }
       break;
     }
     case FIN_BI_ALPHA: {

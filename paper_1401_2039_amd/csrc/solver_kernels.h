@@ -35,6 +35,10 @@ void hop_res(const Launch &l, int par);
 void bnorm(const Launch &l);
 void cg1(const Launch &l, int prec);
 void cg2(const Launch &l, int prec);
+// Conjugate residual on S^dagger S (FP64): the x, r, z update with ||r||^2, and
+// the p, q, u update with ||q||^2 (init: p = z, q = w, u = v).
+void cr1(const Launch &l);
+void cr2(const Launch &l, bool init);
 void bi_p(const Launch &l, int prec);
 void bi_s(const Launch &l, int prec);
 void bi_xr(const Launch &l, int prec);

@@ -20,7 +20,7 @@ template <int S> __device__ __forceinline__ const void *links_of(const SysDesc &
 // `par` out, for the (up to NR) systems of a grouped work item (they share the
 // lattice, so each link is loaded once for all of them).  C_o and C_x are the
 // twisted-mass site factors chio and chix (CHI_*).
-// red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2.
+// red: 0 none; 1 ||out||^2; 2 (rt | out); 3 (out | x) and ||out||^2; 4 (z | out).
 // T waves per item (see hop_wave); padded lanes compute on site 0 and store
 // nothing.  Every wave reaches wave_combine's barrier.
 template <int S, int L, bool DAG, int EPI, int T, int NR, bool NT>
@@ -76,9 +76,9 @@ __global__ __launch_bounds__(WG, HOP_MIN_WAVES(S, T, NR)) void k_hop_sys(const S
       }
       SpinorIO<S>::template store_fast<NT>(d.f[fout], it.s, npad, acc[r]);
       if (red == 1) v[0] = norm12(acc[r]);
-      if (red == 2) {
+      if (red == 2 || red == 4) {
         cpx<R> rt[12];
-        SpinorIO<S>::load(d.f[F_RT], it.s, npad, rt);
+        SpinorIO<S>::load(d.f[red == 2 ? F_RT : F_Z], it.s, npad, rt);
         dot12(rt, acc[r], v[0], v[1]);
       }
     }
@@ -294,6 +294,71 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
     v[0] = norm12(r);
   }
   sys_partial(d, SL_R, it, v);
+}
+
+// Conjugate residual on S^dagger S: X += alpha P; R -= alpha U (U = S P);
+// Z -= alpha Q (Q = S^dagger S P); reduces ||R||^2 (the Schur residual).
+template <int S>
+__global__ __launch_bounds__(WG) void k_cr1(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                            int nwork) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item<1>(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    const R al = (R)d.st->alpha;
+    cpx<R> p[12], x[12], a[12], b[12];
+    SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+    SpinorIO<S>::load(d.f[F_X], it.s, d.npad, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale(al, p[k]));
+    SpinorIO<S>::store(d.f[F_X], it.s, d.npad, x);
+    SpinorIO<S>::load(d.f[F_R], it.s, d.npad, a);
+    SpinorIO<S>::load(d.f[F_T], it.s, d.npad, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = csub(a[k], cscale(al, b[k]));
+    SpinorIO<S>::store(d.f[F_R], it.s, d.npad, a);
+    v[0] = norm12(a);
+    SpinorIO<S>::load(d.f[F_Z], it.s, d.npad, a);
+    SpinorIO<S>::load(d.f[F_AP], it.s, d.npad, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = csub(a[k], cscale(al, b[k]));
+    SpinorIO<S>::store(d.f[F_Z], it.s, d.npad, a);
+  }
+  sys_partial(d, SL_R, it, v);
+}
+
+// Conjugate residual: P = Z + beta P; Q = W + beta Q; U = V + beta U (INIT:
+// beta = 0, old values not read); reduces ||Q||^2.
+template <int S, bool INIT>
+__global__ __launch_bounds__(WG) void k_cr2(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                            int nwork) {
+  using R = typename SpinorIO<S>::R;
+  const Item it = fetch_item<1>(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_RUN)) return;
+  double v[NV] = {0.0, 0.0, 0.0};
+  if (it.s < d.g.vh) {
+    const R be = (R)d.st->beta;
+    const int src[3] = {F_Z, F_W, F_RT}, dst[3] = {F_P, F_AP, F_T};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      cpx<R> a[12];
+      SpinorIO<S>::load(d.f[src[f]], it.s, d.npad, a);
+      if (!INIT) {
+        cpx<R> b[12];
+        SpinorIO<S>::load(d.f[dst[f]], it.s, d.npad, b);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) a[k] = cadd(a[k], cscale(be, b[k]));
+      }
+      SpinorIO<S>::store(d.f[dst[f]], it.s, d.npad, a);
+      if (f == 1) v[0] = norm12(a);
+    }
+  }
+  sys_partial(d, SL_AP, it, v);
 }
 
 // CGNR: P = Z + beta P
@@ -524,6 +589,17 @@ void cg2(const Launch &l, int prec) {
   if (prec == S_F64) hipLaunchKernelGGL(k_cg2<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else if (prec == S_F32) hipLaunchKernelGGL(k_cg2<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
   else hipLaunchKernelGGL(k_cg2<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void cr1(const Launch &l) {
+  hipLaunchKernelGGL(k_cr1<S_F64>, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  reduce(l, SL_R, FIN_NR, ST_RUN);
+}
+
+void cr2(const Launch &l, bool init) {
+  if (init) hipLaunchKernelGGL((k_cr2<S_F64, true>), grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_cr2<S_F64, false>), grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
+  reduce(l, SL_AP, FIN_CR_ALPHA, ST_RUN);
 }
 
 void bi_p(const Launch &l, int prec) {

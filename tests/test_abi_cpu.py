@@ -86,3 +86,24 @@ def test_null_handles_rejected():
     assert lib.qiral_solve(None, one, one, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
     assert lib.qiral_solve_batch(None, None, None, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
     assert lib.qiral_lattice_query(None, None, None) == L.ERR_INVALID_ARG
+
+
+def test_solve_params_validation():
+    """Parameter checks run before the lattice handle or any HIP call is used, so
+    a stand-in handle exercises them on the CPU."""
+    lib = L.load()
+    one = ctypes.c_void_p(1)
+    info = (L.SolveInfo * 1)()
+
+    def solve(**kw):
+        p = api.solve_params(**kw)
+        return lib.qiral_solve(one, one, one, 1, ctypes.byref(p), info, None)
+
+    assert solve(tol=0.0) == L.ERR_INVALID_ARG
+    assert solve(maxiter=0) == L.ERR_INVALID_ARG
+    assert solve(solver=9) == L.ERR_INVALID_ARG
+    assert solve(inner_prec=7) == L.ERR_INVALID_ARG
+    assert solve(inner_prec=L.F32, delta=1.5) == L.ERR_INVALID_ARG
+    assert solve(solver=L.FGMRES_NN) == L.ERR_INVALID_ARG            # no network
+    assert solve(solver=L.CRNR_EO, inner_prec=L.F32) == L.ERR_UNSUPPORTED
+    assert b"conjugate residual" in lib.qiral_last_error()

@@ -64,6 +64,45 @@ def test_mixed_c0(c0, prec, solver):
     assert _resid(cfg, host(x)[0]) <= 1e-10
 
 
+def test_crnr_f64_c0(c0):
+    """Conjugate residual on the Schur normal equations: the oracle's D judges the
+    residual, the oracle's CR the iteration count (within 2) and the solution."""
+    cfg, lat, _, _ = c0
+    say("crnr f64 C0")
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.CRNR_EO)
+    assert st == 0, info
+    xg = host(x)[0]
+    assert _resid(cfg, xg) <= 1e-10
+    xc, ci = S.solve_eo_crnr(cfg["U"], cfg["kappa"], 0.0, cfg["b"][0], tol=1e-10)
+    assert abs(info[0]["iterations"] - ci["iterations"]) <= 2, (info[0]["iterations"], ci["iterations"])
+    assert np.sqrt(W.norm2(xg - xc) / W.norm2(xc)) < 1e-9
+    # 4 hops per iteration plus the start (r: 2, z, v, w: 6)
+    assert info[0]["hop_applications"] == 4 * info[0]["iterations"] + 8
+
+
+def test_crnr_multi_rhs_and_batch():
+    say("crnr multi-rhs and batch")
+    dims = (4, 4, 2, 4)
+    cfg = latgen.small_config(dims, seed=32, kind="expih", eps=0.4, nrhs=3)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.CRNR_EO)
+    assert st == 0
+    xs = host(x)
+    for r in range(3):
+        assert S.true_rel_residual(cfg["U"], 0.12, 0.0, xs[r], cfg["b"][r]) <= 1e-10
+        x1, st1, _ = lat.solve(dev(cfg["b"][r:r + 1]), tol=1e-10, solver=q.CRNR_EO)
+        assert st1 == 0 and np.array_equal(host(x1)[0], xs[r])
+    dimss = [(4, 4, 4, 4), (2, 2, 4, 2), (6, 4, 2, 4)]
+    cfgs = [latgen.small_config(d, seed=40 + i, kind="expih", eps=0.3, kappa=0.10 + 0.01 * i) for i, d in enumerate(dimss)]
+    lats = [q.Lattice(c["dims"], c["kappa"], c["U"]) for c in cfgs]
+    bs = [dev(c["b"]) for c in cfgs]
+    xs = [torch.zeros_like(b) for b in bs]
+    st, info = q.qiral_solve_batch([l.handle for l in lats], dimss, xs, bs, q.solve_params(tol=1e-10, solver=q.CRNR_EO))
+    assert st == 0
+    for c, xx in zip(cfgs, xs):
+        assert S.true_rel_residual(c["U"], c["kappa"], 0.0, host(xx)[0], c["b"][0]) <= 1e-10
+
+
 def test_multi_rhs_equals_single():
     dims = (4, 4, 2, 4)
     say("multi-rhs", dims)

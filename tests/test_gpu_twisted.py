@@ -72,12 +72,13 @@ def test_twisted_mass_changes_the_operator(tm):
     assert abs(diff - want) < 1e-12 * max(1.0, want)
 
 
-@pytest.mark.parametrize("form", ["cgnr_f64", "cgnr_f32", "cgnr_f16s", "bicgstab_f64", "bicgstab_f32"])
+@pytest.mark.parametrize("form", ["cgnr_f64", "cgnr_f32", "cgnr_f16s", "bicgstab_f64", "bicgstab_f32", "crnr_f64"])
 def test_twisted_solves(tm, form):
     dims, cfg, lat = tm
     say("twisted solve", dims, form)
     kw = {"cgnr_f64": {}, "cgnr_f32": dict(inner_prec=q.F32), "cgnr_f16s": dict(inner_prec=q.F16S),
-          "bicgstab_f64": dict(solver=q.BICGSTAB_EO), "bicgstab_f32": dict(solver=q.BICGSTAB_EO, inner_prec=q.F32)}[form]
+          "bicgstab_f64": dict(solver=q.BICGSTAB_EO), "bicgstab_f32": dict(solver=q.BICGSTAB_EO, inner_prec=q.F32),
+          "crnr_f64": dict(solver=q.CRNR_EO)}[form]
     x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, **kw)
     assert st == 0, info
     xs = host(x)
