@@ -71,8 +71,8 @@ typedef enum { QIRAL_F64 = 0, QIRAL_F32 = 1, QIRAL_F16S = 2 } qiral_prec;
 typedef enum { QIRAL_RECON18 = 18, QIRAL_RECON12 = 12 } qiral_recon;
 typedef enum { QIRAL_EVEN = 0, QIRAL_ODD = 1, QIRAL_FULL = 2 } qiral_subset;
 typedef enum {
-  QIRAL_OP_D = 0,        /* full-lattice D = 1 - kappa H                           */
-  QIRAL_OP_DDAG = 1,     /* D^dagger = 1 - kappa H^dagger                          */
+  QIRAL_OP_D = 0,        /* full-lattice D = A - kappa H (A = 1 + 2 i kappa mu g5)  */
+  QIRAL_OP_DDAG = 1,     /* D^dagger = A^dagger - kappa H^dagger                    */
   QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = A - kappa^2 H_oe A^-1 H_eo */
   QIRAL_OP_SCHUR_DAG = 3 /* S^dagger (see qiral_apply_M)                             */
 } qiral_op;
