@@ -436,6 +436,7 @@ extern "C" qiral_status qiral_lattice_destroy(qiral_lattice *lat) {
   hipError_t e2 = lat->g32 ? hipFree(lat->g32) : hipSuccess;
   hipError_t e3 = lat->g16 ? hipFree(lat->g16) : hipSuccess;
   hipError_t e4 = lat->ws ? hipFree(lat->ws) : hipSuccess;
+  if (lat->pinned) (void)hipHostFree(lat->pinned);
   delete lat;
   if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFree");

@@ -17,6 +17,8 @@ struct qiral_lattice {
   size_t gauge_bytes = 0;
   void *ws = nullptr;    // solver workspace, grown on demand
   size_t ws_bytes = 0;
+  void *pinned = nullptr;   // pinned host buffer for the solver's state copies, grown on demand
+  size_t pinned_bytes = 0;
   int device = 0;
   int tuned_nr[3][5] = {};   // autotuned right-hand sides per lane [prec][min(nrhs,4)], 0 = not tuned
   int tuned_t[3][5] = {};    // autotuned waves per site block, same index, 0 = not tuned

@@ -287,7 +287,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     }
   };
 
-  const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+  const int chunk = prm->check_every > 0 ? prm->check_every : 4;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   const bool use_graph = prm->use_graph && s != nullptr;
@@ -302,6 +302,47 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     QIRAL_HIP(hipStreamSynchronize(s));
     return QIRAL_OK;
   };
+  // Two pinned copies of the states, so that the host examines the states after
+  // one chunk of iterations while the next chunk already runs.
+  const size_t sbytes = sizeof(SysState) * nsys;
+  if (owner->pinned_bytes < 2 * sbytes) {
+    if (owner->pinned) (void)hipHostFree(owner->pinned);
+    owner->pinned = nullptr;
+    owner->pinned_bytes = 0;
+    QIRAL_HIP(hipHostMalloc(&owner->pinned, 2 * sbytes, hipHostMallocDefault));
+    owner->pinned_bytes = 2 * sbytes;
+  }
+  SysState *hbuf[2] = {(SysState *)owner->pinned, (SysState *)owner->pinned + nsys};
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() { for (hipEvent_t x : e) if (x) (void)hipEventDestroy(x); }
+  } ev;
+  for (int k = 0; k < 2; ++k) QIRAL_HIP(hipEventCreateWithFlags(&ev.e[k], hipEventDisableTiming));
+  auto enqueue_chunk = [&]() -> qiral_status {
+    if (use_graph) {
+      if (!gexec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        for (int k = 0; k < chunk; ++k) iteration();
+        e = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipStreamEndCapture"); }
+        e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphInstantiate"); }
+      }
+      hipError_t e = hipGraphLaunch(gexec, s);
+      if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
+    } else {
+      for (int k = 0; k < chunk; ++k) iteration();
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "solver iteration");
+    }
+    return QIRAL_OK;
+  };
+  auto post_copy = [&](int k) -> qiral_status {
+    QIRAL_HIP(hipMemcpyAsync(hbuf[k], ws + lay.off_state, sbytes, hipMemcpyDeviceToHost, s));
+    QIRAL_HIP(hipEventRecord(ev.e[k], s));
+    return QIRAL_OK;
+  };
 
   int restarts = 0;
   std::vector<double> true_rel(nsys, 0.0);
@@ -309,33 +350,24 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   while (true) {
     start_krylov();
     QIRAL_HIP(hipGetLastError());
-    long enqueued = 0;
-    // iterations until every system is done
+    // Iterations until every system is done.  The next chunk is queued before
+    // the states after the previous one are examined, so the GPU does not wait
+    // for the host; systems that are done skip the extra chunk's work.
+    int cur = 0;
+    if ((st = enqueue_chunk()) != QIRAL_OK) return st;
+    if ((st = post_copy(cur)) != QIRAL_OK) { free_graph(); return st; }
+    long enqueued = chunk;
     while (true) {
-      if (use_graph) {
-        if (!gexec) {
-          hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-          if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-          for (int k = 0; k < chunk; ++k) iteration();
-          e = hipStreamEndCapture(s, &graph);
-          if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipStreamEndCapture"); }
-          e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-          if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphInstantiate"); }
-        }
-        hipError_t e = hipGraphLaunch(gexec, s);
-        if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
-      } else {
-        for (int k = 0; k < chunk; ++k) iteration();
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "solver iteration");
-      }
+      if ((st = enqueue_chunk()) != QIRAL_OK) return st;
+      if ((st = post_copy(1 - cur)) != QIRAL_OK) { free_graph(); return st; }
       enqueued += chunk;
-      st = read_states();
-      if (st != QIRAL_OK) { free_graph(); return st; }
+      hipError_t e = hipEventSynchronize(ev.e[cur]);
+      if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipEventSynchronize"); }
       bool all_done = true;
-      for (int i = 0; i < nsys; ++i) all_done = all_done && (hst[i].status & ST_DONE);
+      for (int i = 0; i < nsys; ++i) all_done = all_done && (hbuf[cur][i].status & ST_DONE);
       if (all_done) break;
       if (enqueued > (long)prm->maxiter + 4l * chunk) break;   // device stops at maxiter; safety net
+      cur = 1 - cur;
     }
     // reconstruct x_e, export, FP64 true residual
     hop_sys(L, S_F64, false, 1, F_XH, F_XE, F_BE, 0, A_KAPPA, ST_ANY, 0, 0, FIN_NONE, CHI_AINV);   // x_e

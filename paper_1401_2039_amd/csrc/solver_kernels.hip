@@ -197,12 +197,18 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
 constexpr int RED_WG = 1024;
 __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int fin,
                                                    int mask) {
+  static_assert(sizeof(SysState) % 8 == 0 && sizeof(SysState) / 8 <= RED_WG, "state copy");
+  constexpr int NW8 = (int)(sizeof(SysState) / 8);
   const SysDesc &d = sdesc[blockIdx.x];
-  const int status = d.st->status;   // tested after the partials' loads are issued
+  // The system's state is copied to LDS while the partials load, so the scalar
+  // step below does not wait for another round trip to memory; the whole state
+  // is written back afterwards (no other kernel runs meanwhile).
+  __shared__ SysState sst;
+  const int tid = threadIdx.x, w = tid >> 6;
+  if (tid < NW8) ((unsigned long long *)&sst)[tid] = ((const unsigned long long *)d.st)[tid];
   const int np = d.g.nb;   // one partial per block
   const double *p = d.part + (size_t)slot * NV * (d.g.nb * 4);
   __shared__ double red[NV][RED_WG / WAVE];
-  const int tid = threadIdx.x, w = tid >> 6;
   const int npair = np >> 1;
   const double2 *q[NV];
 #pragma unroll
@@ -228,7 +234,6 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
 #pragma unroll
       for (int j = 0; j < 4; ++j) a[i][j] += x[i][j].x + x[i][j].y;
   }
-  if (!(status & mask)) return;   // uniform over the work-group
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = (a[i][0] + a[i][1]) + (a[i][2] + a[i][3]);
@@ -237,6 +242,7 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
     if (lane_id() == 0) red[i][w] = s;
   }
   __syncthreads();
+  if (!(sst.status & mask)) return;   // uniform over the work-group
   if (tid == 0) {
     double t[NV];
 #pragma unroll
@@ -245,8 +251,10 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
       for (int j = 0; j < RED_WG / WAVE; ++j) s += red[i][j];
       t[i] = s;
     }
-    finalize(d.st, fin, slot, t);
+    finalize(&sst, fin, slot, t);
   }
+  __syncthreads();
+  if (tid < NW8) ((unsigned long long *)d.st)[tid] = ((const unsigned long long *)&sst)[tid];
 }
 
 // ||b||^2 over both parities.
