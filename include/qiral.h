@@ -144,7 +144,7 @@ qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, 
 
 /* Autotune the hop's launch shape for this lattice, precision and number of
  * right-hand sides (waves per 64-site block 1 (F16S only), 2 or 4 (FP64: 4 only);
- * right-hand sides per lane 1..4, FP64 1, FP32 on 2 waves 1..2, 1 wave 1) by
+ * right-hand sides per lane 1..4, FP64 1..2, FP32 on 2 waves 1..2, 1 wave 1) by
  * timing each candidate on the stream; later hops and solves on this handle use
  * the fastest.  If the environment variable QIRAL_TUNE_CACHE names a file, the
  * result is looked up there first and stored there (JSON).  Allocates and frees

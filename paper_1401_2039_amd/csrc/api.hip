@@ -248,13 +248,14 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
   const long nb = lat->geo.nb;
   if (const char *e = getenv("QIRAL_HOP_NR")) c.nr = atoi(e);
   else c.nr = tuned_nr(lat, prec, (int)nrhs);
-  c.nr = std::max(1, std::min(c.nr, prec == QIRAL_F64 ? 1 : 4));   // FP64 with 2 RHS per lane spills
+  c.nr = std::max(1, std::min(c.nr, 4));
   if (c.nr > nrhs) c.nr = (int)nrhs;
   const long nitems = nb * ((nrhs + c.nr - 1) / c.nr);
   c.t = hop_split(prec, nitems);
   const int tt = lat->tuned_t[prec][nrhs < 4 ? nrhs : 4];
   if (tt && !getenv("QIRAL_HOP_SPLIT") && hop_nr_max(prec, tt) >= 1) c.t = tt;
   if (c.nr > hop_nr_max(prec, c.t)) c.t = (c.t == 1 && c.nr <= hop_nr_max(prec, 2)) ? 2 : 4;
+  c.nr = std::min(c.nr, hop_nr_max(prec, c.t));   // FP64 takes at most 2
   return c;
 }
 

@@ -47,10 +47,10 @@ const void *links_for(const qiral_lattice *lat, int prec);
 struct HopCfg { int t = 4, nr = 1; };
 // Largest number of right-hand sides per lane that a hop of storage precision
 // S with T waves per site block keeps in registers; 0: the split is not built
-// (FP64 needs T = 4; one wave per block fits only the F16S hop with one RHS;
-// FP32 on 2 waves per block spills at 3 RHS).
+// (FP64 needs T = 4 and spills at 3 RHS; one wave per block fits only the F16S
+// hop with one RHS; FP32 on 2 waves per block spills at 3 RHS).
 constexpr int hop_nr_max(int S, int T) {
-  return S == 0 ? (T == 4 ? 1 : 0) : T == 1 ? (S == 2 ? 1 : 0) : (S == 1 && T == 2) ? 2 : 4;
+  return S == 0 ? (T == 4 ? 2 : 0) : T == 1 ? (S == 2 ? 1 : 0) : (S == 1 && T == 2) ? 2 : 4;
 }
 int hop_split(int prec, long nwork);
 // Streaming (non-temporal) link loads and output stores for hops whose working

@@ -106,7 +106,7 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     double best = 1e30;
-    const int nrmax = prec == QIRAL_F64 ? 1 : 4;
+    const int nrmax = 4;   // further limited per shape by hop_nr_max
     for (int tt : {1, 2, 4}) {
       for (int n = 1; n <= std::min(std::min(nrmax, hop_nr_max(prec, tt)), (int)nrhs); ++n) {
         HopCfg c;

@@ -157,7 +157,7 @@ def _r12_near(U, x):
     return Ur
 
 
-@pytest.mark.parametrize("prec", [q.F32, q.F16S], ids=["f32", "f16s"])
+@pytest.mark.parametrize("prec", [q.F64, q.F32, q.F16S], ids=["f64", "f32", "f16s"])
 def test_launch_shapes_multi_rhs(prec, monkeypatch):
     """Every hop launch shape (1 (F16S), 2 or 4 waves per site block, 1..4
     right-hand sides per lane, including a last group with fewer) gives the
@@ -167,7 +167,9 @@ def test_launch_shapes_multi_rhs(prec, monkeypatch):
     cfg = latgen.small_config(dims, seed=50, kind="expih", eps=0.4, nrhs=5)
     lat = q.Lattice(dims, 0.12, cfg["U"])
     U, b = cfg["U"], cfg["b"]
-    if prec == q.F32:
+    if prec == q.F64:
+        Ur, br = U, b
+    elif prec == q.F32:
         Ur, br = storage.round_links_r12(U, np.complex64), storage.round_f32(b)
     else:
         Ur, br = storage.round_links_r12(U, "f16"), storage.round_f16s(b)
@@ -181,7 +183,8 @@ def test_launch_shapes_multi_rhs(prec, monkeypatch):
             lat.dslash_eo(out, src, 0, 0, prec, nrhs=5)
             got = host(lat.export_field(out, 0, prec, nrhs=5))
             for r in range(5):
-                assert parity_rel(got[r], want[r], 0) < (2e-6 if prec == q.F32 else 2e-3), (t, nr, r)
+                bar = {q.F64: 1e-12, q.F32: 2e-6, q.F16S: 2e-3}[prec]
+                assert parity_rel(got[r], want[r], 0) < bar, (t, nr, r)
 
 
 def test_tune_and_tuned_solve(tmp_path, monkeypatch):
