@@ -213,3 +213,51 @@ def test_block_order_solve_bitwise(monkeypatch):
         assert torch.equal(res[0][0], res[1][0]) and res[0][1] == res[1][1], (prec, nrhs)
     for r in range(3):
         assert S.true_rel_residual(cfg["U"], 0.12, 0.0, host(res[1][0])[r], cfg["b"][r]) <= 1e-10
+
+
+@pytest.mark.parametrize("solver", [q.CGNR_EO, q.BICGSTAB_EO, q.CRNR_EO], ids=["cgnr", "bicgstab", "crnr"])
+def test_zero_source(solver):
+    """b = 0: the solve stops at once with x = 0 (no 0/0 in the recurrences)."""
+    dims = (4, 4, 2, 4)
+    say("zero source", solver)
+    cfg = latgen.small_config(dims, seed=33, kind="expih", eps=0.3)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    b = np.zeros_like(cfg["b"])
+    for prec in ((q.F64, q.F32) if solver != q.CRNR_EO else (q.F64,)):
+        x, st, info = lat.solve(dev(b), tol=1e-10, solver=solver, inner_prec=prec)
+        assert st == 0 and info[0]["iterations"] == 0 and info[0]["true_rel_resid"] == 0.0
+        assert np.count_nonzero(host(x)) == 0
+
+
+def test_kappa_zero_is_the_identity():
+    """kappa = 0 leaves D = 1 (the twisted term 2 i kappa mu g5 vanishes with it):
+    the solve returns x = b after at most one iteration."""
+    dims = (4, 2, 2, 4)
+    say("kappa zero")
+    cfg = latgen.small_config(dims, seed=34, kind="haar")
+    for mu in (0.0, 0.3):
+        lat = q.Lattice(dims, 0.0, cfg["U"], mu=mu)
+        x, st, info = lat.solve(dev(cfg["b"]), tol=1e-12)
+        assert st == 0 and info[0]["iterations"] <= 1
+        want = W.apply_Ainv(0.0, mu, cfg["b"][0])
+        assert np.abs(host(x)[0] - want).max() <= 1e-15 * np.abs(want).max()
+
+
+def test_255_right_hand_sides():
+    """The largest batch one call takes (255 systems: the work items' system field
+    is 8 bits), on a 2^4 lattice; a few are compared with single solves."""
+    dims = (2, 2, 2, 2)
+    say("255 rhs")
+    cfg = latgen.small_config(dims, seed=35, kind="expih", eps=0.4, nrhs=255)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10)
+    assert st == 0 and len(info) == 255
+    xs = host(x)
+    for r in (0, 31, 32, 127, 254):
+        assert S.true_rel_residual(cfg["U"], 0.12, 0.0, xs[r], cfg["b"][r]) <= 1e-10
+        x1, st1, _ = lat.solve(dev(cfg["b"][r:r + 1]), tol=1e-10)
+        assert st1 == 0 and np.array_equal(host(x1)[0], xs[r])
+    with pytest.raises(q.QiralError):
+        q.qiral_solve(lat.handle, dims, torch.zeros((256,) + cfg["b"].shape[1:], dtype=torch.complex128, device="cuda"),
+                      torch.zeros((256,) + cfg["b"].shape[1:], dtype=torch.complex128, device="cuda"), 256,
+                      q.solve_params(tol=1e-10))
