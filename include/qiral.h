@@ -38,7 +38,8 @@
  *   description of the last failure.
  *
  *   Memory: a lattice handle owns the device memory of its packed links and
- *   of the solver workspace (grown on demand, released by
+ *   of the solver workspace, plus a small pinned host buffer for the solver's
+ *   convergence polls (both grown on demand, released by
  *   qiral_lattice_destroy).  Every other device buffer belongs to the caller.
  *   Calls on one handle must not overlap in time (they share its workspace).
  */
