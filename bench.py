@@ -352,8 +352,17 @@ def suite(lat1, q, latgen, np, torch, path=None, parts=(), hop_reps=None):
 
 
 def suite_c1(lat1, q, latgen, torch, path, timed_solve):
+    """Every solver form on the 16^3x32 workload, each judged against the oracle:
+    its true residual under the oracle's D, and its distance to the oracle's own
+    FP64 eo-CGNR solution."""
+    import time as _t
+    import numpy as np
+    from oracle import solvers as S, wilson as W
     cfg = latgen.make_config(1)
     b1 = torch.from_numpy(cfg["b"]).cuda()
+    t0 = _t.perf_counter()
+    xo, oinfo = S.solve_eo_cgnr(cfg["U"], cfg["kappa"], 0.0, cfg["b"][0], tol=1e-10)
+    log(f"[suite] oracle eo-CGNR on 16^3x32: {oinfo['iterations']} iterations in {_t.perf_counter() - t0:.1f}s")
     for name, kw in [("cgnr_f64", dict(inner_prec=q.F64)), ("cgnr_f32", dict(inner_prec=q.F32)),
                      ("cgnr_f16s", dict(inner_prec=q.F16S)), ("bicgstab_f64", dict(solver=q.BICGSTAB_EO)),
                      ("bicgstab_f32", dict(solver=q.BICGSTAB_EO, inner_prec=q.F32)),
@@ -361,10 +370,15 @@ def suite_c1(lat1, q, latgen, torch, path, timed_solve):
                      ("cgnr_f32_graph", dict(inner_prec=q.F32, use_graph=1))]:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            t, st, info, _ = timed_solve(lat1, b1, tol=1e-10, **kw)
+            t, st, info, x = timed_solve(lat1, b1, tol=1e-10, **kw)
+        stream.synchronize()
+        xg = x.cpu().numpy()[0]
         _emit({"kind": "solve", "workload": "16^3x32 eps0.3 k0.12 1rhs", "form": name, "seconds": round(t, 6),
                "status": st, "iterations": info[0]["iterations"], "reliable_updates": info[0]["reliable_updates"],
-               "true_rel_resid": info[0]["true_rel_resid"], "hops": info[0]["hop_applications"]}, path)
+               "true_rel_resid": info[0]["true_rel_resid"], "hops": info[0]["hop_applications"],
+               "oracle_judged_resid": S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, xg, cfg["b"][0]),
+               "rel_err_vs_oracle_x": float(np.sqrt(W.norm2(xg - xo) / W.norm2(xo))),
+               "oracle_iterations": oinfo["iterations"]}, path)
 
 
 
