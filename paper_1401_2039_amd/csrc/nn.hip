@@ -71,12 +71,12 @@ __device__ __forceinline__ void transport(const cpx<float> u[9], const cpx<float
       cpx<float> r;
       if (!adj) {
         r = cmul(u[3 * a], psi[s]);
-        r = cadd(r, cmul(u[3 * a + 1], psi[4 + s]));
-        r = cadd(r, cmul(u[3 * a + 2], psi[8 + s]));
+        r = cmac(u[3 * a + 1], psi[4 + s], r);
+        r = cmac(u[3 * a + 2], psi[8 + s], r);
       } else {
         r = cjmul(u[a], psi[s]);
-        r = cadd(r, cjmul(u[3 + a], psi[4 + s]));
-        r = cadd(r, cjmul(u[6 + a], psi[8 + s]));
+        r = cjmac(u[3 + a], psi[4 + s], r);
+        r = cjmac(u[6 + a], psi[8 + s], r);
       }
       t[4 * a + s] = r;
     }
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
           for (int q = 0; q < 4; ++q) {
             const cpx<float> wr = cmake(W[4 * r + q].x, W[4 * r + q].y);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) m[4 * a + r] = cadd(m[4 * a + r], cmul(wr, psi[4 * a + q]));
+            for (int a = 0; a < 3; ++a) m[4 * a + r] = cmac(wr, psi[4 * a + q], m[4 * a + r]);
           }
       }
       if (p == 0) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
             for (int q = 0; q < 4; ++q) {
               const cpx<float> wr = cmake(W[4 * r + q].x, W[4 * r + q].y);
 #pragma unroll
-              for (int a = 0; a < 3; ++a) acc[ii][4 * a + r] = cadd(acc[ii][4 * a + r], cmul(wr, t[4 * a + q]));
+              for (int a = 0; a < 3; ++a) acc[ii][4 * a + r] = cmac(wr, t[4 * a + q], acc[ii][4 * a + r]);
             }
           }
         }
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(Geo g, const void *__restrict
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[4 * r + q] = cadd(acc[4 * r + q], cjmul(t[4 * a + q], gg[4 * a + r]));
+        for (int a = 0; a < 3; ++a) acc[4 * r + q] = cjmac(t[4 * a + q], gg[4 * a + r], acc[4 * r + q]);
   }
   // fixed-order block reduction
   __shared__ double red[32][4];

@@ -55,6 +55,21 @@ template <class R> __device__ __forceinline__ cpx<R> cjmul(cpx<R> a, cpx<R> b) {
   return cmake(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
 template <class R> __device__ __forceinline__ cpx<R> cscale(R s, cpx<R> a) { return cmake(s * a.re, s * a.im); }
+// s * a + b (FP32), one rounding per part
+__device__ __forceinline__ cpx<float> cfma(float s, cpx<float> a, cpx<float> b) {
+  return cmake(__builtin_fmaf(s, a.re, b.re), __builtin_fmaf(s, a.im, b.im));
+}
+__device__ __forceinline__ float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a * b + c and conj(a) * b + c as chains of fused multiply-adds (4 per
+// complex product; the compiler does not fuse an add into a product's result)
+template <class R> __device__ __forceinline__ cpx<R> cmac(cpx<R> a, cpx<R> b, cpx<R> c) {
+  return cmake(rfma(a.re, b.re, rfma(-a.im, b.im, c.re)), rfma(a.re, b.im, rfma(a.im, b.re, c.im)));
+}
+template <class R> __device__ __forceinline__ cpx<R> cjmac(cpx<R> a, cpx<R> b, cpx<R> c) {
+  return cmake(rfma(a.re, b.re, rfma(a.im, b.im, c.re)), rfma(a.re, b.im, rfma(-a.im, b.re, c.im)));
+}
+template <class R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return cmake(-a.re, -a.im); }
 // multiply by +i and -i
 template <class R> __device__ __forceinline__ cpx<R> ci(cpx<R> a) { return cmake(-a.im, a.re); }
 template <class R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) { return cmake(a.im, -a.re); }
@@ -184,6 +199,19 @@ template <> struct SpinorIO<S_F16S> {
         v[4 * j + c] = cmake(h2f((unsigned short)(w[c] & 0xffffu)) * sc, h2f((unsigned short)(w[c] >> 16)) * sc);
     }
   }
+  // The stored FP16 values, unscaled, and the site's scale: the value is sc * v.
+  __device__ static void load_raw(const void *base, int s, size_t npad, cpx<float> v[12], float &sc) {
+    const uint4 *p = (const uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
+    sc = scale_ptr(base, npad)[s];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint4 q = p[j * WAVE];
+      unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        v[4 * j + c] = cmake(h2f((unsigned short)(w[c] & 0xffffu)), h2f((unsigned short)(w[c] >> 16)));
+    }
+  }
   // Quantise: scale = max |real| over the site's 24 reals, half = RNE(real / scale).
   __device__ static void store(void *base, int s, size_t npad, const cpx<float> v[12]) {
     float m = 0.f;
@@ -244,9 +272,9 @@ enum { L_F64R18 = 0, L_F32R12 = 1, L_F16R12 = 2 };
 template <class R> __device__ __forceinline__ void recon_row2(cpx<R> u[9]) {
   // u[6 + c] = conj( (row0 x row1)_c )
   cpx<R> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
-  cpx<R> c0 = csub(cmul(a1, b2), cmul(a2, b1));
-  cpx<R> c1 = csub(cmul(a2, b0), cmul(a0, b2));
-  cpx<R> c2 = csub(cmul(a0, b1), cmul(a1, b0));
+  cpx<R> c0 = cmac(a1, b2, cneg(cmul(a2, b1)));
+  cpx<R> c1 = cmac(a2, b0, cneg(cmul(a0, b2)));
+  cpx<R> c2 = cmac(a0, b1, cneg(cmul(a1, b0)));
   u[6] = cmake(c0.re, -c0.im);
   u[7] = cmake(c1.re, -c1.im);
   u[8] = cmake(c2.re, -c2.im);
@@ -320,12 +348,12 @@ __device__ __forceinline__ void su3_mul(const cpx<R> u[9], const cpx<R> h[6], cp
       cpx<R> r;
       if (!ADJ) {
         r = cmul(u[3 * a + 0], h[0 + sp]);
-        r = cadd(r, cmul(u[3 * a + 1], h[2 + sp]));
-        r = cadd(r, cmul(u[3 * a + 2], h[4 + sp]));
+        r = cmac(u[3 * a + 1], h[2 + sp], r);
+        r = cmac(u[3 * a + 2], h[4 + sp], r);
       } else {
         r = cjmul(u[0 + a], h[0 + sp]);
-        r = cadd(r, cjmul(u[3 + a], h[2 + sp]));
-        r = cadd(r, cjmul(u[6 + a], h[4 + sp]));
+        r = cjmac(u[3 + a], h[2 + sp], r);
+        r = cjmac(u[6 + a], h[4 + sp], r);
       }
       w[2 * a + sp] = r;
     }
@@ -381,6 +409,12 @@ template <int S, int N> struct FieldLd {
   const void *base[N];
   size_t npad;
   __device__ __forceinline__ void operator()(int r, int s, cpx<R> v[12]) const { SpinorIO<S>::load(base[r], s, npad, v); }
+  // F16S: the hop reads the unscaled FP16 values and applies the site scale
+  // once, in its accumulation (see hop_term)
+  static constexpr bool RAW = S == S_F16S;
+  __device__ __forceinline__ void raw(int r, int s, cpx<R> v[12], R &sc) const {
+    if constexpr (RAW) SpinorIO<S>::load_raw(base[r], s, npad, v, sc);
+  }
 };
 
 // Sum of an FP64 field and an FP32 field (the solution of a mixed-precision
@@ -388,6 +422,8 @@ template <int S, int N> struct FieldLd {
 struct SumLd {
   using R = double;
   static constexpr int NF = 1;
+  static constexpr bool RAW = false;
+  __device__ __forceinline__ void raw(int, int, cpx<double> *, double &) const {}
   const void *a;   // F64
   const void *b;   // F32, or null
   size_t npad;
@@ -444,11 +480,34 @@ __device__ __forceinline__ void hop_term(const Geo &g, const void *gauge, const 
 #pragma unroll
   for (int r = 0; r < Ld::NF; ++r) {
     cpx<R> psi[12], h[6], w[6];
-    ld(r, n, psi);
+    R sc = (R)1;
+    if constexpr (Ld::RAW) {
+      // F16S: project the unscaled FP16 values.  Each real of h is one
+      // mixed-precision fma (FP16 sources converted in the instruction), with
+      // a multiplier of 1 the compiler cannot fold away; the site scale sc
+      // enters below, as the multiplier of the accumulation (or of h for the
+      // term that initialises the accumulators).
+      ld.raw(r, n, psi, sc);
+      R one = (R)1;
+      asm volatile("" : "+s"(one));
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      h[2 * cc] = cadd(psi[4 * cc], cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]));
-      h[2 * cc + 1] = cadd(psi[4 * cc + 1], cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]));
+      for (int cc = 0; cc < 3; ++cc) {
+        const cpx<R> l0 = cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]), l1 = cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]);
+        h[2 * cc] = cmake(__builtin_fmaf(l0.re, one, psi[4 * cc].re), __builtin_fmaf(l0.im, one, psi[4 * cc].im));
+        h[2 * cc + 1] =
+            cmake(__builtin_fmaf(l1.re, one, psi[4 * cc + 1].re), __builtin_fmaf(l1.im, one, psi[4 * cc + 1].im));
+      }
+      if (FIRST && DIR == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = cscale(sc, h[k]);
+      }
+    } else {
+      ld(r, n, psi);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        h[2 * cc] = cadd(psi[4 * cc], cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]));
+        h[2 * cc + 1] = cadd(psi[4 * cc + 1], cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]));
+      }
     }
     su3_mul<DIR == 1>(u, h, w);
 #pragma unroll
@@ -458,6 +517,11 @@ __device__ __forceinline__ void hop_term(const Geo &g, const void *gauge, const 
       const cpx<R> lo1 = cph<B::e1 + ph>(w[2 * cc + B::j1]);
       if (FIRST && DIR == 0) {
         acc[r][4 * cc] = w0; acc[r][4 * cc + 1] = w1; acc[r][4 * cc + 2] = lo0; acc[r][4 * cc + 3] = lo1;
+      } else if constexpr (Ld::RAW) {
+        acc[r][4 * cc] = cfma(sc, w0, acc[r][4 * cc]);
+        acc[r][4 * cc + 1] = cfma(sc, w1, acc[r][4 * cc + 1]);
+        acc[r][4 * cc + 2] = cfma(sc, lo0, acc[r][4 * cc + 2]);
+        acc[r][4 * cc + 3] = cfma(sc, lo1, acc[r][4 * cc + 3]);
       } else {
         acc[r][4 * cc] = cadd(acc[r][4 * cc], w0);
         acc[r][4 * cc + 1] = cadd(acc[r][4 * cc + 1], w1);
