@@ -112,7 +112,7 @@ def main():
 
     def solve(prec, use_graph=0):
         st, info = q.qiral_solve(lat.handle, dims, x, b, 1,
-                                 q.solve_params(tol=1e-10, inner_prec=prec, delta=0.1, use_graph=use_graph))
+                                 q.solve_params(tol=1e-10, inner_prec=prec, use_graph=use_graph))
         if st != 0:
             raise RuntimeError(f"solve failed: status {st} {info}")
         return info[0]
