@@ -126,11 +126,21 @@ template <> struct SpinorIO<S_F64> {
   using R = double;
   static constexpr int UNITS = 12;
   static constexpr size_t SITE_BYTES = 192;
-  __device__ static void load(const void *base, int s, size_t npad, cpx<double> v[12]) {
+  struct Raw { double2 q[12]; };
+  __device__ static void fetch(const void *base, int s, size_t npad, Raw &r) {
     (void)npad;
     const double2 *p = (const double2 *)base + (size_t)(s >> 6) * (12 * WAVE) + (s & 63);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) { double2 q = p[k * WAVE]; v[k] = cmake(q.x, q.y); }
+    for (int k = 0; k < 12; ++k) r.q[k] = p[k * WAVE];
+  }
+  __device__ static void decode(const Raw &r, cpx<double> v[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = cmake(r.q[k].x, r.q[k].y);
+  }
+  __device__ static void load(const void *base, int s, size_t npad, cpx<double> v[12]) {
+    Raw r;
+    fetch(base, s, npad, r);
+    decode(r, v);
   }
   __device__ static void store(void *base, int s, size_t npad, const cpx<double> v[12]) {
     (void)npad;
@@ -151,15 +161,24 @@ template <> struct SpinorIO<S_F32> {
   using R = float;
   static constexpr int UNITS = 6;
   static constexpr size_t SITE_BYTES = 96;
-  __device__ static void load(const void *base, int s, size_t npad, cpx<float> v[12]) {
+  struct Raw { float4 q[6]; };
+  __device__ static void fetch(const void *base, int s, size_t npad, Raw &r) {
     (void)npad;
     const float4 *p = (const float4 *)base + (size_t)(s >> 6) * (6 * WAVE) + (s & 63);
 #pragma unroll
+    for (int j = 0; j < 6; ++j) r.q[j] = p[j * WAVE];
+  }
+  __device__ static void decode(const Raw &r, cpx<float> v[12]) {
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
-      float4 q = p[j * WAVE];
-      v[2 * j] = cmake(q.x, q.y);
-      v[2 * j + 1] = cmake(q.z, q.w);
+      v[2 * j] = cmake(r.q[j].x, r.q[j].y);
+      v[2 * j + 1] = cmake(r.q[j].z, r.q[j].w);
     }
+  }
+  __device__ static void load(const void *base, int s, size_t npad, cpx<float> v[12]) {
+    Raw r;
+    fetch(base, s, npad, r);
+    decode(r, v);
   }
   __device__ static void store(void *base, int s, size_t npad, const cpx<float> v[12]) {
     (void)npad;
@@ -200,17 +219,27 @@ template <> struct SpinorIO<S_F16S> {
     }
   }
   // The stored FP16 values, unscaled, and the site's scale: the value is sc * v.
-  __device__ static void load_raw(const void *base, int s, size_t npad, cpx<float> v[12], float &sc) {
+  struct Raw { uint4 q[3]; float sc; };
+  __device__ static void fetch(const void *base, int s, size_t npad, Raw &r) {
     const uint4 *p = (const uint4 *)base + (size_t)(s >> 6) * (3 * WAVE) + (s & 63);
-    sc = scale_ptr(base, npad)[s];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.q[j] = p[j * WAVE];
+    r.sc = scale_ptr(base, npad)[s];
+  }
+  __device__ static void decode_raw(const Raw &r, cpx<float> v[12], float &sc) {
+    sc = r.sc;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint4 q = p[j * WAVE];
-      unsigned w[4] = {q.x, q.y, q.z, q.w};
+      unsigned w[4] = {r.q[j].x, r.q[j].y, r.q[j].z, r.q[j].w};
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         v[4 * j + c] = cmake(h2f((unsigned short)(w[c] & 0xffffu)), h2f((unsigned short)(w[c] >> 16)));
     }
+  }
+  __device__ static void load_raw(const void *base, int s, size_t npad, cpx<float> v[12], float &sc) {
+    Raw r;
+    fetch(base, s, npad, r);
+    decode_raw(r, v, sc);
   }
   // Quantise: scale = max |real| over the site's 24 reals, half = RNE(real / scale).
   __device__ static void store(void *base, int s, size_t npad, const cpx<float> v[12]) {
@@ -282,46 +311,80 @@ template <class R> __device__ __forceinline__ void recon_row2(cpx<R> u[9]) {
 
 template <int L> struct LinkIO;
 
+// Each link store has fetch (the loads only, into Raw), decode (conversion
+// and row-2 rebuild) and load (both).
 template <> struct LinkIO<L_F64R18> {
   using R = double;
   static constexpr size_t LINK_BYTES = 144;
+  struct Raw { double2 q[9]; };
   template <bool NT = false>
-  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {
+  __device__ static void fetch(const void *g, int par, int mu, int s, int nb, Raw &r) {
     const double2 *p = (const double2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 9) * WAVE + (s & 63);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) { double2 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE]; u[j] = cmake(q.x, q.y); }
+    for (int j = 0; j < 9; ++j) r.q[j] = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
+  }
+  __device__ static void decode(const Raw &r, cpx<double> u[9]) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) u[j] = cmake(r.q[j].x, r.q[j].y);
+  }
+  template <bool NT = false>
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {
+    Raw r;
+    fetch<NT>(g, par, mu, s, nb, r);
+    decode(r, u);
   }
 };
 
 template <> struct LinkIO<L_F32R12> {
   using R = float;
   static constexpr size_t LINK_BYTES = 48;
+  struct Raw { float4 q[3]; };
   template <bool NT = false>
-  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+  __device__ static void fetch(const void *g, int par, int mu, int s, int nb, Raw &r) {
     const float4 *p = (const float4 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
+    for (int j = 0; j < 3; ++j) r.q[j] = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
+  }
+  __device__ static void decode(const Raw &r, cpx<float> u[9]) {
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float4 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
-      u[2 * j] = cmake(q.x, q.y);
-      u[2 * j + 1] = cmake(q.z, q.w);
+      u[2 * j] = cmake(r.q[j].x, r.q[j].y);
+      u[2 * j + 1] = cmake(r.q[j].z, r.q[j].w);
     }
     recon_row2(u);
+  }
+  template <bool NT = false>
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+    Raw r;
+    fetch<NT>(g, par, mu, s, nb, r);
+    decode(r, u);
   }
 };
 
 template <> struct LinkIO<L_F16R12> {
   using R = float;
   static constexpr size_t LINK_BYTES = 24;
+  struct Raw { uint2 q[3]; };
   template <bool NT = false>
-  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+  __device__ static void fetch(const void *g, int par, int mu, int s, int nb, Raw &r) {
     const uint2 *p = (const uint2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 3) * WAVE + (s & 63);
 #pragma unroll
+    for (int j = 0; j < 3; ++j) r.q[j] = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
+  }
+  __device__ static void decode(const Raw &r, cpx<float> u[9]) {
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint2 q = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
+      const uint2 q = r.q[j];
       u[2 * j] = cmake(h2f((unsigned short)(q.x & 0xffffu)), h2f((unsigned short)(q.x >> 16)));
       u[2 * j + 1] = cmake(h2f((unsigned short)(q.y & 0xffffu)), h2f((unsigned short)(q.y >> 16)));
     }
     recon_row2(u);
+  }
+  template <bool NT = false>
+  __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<float> u[9]) {
+    Raw r;
+    fetch<NT>(g, par, mu, s, nb, r);
+    decode(r, u);
   }
 };
 
@@ -415,6 +478,18 @@ template <int S, int N> struct FieldLd {
   __device__ __forceinline__ void raw(int r, int s, cpx<R> v[12], R &sc) const {
     if constexpr (RAW) SpinorIO<S>::load_raw(base[r], s, npad, v, sc);
   }
+  // One FP32 field: the hop issues the loads of both directions of a dimension
+  // before it uses either (hop_mu), one memory round trip instead of two.
+  // Measured: 6% off the latency-bound 16^3x32 hop; the F16S hop, bound by its
+  // vector work, lost occupancy and ran up to 11% slower, and the FP64 hop has
+  // no registers to spare.
+  static constexpr bool PAIR = N == 1 && S == S_F32;
+  using Raw = typename SpinorIO<S>::Raw;
+  __device__ __forceinline__ void fetch(int r, int s, Raw &w) const { SpinorIO<S>::fetch(base[r], s, npad, w); }
+  __device__ __forceinline__ void decode(const Raw &w, cpx<R> v[12], R &sc) const {
+    if constexpr (RAW) SpinorIO<S>::decode_raw(w, v, sc);
+    else { SpinorIO<S>::decode(w, v); sc = (R)1; }
+  }
 };
 
 // Sum of an FP64 field and an FP32 field (the solution of a mixed-precision
@@ -423,6 +498,7 @@ struct SumLd {
   using R = double;
   static constexpr int NF = 1;
   static constexpr bool RAW = false;
+  static constexpr bool PAIR = false;
   __device__ __forceinline__ void raw(int, int, cpx<double> *, double &) const {}
   const void *a;   // F64
   const void *b;   // F32, or null
@@ -462,81 +538,132 @@ template <int F, class R> __device__ __forceinline__ cpx<R> cph(cpx<R> z) {
 // backward neighbour with U_mu(x - mu)^+ and (1 + gamma_mu) (DAG: 1 - gamma_mu).
 // Each link is loaded and rebuilt once for all fields.  FIRST: the term
 // initialises the accumulators.
+// The arithmetic of one term for one field: project psi (RAW: the unscaled
+// FP16 values of an F16S site with scale sc), multiply by the link, rebuild
+// the lower half and accumulate.
+template <int MU, int DIR, bool DAG, bool FIRST, bool RAW, class R>
+__device__ __forceinline__ void term_acc(const cpx<R> u[9], const cpx<R> psi[12], R sc, cpx<R> acc[12]) {
+  using B = SpinB<MU>;
+  constexpr int ph = ((DIR == 0) == DAG) ? 0 : 2;   // the projection sign as a phase
+  cpx<R> h[6], w[6];
+  if constexpr (RAW) {
+    // F16S: each real of h is one mixed-precision fma (FP16 sources converted
+    // in the instruction), with a multiplier of 1 the compiler cannot fold
+    // away; the site scale sc enters below, as the multiplier of the
+    // accumulation (or of h for the term that initialises the accumulators).
+    R one = (R)1;
+    asm volatile("" : "+s"(one));
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const cpx<R> l0 = cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]), l1 = cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]);
+      h[2 * cc] = cmake(__builtin_fmaf(l0.re, one, psi[4 * cc].re), __builtin_fmaf(l0.im, one, psi[4 * cc].im));
+      h[2 * cc + 1] =
+          cmake(__builtin_fmaf(l1.re, one, psi[4 * cc + 1].re), __builtin_fmaf(l1.im, one, psi[4 * cc + 1].im));
+    }
+    if (FIRST && DIR == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = cscale(sc, h[k]);
+    }
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      h[2 * cc] = cadd(psi[4 * cc], cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]));
+      h[2 * cc + 1] = cadd(psi[4 * cc + 1], cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]));
+    }
+  }
+  su3_mul<DIR == 1>(u, h, w);
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const cpx<R> w0 = w[2 * cc], w1 = w[2 * cc + 1];
+    const cpx<R> lo0 = cph<B::e0 + ph>(w[2 * cc + B::j0]);
+    const cpx<R> lo1 = cph<B::e1 + ph>(w[2 * cc + B::j1]);
+    if (FIRST && DIR == 0) {
+      acc[4 * cc] = w0; acc[4 * cc + 1] = w1; acc[4 * cc + 2] = lo0; acc[4 * cc + 3] = lo1;
+    } else if constexpr (RAW) {
+      acc[4 * cc] = cfma(sc, w0, acc[4 * cc]);
+      acc[4 * cc + 1] = cfma(sc, w1, acc[4 * cc + 1]);
+      acc[4 * cc + 2] = cfma(sc, lo0, acc[4 * cc + 2]);
+      acc[4 * cc + 3] = cfma(sc, lo1, acc[4 * cc + 3]);
+    } else {
+      acc[4 * cc] = cadd(acc[4 * cc], w0);
+      acc[4 * cc + 1] = cadd(acc[4 * cc + 1], w1);
+      acc[4 * cc + 2] = cadd(acc[4 * cc + 2], lo0);
+      acc[4 * cc + 3] = cadd(acc[4 * cc + 3], lo1);
+    }
+  }
+}
+
+template <class R, class RL> __device__ __forceinline__ void link_cvt(const cpx<RL> u0[9], cpx<R> u[9]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+}
+
 template <int MU, int DIR, bool DAG, bool FIRST, int L, bool NT, class Ld>
 __device__ __forceinline__ void hop_term(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
                                          cpx<typename Ld::R> acc[Ld::NF][12]) {
   using R = typename Ld::R;
-  using B = SpinB<MU>;
-  constexpr int ph = ((DIR == 0) == DAG) ? 0 : 2;   // the projection sign as a phase
   const int n = nbr(g, c, MU, DIR == 0);
   cpx<R> u[9];
   {
     cpx<typename LinkIO<L>::R> u0[9];
     if (DIR == 0) LinkIO<L>::template load<NT>(gauge, p, MU, c.s, g.nb, u0);
     else LinkIO<L>::template load<NT>(gauge, 1 - p, MU, n, g.nb, u0);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) u[j] = cmake((R)u0[j].re, (R)u0[j].im);
+    link_cvt(u0, u);
   }
 #pragma unroll
   for (int r = 0; r < Ld::NF; ++r) {
-    cpx<R> psi[12], h[6], w[6];
+    cpx<R> psi[12];
     R sc = (R)1;
-    if constexpr (Ld::RAW) {
-      // F16S: project the unscaled FP16 values.  Each real of h is one
-      // mixed-precision fma (FP16 sources converted in the instruction), with
-      // a multiplier of 1 the compiler cannot fold away; the site scale sc
-      // enters below, as the multiplier of the accumulation (or of h for the
-      // term that initialises the accumulators).
-      ld.raw(r, n, psi, sc);
-      R one = (R)1;
-      asm volatile("" : "+s"(one));
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        const cpx<R> l0 = cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]), l1 = cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]);
-        h[2 * cc] = cmake(__builtin_fmaf(l0.re, one, psi[4 * cc].re), __builtin_fmaf(l0.im, one, psi[4 * cc].im));
-        h[2 * cc + 1] =
-            cmake(__builtin_fmaf(l1.re, one, psi[4 * cc + 1].re), __builtin_fmaf(l1.im, one, psi[4 * cc + 1].im));
-      }
-      if (FIRST && DIR == 0) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) h[k] = cscale(sc, h[k]);
-      }
-    } else {
-      ld(r, n, psi);
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        h[2 * cc] = cadd(psi[4 * cc], cph<B::f0 + ph>(psi[4 * cc + 2 + B::j0]));
-        h[2 * cc + 1] = cadd(psi[4 * cc + 1], cph<B::f1 + ph>(psi[4 * cc + 2 + B::j1]));
-      }
-    }
-    su3_mul<DIR == 1>(u, h, w);
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const cpx<R> w0 = w[2 * cc], w1 = w[2 * cc + 1];
-      const cpx<R> lo0 = cph<B::e0 + ph>(w[2 * cc + B::j0]);
-      const cpx<R> lo1 = cph<B::e1 + ph>(w[2 * cc + B::j1]);
-      if (FIRST && DIR == 0) {
-        acc[r][4 * cc] = w0; acc[r][4 * cc + 1] = w1; acc[r][4 * cc + 2] = lo0; acc[r][4 * cc + 3] = lo1;
-      } else if constexpr (Ld::RAW) {
-        acc[r][4 * cc] = cfma(sc, w0, acc[r][4 * cc]);
-        acc[r][4 * cc + 1] = cfma(sc, w1, acc[r][4 * cc + 1]);
-        acc[r][4 * cc + 2] = cfma(sc, lo0, acc[r][4 * cc + 2]);
-        acc[r][4 * cc + 3] = cfma(sc, lo1, acc[r][4 * cc + 3]);
-      } else {
-        acc[r][4 * cc] = cadd(acc[r][4 * cc], w0);
-        acc[r][4 * cc + 1] = cadd(acc[r][4 * cc + 1], w1);
-        acc[r][4 * cc + 2] = cadd(acc[r][4 * cc + 2], lo0);
-        acc[r][4 * cc + 3] = cadd(acc[r][4 * cc + 3], lo1);
-      }
-    }
+    if constexpr (Ld::RAW) ld.raw(r, n, psi, sc);
+    else ld(r, n, psi);
+    term_acc<MU, DIR, DAG, FIRST, Ld::RAW>(u, psi, sc, acc[r]);
   }
+}
+
+// The loads of one term of a single-field loader (see FieldLd::PAIR).
+template <int L, class Ld> struct TermIn {
+  typename LinkIO<L>::Raw lr;
+  typename Ld::Raw sr;
+};
+
+template <int MU, int DIR, int L, bool NT, class Ld>
+__device__ __forceinline__ void term_fetch(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
+                                           TermIn<L, Ld> &in) {
+  const int n = nbr(g, c, MU, DIR == 0);
+  if (DIR == 0) LinkIO<L>::template fetch<NT>(gauge, p, MU, c.s, g.nb, in.lr);
+  else LinkIO<L>::template fetch<NT>(gauge, 1 - p, MU, n, g.nb, in.lr);
+  ld.fetch(0, n, in.sr);
+}
+
+template <int MU, int DIR, bool DAG, bool FIRST, int L, class Ld>
+__device__ __forceinline__ void term_use(const Ld &ld, const TermIn<L, Ld> &in, cpx<typename Ld::R> acc[12]) {
+  using R = typename Ld::R;
+  cpx<R> u[9], psi[12];
+  {
+    cpx<typename LinkIO<L>::R> u0[9];
+    LinkIO<L>::decode(in.lr, u0);
+    link_cvt(u0, u);
+  }
+  R sc;
+  ld.decode(in.sr, psi, sc);
+  term_acc<MU, DIR, DAG, FIRST, Ld::RAW>(u, psi, sc, acc);
 }
 
 template <int MU, bool DAG, bool FIRST, int L, bool NT, class Ld>
 __device__ __forceinline__ void hop_mu(const Geo &g, const void *gauge, const Ld &ld, const SiteC &c, int p,
                                        cpx<typename Ld::R> acc[Ld::NF][12]) {
-  hop_term<MU, 0, DAG, FIRST, L, NT>(g, gauge, ld, c, p, acc);
-  hop_term<MU, 1, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+  if constexpr (Ld::PAIR) {
+    TermIn<L, Ld> f, b;
+    term_fetch<MU, 0, L, NT>(g, gauge, ld, c, p, f);
+    term_fetch<MU, 1, L, NT>(g, gauge, ld, c, p, b);
+    // keep the scheduler from sinking the second fetch below the first use
+    __builtin_amdgcn_sched_barrier(0);
+    term_use<MU, 0, DAG, FIRST, L>(ld, f, acc[0]);
+    term_use<MU, 1, DAG, false, L>(ld, b, acc[0]);
+  } else {
+    hop_term<MU, 0, DAG, FIRST, L, NT>(g, gauge, ld, c, p, acc);
+    hop_term<MU, 1, DAG, false, L, NT>(g, gauge, ld, c, p, acc);
+  }
 }
 
 // acc[r] = this wave group's part of (H psi_r)(s) (DAG: H^dagger) for output
