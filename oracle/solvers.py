@@ -9,6 +9,10 @@
   an addition to the paper's solvers, on the same Schur system.
 * ``fgmres``: flexible GMRES(m) with a right preconditioner that may change
   between iterations (Saad, SIAM J. Sci. Comput. 14, 1993).
+* ``fcg``: flexible conjugate gradients (Notay, SIAM J. Sci. Comput. 22,
+  2000) for a Hermitian positive definite operator with a preconditioner that
+  may vary between steps; ``solve_fcg_normal`` runs it on the normal equations
+  D^dag D x = D^dag b with the preconditioner N N^dag of a network N ~ D^-1.
 * ``crnr``: the conjugate residual method (Saad, Iterative Methods for Sparse
   Linear Systems, 2nd ed., Alg. 6.20) on the normal equations A^dag A x =
   A^dag b, a residual-minimising counterpart of CGNR (Sec. 5 compares CGNR with
@@ -246,3 +250,46 @@ def fgmres(apply_A, b, precond, m=20, tol=1e-10, maxiter=1000, x0=None):
             x = x + y[j] * Z[j]
         cycles += 1
     return x, steps, cycles
+
+
+def fcg(apply_A, b, precond, eps=0.0, maxiter=1000, x0=None, mmax=1, done=None):
+    """Truncated flexible CG for A x = b, A Hermitian positive definite.  Each
+    step preconditions the residual, z = precond(r), makes it A-conjugate to
+    the last mmax directions, p = z - sum_i ((A p_i | z) / (p_i | A p_i)) p_i,
+    and moves along p by alpha = (p | r) / (p | A p).  With a fixed Hermitian
+    positive definite preconditioner (and mmax >= 1) this is preconditioned
+    CG; with the identity it is CG.  Stops when (r | r) <= eps, or when
+    done(x) is true if given.  Returns (x, iterations, history of (r | r))."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    dirs = []   # (p_i, A p_i, (p_i | A p_i)) of the last mmax steps
+    hist = [W.norm2(r)]
+    it = 0
+    while it < maxiter and not (done(x) if done is not None else hist[-1] <= eps):
+        z = precond(r)
+        p = z.copy()
+        for pi, qi, di in dirs:
+            p = p - (W.inner(qi, z) / di) * pi
+        q = apply_A(p)
+        d = W.inner(p, q).real
+        if not d > 0:
+            break
+        alpha = W.inner(p, r) / d
+        x = x + alpha * p
+        r = r - alpha * q
+        dirs.append((p, q, d))
+        dirs = dirs[-mmax:]
+        hist.append(W.norm2(r))
+        it += 1
+    return x, it, hist
+
+
+def solve_fcg_normal(U, kappa, mu, b, apply_N, apply_Ndag, tol=1e-10, maxiter=1000):
+    """FCG(1) on D^dag D x = D^dag b, preconditioned by N N^dag, stopping when
+    the full-system residual ||b - D x|| is at most tol ||b||."""
+    A = lambda v: W.apply_Ddag(U, kappa, mu, W.apply_D(U, kappa, mu, v))
+    c = W.apply_Ddag(U, kappa, mu, b)
+    lim = tol * np.sqrt(W.norm2(b))
+    done = lambda x: np.sqrt(W.norm2(b - W.apply_D(U, kappa, mu, x))) <= lim
+    x, it, _ = fcg(A, c, lambda r: apply_N(apply_Ndag(r)), maxiter=maxiter, done=done)
+    return x, dict(iterations=it, true_rel_resid=true_rel_residual(U, kappa, mu, x, b))

@@ -57,6 +57,68 @@ def test_fgmres_c0(c0):
     assert stepsn < steps
 
 
+def test_fcg_identity_is_cgnr(c0):
+    """FCG with the identity on D^dag D x = D^dag b takes CGNR's iterates."""
+    cfg, xd = c0
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    D = lambda v: W.apply_D(U, k, 0.0, v)
+    Dd = lambda v: W.apply_Ddag(U, k, 0.0, v)
+    for n in (1, 4, 10):
+        xf, itf, _ = S.fcg(lambda v: Dd(D(v)), Dd(b), lambda r: r, maxiter=n)
+        xc, itc, _ = S.cgnr(D, Dd, b, 0.0, maxiter=n)
+        assert itf == itc == n
+        assert _rel(xf, xc) < 1e-11, n
+
+
+def test_fcg_normal_with_network_c0(c0):
+    """FCG on the normal equations with N N^dag (N: the Neumann-2 network) reaches
+    the direct solution, in fewer steps than with the identity."""
+    cfg, xd = c0
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    w = ptc.neumann2_weights(k)
+    N = lambda v: ptc.network(U, w, v)
+    Nd = lambda v: ptc.network_adjoint(U, w, v)
+    x, info = S.solve_fcg_normal(U, k, 0.0, b, N, Nd, tol=1e-10)
+    assert info["true_rel_resid"] <= 1e-10
+    assert _rel(x, xd) < 1e-9
+    x1, info1 = S.solve_fcg_normal(U, k, 0.0, b, lambda v: v, lambda v: v, tol=1e-10)
+    assert info1["true_rel_resid"] <= 1e-10
+    assert info["iterations"] < info1["iterations"]
+
+
+def test_fcg_directions_are_conjugate_with_a_varying_preconditioner(c0):
+    """With a preconditioner that changes every step, each new FCG direction is
+    still A-conjugate to the last mmax ones (the step that makes FCG flexible),
+    and the iteration still converges."""
+    cfg, _ = c0
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    A0 = lambda v: W.apply_Ddag(U, k, 0.0, W.apply_D(U, k, 0.0, v))
+    ps = []
+
+    def A(v):
+        ps.append(v.copy())
+        return A0(v)
+
+    rng = np.random.default_rng(3)
+    shape = b.shape
+
+    def precond(r):   # a different positive diagonal every call
+        return r * rng.uniform(0.5, 2.0, size=shape)
+
+    c = W.apply_Ddag(U, k, 0.0, b)
+    for mmax in (1, 3):
+        ps.clear()
+        x, it, hist = S.fcg(A, c, precond, eps=(1e-10) ** 2 * W.norm2(c), maxiter=400, mmax=mmax)
+        assert hist[-1] <= (1e-10) ** 2 * W.norm2(c), (mmax, it)
+        Ap = [A0(p) for p in ps]
+        nA = [np.sqrt(W.inner(p, q).real) for p, q in zip(ps, Ap)]
+        worst = 0.0
+        for i in range(1, min(len(ps), 30)):
+            for j in range(max(0, i - mmax), i):
+                worst = max(worst, abs(W.inner(ps[i], Ap[j])) / (nA[i] * nA[j]))
+        assert worst < 1e-10, (mmax, worst)
+
+
 def test_eo_crnr_c0(c0):
     cfg, xd = c0
     x, info = S.solve_eo_crnr(cfg["U"], cfg["kappa"], 0.0, cfg["b"][0], tol=1e-10)
