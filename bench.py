@@ -466,8 +466,8 @@ def suite_c3(q, latgen, torch, path, timed_solve):
 
 def suite_c4(q, latgen, torch, path, timed_solve):
     """24^3x48, exp(0.5 i H), kappa 0.125, 12 Gaussian sources: the 2-layer network
-    (8 hidden channels) trained on 2048 pairs (D v, v), FGMRES(20) with it, against
-    plain even-odd CGNR in FP64 and the mixed batched CGNR."""
+    (8 hidden channels) trained on 2048 pairs (D v, v), FGMRES(20) and FCG with it,
+    against plain even-odd CGNR in FP64 and the mixed batched CGNR."""
     import time as _t
     import numpy as np
     c4 = latgen.make_config(4)
@@ -501,6 +501,18 @@ def suite_c4(q, latgen, torch, path, timed_solve):
            "seconds": round(t_nn, 4), "status": st, "iterations": [i["iterations"] for i in info],
            "fell_back": [i["fell_back"] for i in info],
            "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    # flexible CG on the normal equations with N N^dagger, same network
+    pf = q.solve_params(solver=q.FCG_NN, tol=1e-10, maxiter=4000)
+    pf.precond = net.handle
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    st, info = q.qiral_solve(lat.handle, lat.dims, x, b, 12, pf)
+    t_fcg = _t.perf_counter() - t0
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "fcg_trained",
+           "seconds": round(t_fcg, 4), "status": st, "iterations": [i["iterations"] for i in info],
+           "fell_back": [i["fell_back"] for i in info],
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
     tseq = 0.0
     its = []
     for r in range(12):
@@ -515,7 +527,7 @@ def suite_c4(q, latgen, torch, path, timed_solve):
            "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
     gain = tseq - t_nn
     _emit({"kind": "summary", "workload": "24^3x48 eps0.5 k0.125", "training_s": round(t_train, 3),
-           "fgmres_12rhs_s": round(t_nn, 4), "cgnr_f64_12rhs_s": round(tseq, 4),
+           "fgmres_12rhs_s": round(t_nn, 4), "fcg_12rhs_s": round(t_fcg, 4), "cgnr_f64_12rhs_s": round(tseq, 4),
            "break_even_solves_of_12": (round(t_train / gain, 2) if gain > 0 else None)}, path)
     net.close()
     lat.close()

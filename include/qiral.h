@@ -81,10 +81,14 @@ typedef enum {
   QIRAL_CGNR_EO = 0,     /* CGNR (Fig. "CG") on the Schur system ("schur" template) */
   QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system      */
   QIRAL_FGMRES_NN = 2,   /* FGMRES(m) on D with the learned preconditioner          */
-  QIRAL_CRNR_EO = 3      /* conjugate residual (Saad, Alg. 6.20) on the Schur normal
+  QIRAL_CRNR_EO = 3,     /* conjugate residual (Saad, Alg. 6.20) on the Schur normal
                             equations S^dagger S x_o = S^dagger b_hat, stopping on the
                             Schur residual like CGNR; FP64 only (inner_prec F64,
                             otherwise QIRAL_ERR_UNSUPPORTED)                          */
+  QIRAL_FCG_NN = 4       /* flexible CG (Notay, SIAM J. Sci. Comput. 22, 2000), FCG(1),
+                            on the normal equations D^dagger D x = D^dagger b with the
+                            preconditioner N N^dagger of the learned network N; stops
+                            on ||b - D x||; FP64 (inner_prec F64)                    */
 } qiral_solver;
 
 /* Bit i of lo_precs asks lattice_create for a packed link store of precision i. */
@@ -154,7 +158,8 @@ qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, int32
                         double *best_us, qiral_stream_t stream);
 
 typedef struct {
-  qiral_solver solver; /* QIRAL_CGNR_EO (default), QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN, QIRAL_CRNR_EO */
+  qiral_solver solver; /* QIRAL_CGNR_EO (default), QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN,
+                          QIRAL_CRNR_EO, QIRAL_FCG_NN                                    */
   double tol;          /* relative FP64 residual ||b - D x|| / ||b|| to reach (e.g. 1e-10)   */
   int32_t maxiter;     /* iteration limit (outer iterations of the solver)                    */
   qiral_prec inner_prec; /* F64: plain solve.  F32/F16S: reduced-precision iterations with
@@ -162,9 +167,10 @@ typedef struct {
   double delta;        /* reliable-update trigger: ||r|| < delta * max ||r|| since last one,
                           in (0, 1); 0.01 keeps the FP64 iteration counts on the workloads
                           tried (F32 and F16S) with 4-5 updates per 1e-10 solve           */
-  int32_t restart;     /* FGMRES restart length m                                            */
-  const qiral_nn *precond; /* learned preconditioner for QIRAL_FGMRES_NN                       */
-  int32_t fallback_cg; /* FGMRES: on stagnation continue with eo-CGNR from the current x      */
+  int32_t restart;     /* FGMRES restart length m (FCG keeps one previous direction)           */
+  const qiral_nn *precond; /* learned preconditioner for QIRAL_FGMRES_NN and QIRAL_FCG_NN       */
+  int32_t fallback_cg; /* FGMRES, FCG: on stagnation or breakdown continue with eo-CGNR from
+                          the current x                                                    */
   int32_t x0_is_guess; /* start from the x passed in instead of 0                              */
   int32_t use_graph;   /* capture the iteration in a HIP graph and replay it                   */
   int32_t check_every; /* iterations enqueued between convergence checks (0: automatic)        */
@@ -174,7 +180,7 @@ typedef struct {
   int32_t iterations;        /* solver iterations                                   */
   int32_t reliable_updates;  /* FP64 residual replacements (mixed precision)        */
   int32_t converged;         /* 1 if true_rel_resid <= tol                          */
-  int32_t fell_back;         /* FGMRES switched to CGNR                             */
+  int32_t fell_back;         /* FGMRES or FCG switched to CGNR                      */
   double true_rel_resid;     /* ||b - D x|| / ||b|| recomputed in FP64 at the end   */
   double seconds;            /* wall time of the call                               */
   int64_t hop_applications;  /* H_eo / H_oe applications (units of V/2 sites)       */
@@ -206,7 +212,7 @@ qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_cano
  * runs in FP32 on the lattice's FP32 links, on packed FP32 FULL fields.  It is
  * created with the weights of 1 + kappa H + kappa^2 H^2 (channel 0 carries psi,
  * channel 1 carries H psi).  It is used by qiral_solve with solver
- * QIRAL_FGMRES_NN and params.precond pointing to it. */
+ * QIRAL_FGMRES_NN or QIRAL_FCG_NN and params.precond pointing to it. */
 
 /* hidden = 2, 4 or 8; the lattice needs FP32 links.  The handle owns its device
  * memory (weights, optimiser state, activations, FGMRES workspace). */

@@ -19,7 +19,7 @@ F64, F32, F16S = 0, 1, 2
 RECON18, RECON12 = 18, 12
 EVEN, ODD, FULL = 0, 1, 2
 OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG = 0, 1, 2, 3
-CGNR_EO, BICGSTAB_EO, FGMRES_NN, CRNR_EO = 0, 1, 2, 3
+CGNR_EO, BICGSTAB_EO, FGMRES_NN, CRNR_EO, FCG_NN = 0, 1, 2, 3, 4
 LINKS_F32, LINKS_F16 = 1 << F32, 1 << F16S
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR_BAD_DIMS",

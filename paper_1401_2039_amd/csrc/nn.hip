@@ -381,13 +381,31 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ part, in
 
 // ---------------------------------------------------------------------------
 // FP64 full-field vector kernels for FGMRES (both halves, padding stays zero)
-__global__ __launch_bounds__(256) void k_cvt64to32(const double2 *__restrict__ a, float2 *__restrict__ b, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+// Packed F64 full field <-> packed F32 full field, site by site (the two
+// layouts order a site's components differently within a 64-site block, so
+// the conversion goes through the spinor loaders).  One thread per padded
+// site of either parity; padding sites are copied too (they hold zeros).
+__global__ __launch_bounds__(256) void k_cvt64to32(Geo g, const void *__restrict__ a, void *__restrict__ b) {
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * npad) return;
+  const int par = (int)(gid / npad), s = (int)(gid % npad);
+  cpx<double> v[12];
+  SpinorIO<S_F64>::load((const char *)a + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, v);
+  cpx<float> w[12];
+  cvt12(v, w);
+  SpinorIO<S_F32>::store((char *)b + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, w);
 }
-__global__ __launch_bounds__(256) void k_cvt32to64(const float2 *__restrict__ a, double2 *__restrict__ b, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = make_double2((double)a[i].x, (double)a[i].y);
+__global__ __launch_bounds__(256) void k_cvt32to64(Geo g, const void *__restrict__ a, void *__restrict__ b) {
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * npad) return;
+  const int par = (int)(gid / npad), s = (int)(gid % npad);
+  cpx<float> v[12];
+  SpinorIO<S_F32>::load((const char *)a + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, v);
+  cpx<double> w[12];
+  cvt12(v, w);
+  SpinorIO<S_F64>::store((char *)b + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, w);
 }
 
 // Complex dots (V_i | w) for i < k, with partials per work-group.
@@ -478,6 +496,35 @@ __global__ __launch_bounds__(256) void k_bminus(const double2 *__restrict__ b, d
   if (i < n) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
 }
 
+// FCG step: x += alpha p, r -= alpha q, s -= alpha w (alpha = coef[0]); partial
+// sums of |s|^2 per work-group
+__global__ __launch_bounds__(256) void k_fcg_upd(const double2 *__restrict__ coef, const double2 *__restrict__ p,
+                                                 const double2 *__restrict__ q, const double2 *__restrict__ w,
+                                                 double2 *__restrict__ x, double2 *__restrict__ r,
+                                                 double2 *__restrict__ sv, size_t n, double *__restrict__ part) {
+  __shared__ double red[4];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  if (i < n) {
+    const double2 al = coef[0], pv = p[i], qv = q[i], wv = w[i];
+    double2 xv = x[i], rv = r[i], s = sv[i];
+    xv.x += al.x * pv.x - al.y * pv.y;
+    xv.y += al.x * pv.y + al.y * pv.x;
+    rv.x -= al.x * qv.x - al.y * qv.y;
+    rv.y -= al.x * qv.y + al.y * qv.x;
+    s.x -= al.x * wv.x - al.y * wv.y;
+    s.y -= al.x * wv.y + al.y * wv.x;
+    x[i] = xv;
+    r[i] = rv;
+    sv[i] = s;
+    a = s.x * s.x + s.y * s.y;
+  }
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // partial sums of ||f||^2 over the sites of a packed F32 full field
 __global__ __launch_bounds__(256) void k_norm32(Geo g, const void *__restrict__ f, double *__restrict__ part) {
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
@@ -561,6 +608,16 @@ hipError_t apply_D_full(const qiral_lattice *lat, int prec, void *out, const voi
   hipError_t e = launch_hop(lat, prec, 0, 0, 1, -lat->kappa, io, oe, ie, 1, s, CHI_ONE, CHI_A);
   if (e != hipSuccess) return e;
   return launch_hop(lat, prec, 0, 1, 1, -lat->kappa, ie, oo, io, 1, s, CHI_ONE, CHI_A);
+}
+
+// D^dagger on a packed full field (out = A^dagger in - kappa H^dagger in)
+hipError_t apply_Ddag_full(const qiral_lattice *lat, int prec, void *out, const void *in, hipStream_t s) {
+  const size_t hb = half_bytes(lat->geo, prec);
+  const char *ie = (const char *)in, *io = ie + hb;
+  char *oe = (char *)out, *oo = oe + hb;
+  hipError_t e = launch_hop(lat, prec, 1, 0, 1, -lat->kappa, io, oe, ie, 1, s, CHI_ONE, CHI_ADAG);
+  if (e != hipSuccess) return e;
+  return launch_hop(lat, prec, 1, 1, 1, -lat->kappa, ie, oo, io, 1, s, CHI_ONE, CHI_ADAG);
 }
 
 void neumann2(int hidden, double kappa, std::vector<float2> &w) {
@@ -689,16 +746,21 @@ extern "C" qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void
   return QIRAL_OK;
 }
 
+// out = N^dagger(in) = L1^dagger L2^dagger in, packed F32 full fields (uses the
+// handle's adjoint-weight and activation buffers)
+hipError_t nn_apply_adjoint_dev(qiral_nn *nn, void *out, const void *in, hipStream_t s) {
+  const int H = nn->hidden;
+  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
+  hipError_t e = layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w, nn->wadj, H, 1);
+  return layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s);
+}
+
 extern "C" qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
   if (!nn || !out || !in) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
   if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
-  hipStream_t s = (hipStream_t)stream;
-  const int H = nn->hidden;
-  // N^dagger = L1^dagger L2^dagger
-  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
-  QIRAL_HIP(layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s));
-  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w, nn->wadj, H, 1);
-  QIRAL_HIP(layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s));
+  QIRAL_HIP(nn_apply_adjoint_dev(nn, out, in, (hipStream_t)stream));
   return QIRAL_OK;
 }
 
@@ -814,6 +876,7 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
   const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
   const size_t n2 = f64 / 16;   // complex entries of a full F64 field (padding included, kept zero)
   const int nbk = nblk(n2);
+  const int nsite_blk = nblk(2 * npad_of(g));   // one thread per padded site (layout conversions)
   // workspace: V[m+1], Z[m], B, X, W, R (F64 full), two F32 full fields, partials, coefficients
   const size_t need = (size_t)(2 * m + 5) * f64 + 2 * f32 + sizeof(double) * ((size_t)2 * (m + 1) * nbk + 4 * 64 + nbk);
   if (nn->gws_bytes < need) {
@@ -880,9 +943,9 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
     int k = 0;
     for (int j = 0; j < m && steps < prm->maxiter; ++j) {
       // Z_j = N(V_j) in FP32, W = D Z_j in FP64
-      hipLaunchKernelGGL(k_cvt64to32, dim3(nbk), dim3(256), 0, s, V + j * vs, (float2 *)in32, n2);
+      hipLaunchKernelGGL(k_cvt64to32, dim3(nsite_blk), dim3(256), 0, s, g, V + j * vs, in32);
       QIRAL_HIP(nn_apply_dev(nn, out32, in32, s));
-      hipLaunchKernelGGL(k_cvt32to64, dim3(nbk), dim3(256), 0, s, (const float2 *)out32, Z + j * vs, n2);
+      hipLaunchKernelGGL(k_cvt32to64, dim3(nsite_blk), dim3(256), 0, s, g, out32, Z + j * vs);
       QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, Z + j * vs, s));
       hops += 2;
       // classical Gram-Schmidt, twice
@@ -964,6 +1027,161 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
     (void)fell_back;
   } else if (rn > target) {
     set_error("tolerance not reached within maxiter");
+    result = QIRAL_ERR_NOT_CONVERGED;
+  }
+  info->converged = (result == QIRAL_OK);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+
+// Flexible CG (Notay 2000), FCG(1), on D^dagger D x = D^dagger b with the
+// preconditioner z = N (N^dagger r) of the network (FP32).  The network is a
+// fixed linear map, so one previous direction is enough (as in preconditioned
+// CG); the flexible coefficient beta = (A p_prev | z) / (p_prev | A p_prev)
+// keeps the directions A-conjugate although z carries FP32 rounding.  The FP64
+// residual s = b - D x is updated alongside the normal residual r = D^dagger s
+// and decides convergence; the true residual is recomputed at the end.
+qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
+                     qiral_solve_info *info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  qiral_nn *nn = (qiral_nn *)prm->precond;
+  if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
+  const Geo &g = lat->geo;
+  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
+  const size_t n2 = f64 / 16;
+  const int nbk = nblk(n2);
+  const int nsite_blk = nblk(2 * npad_of(g));
+  // workspace: B X S W P Z, then R and Q adjacent (one two-vector dot), three F32 fields, partials
+  const size_t need = 8 * f64 + 3 * f32 + sizeof(double) * ((size_t)4 * nbk + 4 * 64 + nbk);
+  if (nn->gws_bytes < need) {
+    if (nn->gws) (void)hipFree(nn->gws);
+    nn->gws = nullptr;
+    nn->gws_bytes = 0;
+    hipError_t e = hipMalloc(&nn->gws, need);
+    if (e != hipSuccess) return fail(QIRAL_ERR_WORKSPACE, "hipMalloc(FCG workspace)");
+    nn->gws_bytes = need;
+  }
+  char *p = (char *)nn->gws;
+  double2 *B = (double2 *)p; p += f64;
+  double2 *X = (double2 *)p; p += f64;
+  double2 *Sv = (double2 *)p; p += f64;
+  double2 *Wv = (double2 *)p; p += f64;
+  double2 *P = (double2 *)p; p += f64;
+  double2 *Z = (double2 *)p; p += f64;
+  double2 *R = (double2 *)p; p += f64;
+  double2 *Q = (double2 *)p; p += f64;   // must follow R (stride n2)
+  void *in32 = p; p += f32;
+  void *mid32 = p; p += f32;
+  void *out32 = p; p += f32;
+  double *part = (double *)p; p += sizeof(double) * 4 * nbk;
+  double2 *coef = (double2 *)p; p += sizeof(double) * 2 * 64;
+  double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
+  double *npart = (double *)p;
+  if ((char *)(npart + nbk) > (char *)nn->gws + nn->gws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace layout");
+
+  QIRAL_HIP(hipMemsetAsync(nn->gws, 0, 8 * f64 + 3 * f32, s));
+  import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
+  if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
+  auto read = [&](void *dst, const void *src, size_t bytes) -> qiral_status {
+    QIRAL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    QIRAL_HIP(hipStreamSynchronize(s));
+    return QIRAL_OK;
+  };
+  auto norm = [&](const double2 *v, double &out) -> qiral_status {
+    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, v, n2, npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    return read(&out, nrm, sizeof(double));
+  };
+  // S = B - D X, R = D^dagger S; returns ||S||
+  auto residuals = [&](double &sn) -> qiral_status {
+    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Sv, X, s));
+    hipLaunchKernelGGL(k_bminus, dim3(nbk), dim3(256), 0, s, B, Sv, n2);
+    QIRAL_HIP(apply_Ddag_full(lat, QIRAL_F64, R, Sv, s));
+    double s2 = 0;
+    qiral_status st = norm(Sv, s2);
+    sn = std::sqrt(s2);
+    return st;
+  };
+  double bn2 = 0;
+  qiral_status st = norm(B, bn2);
+  if (st != QIRAL_OK) return st;
+  const double bn = std::sqrt(bn2), target = prm->tol * bn;
+  double sn = 0;
+  if ((st = residuals(sn)) != QIRAL_OK) return st;
+  long long hops = 4;
+  int it = 0, since_best = 0;
+  bool broke = false;
+  double best = sn, dprev = 0;
+  while (sn > target && it < prm->maxiter) {
+    // Z = N (N^dagger R) in FP32
+    hipLaunchKernelGGL(k_cvt64to32, dim3(nsite_blk), dim3(256), 0, s, g, R, in32);
+    QIRAL_HIP(nn_apply_adjoint_dev(nn, mid32, in32, s));
+    QIRAL_HIP(nn_apply_dev(nn, out32, mid32, s));
+    hipLaunchKernelGGL(k_cvt32to64, dim3(nsite_blk), dim3(256), 0, s, g, out32, Z);
+    if (it > 0) {
+      // Z -= ((Q | Z) / (P | Q)) P, then P <- Z
+      hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, Q, n2, 1, Z, n2, part);
+      hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, part, nbk, coef);
+      double2 c;
+      if ((st = read(&c, coef, sizeof c)) != QIRAL_OK) return st;
+      const double2 mb = make_double2(-c.x / dprev, -c.y / dprev);
+      QIRAL_HIP(hipMemcpyAsync(coef, &mb, sizeof mb, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, P, n2, 1, coef, 1.0, Z, n2);
+    }
+    std::swap(P, Z);
+    // W = D P, Q = D^dagger W, (P | Q) = ||W||^2, (P | R) = conj((R | P))
+    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, P, s));
+    QIRAL_HIP(apply_Ddag_full(lat, QIRAL_F64, Q, Wv, s));
+    hops += 4;
+    hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, R, n2, 1, P, n2, part);
+    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, part, nbk, coef);
+    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, Wv, n2, npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    double2 rp;
+    double d = 0;
+    if ((st = read(&rp, coef, sizeof rp)) != QIRAL_OK) return st;
+    if ((st = read(&d, nrm, sizeof d)) != QIRAL_OK) return st;
+    if (!(d > 0) || !std::isfinite(d)) { broke = true; break; }   // P = 0: the preconditioner returned 0
+    const double2 al = make_double2(rp.x / d, -rp.y / d);
+    QIRAL_HIP(hipMemcpyAsync(coef, &al, sizeof al, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fcg_upd, dim3(nbk), dim3(256), 0, s, coef, P, Q, Wv, X, R, Sv, n2, npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    double s2 = 0;
+    if ((st = read(&s2, nrm, sizeof s2)) != QIRAL_OK) return st;
+    sn = std::sqrt(s2);
+    dprev = d;
+    ++it;
+    if (!std::isfinite(sn)) break;
+    if (sn < 0.99 * best) { best = sn; since_best = 0; }
+    else if (++since_best >= 50 && prm->fallback_cg) { broke = true; break; }   // stagnation
+  }
+  // the true residual of the FCG iterate
+  if ((st = residuals(sn)) != QIRAL_OK) return st;
+  hops += 2;
+  export_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
+  QIRAL_HIP(hipStreamSynchronize(s));
+  qiral_status result = QIRAL_OK;
+  info->iterations = it;
+  info->reliable_updates = 0;
+  info->fell_back = 0;
+  info->hop_applications = hops;
+  info->true_rel_resid = bn > 0 ? sn / bn : sn;
+  if (!std::isfinite(sn)) {
+    set_error("a NaN or Inf appeared in FCG");
+    result = QIRAL_ERR_NONFINITE;
+  } else if (sn > target && prm->fallback_cg) {
+    qiral_solve_params cg = *prm;
+    cg.solver = QIRAL_CGNR_EO;
+    cg.x0_is_guess = 1;
+    qiral_solve_info ci;
+    memset(&ci, 0, sizeof ci);
+    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, &ci, s);
+    info->iterations = it + ci.iterations;
+    info->true_rel_resid = ci.true_rel_resid;
+    info->hop_applications = hops + ci.hop_applications;
+    info->fell_back = 1;
+  } else if (sn > target) {
+    set_error(broke ? "FCG broke down (the preconditioner returned zero)" : "tolerance not reached within maxiter");
     result = QIRAL_ERR_NOT_CONVERGED;
   }
   info->converged = (result == QIRAL_OK);

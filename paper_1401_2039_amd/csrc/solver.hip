@@ -36,6 +36,8 @@ void import_field(const Geo &g, const double *src, void *dst, int subset, int pr
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
 qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
                         qiral_solve_info *info, hipStream_t s);
+qiral_status run_fcg(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+                     qiral_solve_info *info, hipStream_t s);
 }  // namespace qiral
 
 using namespace qiral;
@@ -426,7 +428,7 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(QIRAL_ERR_INVALID_ARG, "tol must be positive");
   if (p->maxiter < 1) return fail(QIRAL_ERR_INVALID_ARG, "maxiter must be >= 1");
   if (p->solver != QIRAL_CGNR_EO && p->solver != QIRAL_BICGSTAB_EO && p->solver != QIRAL_FGMRES_NN &&
-      p->solver != QIRAL_CRNR_EO)
+      p->solver != QIRAL_CRNR_EO && p->solver != QIRAL_FCG_NN)
     return fail(QIRAL_ERR_INVALID_ARG, "bad solver");
   if (p->inner_prec != QIRAL_F64 && p->inner_prec != QIRAL_F32 && p->inner_prec != QIRAL_F16S)
     return fail(QIRAL_ERR_INVALID_ARG, "bad inner precision");
@@ -436,6 +438,9 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (p->solver == QIRAL_CRNR_EO && p->inner_prec != QIRAL_F64)
     return fail(QIRAL_ERR_UNSUPPORTED, "the conjugate residual solver runs in FP64 (inner_prec F64)");
   if (p->solver == QIRAL_FGMRES_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FGMRES needs a precond network");
+  if (p->solver == QIRAL_FCG_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FCG needs a precond network");
+  if ((p->solver == QIRAL_FGMRES_NN || p->solver == QIRAL_FCG_NN) && p->inner_prec != QIRAL_F64)
+    return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES and FCG run in FP64 (inner_prec F64)");
   return QIRAL_OK;
 }
 
@@ -460,13 +465,12 @@ extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const d
   if (!links_for(lat, params->inner_prec))
     return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (see lo_precs)");
   const size_t stride = (size_t)lat->geo.vh * 2 * 24;
-  if (params->solver == QIRAL_FGMRES_NN) {
-    if (params->inner_prec != QIRAL_F64) return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES runs in FP64 (inner_prec F64)");
+  if (params->solver == QIRAL_FGMRES_NN || params->solver == QIRAL_FCG_NN) {
     // one right-hand side after the other
+    auto run = params->solver == QIRAL_FGMRES_NN ? run_fgmres : run_fcg;
     qiral_status worst = QIRAL_OK;
     for (int r = 0; r < nrhs; ++r) {
-      qiral_status s = run_fgmres(lat, x_canon + r * stride, b_canon + r * stride, params, info + r,
-                                  (hipStream_t)stream);
+      qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, params, info + r, (hipStream_t)stream);
       if (s != QIRAL_OK && s != QIRAL_ERR_NOT_CONVERGED) return s;
       if (s != QIRAL_OK) worst = s;
     }
@@ -486,6 +490,8 @@ extern "C" qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *co
   if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
   qiral_status st = check_params(params);
   if (st != QIRAL_OK) return st;
+  if (params->solver == QIRAL_FGMRES_NN || params->solver == QIRAL_FCG_NN)
+    return fail(QIRAL_ERR_UNSUPPORTED, "the learned-preconditioner solvers take one lattice (qiral_solve)");
   std::vector<SysIn> sys(nsys);
   for (int i = 0; i < nsys; ++i) {
     if (!lats[i] || !x_canon[i] || !b_canon[i]) return fail(QIRAL_ERR_INVALID_ARG, "a system pointer is NULL");

@@ -107,3 +107,19 @@ def test_solve_params_validation():
     assert solve(solver=L.FGMRES_NN) == L.ERR_INVALID_ARG            # no network
     assert solve(solver=L.CRNR_EO, inner_prec=L.F32) == L.ERR_UNSUPPORTED
     assert b"conjugate residual" in lib.qiral_last_error()
+    assert solve(solver=L.FCG_NN) == L.ERR_INVALID_ARG                # no network
+    assert solve(solver=L.FCG_NN, precond=1, inner_prec=L.F32) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.FGMRES_NN, precond=1, inner_prec=L.F16S) == L.ERR_UNSUPPORTED
+
+
+def test_batch_rejects_learned_solvers():
+    """FGMRES and FCG take one lattice: the batch entry refuses them before it
+    reads the lattice table."""
+    lib = L.load()
+    info = (L.SolveInfo * 1)()
+    arr = (ctypes.c_void_p * 1)(1)
+    for solver in (L.FGMRES_NN, L.FCG_NN):
+        p = api.solve_params(solver=solver, precond=1)
+        assert lib.qiral_solve_batch(arr, arr, arr, 1, ctypes.byref(p), info, None) == L.ERR_UNSUPPORTED
+        assert b"one lattice" in lib.qiral_last_error()
+

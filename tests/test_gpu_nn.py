@@ -1,7 +1,9 @@
 """The learned preconditioner on the GPU against the oracle's PTC network:
 closed-form initial weights, forward and adjoint layers with random weights,
-the weight gradient, the Philox training vectors, training, and FGMRES with its
-CGNR fallback (every solve judged by the oracle's true residual)."""
+the weight gradient, the Philox training vectors, training, FGMRES and FCG with
+the network (step counts against the oracle's own FGMRES and FCG with the same
+weights) and their CGNR fallback (every solve judged by the oracle's true
+residual)."""
 import numpy as np
 import pytest
 import torch
@@ -9,6 +11,7 @@ import torch
 import latgen
 from oracle import ptc, solvers as S, storage, wilson as W
 import paper_1401_2039_amd as q
+from paper_1401_2039_amd._lib import ERR_NOT_CONVERGED
 from gpu_util import say, dev, host
 from philox_ref import site_normals
 
@@ -137,3 +140,58 @@ def test_fgmres_with_network():
     st, info = q.qiral_solve(lat.handle, lat.dims, x2, dev(cfg["b"]), 1, params)
     assert st == 0 and info[0]["fell_back"] == 1
     assert S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, host(x2)[0], cfg["b"][0]) <= 1e-10
+
+
+def _c0_neumann():
+    cfg = latgen.make_config(0)
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    lat = q.Lattice(cfg["dims"], k, U)
+    net = q.Network(lat, 8)   # created with the Neumann-2 weights
+    w = ptc.neumann2_weights(k)
+    return cfg, lat, net, w
+
+
+def test_fgmres_steps_match_oracle():
+    """FGMRES(20) preconditioned by the Neumann-2 network takes the oracle's
+    number of steps (the network runs in FP32 on FP32 links, so within one)."""
+    say("fgmres steps vs oracle")
+    cfg, lat, net, w = _c0_neumann()
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    _, steps_o, _ = S.fgmres(lambda v: W.apply_D(U, k, 0.0, v), b, lambda v: ptc.network(U, w, v), m=20, tol=1e-10)
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.FGMRES_NN, restart=20, maxiter=500,
+                            precond=net.handle, fallback_cg=0)
+    assert st == 0 and info[0]["fell_back"] == 0
+    assert abs(info[0]["iterations"] - steps_o) <= 1, (info[0]["iterations"], steps_o)
+    assert S.true_rel_residual(U, k, 0.0, host(x)[0], b) <= 1e-10
+    net.close()
+    lat.close()
+
+
+def test_fcg_with_network():
+    """FCG(1) on the normal equations with N N^dagger: the oracle's iteration
+    count (within two: FP32 network) and its solution; a zeroed network makes
+    FCG break down and the CGNR fallback still solves."""
+    say("fcg")
+    cfg, lat, net, w = _c0_neumann()
+    U, k, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    xo, info_o = S.solve_fcg_normal(U, k, 0.0, b, lambda v: ptc.network(U, w, v),
+                                    lambda v: ptc.network_adjoint(U, w, v), tol=1e-10)
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.FCG_NN, maxiter=500, precond=net.handle,
+                            fallback_cg=0)
+    assert st == 0 and info[0]["fell_back"] == 0 and info[0]["converged"] == 1, info[0]
+    assert abs(info[0]["iterations"] - info_o["iterations"]) <= 2, (info[0]["iterations"], info_o["iterations"])
+    xg = host(x)[0]
+    assert S.true_rel_residual(U, k, 0.0, xg, b) <= 1e-10
+    assert _rel(xg, xo) < 1e-8
+    w1, w2 = net.get_weights()
+    net.set_weights(np.zeros_like(w1), np.zeros_like(w2))
+    x2, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.FCG_NN, maxiter=500, precond=net.handle)
+    assert st == 0 and info[0]["fell_back"] == 1, info[0]
+    assert S.true_rel_residual(U, k, 0.0, host(x2)[0], b) <= 1e-10
+    # without the fallback the breakdown is reported, not hidden
+    x3, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, solver=q.FCG_NN, maxiter=500, precond=net.handle,
+                             fallback_cg=0)
+    assert st == ERR_NOT_CONVERGED
+    assert info[0]["converged"] == 0
+    net.close()
+    lat.close()
