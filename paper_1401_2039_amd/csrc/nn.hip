@@ -948,8 +948,12 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
       hipLaunchKernelGGL(k_cvt32to64, dim3(nsite_blk), dim3(256), 0, s, g, out32, Z + j * vs);
       QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, Z + j * vs, s));
       hops += 2;
-      // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt with selective reorthogonalisation (Daniel,
+      // Gragg, Kaufman and Stewart 1976): a second pass only when the first
+      // removed more than half of w's squared norm, i.e. when cancellation
+      // may have left w short of orthogonal to V
       std::vector<C> h(j + 2, C(0));
+      double w2 = 0;
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, Wv, n2, part);
         hipLaunchKernelGGL(k_mdot_final, dim3(j + 1), dim3(256), 0, s, part, nbk, coef);
@@ -957,10 +961,14 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
         std::vector<double2> c(j + 1);
         QIRAL_HIP(hipMemcpyAsync(c.data(), coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
         QIRAL_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) h[i] += C(c[i].x, c[i].y);
+        double c2 = 0;
+        for (int i = 0; i <= j; ++i) {
+          h[i] += C(c[i].x, c[i].y);
+          c2 += c[i].x * c[i].x + c[i].y * c[i].y;
+        }
+        if ((st = norm(Wv, w2)) != QIRAL_OK) return st;
+        if (w2 > 0.5 * (w2 + c2)) break;   // ||w_after||^2 > ||w_before||^2 / 2
       }
-      double w2 = 0;
-      if ((st = norm(Wv, w2)) != QIRAL_OK) return st;
       h[j + 1] = std::sqrt(w2);
       hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, s, Wv, nrm, V + (j + 1) * vs, n2);
       // Givens rotations on the new column
