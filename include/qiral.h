@@ -197,7 +197,9 @@ qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_ca
                          const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream);
 
 /* Solve nsys independent systems D_i x_i = b_i (one right-hand side each, each on
- * its own lattice, of any size) in one set of grouped launches. */
+ * its own lattice, of any size) in one set of grouped launches.  The solvers
+ * with the learned preconditioner (QIRAL_FGMRES_NN, QIRAL_FCG_NN) take one
+ * lattice and return QIRAL_ERR_UNSUPPORTED here. */
 qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_canon, const double *const *b_canon,
                                int32_t nsys, const qiral_solve_params *params, qiral_solve_info *info,
                                qiral_stream_t stream);
