@@ -1059,7 +1059,7 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
   const size_t n2 = f64 / 16;
   const int nbk = nblk(n2);
   const int nsite_blk = nblk(2 * npad_of(g));
-  // workspace: B X S W P Z, then R and Q adjacent (one two-vector dot), three F32 fields, partials
+  // workspace: B X S W P Z R Q (FP64 full fields), three F32 fields, partials
   const size_t need = 8 * f64 + 3 * f32 + sizeof(double) * ((size_t)4 * nbk + 4 * 64 + nbk);
   if (nn->gws_bytes < need) {
     if (nn->gws) (void)hipFree(nn->gws);
@@ -1077,7 +1077,7 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
   double2 *P = (double2 *)p; p += f64;
   double2 *Z = (double2 *)p; p += f64;
   double2 *R = (double2 *)p; p += f64;
-  double2 *Q = (double2 *)p; p += f64;   // must follow R (stride n2)
+  double2 *Q = (double2 *)p; p += f64;
   void *in32 = p; p += f32;
   void *mid32 = p; p += f32;
   void *out32 = p; p += f32;
