@@ -12,7 +12,9 @@ and hop application times the hop applications the solve made, divided by the
 solve's wall time.  The JSON line also carries the solve's time to solution, the
 plain FP64 even-odd CGNR on the same GPU for comparison, a roofline entry for the
 dominant kernel (the FP32 reconstruct-12 even-odd hop: median of 5 trials of
-back-to-back launches timed with HIP events on the stream it runs on, against
+back-to-back launches queued behind a spin kernel, so that the host's per-call
+cost does not leave the GPU idle, timed with HIP events on the stream it runs
+on, against
 the published 8 TB/s and against a measured 1 GiB device copy; HBM traffic from
 the committed counter summary while the hop sources are unchanged), the one-time
 link packing time, and the CPU oracle timed on a bounded sample (seconds and
@@ -150,16 +152,17 @@ def main():
     out = lat.field(q.EVEN, q.F32)
     for _ in range(20):
         lat.dslash_eo(out, src, 0, 0, q.F32)
-    trials = []
-    for _ in range(5):   # median of 5 trials of hop_reps back-to-back launches
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.hop_reps):
-            lat.dslash_eo(out, src, 0, 0, q.F32)
-        e1.record(stream)
-        e1.synchronize()
-        trials.append(e0.elapsed_time(e1) * 1e3 / args.hop_reps)
-    hop_us = statistics.median(trials)
+    # the same launches without a filled queue: the host's enqueue rate bounds this one
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.hop_reps):
+        lat.dslash_eo(out, src, 0, 0, q.F32)
+    e1.record(stream)
+    e1.synchronize()
+    unfilled_us = e0.elapsed_time(e1) * 1e3 / args.hop_reps
+    hop_us, host_us = timed_launches(torch, stream, lambda: lat.dslash_eo(out, src, 0, 0, q.F32), args.hop_reps)
+    log(f"[bench] F32 hop 16^3x32: {unfilled_us:.2f} us/launch enqueued one by one, "
+        f"{hop_us:.2f} us/launch from a filled queue, host {host_us:.2f} us per call")
     hop_bytes = HOP_BYTES["f32"] * vh
     achieved = hop_bytes / (hop_us * 1e-6) / 1e9
     dslash_gflops = FLOP_PER_SITE * vh / (hop_us * 1e-6) / 1e9
@@ -213,7 +216,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "source_sha256": hop_source_hash(),
-                     "launch_us": round(hop_us, 3), "bytes_per_launch": hop_bytes,
+                     "launch_us": round(hop_us, 3), "launch_us_enqueued_one_by_one": round(unfilled_us, 3),
+                     "host_us_per_call": round(host_us, 3), "bytes_per_launch": hop_bytes,
                      "fits_last_level_cache": True, "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
         "gauge_pack_ms": round(pack_ms, 3),
@@ -257,6 +261,35 @@ def _emit(rec, path):
             f.write(json.dumps(rec) + "\n")
 
 
+def timed_launches(torch, stream, launch, reps, trials=5):
+    """Median over `trials` of the per-launch time of `reps` back-to-back calls of
+    `launch`, from HIP events on `stream`.  Each trial first queues a spin kernel
+    long enough to cover the host's enqueueing of all `reps` launches, so the
+    events bracket GPU time only (the kernels and the gaps the hardware leaves
+    between them), not the Python binding's per-call cost.  Returns (us per
+    launch, host us per enqueued launch)."""
+    import statistics
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # spin-kernel clock rate: cycles per microsecond
+    e0.record(stream)
+    torch.cuda._sleep(1 << 20)
+    e1.record(stream)
+    e1.synchronize()
+    cyc_per_us = (1 << 20) / max(e0.elapsed_time(e1) * 1e3, 1.0)
+    host_us, per_launch = 50.0, []
+    for _ in range(trials):
+        torch.cuda._sleep(int(cyc_per_us * (2.0 * host_us * reps + 500.0)))
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            launch()
+        e1.record(stream)
+        host_us = (time.perf_counter() - t0) * 1e6 / reps
+        e1.synchronize()
+        per_launch.append(e0.elapsed_time(e1) * 1e3 / reps)
+    return statistics.median(per_launch), host_us
+
+
 def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None, psi=None):
     """Average duration of one even-odd hop launch (HIP events on the launch stream):
     warm (back to back) and, with a flush buffer, cold (median of single launches,
@@ -272,13 +305,7 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None, psi=None)
     stream = torch.cuda.current_stream()
     for _ in range(5):
         lat.dslash_eo(out, src, 0, 0, prec, nrhs)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        lat.dslash_eo(out, src, 0, 0, prec, nrhs)
-    e1.record(stream)
-    e1.synchronize()
-    warm = e0.elapsed_time(e1) * 1e3 / reps
+    warm, _ = timed_launches(torch, stream, lambda: lat.dslash_eo(out, src, 0, 0, prec, nrhs), reps, trials=3)
     cold = None
     if flush is not None:
         ts = []
