@@ -99,11 +99,14 @@ __global__ __launch_bounds__(WG, 2) void k_hop_sum(const SysDesc *__restrict__ s
   const Item it = fetch_item<T64>(work, nwork);
   const SysDesc &d = sdesc[it.sys];
   const bool on = it.active && (d.st->status & ST_UPDATE);
-  const bool site_ok = on && it.s < d.g.vh;
+  // One work item per block, so `on` is the same in every wave of the block and
+  // a block with no update pending (most iterations) leaves before the barrier.
+  static_assert(WG / WAVE == T64, "k_hop_sum: one work item per block");
+  if (!on) return;
+  const bool site_ok = it.s < d.g.vh;
   cpx<double> acc[1][12];
   SumLd ld{d.f[F_XH], HASLO ? d.f[F_X] : nullptr, d.npad};
-  if (on) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
-  else zero_acc<1>(acc);
+  hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 0, it.grp, acc);
   wave_combine<T64, 1>(acc, it.slot, it.grp, lds);
   if (site_ok && it.grp == 0) {
     apply_chi(acc[0], CHI_AINV, d.tmu);
@@ -122,14 +125,15 @@ __global__ __launch_bounds__(WG, 2) void k_hop_upd(const SysDesc *__restrict__ s
   const Item it = fetch_item<T64>(work, nwork);
   const SysDesc &d = sdesc[it.sys];
   const bool on = it.active && (d.st->status & ST_UPDATE);
-  const bool site_ok = on && it.s < d.g.vh;
+  // block-uniform, as in k_hop_sum
+  static_assert(WG / WAVE == T64, "k_hop_upd: one work item per block");
+  if (!on) return;
+  const bool site_ok = it.s < d.g.vh;
   double v[NV] = {0.0, 0.0, 0.0};
   cpx<double> acc1[1][12];
   FieldLd<S_F64, 1> ld{{d.f[F_T64]}, d.npad};
-  if (on) hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc1);
-  else zero_acc<1>(acc1);
+  hop_wave<L_F64R18, false, T64, false>(d.g, d.g64, ld, site_ok ? it.s : 0, 1, it.grp, acc1);
   wave_combine<T64, 1>(acc1, it.slot, it.grp, lds);
-  if (!on) return;
   cpx<double> *acc = acc1[0];
   if (site_ok && it.grp == 0) {
     cpx<double> y[12], b[12];
@@ -200,6 +204,9 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
   static_assert(sizeof(SysState) % 8 == 0 && sizeof(SysState) / 8 <= RED_WG, "state copy");
   constexpr int NW8 = (int)(sizeof(SysState) / 8);
   const SysDesc &d = sdesc[blockIdx.x];
+  // The reliable-update reduction has nothing to do in most iterations: look at
+  // the state first there (the other reductions almost always run).
+  if (fin == FIN_UPDATE && !(d.st->status & mask)) return;   // uniform over the work-group
   // The system's state is copied to LDS while the partials load, so the scalar
   // step below does not wait for another round trip to memory; the whole state
   // is written back afterwards (no other kernel runs meanwhile).
