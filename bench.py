@@ -278,7 +278,7 @@ def timed_launches(torch, stream, launch, reps, trials=5):
     cyc_per_us = (1 << 20) / max(e0.elapsed_time(e1) * 1e3, 1.0)
     host_us, per_launch = 50.0, []
     for _ in range(trials):
-        torch.cuda._sleep(int(cyc_per_us * (2.0 * host_us * reps + 500.0)))
+        torch.cuda._sleep(int(cyc_per_us * min(2.0 * host_us * reps + 500.0, 1e5)))   # at most 0.1 s
         t0 = time.perf_counter()
         e0.record(stream)
         for _ in range(reps):
