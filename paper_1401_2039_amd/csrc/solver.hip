@@ -320,7 +320,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     ~Events() { for (hipEvent_t x : e) if (x) (void)hipEventDestroy(x); }
   } ev;
   for (int k = 0; k < 2; ++k) QIRAL_HIP(hipEventCreateWithFlags(&ev.e[k], hipEventDisableTiming));
-  auto enqueue_chunk = [&]() -> qiral_status {
+  auto enqueue_chunk = [&](int n) -> qiral_status {
     if (use_graph) {
       if (!gexec) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -334,7 +334,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
       hipError_t e = hipGraphLaunch(gexec, s);
       if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
     } else {
-      for (int k = 0; k < chunk; ++k) iteration();
+      for (int k = 0; k < n; ++k) iteration();
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "solver iteration");
     }
@@ -356,19 +356,48 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     // the states after the previous one are examined, so the GPU does not wait
     // for the host; systems that are done skip the extra chunk's work.
     int cur = 0;
-    if ((st = enqueue_chunk()) != QIRAL_OK) return st;
+    if ((st = enqueue_chunk(chunk)) != QIRAL_OK) return st;
     if ((st = post_copy(cur)) != QIRAL_OK) { free_graph(); return st; }
     long enqueued = chunk;
+    // With the automatic chunk and no graph, the chunk after the queued one is
+    // shortened when every running system is expected to stop within the
+    // queued one: the CG-type residual norms fall about geometrically, so the
+    // rate over the last checks predicts the iterations left.  This only
+    // decides how many iterations the host queues ahead; the device decides
+    // convergence, so the iterates do not change.
+    const bool adaptive = !use_graph && prm->check_every <= 0 && (!bicg);
+    std::vector<double> prev_nr(nsys, -1.0);
+    std::vector<int> prev_it(nsys, -1);
+    int next = chunk;
     while (true) {
-      if ((st = enqueue_chunk()) != QIRAL_OK) return st;
+      const int ahead = next;
+      if ((st = enqueue_chunk(ahead)) != QIRAL_OK) return st;
       if ((st = post_copy(1 - cur)) != QIRAL_OK) { free_graph(); return st; }
-      enqueued += chunk;
+      enqueued += ahead;
       hipError_t e = hipEventSynchronize(ev.e[cur]);
       if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipEventSynchronize"); }
       bool all_done = true;
       for (int i = 0; i < nsys; ++i) all_done = all_done && (hbuf[cur][i].status & ST_DONE);
       if (all_done) break;
       if (enqueued > (long)prm->maxiter + 4l * chunk) break;   // device stops at maxiter; safety net
+      if (adaptive) {
+        int need = 1;
+        for (int i = 0; i < nsys; ++i) {
+          const SysState &x = hbuf[cur][i];
+          if (x.status & ST_DONE) continue;
+          double left = 1e30;   // predicted iterations left after the examined chunk
+          if (prev_it[i] >= 0 && x.iter > prev_it[i] && x.nr > x.thr2 && x.nr < prev_nr[i] && x.thr2 > 0.0) {
+            const double rate = std::log(x.nr / prev_nr[i]) / (double)(x.iter - prev_it[i]);   // < 0
+            left = std::log(x.thr2 / x.nr) / rate;
+          }
+          prev_it[i] = x.iter;
+          prev_nr[i] = x.nr;
+          const double after = left - (double)ahead;   // still needed after the queued chunk
+          const int n = after >= (double)chunk ? chunk : std::max(1, (int)std::ceil(after));
+          need = std::max(need, n);
+        }
+        next = need;
+      }
       cur = 1 - cur;
     }
     // reconstruct x_e, export, FP64 true residual
