@@ -12,8 +12,14 @@ inputs.
   scale is the largest of their magnitudes (FP32); each real is stored as the
   FP16 nearest to (value / scale) computed in FP32; a site of zeros has scale
   0 and stores zeros.  The represented value is FP32(half) * scale.
-* Reconstruct-12 links: rows 0 and 1 of each SU(3) link are stored rounded; row
-  2 is conj(row0 x row1), exact for a special unitary matrix.
+* Reconstruct-12 links: rows 0 and 1 of each SU(3) link are stored rounded
+  (each real rounded once, from FP64 straight to the nearest FP32 or FP16, ties
+  to even; no intermediate FP32 step for FP16); row 2 is conj(row0 x row1),
+  exact for a special unitary matrix.
+
+Pins: tests/test_oracle_storage.py, tests/test_half_rounding.py (FP16 rounding
+against an exhaustive nearest-value search on doubles where rounding through
+FP32 first would differ).
 """
 import numpy as np
 
