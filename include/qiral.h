@@ -37,11 +37,15 @@
  *   exception crosses the ABI.  qiral_last_error() gives a thread-local
  *   description of the last failure.
  *
- *   Memory: a lattice handle owns the device memory of its packed links and
- *   of the solver workspace, plus a small pinned host buffer for the solver's
- *   convergence polls (both grown on demand, released by
- *   qiral_lattice_destroy).  Every other device buffer belongs to the caller.
- *   Calls on one handle must not overlap in time (they share its workspace).
+ *   Memory: the caller owns every device buffer -- canonical and packed fields,
+ *   the packed link stores, the solver workspace and the network's memory --
+ *   sized by qiral_field_bytes, qiral_gauge_bytes, qiral_solve_workspace_bytes
+ *   and qiral_nn_bytes.  The library allocates no device memory.  A lattice
+ *   handle holds host-side state only: the geometry, kappa, mu, pointers to the
+ *   caller's link stores, and what qiral_lattice_create makes once so that
+ *   later calls allocate nothing: a 224 KiB pinned host buffer for the solver's
+ *   convergence polls and four HIP events.  Calls on one handle must not
+ *   overlap in time (they share the poll buffer and events).
  */
 #ifndef QIRAL_H
 #define QIRAL_H
@@ -65,7 +69,7 @@ typedef enum {
   QIRAL_ERR_NOT_CONVERGED = 5, /* tolerance not met within maxiter; x and info hold
                                   the last iterate and its residual                */
   QIRAL_ERR_NONFINITE = 6,     /* a NaN or Inf appeared in a reduction              */
-  QIRAL_ERR_WORKSPACE = 7      /* device memory for the workspace not available    */
+  QIRAL_ERR_WORKSPACE = 7      /* workspace missing or smaller than its size query  */
 } qiral_status;
 
 typedef enum { QIRAL_F64 = 0, QIRAL_F32 = 1, QIRAL_F16S = 2 } qiral_prec;
@@ -91,9 +95,8 @@ typedef enum {
                             on ||b - D x||; FP64 (inner_prec F64)                    */
 } qiral_solver;
 
-/* Bit i of lo_precs asks lattice_create for a packed link store of precision i. */
-#define QIRAL_LINKS_F32 (1u << QIRAL_F32)
-#define QIRAL_LINKS_F16 (1u << QIRAL_F16S)
+/* The most systems (right-hand sides, or lattices of a batch) one solve takes. */
+#define QIRAL_MAX_SYSTEMS 255
 
 typedef struct qiral_lattice qiral_lattice; /* opaque, host-side */
 typedef struct qiral_nn qiral_nn;           /* opaque, learned preconditioner */
@@ -105,20 +108,34 @@ const char *qiral_last_error(void);
  * to whole 64-site blocks, times nrhs.  Returns 0 on invalid arguments. */
 size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec prec, int32_t nrhs);
 
-/* Create a lattice: packs the canonical links (device, complex128, see above)
- * into an FP64 reconstruct-18 store and, for each bit of lo_precs, a
- * reduced-precision store (FP32 or FP16 links, lo_recon = 12 keeps rows 0 and 1
- * and rebuilds row 2 = conj(row0 x row1), exact for SU(3)).  gauge_canon may be
- * freed once the call returns.  kappa is the hopping parameter and mu the
- * twisted-mass parameter of the operator of Fig. "dirac",
+/* Bytes of a packed link store (the forward links of both parities, padded to
+ * whole 64-site blocks): prec QIRAL_F64 with QIRAL_RECON18 (144 B per link),
+ * QIRAL_F32 with QIRAL_RECON12 (48 B) or QIRAL_F16S with QIRAL_RECON12 (24 B;
+ * FP16 links carry no scale, |U_ab| <= 1).  Reconstruct-12 keeps rows 0 and 1
+ * and rebuilds row 2 = conj(row0 x row1), exact for SU(3).  Returns 0 for other
+ * combinations or invalid dims. */
+size_t qiral_gauge_bytes(const int32_t dims[4], qiral_prec prec, qiral_recon recon);
+
+/* Create a lattice handle.  Packs the canonical links (device, complex128, see
+ * above) into the caller's stores: gauge_f64 (required, qiral_gauge_bytes(dims,
+ * QIRAL_F64, QIRAL_RECON18) bytes) and, if not NULL, gauge_f32 and gauge_f16
+ * (reconstruct-12 stores of FP32 and FP16 links for the reduced-precision hops
+ * and solves).  Each real is rounded once from FP64 to the nearest FP32 / FP16
+ * (ties to even).  The stores must be 16-byte aligned, distinct, and outlive
+ * the handle; gauge_canon may be freed once the call returns.  kappa is the
+ * hopping parameter and mu the twisted-mass parameter of the operator of Fig.
+ * "dirac",
  *   D = A - kappa H,   A = 1 + 2 i kappa mu g5   (A = 1 for mu = 0);
- * every operator, solve and true residual on the handle uses this D. */
+ * every operator, solve and true residual on the handle uses this D.  Blocking
+ * (synchronises the stream).  Allocates the handle's pinned poll buffer and
+ * events (see Memory above). */
 qiral_status qiral_lattice_create(qiral_lattice **lat, const int32_t dims[4], double kappa, double mu,
-                                  const double *gauge_canon, uint32_t lo_precs, qiral_recon lo_recon,
+                                  const double *gauge_canon, void *gauge_f64, void *gauge_f32, void *gauge_f16,
                                   qiral_stream_t stream);
+/* Releases the handle's host resources; the caller's buffers are untouched. */
 qiral_status qiral_lattice_destroy(qiral_lattice *lat);
-/* Sites per parity and bytes of device memory held by the handle. */
-qiral_status qiral_lattice_query(const qiral_lattice *lat, int64_t *sites_per_parity, int64_t *device_bytes);
+/* Sites per parity and bytes of the caller's link stores the handle uses. */
+qiral_status qiral_lattice_query(const qiral_lattice *lat, int64_t *sites_per_parity, int64_t *gauge_bytes);
 
 /* Canonical (device complex128, [rhs][t][z][y][x][c][s]) <-> packed.  Import reads
  * the sites of the subset and writes dst; export writes only the canonical sites
@@ -151,11 +168,14 @@ qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, 
  * right-hand sides (waves per 64-site block 1 (F16S only), 2 or 4 (FP64: 4 only);
  * right-hand sides per lane 1..4, FP64 1..2, FP32 on 2 waves 1..2, 1 wave 1) by
  * timing each candidate on the stream; later hops and solves on this handle use
- * the fastest.  If the environment variable QIRAL_TUNE_CACHE names a file, the
- * result is looked up there first and stored there (JSON).  Allocates and frees
- * two temporary fields.  Outputs may be NULL; best_us is 0 on a cache hit. */
-qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, int32_t *best_t, int32_t *best_nr,
-                        double *best_us, qiral_stream_t stream);
+ * the fastest.  in and out are two distinct packed half-fields of precision prec
+ * and nrhs fields (qiral_field_bytes(dims, QIRAL_EVEN, prec, nrhs) bytes each)
+ * owned by the caller; in is zeroed, out overwritten.  If the environment
+ * variable QIRAL_TUNE_CACHE names a file, the result is looked up there first
+ * and stored there (JSON).  Blocking.  Outputs may be NULL; best_us is 0 on a
+ * cache hit. */
+qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, void *in, void *out, int32_t *best_t,
+                        int32_t *best_nr, double *best_us, qiral_stream_t stream);
 
 typedef struct {
   qiral_solver solver; /* QIRAL_CGNR_EO (default), QIRAL_BICGSTAB_EO, QIRAL_FGMRES_NN,
@@ -186,23 +206,39 @@ typedef struct {
   int64_t hop_applications;  /* H_eo / H_oe applications (units of V/2 sites)       */
 } qiral_solve_info;
 
+/* Device bytes of the workspace a qiral_solve call with these parameters and
+ * nrhs right-hand sides needs on this lattice (0 for invalid arguments).  It
+ * holds the Krylov vectors (5, 7 or 8 half-fields per right-hand side in the
+ * iterate precision, plus 6 FP64 half-fields and, mixed, one FP32), the system
+ * and work tables, per-system states and reduction partials; for FGMRES/FCG, the
+ * flexible solver's FP64 full fields (the larger of that and its CGNR fallback). */
+size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params, int32_t nrhs);
+/* The same for qiral_solve_batch over nsys lattices (0 for FGMRES/FCG). */
+size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *lats, int32_t nsys,
+                                         const qiral_solve_params *params);
+
 /* Solve D x = b for nrhs right-hand sides on one lattice.  The Krylov solvers run
  * on the Schur system S x_o = b_hat of the odd sites, b_hat = b_o + kappa H_oe
  * A^-1 b_e, and rebuild x_e = A^-1 (b_e + kappa H_eo x_o) (template "schur").
  * x_canon and b_canon are canonical full fields (device); info points to nrhs
- * host structs.  Blocking:
- * returns after the stream has drained.  Returns QIRAL_ERR_NOT_CONVERGED if any
- * right-hand side missed the tolerance. */
+ * host structs.  ws is the caller's device workspace: 256-byte aligned and at
+ * least qiral_solve_workspace_bytes(lat, params, nrhs) bytes, else
+ * QIRAL_ERR_WORKSPACE (checked before any HIP call); its contents on entry do
+ * not matter and are overwritten.  The call allocates no device memory.
+ * Blocking: returns after the stream has drained.  Returns
+ * QIRAL_ERR_NOT_CONVERGED if any right-hand side missed the tolerance. */
 qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
-                         const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream);
+                         const qiral_solve_params *params, void *ws, size_t ws_bytes, qiral_solve_info *info,
+                         qiral_stream_t stream);
 
 /* Solve nsys independent systems D_i x_i = b_i (one right-hand side each, each on
- * its own lattice, of any size) in one set of grouped launches.  The solvers
- * with the learned preconditioner (QIRAL_FGMRES_NN, QIRAL_FCG_NN) take one
- * lattice and return QIRAL_ERR_UNSUPPORTED here. */
+ * its own lattice, of any size) in one set of grouped launches, in the caller's
+ * workspace ws (qiral_solve_batch_workspace_bytes).  The solvers with the
+ * learned preconditioner (QIRAL_FGMRES_NN, QIRAL_FCG_NN) take one lattice and
+ * return QIRAL_ERR_UNSUPPORTED here. */
 qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_canon, const double *const *b_canon,
-                               int32_t nsys, const qiral_solve_params *params, qiral_solve_info *info,
-                               qiral_stream_t stream);
+                               int32_t nsys, const qiral_solve_params *params, void *ws, size_t ws_bytes,
+                               qiral_solve_info *info, qiral_stream_t stream);
 
 /* ---- Learned preconditioner (an addition to the paper's method) -----------
  * A 2-layer parallel-transport network 1 -> hidden -> 1 channels:
@@ -216,14 +252,23 @@ qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_cano
  * channel 1 carries H psi).  It is used by qiral_solve with solver
  * QIRAL_FGMRES_NN or QIRAL_FCG_NN and params.precond pointing to it. */
 
-/* hidden = 2, 4 or 8; the lattice needs FP32 links.  The handle owns its device
- * memory (weights, optimiser state, activations, FGMRES workspace). */
-qiral_status qiral_nn_create(qiral_nn **nn, qiral_lattice *lat, int32_t hidden);
+/* Device bytes of a network with `hidden` channels (2, 4 or 8) on this lattice:
+ * weights, adjoint weights, Adam moments, gradient, partial sums, the hidden
+ * activations and their gradient (hidden FP32 full fields each), four FP32 full
+ * fields for training pairs, and 256 training losses.  0 for invalid arguments. */
+size_t qiral_nn_bytes(const qiral_lattice *lat, int32_t hidden);
+/* Create a network in the caller's device memory mem (256-byte aligned, at least
+ * qiral_nn_bytes bytes, else QIRAL_ERR_WORKSPACE), which must outlive it; the
+ * lattice needs FP32 links (gauge_f32).  Blocking (synchronises the stream). */
+qiral_status qiral_nn_create(qiral_nn **nn, qiral_lattice *lat, int32_t hidden, void *mem, size_t mem_bytes,
+                             qiral_stream_t stream);
+/* Releases the handle; the caller's memory is untouched. */
 qiral_status qiral_nn_destroy(qiral_nn *nn);
 /* Number of complex weights (host arrays hold 2x as many floats). */
 size_t qiral_nn_num_weights(const qiral_nn *nn);
-qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w_host, size_t count);
-qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w_host, size_t count);
+/* Copy the weights from / to the host (blocking on the stream). */
+qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w_host, size_t count, qiral_stream_t stream);
+qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w_host, size_t count, qiral_stream_t stream);
 /* out = N(in) and out = N^dagger(in) on packed FP32 full fields (no aliasing). */
 qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void *in, qiral_stream_t stream);
 qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream);

@@ -20,7 +20,10 @@ RECON18, RECON12 = 18, 12
 EVEN, ODD, FULL = 0, 1, 2
 OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG = 0, 1, 2, 3
 CGNR_EO, BICGSTAB_EO, FGMRES_NN, CRNR_EO, FCG_NN = 0, 1, 2, 3, 4
+# which reduced-precision link stores the binding allocates for a lattice (a
+# binding-side choice: the C call takes one pointer per store)
 LINKS_F32, LINKS_F16 = 1 << F32, 1 << F16S
+MAX_SYSTEMS = 255
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR_BAD_DIMS",
                 ERR_UNSUPPORTED: "ERR_UNSUPPORTED", ERR_HIP: "ERR_HIP", ERR_NOT_CONVERGED: "ERR_NOT_CONVERGED",
@@ -28,11 +31,13 @@ STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR
 
 # Every function the header declares (checked by the tests against the library's exports).
 EXPORTS = [
-    "qiral_status_string", "qiral_last_error", "qiral_field_bytes", "qiral_lattice_create",
+    "qiral_status_string", "qiral_last_error", "qiral_gauge_bytes", "qiral_field_bytes", "qiral_lattice_create",
     "qiral_lattice_destroy", "qiral_lattice_query", "qiral_field_import", "qiral_field_export",
-    "qiral_dslash_eo", "qiral_apply_M", "qiral_tune", "qiral_solve", "qiral_solve_batch",
-    "qiral_nn_create", "qiral_nn_destroy", "qiral_nn_num_weights", "qiral_nn_set_weights", "qiral_nn_get_weights",
-    "qiral_nn_apply", "qiral_nn_apply_adjoint", "qiral_nn_sample", "qiral_nn_grad", "qiral_nn_train",
+    "qiral_dslash_eo", "qiral_apply_M", "qiral_tune", "qiral_solve_workspace_bytes",
+    "qiral_solve_batch_workspace_bytes", "qiral_solve", "qiral_solve_batch",
+    "qiral_nn_bytes", "qiral_nn_create", "qiral_nn_destroy", "qiral_nn_num_weights", "qiral_nn_set_weights",
+    "qiral_nn_get_weights", "qiral_nn_apply", "qiral_nn_apply_adjoint", "qiral_nn_sample", "qiral_nn_grad",
+    "qiral_nn_train",
 ]
 
 
@@ -76,28 +81,32 @@ def load():
     sig = {
         "qiral_status_string": (ctypes.c_char_p, [I]),
         "qiral_last_error": (ctypes.c_char_p, []),
+        "qiral_gauge_bytes": (S, [dims_t, I, I]),
         "qiral_field_bytes": (S, [dims_t, I, I, I]),
-        "qiral_lattice_create": (I, [ctypes.POINTER(P), dims_t, D, D, P, ctypes.c_uint32, I, P]),
+        "qiral_lattice_create": (I, [ctypes.POINTER(P), dims_t, D, D, P, P, P, P, P]),
         "qiral_lattice_destroy": (I, [P]),
         "qiral_lattice_query": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "qiral_field_import": (I, [P, P, P, I, I, I, P]),
         "qiral_field_export": (I, [P, P, P, I, I, I, P]),
         "qiral_dslash_eo": (I, [P, P, P, I, I, I, I, P]),
         "qiral_apply_M": (I, [P, P, P, P, I, I, I, P]),
-        "qiral_tune": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+        "qiral_tune": (I, [P, I, I, P, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_double), P]),
-        "qiral_solve": (I, [P, P, P, I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
+        "qiral_solve_workspace_bytes": (S, [P, ctypes.POINTER(SolveParams), I]),
+        "qiral_solve_batch_workspace_bytes": (S, [ctypes.POINTER(P), I, ctypes.POINTER(SolveParams)]),
+        "qiral_solve": (I, [P, P, P, I, ctypes.POINTER(SolveParams), P, S, ctypes.POINTER(SolveInfo), P]),
         "qiral_solve_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I,
-                                  ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
+                                  ctypes.POINTER(SolveParams), P, S, ctypes.POINTER(SolveInfo), P]),
     }
     U64 = ctypes.c_uint64
     DP = ctypes.POINTER(ctypes.c_double)
     sig.update({
-        "qiral_nn_create": (I, [ctypes.POINTER(P), P, I]),
+        "qiral_nn_bytes": (S, [P, I]),
+        "qiral_nn_create": (I, [ctypes.POINTER(P), P, I, P, S, P]),
         "qiral_nn_destroy": (I, [P]),
         "qiral_nn_num_weights": (S, [P]),
-        "qiral_nn_set_weights": (I, [P, P, S]),
-        "qiral_nn_get_weights": (I, [P, P, S]),
+        "qiral_nn_set_weights": (I, [P, P, S, P]),
+        "qiral_nn_get_weights": (I, [P, P, S, P]),
         "qiral_nn_apply": (I, [P, P, P, P]),
         "qiral_nn_apply_adjoint": (I, [P, P, P, P]),
         "qiral_nn_sample": (I, [P, P, U64, U64, DP, P]),

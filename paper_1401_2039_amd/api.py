@@ -45,13 +45,30 @@ def qiral_field_bytes(dims, subset, prec, nrhs=1):
     return int(L.load().qiral_field_bytes(L.dims_arg(dims), subset, prec, nrhs))
 
 
-def qiral_lattice_create(dims, kappa, gauge_canon, lo_precs=L.LINKS_F32 | L.LINKS_F16, lo_recon=L.RECON12, mu=0.0,
-                         stream=None):
+def qiral_gauge_bytes(dims, prec, recon=None):
+    if recon is None:
+        recon = L.RECON18 if prec == L.F64 else L.RECON12
+    return int(L.load().qiral_gauge_bytes(L.dims_arg(dims), prec, recon))
+
+
+def _bytes_tensor(n, device="cuda"):
+    """A device buffer of n bytes (uint8; torch's allocations are 512-byte aligned)."""
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+def qiral_lattice_create(dims, kappa, gauge_canon, gauge_f64, gauge_f32=None, gauge_f16=None, mu=0.0, stream=None):
+    """Create a handle whose packed links live in the given uint8 CUDA tensors
+    (sized by qiral_gauge_bytes); they must outlive the handle."""
     lib = L.load()
     ptr = _need_cuda(gauge_canon, "gauge_canon", torch.complex128, _volume(dims) * 4 * 9 * 16)
+    g64 = _need_cuda(gauge_f64, "gauge_f64", nbytes=qiral_gauge_bytes(dims, L.F64))
+    g32 = ctypes.c_void_p(None) if gauge_f32 is None else \
+        _need_cuda(gauge_f32, "gauge_f32", nbytes=qiral_gauge_bytes(dims, L.F32))
+    g16 = ctypes.c_void_p(None) if gauge_f16 is None else \
+        _need_cuda(gauge_f16, "gauge_f16", nbytes=qiral_gauge_bytes(dims, L.F16S))
     h = ctypes.c_void_p()
-    L.check(lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), float(kappa), float(mu), ptr,
-                                     int(lo_precs), int(lo_recon), _stream(stream)), "qiral_lattice_create")
+    L.check(lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), float(kappa), float(mu), ptr, g64, g32, g16,
+                                     _stream(stream)), "qiral_lattice_create")
     return h.value
 
 
@@ -93,11 +110,15 @@ def qiral_apply_M(handle, dims, out, inp, tmp, op, prec, nrhs=1, stream=None):
             "qiral_apply_M")
 
 
-def qiral_tune(handle, prec, nrhs=1, stream=None):
-    """Autotune the hop launch shape; returns (waves per site block, rhs per lane, microseconds)."""
+def qiral_tune(handle, dims, prec, inp, out, nrhs=1, stream=None):
+    """Autotune the hop launch shape on two caller half-fields; returns (waves per
+    site block, rhs per lane, microseconds)."""
+    need = qiral_field_bytes(dims, L.EVEN, prec, nrhs)
+    i = _need_cuda(inp, "in", nbytes=need)
+    o = _need_cuda(out, "out", nbytes=need)
     t, nr, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-    L.check(L.load().qiral_tune(ctypes.c_void_p(handle), int(prec), int(nrhs), ctypes.byref(t), ctypes.byref(nr),
-                                ctypes.byref(us), _stream(stream)), "qiral_tune")
+    L.check(L.load().qiral_tune(ctypes.c_void_p(handle), int(prec), int(nrhs), i, o, ctypes.byref(t),
+                                ctypes.byref(nr), ctypes.byref(us), _stream(stream)), "qiral_tune")
     return t.value, nr.value, us.value
 
 
@@ -107,26 +128,53 @@ def solve_params(solver=L.CGNR_EO, tol=1e-10, maxiter=10000, inner_prec=L.F64, d
                          use_graph, check_every)
 
 
-def qiral_solve(handle, dims, x_canon, b_canon, nrhs, params, stream=None):
+def qiral_solve_workspace_bytes(handle, params, nrhs=1):
+    return int(L.load().qiral_solve_workspace_bytes(ctypes.c_void_p(handle), ctypes.byref(params), int(nrhs)))
+
+
+def qiral_solve_batch_workspace_bytes(handles, params):
+    n = len(handles)
+    hp = (ctypes.c_void_p * n)(*handles)
+    return int(L.load().qiral_solve_batch_workspace_bytes(hp, n, ctypes.byref(params)))
+
+
+def _ws_arg(ws):
+    if ws is None:
+        return ctypes.c_void_p(None), 0
+    return _need_cuda(ws, "ws"), ws.numel() * ws.element_size()
+
+
+def qiral_solve(handle, dims, x_canon, b_canon, nrhs, params, ws="auto", stream=None):
+    """ws: a uint8 CUDA tensor of at least qiral_solve_workspace_bytes bytes, None
+    (passes NULL), or "auto" (a torch tensor of the queried size for this call)."""
     n = _volume(dims) * 12 * 16 * nrhs
     x = _need_cuda(x_canon, "x_canon", torch.complex128, n)
     b = _need_cuda(b_canon, "b_canon", torch.complex128, n)
+    if isinstance(ws, str):
+        need = qiral_solve_workspace_bytes(handle, params, nrhs)
+        ws = _bytes_tensor(need) if need else None
+    wp, wn = _ws_arg(ws)
     infos = (L.SolveInfo * nrhs)()
-    st = L.load().qiral_solve(ctypes.c_void_p(handle), x, b, nrhs, ctypes.byref(params), infos, _stream(stream))
+    st = L.load().qiral_solve(ctypes.c_void_p(handle), x, b, nrhs, ctypes.byref(params), wp, wn, infos,
+                              _stream(stream))
     if st not in (L.OK, L.ERR_NOT_CONVERGED):
         L.check(st, "qiral_solve")
     return st, [i.as_dict() for i in infos]
 
 
-def qiral_solve_batch(handles, dims_list, xs, bs, params, stream=None):
+def qiral_solve_batch(handles, dims_list, xs, bs, params, ws="auto", stream=None):
     n = len(handles)
     hp = (ctypes.c_void_p * n)(*handles)
     xp = (ctypes.c_void_p * n)(*[_need_cuda(x, "x", torch.complex128, _volume(d) * 192).value
                                  for x, d in zip(xs, dims_list)])
     bp = (ctypes.c_void_p * n)(*[_need_cuda(b, "b", torch.complex128, _volume(d) * 192).value
                                  for b, d in zip(bs, dims_list)])
+    if isinstance(ws, str):
+        need = qiral_solve_batch_workspace_bytes(handles, params)
+        ws = _bytes_tensor(need) if need else None
+    wp, wn = _ws_arg(ws)
     infos = (L.SolveInfo * n)()
-    st = L.load().qiral_solve_batch(hp, xp, bp, n, ctypes.byref(params), infos, _stream(stream))
+    st = L.load().qiral_solve_batch(hp, xp, bp, n, ctypes.byref(params), wp, wn, infos, _stream(stream))
     if st not in (L.OK, L.ERR_NOT_CONVERGED):
         L.check(st, "qiral_solve_batch")
     return st, [i.as_dict() for i in infos]
@@ -142,7 +190,13 @@ class Lattice:
         self.mu = float(mu)
         g = gauge if isinstance(gauge, torch.Tensor) else torch.from_numpy(gauge)
         g = g.to(device=device, dtype=torch.complex128).contiguous()
-        self.handle = qiral_lattice_create(self.dims, self.kappa, g, lo_precs, mu=self.mu)
+        # the packed link stores: device memory this object owns for the handle's lifetime
+        self.gauge_f64 = _bytes_tensor(qiral_gauge_bytes(self.dims, L.F64), device)
+        self.gauge_f32 = _bytes_tensor(qiral_gauge_bytes(self.dims, L.F32), device) if lo_precs & L.LINKS_F32 else None
+        self.gauge_f16 = _bytes_tensor(qiral_gauge_bytes(self.dims, L.F16S), device) if lo_precs & L.LINKS_F16 else None
+        self.handle = qiral_lattice_create(self.dims, self.kappa, g, self.gauge_f64, self.gauge_f32, self.gauge_f16,
+                                           mu=self.mu)
+        self.ws = None
 
     def close(self):
         if self.handle:
@@ -182,13 +236,23 @@ class Lattice:
         qiral_apply_M(self.handle, self.dims, out, inp, tmp, op, prec, nrhs)
 
     def tune(self, prec, nrhs=1):
-        return qiral_tune(self.handle, prec, nrhs)
+        a, b = self.field(L.EVEN, prec, nrhs), self.field(L.EVEN, prec, nrhs)
+        return qiral_tune(self.handle, self.dims, prec, a, b, nrhs)
+
+    def workspace(self, params, nrhs=1):
+        """The solver workspace for these parameters, kept and grown on demand."""
+        need = qiral_solve_workspace_bytes(self.handle, params, nrhs)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = None
+            self.ws = _bytes_tensor(need)
+        return self.ws
 
     def solve(self, b_canon, x_canon=None, **kw):
         b_canon = b_canon.contiguous()
         nrhs = b_canon.shape[0]
         x = self.canon(nrhs) if x_canon is None else x_canon
-        st, info = qiral_solve(self.handle, self.dims, x, b_canon, nrhs, solve_params(**kw))
+        prm = solve_params(**kw)
+        st, info = qiral_solve(self.handle, self.dims, x, b_canon, nrhs, prm, ws=self.workspace(prm, nrhs))
         return x, st, info
 
 
@@ -201,8 +265,10 @@ class Network:
         self.lat = lattice
         self.hidden = hidden
         h = ctypes.c_void_p()
-        L.check(L.load().qiral_nn_create(ctypes.byref(h), ctypes.c_void_p(lattice.handle), int(hidden)),
-                "qiral_nn_create")
+        nbytes = int(L.load().qiral_nn_bytes(ctypes.c_void_p(lattice.handle), int(hidden)))
+        self.mem = _bytes_tensor(nbytes)   # the network's device memory, owned here
+        L.check(L.load().qiral_nn_create(ctypes.byref(h), ctypes.c_void_p(lattice.handle), int(hidden),
+                                         _need_cuda(self.mem, "mem"), nbytes, _stream()), "qiral_nn_create")
         self.handle = h.value
         self.nw = int(L.load().qiral_nn_num_weights(ctypes.c_void_p(self.handle)))
         self._np = np
@@ -223,7 +289,7 @@ class Network:
         np = self._np
         buf = np.zeros(2 * self.nw, dtype=np.float32)
         L.check(L.load().qiral_nn_get_weights(ctypes.c_void_p(self.handle), buf.ctypes.data_as(ctypes.c_void_p),
-                                              self.nw), "qiral_nn_get_weights")
+                                              self.nw, _stream()), "qiral_nn_get_weights")
         c = buf.view(np.complex64)
         H = self.hidden
         n1 = 9 * H * 16
@@ -235,7 +301,7 @@ class Network:
         assert c.size == self.nw
         buf = np.ascontiguousarray(c).view(np.float32)
         L.check(L.load().qiral_nn_set_weights(ctypes.c_void_p(self.handle), buf.ctypes.data_as(ctypes.c_void_p),
-                                              self.nw), "qiral_nn_set_weights")
+                                              self.nw, _stream()), "qiral_nn_set_weights")
 
     def apply(self, out, inp, adjoint=False):
         fn = L.load().qiral_nn_apply_adjoint if adjoint else L.load().qiral_nn_apply

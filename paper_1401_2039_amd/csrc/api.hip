@@ -67,24 +67,20 @@ size_t half_bytes(const Geo &g, int prec) { return npad_of(g) * site_bytes(prec)
 const void *links_for(const qiral_lattice *lat, int prec) {
   return prec == QIRAL_F64 ? lat->g64 : prec == QIRAL_F32 ? lat->g32 : lat->g16;
 }
-qiral_status ensure_workspace(qiral_lattice *lat, size_t bytes) {
-  if (bytes <= lat->ws_bytes) return QIRAL_OK;
-  if (lat->ws) {
-    hipError_t e = hipFree(lat->ws);
-    lat->ws = nullptr;
-    lat->ws_bytes = 0;
-    if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
-  }
-  hipError_t e = hipMalloc(&lat->ws, bytes);
-  if (e != hipSuccess) {
-    lat->ws = nullptr;
-    set_error(std::string("hipMalloc(workspace): ") + hipGetErrorString(e));
-    return QIRAL_ERR_WORKSPACE;
-  }
-  lat->ws_bytes = bytes;
-  return QIRAL_OK;
+size_t link_store_bytes(const Geo &g, int prec) {
+  const size_t link = prec == QIRAL_F64 ? LinkIO<L_F64R18>::LINK_BYTES
+                    : prec == QIRAL_F32 ? LinkIO<L_F32R12>::LINK_BYTES
+                    : prec == QIRAL_F16S ? LinkIO<L_F16R12>::LINK_BYTES : 0;
+  return 8 * npad_of(g) * link;   // 4 forward links per site of each parity
 }
 }  // namespace qiral
+
+extern "C" size_t qiral_gauge_bytes(const int32_t dims[4], qiral_prec prec, qiral_recon recon) {
+  if (check_dims(dims) != QIRAL_OK || !valid_prec(prec)) return 0;
+  if ((prec == QIRAL_F64) != (recon == QIRAL_RECON18)) return 0;   // F64: 18 reals; F32, F16: 12
+  if (recon != QIRAL_RECON18 && recon != QIRAL_RECON12) return 0;
+  return link_store_bytes(make_geo(dims), prec);
+}
 
 extern "C" size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec prec, int32_t nrhs) {
   if (check_dims(dims) != QIRAL_OK || !valid_prec(prec) || nrhs < 1) return 0;
@@ -375,55 +371,67 @@ hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int p, int
 
 // ---------------------------------------------------------------------------
 // lattice handle
+static void release_handle(qiral_lattice *lat) {
+  for (hipEvent_t e : lat->poll_ev) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : lat->time_ev) if (e) (void)hipEventDestroy(e);
+  if (lat->pinned) (void)hipHostFree(lat->pinned);
+  delete lat;
+}
+
 extern "C" qiral_status qiral_lattice_create(qiral_lattice **out, const int32_t dims[4], double kappa, double mu,
-                                             const double *gauge_canon, uint32_t lo_precs, qiral_recon lo_recon,
-                                             qiral_stream_t stream) {
+                                             const double *gauge_canon, void *gauge_f64, void *gauge_f32,
+                                             void *gauge_f16, qiral_stream_t stream) {
   if (!out) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
   *out = nullptr;
   qiral_status st = check_dims(dims);
   if (st != QIRAL_OK) return st;
   if (!gauge_canon) return fail(QIRAL_ERR_INVALID_ARG, "gauge_canon is NULL");
+  if (!gauge_f64) return fail(QIRAL_ERR_INVALID_ARG, "gauge_f64 is NULL (the FP64 store is required)");
   if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(QIRAL_ERR_INVALID_ARG, "kappa and mu must be finite");
-  if (lo_precs & ~(uint32_t)(QIRAL_LINKS_F32 | QIRAL_LINKS_F16))
-    return fail(QIRAL_ERR_INVALID_ARG, "lo_precs may only hold QIRAL_LINKS_F32 and QIRAL_LINKS_F16");
-  if (lo_recon != QIRAL_RECON12 && lo_recon != QIRAL_RECON18)
-    return fail(QIRAL_ERR_INVALID_ARG, "lo_recon must be QIRAL_RECON12 or QIRAL_RECON18");
-  if (lo_precs && lo_recon != QIRAL_RECON12)
-    return fail(QIRAL_ERR_UNSUPPORTED, "reduced-precision links are stored reconstruct-12 only");
+  for (const void *p : {gauge_f64, gauge_f32, gauge_f16})
+    if (((uintptr_t)p & 15) != 0) return fail(QIRAL_ERR_INVALID_ARG, "link stores must be 16-byte aligned");
+  if ((gauge_f32 && (gauge_f32 == gauge_f64 || gauge_f32 == gauge_f16)) || (gauge_f16 && gauge_f16 == gauge_f64))
+    return fail(QIRAL_ERR_INVALID_ARG, "the link stores must be distinct buffers");
 
   qiral_lattice *lat = new qiral_lattice();
   for (int i = 0; i < 4; ++i) lat->dims[i] = dims[i];
   lat->geo = make_geo(dims);
   lat->kappa = kappa;
   lat->mu = mu;
+  lat->g64 = gauge_f64;
+  lat->g32 = gauge_f32;
+  lat->g16 = gauge_f16;
   hipStream_t s = (hipStream_t)stream;
   const Geo &g = lat->geo;
-  const size_t nlinks = 8 * npad_of(g);
   auto cleanup = [&](qiral_status r) {
-    if (lat->g64) (void)hipFree(lat->g64);
-    if (lat->g32) (void)hipFree(lat->g32);
-    if (lat->g16) (void)hipFree(lat->g16);
-    delete lat;
+    release_handle(lat);
     return r;
   };
   hipError_t e = hipGetDevice(&lat->device);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
-  const int nblk = (int)((nlinks + WG - 1) / WG);
-  e = hipMalloc(&lat->g64, nlinks * LinkIO<L_F64R18>::LINK_BYTES);
-  if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f64)"));
-  hipLaunchKernelGGL(k_pack_gauge<L_F64R18>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g64);
-  lat->gauge_bytes = nlinks * LinkIO<L_F64R18>::LINK_BYTES;
-  if (lo_precs & QIRAL_LINKS_F32) {
-    e = hipMalloc(&lat->g32, nlinks * LinkIO<L_F32R12>::LINK_BYTES);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f32)"));
-    hipLaunchKernelGGL(k_pack_gauge<L_F32R12>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g32);
-    lat->gauge_bytes += nlinks * LinkIO<L_F32R12>::LINK_BYTES;
+  // host-side resources of later solves and tuning, made once here
+  e = hipHostMalloc(&lat->pinned, poll_bytes(), hipHostMallocDefault);
+  if (e != hipSuccess) { lat->pinned = nullptr; return cleanup(hip_fail(e, "hipHostMalloc(state polls)")); }
+  lat->pinned_bytes = poll_bytes();
+  for (hipEvent_t &ev : lat->poll_ev) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) { ev = nullptr; return cleanup(hip_fail(e, "hipEventCreate")); }
   }
-  if (lo_precs & QIRAL_LINKS_F16) {
-    e = hipMalloc(&lat->g16, nlinks * LinkIO<L_F16R12>::LINK_BYTES);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(links f16)"));
+  for (hipEvent_t &ev : lat->time_ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) { ev = nullptr; return cleanup(hip_fail(e, "hipEventCreate")); }
+  }
+  const size_t nlinks = 8 * npad_of(g);
+  const int nblk = (int)((nlinks + WG - 1) / WG);
+  hipLaunchKernelGGL(k_pack_gauge<L_F64R18>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g64);
+  lat->gauge_bytes = link_store_bytes(g, QIRAL_F64);
+  if (gauge_f32) {
+    hipLaunchKernelGGL(k_pack_gauge<L_F32R12>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g32);
+    lat->gauge_bytes += link_store_bytes(g, QIRAL_F32);
+  }
+  if (gauge_f16) {
     hipLaunchKernelGGL(k_pack_gauge<L_F16R12>, dim3(nblk), dim3(WG), 0, s, g, gauge_canon, lat->g16);
-    lat->gauge_bytes += nlinks * LinkIO<L_F16R12>::LINK_BYTES;
+    lat->gauge_bytes += link_store_bytes(g, QIRAL_F16S);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return cleanup(hip_fail(e, "pack links"));
@@ -435,23 +443,14 @@ extern "C" qiral_status qiral_lattice_create(qiral_lattice **out, const int32_t 
 
 extern "C" qiral_status qiral_lattice_destroy(qiral_lattice *lat) {
   if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
-  hipError_t e1 = lat->g64 ? hipFree(lat->g64) : hipSuccess;
-  hipError_t e2 = lat->g32 ? hipFree(lat->g32) : hipSuccess;
-  hipError_t e3 = lat->g16 ? hipFree(lat->g16) : hipSuccess;
-  hipError_t e4 = lat->ws ? hipFree(lat->ws) : hipSuccess;
-  if (lat->pinned) (void)hipHostFree(lat->pinned);
-  delete lat;
-  if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
-  if (e3 != hipSuccess) return hip_fail(e3, "hipFree");
-  if (e4 != hipSuccess) return hip_fail(e4, "hipFree");
+  release_handle(lat);
   return QIRAL_OK;
 }
 
 extern "C" qiral_status qiral_lattice_query(const qiral_lattice *lat, int64_t *vh, int64_t *bytes) {
   if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
   if (vh) *vh = lat->geo.vh;
-  if (bytes) *bytes = (int64_t)(lat->gauge_bytes + lat->ws_bytes);
+  if (bytes) *bytes = (int64_t)lat->gauge_bytes;
   return QIRAL_OK;
 }
 

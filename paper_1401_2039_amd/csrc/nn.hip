@@ -37,18 +37,15 @@ struct qiral_nn {
   void *act = nullptr;      // hidden activations (H full F32 fields)
   void *gact = nullptr;     // gradient w.r.t. the activations (H fields)
   void *fv = nullptr, *fb = nullptr, *fy = nullptr, *fg = nullptr;   // one full F32 field each
-  double *loss_dev = nullptr;
-  int loss_cap = 0;
+  double *loss_dev = nullptr;   // losses of up to LOSS_CAP training steps
   long adam_step = 0;
-  // FGMRES workspace
-  void *gws = nullptr;
-  size_t gws_bytes = 0;
 };
 
 namespace {
 
 constexpr int NPATH = 9;
 constexpr int WG_CHUNKS = 128;   // site chunks of the weight-gradient reduction
+constexpr int LOSS_CAP = 256;    // training losses kept on the device between copies to the host
 
 qiral_status fail(qiral_status s, const char *m) {
   set_error(m);
@@ -662,80 +659,116 @@ void neumann2(int hidden, double kappa, std::vector<float2> &w) {
 
 // ---------------------------------------------------------------------------
 // C ABI
-extern "C" qiral_status qiral_nn_create(qiral_nn **out, qiral_lattice *lat, int32_t hidden) {
+namespace {
+// Offsets of the network's device memory (one caller-owned buffer).
+struct NnLayout {
+  size_t w, wadj, am, av, grad, part, scal, act, gact, fv, fb, fy, fg, loss, total;
+};
+inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+NnLayout nn_layout(const Geo &g, int hidden) {
+  NnLayout l;
+  const size_t nw = (size_t)2 * NPATH * hidden * 16;
+  const size_t f32 = full_bytes32(g);
+  const int nblocks = nblk(2 * npad_of(g));
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = al256(o + bytes); return at; };
+  l.w = take(sizeof(float2) * nw);
+  l.wadj = take(sizeof(float2) * nw);
+  l.am = take(sizeof(float) * 2 * nw);
+  l.av = take(sizeof(float) * 2 * nw);
+  l.grad = take(sizeof(double) * 2 * nw);
+  l.part = take(sizeof(double) * std::max<size_t>((size_t)NPATH * hidden * WG_CHUNKS * 32, (size_t)nblocks + 64));
+  l.scal = take(sizeof(double) * ((size_t)nblocks + 64));
+  l.act = take(f32 * hidden);
+  l.gact = take(f32 * hidden);
+  l.fv = take(f32);
+  l.fb = take(f32);
+  l.fy = take(f32);
+  l.fg = take(f32);
+  l.loss = take(sizeof(double) * LOSS_CAP);
+  l.total = o;
+  return l;
+}
+bool valid_hidden(int h) { return h == 2 || h == 4 || h == 8; }
+}  // namespace
+
+extern "C" size_t qiral_nn_bytes(const qiral_lattice *lat, int32_t hidden) {
+  if (!lat || !valid_hidden(hidden)) return 0;
+  return nn_layout(lat->geo, hidden).total;
+}
+
+extern "C" qiral_status qiral_nn_create(qiral_nn **out, qiral_lattice *lat, int32_t hidden, void *mem,
+                                        size_t mem_bytes, qiral_stream_t stream) {
   if (!out || !lat) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  if (hidden != 2 && hidden != 4 && hidden != 8) return fail(QIRAL_ERR_UNSUPPORTED, "hidden channels must be 2, 4 or 8");
-  if (!lat->g32) return fail(QIRAL_ERR_INVALID_ARG, "the network needs the lattice's FP32 links (QIRAL_LINKS_F32)");
+  if (!valid_hidden(hidden)) return fail(QIRAL_ERR_UNSUPPORTED, "hidden channels must be 2, 4 or 8");
+  if (!mem) return fail(QIRAL_ERR_WORKSPACE, "mem is NULL (size it with qiral_nn_bytes)");
+  if (((uintptr_t)mem & 255) != 0) return fail(QIRAL_ERR_INVALID_ARG, "mem must be 256-byte aligned");
+  if (!lat->g32) return fail(QIRAL_ERR_INVALID_ARG, "the network needs the lattice's FP32 links (gauge_f32)");
+  const NnLayout l = nn_layout(lat->geo, hidden);
+  if (mem_bytes < l.total) return fail(QIRAL_ERR_WORKSPACE, "mem_bytes is smaller than qiral_nn_bytes");
   qiral_nn *nn = new qiral_nn();
   nn->lat = lat;
   nn->hidden = hidden;
   nn->nw1 = NPATH * hidden * 16;
   nn->nw2 = NPATH * hidden * 16;
   const int nw = nn->nw1 + nn->nw2;
-  const Geo &g = lat->geo;
-  const size_t f32 = full_bytes32(g);
-  const int nblocks = nblk(2 * npad_of(g));
-  auto cleanup = [&](hipError_t e, const char *what) {
-    (void)qiral_nn_destroy(nn);
-    return hip_fail(e, what);
-  };
-  hipError_t e;
-#define NNALLOC(ptr, bytes)                                   \
-  e = hipMalloc((void **)&(ptr), (bytes));                    \
-  if (e != hipSuccess) return cleanup(e, "hipMalloc(nn)");
-  NNALLOC(nn->w, sizeof(float2) * nw);
-  NNALLOC(nn->wadj, sizeof(float2) * nw);
-  NNALLOC(nn->am, sizeof(float) * 2 * nw);
-  NNALLOC(nn->av, sizeof(float) * 2 * nw);
-  NNALLOC(nn->grad, sizeof(double) * 2 * nw);
-  NNALLOC(nn->part, sizeof(double) * std::max<size_t>((size_t)NPATH * hidden * WG_CHUNKS * 32, (size_t)nblocks + 64));
-  NNALLOC(nn->scal, sizeof(double) * ((size_t)nblocks + 64));
-  NNALLOC(nn->act, f32 * hidden);
-  NNALLOC(nn->gact, f32 * hidden);
-  NNALLOC(nn->fv, f32);
-  NNALLOC(nn->fb, f32);
-  NNALLOC(nn->fy, f32);
-  NNALLOC(nn->fg, f32);
-#undef NNALLOC
+  char *m = (char *)mem;
+  nn->w = (float2 *)(m + l.w);
+  nn->wadj = (float2 *)(m + l.wadj);
+  nn->am = (float *)(m + l.am);
+  nn->av = (float *)(m + l.av);
+  nn->grad = (double *)(m + l.grad);
+  nn->part = (double *)(m + l.part);
+  nn->scal = (double *)(m + l.scal);
+  nn->act = m + l.act;
+  nn->gact = m + l.gact;
+  nn->fv = m + l.fv;
+  nn->fb = m + l.fb;
+  nn->fy = m + l.fy;
+  nn->fg = m + l.fg;
+  nn->loss_dev = (double *)(m + l.loss);
+  hipStream_t s = (hipStream_t)stream;
   std::vector<float2> w0;
   neumann2(hidden, lat->kappa, w0);
-  e = hipMemcpy(nn->w, w0.data(), sizeof(float2) * nw, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return cleanup(e, "hipMemcpy(nn weights)");
-  (void)hipMemset(nn->am, 0, sizeof(float) * 2 * nw);
-  (void)hipMemset(nn->av, 0, sizeof(float) * 2 * nw);
-  // activations start at zero so that padding sites stay zero
-  (void)hipMemset(nn->act, 0, f32 * hidden);
-  (void)hipMemset(nn->gact, 0, f32 * hidden);
-  e = hipDeviceSynchronize();
-  if (e != hipSuccess) return cleanup(e, "nn init");
+  hipError_t e = hipMemcpyAsync(nn->w, w0.data(), sizeof(float2) * nw, hipMemcpyHostToDevice, s);
+  // Adam moments start at zero; activations too, so that padding sites stay zero
+  if (e == hipSuccess) e = hipMemsetAsync(nn->am, 0, sizeof(float) * 2 * nw, s);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->av, 0, sizeof(float) * 2 * nw, s);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->act, 0, full_bytes32(lat->geo) * hidden, s);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->gact, 0, full_bytes32(lat->geo) * hidden, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // w0 is a host temporary
+  if (e != hipSuccess) {
+    delete nn;
+    return hip_fail(e, "nn init");
+  }
   *out = nn;
   return QIRAL_OK;
 }
 
 extern "C" qiral_status qiral_nn_destroy(qiral_nn *nn) {
   if (!nn) return fail(QIRAL_ERR_INVALID_ARG, "nn is NULL");
-  void *ptrs[] = {nn->w, nn->wadj, nn->am, nn->av, nn->grad, nn->part, nn->scal, nn->act, nn->gact,
-                  nn->fv, nn->fb, nn->fy, nn->fg, nn->loss_dev, nn->gws};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  delete nn;
+  delete nn;   // the device memory belongs to the caller
   return QIRAL_OK;
 }
 
 extern "C" size_t qiral_nn_num_weights(const qiral_nn *nn) { return nn ? (size_t)(nn->nw1 + nn->nw2) : 0; }
 
-extern "C" qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w, size_t count) {
+extern "C" qiral_status qiral_nn_set_weights(qiral_nn *nn, const float *w, size_t count, qiral_stream_t stream) {
   if (!nn || !w) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
   if (count != (size_t)(nn->nw1 + nn->nw2)) return fail(QIRAL_ERR_INVALID_ARG, "count must equal qiral_nn_num_weights");
-  QIRAL_HIP(hipMemcpy(nn->w, w, sizeof(float2) * count, hipMemcpyHostToDevice));
+  hipStream_t s = (hipStream_t)stream;
+  QIRAL_HIP(hipMemcpyAsync(nn->w, w, sizeof(float2) * count, hipMemcpyHostToDevice, s));
+  QIRAL_HIP(hipStreamSynchronize(s));
   return QIRAL_OK;
 }
 
-extern "C" qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w, size_t count) {
+extern "C" qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w, size_t count, qiral_stream_t stream) {
   if (!nn || !w) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
   if (count != (size_t)(nn->nw1 + nn->nw2)) return fail(QIRAL_ERR_INVALID_ARG, "count must equal qiral_nn_num_weights");
-  QIRAL_HIP(hipMemcpy(w, nn->w, sizeof(float2) * count, hipMemcpyDeviceToHost));
+  hipStream_t s = (hipStream_t)stream;
+  QIRAL_HIP(hipMemcpyAsync(w, nn->w, sizeof(float2) * count, hipMemcpyDeviceToHost, s));
+  QIRAL_HIP(hipStreamSynchronize(s));
   return QIRAL_OK;
 }
 
@@ -829,12 +862,6 @@ extern "C" qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, u
   if (!(lr > 0.0) || !std::isfinite(lr)) return fail(QIRAL_ERR_INVALID_ARG, "lr must be positive");
   if (steps == 0) return QIRAL_OK;
   hipStream_t s = (hipStream_t)stream;
-  if (nn->loss_cap < steps) {
-    if (nn->loss_dev) (void)hipFree(nn->loss_dev);
-    nn->loss_dev = nullptr;
-    QIRAL_HIP(hipMalloc(&nn->loss_dev, sizeof(double) * steps));
-    nn->loss_cap = steps;
-  }
   const Geo &g = nn->lat->geo;
   const int nb = nblk(2 * npad_of(g));
   const int nreal = 2 * (nn->nw1 + nn->nw2);
@@ -845,14 +872,21 @@ extern "C" qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, u
     hipLaunchKernelGGL(k_gauss, dim3(nb), dim3(256), 0, s, g, nn->fv, make_uint2((unsigned)seed, (unsigned)(seed >> 32)),
                        ctr, nn->part);
     QIRAL_HIP(apply_D_full(nn->lat, QIRAL_F32, nn->fb, nn->fv, s));
-    QIRAL_HIP(train_step(nn, nn->fb, nn->fv, nn->loss_dev + k, s));
+    QIRAL_HIP(train_step(nn, nn->fb, nn->fv, nn->loss_dev + k % LOSS_CAP, s));
     nn->adam_step += 1;
     const float c1 = 1.f - powf(b1, (float)nn->adam_step), c2 = 1.f - powf(b2, (float)nn->adam_step);
     hipLaunchKernelGGL(k_adam, dim3((nreal + 255) / 256), dim3(256), 0, s, (float *)nn->w, nn->grad, nn->am, nn->av,
                        nreal, (float)lr, b1, b2, eps, c1, c2);
     QIRAL_HIP(hipGetLastError());
+    // the device keeps LOSS_CAP losses: copy them out when the buffer is full
+    // (the copy is ordered before the steps that overwrite it)
+    const int done = k + 1;
+    if (loss_history && (done % LOSS_CAP == 0 || done == steps)) {
+      const int first = (done - 1) / LOSS_CAP * LOSS_CAP;
+      QIRAL_HIP(hipMemcpyAsync(loss_history + first, nn->loss_dev, sizeof(double) * (done - first),
+                               hipMemcpyDeviceToHost, s));
+    }
   }
-  if (loss_history) QIRAL_HIP(hipMemcpyAsync(loss_history, nn->loss_dev, sizeof(double) * steps, hipMemcpyDeviceToHost, s));
   QIRAL_HIP(hipStreamSynchronize(s));
   return QIRAL_OK;
 }
@@ -861,12 +895,30 @@ extern "C" qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, u
 // FGMRES(m) on D with the network as right preconditioner.
 namespace qiral {
 qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
-                                   qiral_solve_info *info, hipStream_t s);
+                                   void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
+
+// Workspace of FGMRES(m): V[m+1], Z[m], B, X, W, R (F64 full fields), two F32
+// full fields, partials and coefficients; of FCG: B X S W P Z R Q (F64 full), three
+// F32 full fields, partials.
+size_t fgmres_ws_bytes(const Geo &g, int m) {
+  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
+  const int nbk = nblk(f64 / 16);
+  return (size_t)(2 * m + 5) * f64 + 2 * f32 + sizeof(double) * ((size_t)2 * (m + 1) * nbk + 4 * 64 + nbk);
+}
+size_t fcg_ws_bytes(const Geo &g) {
+  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
+  const int nbk = nblk(f64 / 16);
+  return 8 * f64 + 3 * f32 + sizeof(double) * ((size_t)4 * nbk + 4 * 64 + nbk);
+}
+size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm) {
+  if (prm->solver == QIRAL_FGMRES_NN) return fgmres_ws_bytes(lat->geo, prm->restart > 0 ? prm->restart : 20);
+  return fcg_ws_bytes(lat->geo);
+}
 void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
 
 qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
-                        qiral_solve_info *info, hipStream_t s) {
+                        void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   qiral_nn *nn = (qiral_nn *)prm->precond;
   if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
@@ -877,17 +929,8 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
   const size_t n2 = f64 / 16;   // complex entries of a full F64 field (padding included, kept zero)
   const int nbk = nblk(n2);
   const int nsite_blk = nblk(2 * npad_of(g));   // one thread per padded site (layout conversions)
-  // workspace: V[m+1], Z[m], B, X, W, R (F64 full), two F32 full fields, partials, coefficients
-  const size_t need = (size_t)(2 * m + 5) * f64 + 2 * f32 + sizeof(double) * ((size_t)2 * (m + 1) * nbk + 4 * 64 + nbk);
-  if (nn->gws_bytes < need) {
-    if (nn->gws) (void)hipFree(nn->gws);
-    nn->gws = nullptr;
-    nn->gws_bytes = 0;
-    hipError_t e = hipMalloc(&nn->gws, need);
-    if (e != hipSuccess) return fail(QIRAL_ERR_WORKSPACE, "hipMalloc(FGMRES workspace)");
-    nn->gws_bytes = need;
-  }
-  char *p = (char *)nn->gws;
+  if (ws_bytes < fgmres_ws_bytes(g, m)) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace too small");
+  char *p = (char *)ws;
   double2 *V = (double2 *)p; p += (size_t)(m + 1) * f64;
   double2 *Z = (double2 *)p; p += (size_t)m * f64;
   double2 *B = (double2 *)p; p += f64;
@@ -901,9 +944,9 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
   double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
   double *npart = (double *)p;
   const size_t vs = n2;   // stride between vectors of V and Z in complex entries
-  if ((char *)(npart + nbk) > (char *)nn->gws + nn->gws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace layout");
+  if ((char *)(npart + nbk) > (char *)ws + ws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace layout");
 
-  QIRAL_HIP(hipMemsetAsync(nn->gws, 0, (size_t)(2 * m + 5) * f64 + 2 * f32, s));
+  QIRAL_HIP(hipMemsetAsync(ws, 0, (size_t)(2 * m + 5) * f64 + 2 * f32, s));
   import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
   if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
   auto norm = [&](const double2 *v, double &out) -> qiral_status {
@@ -1026,7 +1069,7 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
     cg.x0_is_guess = 1;
     qiral_solve_info ci;
     memset(&ci, 0, sizeof ci);
-    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, &ci, s);
+    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, ws, ws_bytes, &ci, s);
     info->iterations = steps + ci.iterations;
     info->reliable_updates = ci.reliable_updates;
     info->true_rel_resid = ci.true_rel_resid;
@@ -1050,7 +1093,7 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
 // residual s = b - D x is updated alongside the normal residual r = D^dagger s
 // and decides convergence; the true residual is recomputed at the end.
 qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
-                     qiral_solve_info *info, hipStream_t s) {
+                     void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   qiral_nn *nn = (qiral_nn *)prm->precond;
   if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
@@ -1059,17 +1102,8 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
   const size_t n2 = f64 / 16;
   const int nbk = nblk(n2);
   const int nsite_blk = nblk(2 * npad_of(g));
-  // workspace: B X S W P Z R Q (FP64 full fields), three F32 fields, partials
-  const size_t need = 8 * f64 + 3 * f32 + sizeof(double) * ((size_t)4 * nbk + 4 * 64 + nbk);
-  if (nn->gws_bytes < need) {
-    if (nn->gws) (void)hipFree(nn->gws);
-    nn->gws = nullptr;
-    nn->gws_bytes = 0;
-    hipError_t e = hipMalloc(&nn->gws, need);
-    if (e != hipSuccess) return fail(QIRAL_ERR_WORKSPACE, "hipMalloc(FCG workspace)");
-    nn->gws_bytes = need;
-  }
-  char *p = (char *)nn->gws;
+  if (ws_bytes < fcg_ws_bytes(g)) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace too small");
+  char *p = (char *)ws;
   double2 *B = (double2 *)p; p += f64;
   double2 *X = (double2 *)p; p += f64;
   double2 *Sv = (double2 *)p; p += f64;
@@ -1085,9 +1119,9 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
   double2 *coef = (double2 *)p; p += sizeof(double) * 2 * 64;
   double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
   double *npart = (double *)p;
-  if ((char *)(npart + nbk) > (char *)nn->gws + nn->gws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace layout");
+  if ((char *)(npart + nbk) > (char *)ws + ws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace layout");
 
-  QIRAL_HIP(hipMemsetAsync(nn->gws, 0, 8 * f64 + 3 * f32, s));
+  QIRAL_HIP(hipMemsetAsync(ws, 0, 8 * f64 + 3 * f32, s));
   import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
   if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
   auto read = [&](void *dst, const void *src, size_t bytes) -> qiral_status {
@@ -1183,7 +1217,7 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
     cg.x0_is_guess = 1;
     qiral_solve_info ci;
     memset(&ci, 0, sizeof ci);
-    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, &ci, s);
+    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, ws, ws_bytes, &ci, s);
     info->iterations = it + ci.iterations;
     info->true_rel_resid = ci.true_rel_resid;
     info->hop_applications = hops + ci.hop_applications;

@@ -11,14 +11,19 @@ struct qiral_lattice {
   int32_t dims[4];
   qiral::Geo geo;
   double kappa, mu;
+  // packed link stores, owned by the caller (see qiral_gauge_bytes)
   void *g64 = nullptr;   // FP64 reconstruct-18 links
   void *g32 = nullptr;   // FP32 reconstruct-12 links (optional)
   void *g16 = nullptr;   // FP16 reconstruct-12 links (optional)
   size_t gauge_bytes = 0;
-  void *ws = nullptr;    // solver workspace, grown on demand
-  size_t ws_bytes = 0;
-  void *pinned = nullptr;   // pinned host buffer for the solver's state copies, grown on demand
+  // made once by qiral_lattice_create, so that solves allocate nothing: the
+  // pinned host buffer the solver copies its per-system states into (two
+  // copies of QIRAL_MAX_SYSTEMS states), two events that mark those copies, and
+  // two timing events for the autotuner
+  void *pinned = nullptr;
   size_t pinned_bytes = 0;
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  hipEvent_t time_ev[2] = {nullptr, nullptr};
   int device = 0;
   int tuned_nr[3][5] = {};   // autotuned right-hand sides per lane [prec][min(nrhs,4)], 0 = not tuned
   int tuned_t[3][5] = {};    // autotuned waves per site block, same index, 0 = not tuned
@@ -78,7 +83,9 @@ inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi, double a,
                       const void *in, void *out, const void *x, int nrhs, hipStream_t s, int chio = 0, int chix = 0);
 
-// Ensure the handle's workspace holds at least `bytes`.
-qiral_status ensure_workspace(qiral_lattice *lat, size_t bytes);
+// Bytes of a packed link store of the given storage precision (0: not built).
+size_t link_store_bytes(const Geo &g, int prec);
+// Pinned host bytes the solver's state polls need (two copies of every state).
+size_t poll_bytes();
 
 }  // namespace qiral

@@ -34,10 +34,11 @@
 namespace qiral {
 void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
-qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
-                        qiral_solve_info *info, hipStream_t s);
-qiral_status run_fcg(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
-                     qiral_solve_info *info, hipStream_t s);
+qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm, void *ws,
+                        size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
+qiral_status run_fcg(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm, void *ws,
+                     size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
+size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm);
 }  // namespace qiral
 
 using namespace qiral;
@@ -57,16 +58,18 @@ qiral_status fail(qiral_status s, const char *msg) {
   return s;
 }
 
-struct Layout {
-  size_t off_desc, off_work, off_state, off_part, total;
-  std::vector<size_t> off_sys;   // per system: start of its fields
-  std::vector<size_t> part_off;  // per system: offset of its partials (doubles) inside the partial region
-};
-
 // Per-system field sizes
 struct SysSizes {
   size_t hb_it, hb_x, hb64;
   size_t bytes;
+};
+
+struct Layout {
+  size_t off_desc, off_work, off_state, off_part, total;
+  long nwork;
+  std::vector<SysSizes> sz;      // per system: field sizes
+  std::vector<size_t> off_sys;   // per system: start of its fields
+  std::vector<size_t> part_off;  // per system: offset of its partials (doubles) inside the partial region
 };
 
 SysSizes sys_sizes(const Geo &g, int prec, int nit) {
@@ -81,40 +84,62 @@ SysSizes sys_sizes(const Geo &g, int prec, int nit) {
   return z;
 }
 
-qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, const qiral_solve_params *prm,
-                       qiral_solve_info *info, hipStream_t s) {
-  auto t0 = std::chrono::steady_clock::now();
-  const int nsys = (int)sys.size();
-  const int prec = prm->inner_prec;
-  const bool mixed = prec != QIRAL_F64;
-  const bool bicg = prm->solver == QIRAL_BICGSTAB_EO;
-  const bool cr = prm->solver == QIRAL_CRNR_EO;
-  const int nit = bicg ? 7 : cr ? 8 : 5;
+int n_iterate_fields(const qiral_solve_params *prm) {
+  return prm->solver == QIRAL_BICGSTAB_EO ? 7 : prm->solver == QIRAL_CRNR_EO ? 8 : 5;
+}
 
-  // ---- layout
+// Workspace layout of one solve over the systems `sys` (the same for the size
+// query and the solve itself).
+Layout solve_layout(const std::vector<const qiral_lattice *> &lats, const qiral_solve_params *prm) {
+  const int nsys = (int)lats.size();
+  const int nit = n_iterate_fields(prm);
   Layout lay;
-  std::vector<SysSizes> sz(nsys);
   long nwork = 0;
   size_t nparts = 0;
   lay.part_off.resize(nsys);
+  lay.sz.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
-    sz[i] = sys_sizes(sys[i].lat->geo, prec, nit);
-    nwork += sys[i].lat->geo.nb;
+    lay.sz[i] = sys_sizes(lats[i]->geo, prm->inner_prec, nit);
+    nwork += lats[i]->geo.nb;
     lay.part_off[i] = nparts;
-    nparts += (size_t)NSLOT * NV * 4 * sys[i].lat->geo.nb;
+    nparts += (size_t)NSLOT * NV * 4 * lats[i]->geo.nb;
   }
-  if (nwork > (1l << 30)) return fail(QIRAL_ERR_UNSUPPORTED, "too many work items");
+  lay.nwork = nwork;
   size_t off = 0;
   lay.off_desc = off; off = align_up(off + sizeof(SysDesc) * nsys);
   lay.off_work = off; off = align_up(off + 2 * sizeof(uint32_t) * nwork);
   lay.off_state = off; off = align_up(off + sizeof(SysState) * nsys);
   lay.off_part = off; off = align_up(off + sizeof(double) * nparts);
   lay.off_sys.resize(nsys);
-  for (int i = 0; i < nsys; ++i) { lay.off_sys[i] = off; off += sz[i].bytes; }
+  for (int i = 0; i < nsys; ++i) { lay.off_sys[i] = off; off += lay.sz[i].bytes; }
   lay.total = off;
-  qiral_status st = ensure_workspace(owner, lay.total);
-  if (st != QIRAL_OK) return st;
-  char *ws = (char *)owner->ws;
+  return lay;
+}
+
+std::vector<const qiral_lattice *> lattices_of(const std::vector<SysIn> &sys) {
+  std::vector<const qiral_lattice *> l(sys.size());
+  for (size_t i = 0; i < sys.size(); ++i) l[i] = sys[i].lat;
+  return l;
+}
+
+qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, const qiral_solve_params *prm,
+                       void *ws_base, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int nsys = (int)sys.size();
+  const int prec = prm->inner_prec;
+  const bool mixed = prec != QIRAL_F64;
+  const bool bicg = prm->solver == QIRAL_BICGSTAB_EO;
+  const bool cr = prm->solver == QIRAL_CRNR_EO;
+  const int nit = n_iterate_fields(prm);
+
+  // ---- layout
+  const Layout lay = solve_layout(lattices_of(sys), prm);
+  const std::vector<SysSizes> &sz = lay.sz;
+  const long nwork = lay.nwork;
+  if (nwork > (1l << 30)) return fail(QIRAL_ERR_UNSUPPORTED, "too many work items");
+  if (!ws_base || ws_bytes < lay.total) return fail(QIRAL_ERR_WORKSPACE, "workspace smaller than qiral_solve_workspace_bytes");
+  char *ws = (char *)ws_base;
+  qiral_status st = QIRAL_OK;
 
   // ---- system table
   std::vector<SysDesc> desc(nsys);
@@ -304,22 +329,13 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     QIRAL_HIP(hipStreamSynchronize(s));
     return QIRAL_OK;
   };
-  // Two pinned copies of the states, so that the host examines the states after
-  // one chunk of iterations while the next chunk already runs.
+  // Two pinned copies of the states (made with the lattice handle), so that the
+  // host examines the states after one chunk of iterations while the next chunk
+  // already runs.
   const size_t sbytes = sizeof(SysState) * nsys;
-  if (owner->pinned_bytes < 2 * sbytes) {
-    if (owner->pinned) (void)hipHostFree(owner->pinned);
-    owner->pinned = nullptr;
-    owner->pinned_bytes = 0;
-    QIRAL_HIP(hipHostMalloc(&owner->pinned, 2 * sbytes, hipHostMallocDefault));
-    owner->pinned_bytes = 2 * sbytes;
-  }
+  if (owner->pinned_bytes < 2 * sbytes) return fail(QIRAL_ERR_INVALID_ARG, "state poll buffer too small");
   SysState *hbuf[2] = {(SysState *)owner->pinned, (SysState *)owner->pinned + nsys};
-  struct Events {
-    hipEvent_t e[2] = {nullptr, nullptr};
-    ~Events() { for (hipEvent_t x : e) if (x) (void)hipEventDestroy(x); }
-  } ev;
-  for (int k = 0; k < 2; ++k) QIRAL_HIP(hipEventCreateWithFlags(&ev.e[k], hipEventDisableTiming));
+  hipEvent_t *ev = owner->poll_ev;
   auto enqueue_chunk = [&](int n) -> qiral_status {
     if (use_graph) {
       if (!gexec) {
@@ -342,7 +358,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   };
   auto post_copy = [&](int k) -> qiral_status {
     QIRAL_HIP(hipMemcpyAsync(hbuf[k], ws + lay.off_state, sbytes, hipMemcpyDeviceToHost, s));
-    QIRAL_HIP(hipEventRecord(ev.e[k], s));
+    QIRAL_HIP(hipEventRecord(ev[k], s));
     return QIRAL_OK;
   };
 
@@ -374,7 +390,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
       if ((st = enqueue_chunk(ahead)) != QIRAL_OK) return st;
       if ((st = post_copy(1 - cur)) != QIRAL_OK) { free_graph(); return st; }
       enqueued += ahead;
-      hipError_t e = hipEventSynchronize(ev.e[cur]);
+      hipError_t e = hipEventSynchronize(ev[cur]);
       if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipEventSynchronize"); }
       bool all_done = true;
       for (int i = 0; i < nsys; ++i) all_done = all_done && (hbuf[cur][i].status & ST_DONE);
@@ -470,36 +486,78 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (p->solver == QIRAL_FCG_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FCG needs a precond network");
   if ((p->solver == QIRAL_FGMRES_NN || p->solver == QIRAL_FCG_NN) && p->inner_prec != QIRAL_F64)
     return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES and FCG run in FP64 (inner_prec F64)");
+  if (p->solver == QIRAL_FGMRES_NN && p->restart > 64) return fail(QIRAL_ERR_INVALID_ARG, "restart must be <= 64");
   return QIRAL_OK;
 }
 
 }  // namespace
 
 namespace qiral {
+size_t poll_bytes() { return 2 * (size_t)QIRAL_MAX_SYSTEMS * sizeof(SysState); }
+
 qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
-                                   qiral_solve_info *info, hipStream_t s) {
+                                   void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
   std::vector<SysIn> sys{SysIn{lat, x, b}};
-  return run_solve(lat, sys, prm, info, s);
+  return run_solve(lat, sys, prm, ws, ws_bytes, info, s);
 }
 }  // namespace qiral
 
-extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
-                                    const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream) {
+namespace {
+
+bool is_flex(int solver) { return solver == QIRAL_FGMRES_NN || solver == QIRAL_FCG_NN; }
+
+// Workspace of a solve over these lattices (one system each; the right-hand
+// sides of qiral_solve are systems of one lattice).  FGMRES and FCG run one
+// right-hand side at a time in the same workspace and may continue with even-odd
+// CGNR (the fallback) in it.
+size_t ws_need(const std::vector<const qiral_lattice *> &lats, const qiral_solve_params *p) {
+  if (is_flex(p->solver)) {
+    qiral_solve_params cg = *p;
+    cg.solver = QIRAL_CGNR_EO;
+    return std::max(flex_ws_bytes(lats[0], p), solve_layout({lats[0]}, &cg).total);
+  }
+  return solve_layout(lats, p).total;
+}
+
+// The workspace pointer itself (before the handle is read)
+qiral_status check_ws_ptr(const void *ws) {
+  if (!ws) return fail(QIRAL_ERR_WORKSPACE, "ws is NULL (size it with qiral_solve_workspace_bytes)");
+  if (((uintptr_t)ws & 255) != 0) return fail(QIRAL_ERR_INVALID_ARG, "ws must be 256-byte aligned");
+  return QIRAL_OK;
+}
+
+qiral_status check_ws(const void *ws, size_t ws_bytes, size_t need) {
+  qiral_status st = check_ws_ptr(ws);
+  if (st != QIRAL_OK) return st;
+  if (ws_bytes < need) return fail(QIRAL_ERR_WORKSPACE, "ws_bytes is smaller than qiral_solve_workspace_bytes");
+  return QIRAL_OK;
+}
+
+qiral_status check_solve_args(const qiral_lattice *lat, const double *x, const double *b, int nrhs,
+                              const qiral_solve_params *params, const void *ws, const qiral_solve_info *info) {
   if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
-  if (!x_canon || !b_canon) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
-  if (nrhs < 1 || nrhs > 255) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be in [1, 255]");
+  if (!x || !b) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
+  if (nrhs < 1 || nrhs > QIRAL_MAX_SYSTEMS) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be in [1, 255]");
   if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
   qiral_status st = check_params(params);
   if (st != QIRAL_OK) return st;
+  if ((st = check_ws_ptr(ws)) != QIRAL_OK) return st;
   if (!links_for(lat, params->inner_prec))
-    return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (see lo_precs)");
+    return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (gauge_f32 / gauge_f16)");
+  return QIRAL_OK;
+}
+
+// qiral_solve after its argument checks, in the workspace ws.
+qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                      const qiral_solve_params *params, void *ws, size_t ws_bytes, qiral_solve_info *info,
+                      hipStream_t stream) {
   const size_t stride = (size_t)lat->geo.vh * 2 * 24;
-  if (params->solver == QIRAL_FGMRES_NN || params->solver == QIRAL_FCG_NN) {
+  if (is_flex(params->solver)) {
     // one right-hand side after the other
     auto run = params->solver == QIRAL_FGMRES_NN ? run_fgmres : run_fcg;
     qiral_status worst = QIRAL_OK;
     for (int r = 0; r < nrhs; ++r) {
-      qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, params, info + r, (hipStream_t)stream);
+      qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, params, ws, ws_bytes, info + r, stream);
       if (s != QIRAL_OK && s != QIRAL_ERR_NOT_CONVERGED) return s;
       if (s != QIRAL_OK) worst = s;
     }
@@ -507,26 +565,59 @@ extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const d
   }
   std::vector<SysIn> sys(nrhs);
   for (int r = 0; r < nrhs; ++r) sys[r] = SysIn{lat, x_canon + r * stride, b_canon + r * stride};
-  return run_solve(lat, sys, params, info, (hipStream_t)stream);
+  return run_solve(lat, sys, params, ws, ws_bytes, info, stream);
+}
+
+}  // namespace
+
+extern "C" size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params,
+                                              int32_t nrhs) {
+  if (!lat || nrhs < 1 || nrhs > QIRAL_MAX_SYSTEMS || check_params(params) != QIRAL_OK) return 0;
+  if (is_flex(params->solver)) return ws_need({lat}, params);
+  return ws_need(std::vector<const qiral_lattice *>(nrhs, lat), params);
+}
+
+extern "C" size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *lats, int32_t nsys,
+                                                    const qiral_solve_params *params) {
+  if (!lats || nsys < 1 || nsys > QIRAL_MAX_SYSTEMS || check_params(params) != QIRAL_OK) return 0;
+  if (is_flex(params->solver)) return 0;
+  std::vector<const qiral_lattice *> l(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    if (!lats[i]) return 0;
+    l[i] = lats[i];
+  }
+  return ws_need(l, params);
+}
+
+extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                                    const qiral_solve_params *params, void *ws, size_t ws_bytes,
+                                    qiral_solve_info *info, qiral_stream_t stream) {
+  qiral_status st = check_solve_args(lat, x_canon, b_canon, nrhs, params, ws, info);
+  if (st != QIRAL_OK) return st;
+  const size_t need = qiral_solve_workspace_bytes(lat, params, nrhs);
+  if ((st = check_ws(ws, ws_bytes, need)) != QIRAL_OK) return st;
+  return solve_in(lat, x_canon, b_canon, nrhs, params, ws, ws_bytes, info, (hipStream_t)stream);
 }
 
 extern "C" qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_canon,
                                           const double *const *b_canon, int32_t nsys,
-                                          const qiral_solve_params *params, qiral_solve_info *info,
-                                          qiral_stream_t stream) {
+                                          const qiral_solve_params *params, void *ws, size_t ws_bytes,
+                                          qiral_solve_info *info, qiral_stream_t stream) {
   if (!lats || !x_canon || !b_canon) return fail(QIRAL_ERR_INVALID_ARG, "array pointer is NULL");
-  if (nsys < 1 || nsys > 255) return fail(QIRAL_ERR_INVALID_ARG, "nsys must be in [1, 255]");
+  if (nsys < 1 || nsys > QIRAL_MAX_SYSTEMS) return fail(QIRAL_ERR_INVALID_ARG, "nsys must be in [1, 255]");
   if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
   qiral_status st = check_params(params);
   if (st != QIRAL_OK) return st;
-  if (params->solver == QIRAL_FGMRES_NN || params->solver == QIRAL_FCG_NN)
+  if (is_flex(params->solver))
     return fail(QIRAL_ERR_UNSUPPORTED, "the learned-preconditioner solvers take one lattice (qiral_solve)");
+  if ((st = check_ws_ptr(ws)) != QIRAL_OK) return st;
   std::vector<SysIn> sys(nsys);
   for (int i = 0; i < nsys; ++i) {
     if (!lats[i] || !x_canon[i] || !b_canon[i]) return fail(QIRAL_ERR_INVALID_ARG, "a system pointer is NULL");
     if (!links_for(lats[i], params->inner_prec))
-      return fail(QIRAL_ERR_INVALID_ARG, "a lattice holds no links of the inner precision (see lo_precs)");
+      return fail(QIRAL_ERR_INVALID_ARG, "a lattice holds no links of the inner precision (gauge_f32 / gauge_f16)");
     sys[i] = SysIn{lats[i], x_canon[i], b_canon[i]};
   }
-  return run_solve(lats[0], sys, params, info, (hipStream_t)stream);
+  if ((st = check_ws(ws, ws_bytes, qiral_solve_batch_workspace_bytes(lats, nsys, params))) != QIRAL_OK) return st;
+  return run_solve(lats[0], sys, params, ws, ws_bytes, info, (hipStream_t)stream);
 }

@@ -2,7 +2,8 @@
 // 4) and right-hand sides per lane (1..4), timed with HIP events on the caller's stream for one
 // lattice, precision and right-hand-side count.  Results live in the lattice
 // handle and, if QIRAL_TUNE_CACHE names a file, in a JSON cache keyed by
-// (architecture, precision, dims, nrhs) that later handles read.
+// (architecture, precision, dims, nrhs) that later handles read.  The caller
+// passes the two half-fields the timed hops read and write.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cstdio>
@@ -37,7 +38,7 @@ bool cache_lookup(const std::string &key, int &t, int &nr) {
     const size_t i = line.find(pat);
     if (i == std::string::npos) continue;
     int a = 0, b = 0;
-    if (sscanf(line.c_str() + i + pat.size(), "%d, %d", &a, &b) == 2 && (a == 2 || a == 4) && b >= 1 && b <= 4) {
+    if (sscanf(line.c_str() + i + pat.size(), "%d, %d", &a, &b) == 2 && (a == 1 || a == 2 || a == 4) && b >= 1 && b <= 4) {
       t = a;
       nr = b;
       return true;
@@ -80,9 +81,10 @@ int tuned_nr(const qiral_lattice *lat, int prec, int nrhs) {
 }
 }  // namespace qiral
 
-extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, int32_t *best_t,
-                                   int32_t *best_nr, double *best_us, qiral_stream_t stream) {
+extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t nrhs, void *in, void *out,
+                                   int32_t *best_t, int32_t *best_nr, double *best_us, qiral_stream_t stream) {
   if (!lat) { set_error("lat is NULL"); return QIRAL_ERR_INVALID_ARG; }
+  if (!in || !out || in == out) { set_error("in and out must be two distinct half-fields"); return QIRAL_ERR_INVALID_ARG; }
   if (prec != QIRAL_F64 && prec != QIRAL_F32 && prec != QIRAL_F16S) { set_error("bad precision"); return QIRAL_ERR_INVALID_ARG; }
   if (nrhs < 1) { set_error("nrhs must be >= 1"); return QIRAL_ERR_INVALID_ARG; }
   if (!links_for(lat, prec)) { set_error("the lattice holds no links of this precision"); return QIRAL_ERR_INVALID_ARG; }
@@ -96,15 +98,10 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
   } else {
     hipStream_t s = (hipStream_t)stream;
     const size_t fb = half_bytes(lat->geo, prec) * (size_t)nrhs;
-    void *in = nullptr, *out = nullptr;
-    QIRAL_HIP(hipMalloc(&in, fb));
-    hipError_t e = hipMalloc(&out, fb);
-    if (e != hipSuccess) { (void)hipFree(in); return hip_fail(e, "hipMalloc(tune)"); }
     // the values do not change the timing; zeros keep every scale finite
-    (void)hipMemsetAsync(in, 0, fb, s);
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    QIRAL_HIP(hipMemsetAsync(in, 0, fb, s));
+    hipEvent_t e0 = lat->time_ev[0], e1 = lat->time_ev[1];
+    hipError_t e = hipSuccess;
     double best = 1e30;
     const int nrmax = 4;   // further limited per shape by hop_nr_max
     for (int tt : {1, 2, 4}) {
@@ -125,10 +122,6 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
         if (u < best) { best = u; t = tt; nr = n; }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(in);
-    (void)hipFree(out);
     if (e != hipSuccess) return hip_fail(e, "tuning launch");
     lat->tuned_t[prec][idx] = t;
     lat->tuned_nr[prec][idx] = nr;

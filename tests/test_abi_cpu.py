@@ -51,26 +51,42 @@ def test_field_bytes():
     assert api.qiral_field_bytes((4, 4, 4, 4), L.ODD, L.F64, 0) == 0
 
 
-def _create(dims, gauge=1, kappa=0.12, mu=0.0, lo=0, recon=L.RECON12):
+def test_gauge_bytes():
+    # 4^4: 2 blocks of 64 sites per parity, 8 links (4 directions x 2 parities) per padded site
+    n = 8 * 128
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F64) == n * 144
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F32) == n * 48
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F16S) == n * 24
+    assert api.qiral_gauge_bytes((24, 24, 24, 48), L.F32) == 8 * 331776 * 48
+    # the combinations the library does not build, and invalid dims -> 0
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F32, L.RECON18) == 0
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F64, L.RECON12) == 0
+    assert api.qiral_gauge_bytes((4, 4, 4, 4), L.F64, 7) == 0
+    assert api.qiral_gauge_bytes((4, 5, 4, 4), L.F64) == 0
+
+
+def _create(dims, gauge=1, kappa=0.12, mu=0.0, g64=256, g32=None, g16=None):
     lib = L.load()
     h = ctypes.c_void_p()
-    return lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), kappa, mu,
-                                    ctypes.c_void_p(gauge), lo, recon, None), h
+    return lib.qiral_lattice_create(ctypes.byref(h), L.dims_arg(dims), kappa, mu, ctypes.c_void_p(gauge),
+                                    ctypes.c_void_p(g64), ctypes.c_void_p(g32), ctypes.c_void_p(g16), None), h
 
 
 def test_create_validation():
     lib = L.load()
-    assert lib.qiral_lattice_create(None, L.dims_arg((4, 4, 4, 4)), 0.1, 0.0, ctypes.c_void_p(1), 0, 12, None) == L.ERR_INVALID_ARG
+    one = ctypes.c_void_p(256)
+    assert lib.qiral_lattice_create(None, L.dims_arg((4, 4, 4, 4)), 0.1, 0.0, one, one, None, None, None) == L.ERR_INVALID_ARG
     assert _create((3, 4, 4, 4))[0] == L.ERR_BAD_DIMS
     assert _create((4, 4, 0, 4))[0] == L.ERR_BAD_DIMS
     assert _create((4, 4, 4, 4), gauge=0)[0] == L.ERR_INVALID_ARG
+    assert _create((4, 4, 4, 4), g64=None)[0] == L.ERR_INVALID_ARG          # the FP64 store is required
+    assert b"gauge_f64" in lib.qiral_last_error()
     assert _create((4, 4, 4, 4), kappa=float("nan"))[0] == L.ERR_INVALID_ARG
-    assert _create((4, 4, 4, 4), lo=8)[0] == L.ERR_INVALID_ARG
-    assert _create((4, 4, 4, 4), recon=7)[0] == L.ERR_INVALID_ARG
     assert _create((4, 4, 4, 4), mu=float("inf"))[0] == L.ERR_INVALID_ARG
-    st, h = _create((4, 4, 4, 4), lo=L.LINKS_F32, recon=L.RECON18)
-    assert st == L.ERR_UNSUPPORTED and h.value is None
-    assert b"reconstruct" in lib.qiral_last_error()
+    assert _create((4, 4, 4, 4), g32=257)[0] == L.ERR_INVALID_ARG           # misaligned store
+    assert _create((4, 4, 4, 4), g32=256)[0] == L.ERR_INVALID_ARG           # the same buffer twice
+    st, h = _create((4, 4, 4, 4), g16=512, g32=512)
+    assert st == L.ERR_INVALID_ARG and h.value is None
 
 
 def test_null_handles_rejected():
@@ -83,9 +99,17 @@ def test_null_handles_rejected():
     assert lib.qiral_apply_M(None, one, one, one, L.OP_D, L.F64, 1, None) == L.ERR_INVALID_ARG
     p = api.solve_params()
     info = (L.SolveInfo * 1)()
-    assert lib.qiral_solve(None, one, one, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
-    assert lib.qiral_solve_batch(None, None, None, 1, ctypes.byref(p), info, None) == L.ERR_INVALID_ARG
+    ws = ctypes.c_void_p(256)
+    assert lib.qiral_solve(None, one, one, 1, ctypes.byref(p), ws, 1 << 20, info, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_solve_batch(None, None, None, 1, ctypes.byref(p), ws, 1 << 20, info, None) == L.ERR_INVALID_ARG
     assert lib.qiral_lattice_query(None, None, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_tune(None, L.F32, 1, one, one, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_nn_create(None, one, 8, one, 1, None) == L.ERR_INVALID_ARG
+    assert lib.qiral_nn_destroy(None) == L.ERR_INVALID_ARG
+    # size queries answer 0 for invalid arguments
+    assert lib.qiral_solve_workspace_bytes(None, ctypes.byref(p), 1) == 0
+    assert lib.qiral_solve_batch_workspace_bytes(None, 1, ctypes.byref(p)) == 0
+    assert lib.qiral_nn_bytes(None, 8) == 0
 
 
 def test_solve_params_validation():
@@ -97,7 +121,7 @@ def test_solve_params_validation():
 
     def solve(**kw):
         p = api.solve_params(**kw)
-        return lib.qiral_solve(one, one, one, 1, ctypes.byref(p), info, None)
+        return lib.qiral_solve(one, one, one, 1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 20, info, None)
 
     assert solve(tol=0.0) == L.ERR_INVALID_ARG
     assert solve(maxiter=0) == L.ERR_INVALID_ARG
@@ -110,6 +134,28 @@ def test_solve_params_validation():
     assert solve(solver=L.FCG_NN) == L.ERR_INVALID_ARG                # no network
     assert solve(solver=L.FCG_NN, precond=1, inner_prec=L.F32) == L.ERR_UNSUPPORTED
     assert solve(solver=L.FGMRES_NN, precond=1, inner_prec=L.F16S) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.FGMRES_NN, precond=1, restart=65) == L.ERR_INVALID_ARG
+    # an invalid parameter set has no workspace size
+    p = api.solve_params(tol=-1.0)
+    assert lib.qiral_solve_workspace_bytes(one, ctypes.byref(p), 1) == 0
+    assert lib.qiral_solve_workspace_bytes(one, ctypes.byref(api.solve_params()), 0) == 0
+    assert lib.qiral_solve_workspace_bytes(one, ctypes.byref(api.solve_params()), 256) == 0
+
+
+def test_workspace_pointer_checked_before_the_handle():
+    """A missing or misaligned workspace is refused before the lattice handle is
+    read or any HIP call is made (a stand-in handle would fault if it were)."""
+    lib = L.load()
+    one = ctypes.c_void_p(1)
+    info = (L.SolveInfo * 1)()
+    p = api.solve_params()
+    assert lib.qiral_solve(one, one, one, 1, ctypes.byref(p), None, 1 << 30, info, None) == L.ERR_WORKSPACE
+    assert b"qiral_solve_workspace_bytes" in lib.qiral_last_error()
+    assert lib.qiral_solve(one, one, one, 1, ctypes.byref(p), ctypes.c_void_p(4096 + 16), 1 << 30, info,
+                           None) == L.ERR_INVALID_ARG
+    assert b"aligned" in lib.qiral_last_error()
+    arr = (ctypes.c_void_p * 1)(1)
+    assert lib.qiral_solve_batch(arr, arr, arr, 1, ctypes.byref(p), None, 1 << 30, info, None) == L.ERR_WORKSPACE
 
 
 def test_batch_rejects_learned_solvers():
@@ -120,6 +166,7 @@ def test_batch_rejects_learned_solvers():
     arr = (ctypes.c_void_p * 1)(1)
     for solver in (L.FGMRES_NN, L.FCG_NN):
         p = api.solve_params(solver=solver, precond=1)
-        assert lib.qiral_solve_batch(arr, arr, arr, 1, ctypes.byref(p), info, None) == L.ERR_UNSUPPORTED
+        assert lib.qiral_solve_batch(arr, arr, arr, 1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 20, info,
+                                     None) == L.ERR_UNSUPPORTED
         assert b"one lattice" in lib.qiral_last_error()
 

@@ -3,7 +3,7 @@ D, D^dagger, S, S^dagger against the complex128 oracle, element by element.
 
 Bars: FP64 within 1e-12 relative (and 1e-12 of the largest element); FP32 with
 reconstruct-12 links against the oracle applied to the same rounded inputs
-within 2e-6; F16S against the oracle on the same rounded inputs within the FP16
+within 2e-6 relative and 5e-6 of the largest element, element by element; F16S against the oracle on the same rounded inputs within the FP16
 quantisation of the output (2^-11 of each site's scale, plus FP32 rounding).
 Sizes: 4^4 (two blocks), 2^4 and 4x2x2x4 (a block only partly filled), 6x4x2x4
 (a ragged last block), and 16^3x32; 24^3x48 on sampled sites."""
@@ -79,7 +79,9 @@ def test_dslash_eo(setup, prec, dag):
             if prec == q.F64:
                 assert rel < 1e-12 and parity_maxabs(got[r], want, p) < 1e-12 * np.abs(want).max(), rel
             elif prec == q.F32:
-                assert rel < 2e-6, rel
+                # element by element against the largest element (the FP32 sums of
+                # up to 8 terms, each rounded a few times)
+                assert rel < 2e-6 and parity_maxabs(got[r], want, p) < 5e-6 * np.abs(want).max(), rel
             else:
                 # output quantised to FP16 with a per-site scale
                 diff = np.abs(W.project(got[r], p) - want).reshape(-1, 12).max(axis=1)
@@ -100,6 +102,7 @@ def test_apply_M_f64(setup, op):
         got = host(lat.export_field(out, q.FULL, q.F64))[0]
         want = W.apply_D(U, k, 0.0, b) if op == q.OP_D else W.apply_Ddag(U, k, 0.0, b)
         rel = np.sqrt(W.norm2(got - want) / W.norm2(want))
+        assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
     else:
         bo = W.project(b, 1)
         inp = lat.import_field(dev(b[None]), q.ODD, q.F64)
@@ -109,6 +112,7 @@ def test_apply_M_f64(setup, op):
         got = host(lat.export_field(out, q.ODD, q.F64))[0]
         want = W.schur(U, k, 0.0, bo, dagger=(op == q.OP_SCHUR_DAG))
         rel = parity_rel(got, want, 1)
+        assert parity_maxabs(got, want, 1) < 1e-12 * np.abs(want).max()
     assert rel < 1e-12, rel
 
 

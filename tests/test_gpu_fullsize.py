@@ -1,0 +1,135 @@
+"""The workloads at their full sizes, judged by the oracle.
+
+* 24^3x48 with exp(0.4 i H) links: the 12-right-hand-side hop in the
+  configuration the batched solves run it in (autotuned shape, streaming
+  accesses beyond 128 MB), F16S and F32, on sampled sites of several
+  right-hand sides against the oracle's single-site hop on the same rounded
+  inputs; and the batched F16S mixed-precision solve of the 12 point sources,
+  with the true residual of 3 of them recomputed by the oracle's full D.
+* The uneven batch of 32 systems (8 each of 8^4, 12^3x24, 16^3x32, 20^3x40),
+  FP32/FP64 mixed in one HIP-graph-replayed batch: every system's residual
+  under the oracle's D.
+* 24^3x48 with exp(0.5 i H), kappa 0.125: the network trained on 2048 pairs,
+  FGMRES(20) on one of the 12 Gaussian sources, judged by the oracle's D.
+
+Bars: hops as in the small-lattice tests (FP32 2e-6 of the site's largest
+element; F16S the FP16 quantum of the site's scale); solves 1e-10 true
+residual under the oracle's complex128 operator."""
+import numpy as np
+import pytest
+import torch
+
+import latgen
+from oracle import solvers as S, storage, wilson as W
+import paper_1401_2039_amd as q
+from gpu_util import say, dev, host, DevSites, RoundedLinks, sampled_sites
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def c2():
+    say("24^3x48 eps0.4 setup (links and 12 point sources)")
+    cfg = latgen.make_config(2)
+    lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
+    yield cfg, lat
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [q.F32, q.F16S], ids=["f32", "f16s"])
+def test_hop_12rhs_24x48_sampled(c2, prec):
+    cfg, lat = c2
+    dims, U = cfg["dims"], cfg["U"]
+    nrhs = 12
+    say("hop 12 rhs 24^3x48 sampled", prec)
+    t, nr, _ = lat.tune(prec, nrhs)
+    # 12 distinct right-hand sides: phases and scales of one Gaussian field, so
+    # that a right-hand side read or written in the wrong place shows
+    psi = torch.from_numpy(latgen.gaussian_source(2, 1, dims, 1)).cuda()
+    coef = [(1.0 + 0.25 * r) * np.exp(0.7j * r) for r in range(nrhs)]
+    rhs = torch.cat([psi * complex(c) for c in coef]).contiguous()
+    del psi
+    src_full = lat.import_field(rhs, q.FULL, prec)
+    hb = q.qiral_field_bytes(dims, q.EVEN, prec)
+    rnd = storage.round_f32 if prec == q.F32 else storage.round_f16s
+    Ur = RoundedLinks(U, np.complex64 if prec == q.F32 else "f16")
+    rng = np.random.default_rng(4812 + prec)
+    for p, dag in ((0, 0), (1, 1)):
+        # the (1 - p) halves of the 12 full fields, packed consecutively
+        src = torch.cat([src_full[r * 2 * hb + (1 - p) * hb: r * 2 * hb + (2 - p) * hb] for r in range(nrhs)])
+        out = lat.field(q.EVEN, prec, nrhs=nrhs)
+        lat.dslash_eo(out, src, p, dag, prec, nrhs=nrhs)
+        got = lat.export_field(out, p, prec, nrhs=nrhs)
+        del src, out
+        for r in (0, 5, 11):
+            field = DevSites(rhs[r], rnd)
+            for x in sampled_sites(rng, dims, p, 8):
+                want = W.hop_site(Ur, field, x, dagger=bool(dag))
+                g = got[r, x[3], x[2], x[1], x[0]].cpu().numpy()
+                err = np.abs(g - want).max()
+                scale = np.abs(np.stack([want.real, want.imag])).max()
+                if prec == q.F32:
+                    assert err <= 2e-6 * np.abs(want).max(), (t, nr, r, x, err)
+                else:
+                    assert err <= (2.0 ** -11) * scale * 1.01 + 1e-6 * scale, (t, nr, r, x, err, scale)
+        del got
+    del rhs, src_full
+
+
+def test_batched_f16s_point_sources_24x48(c2):
+    cfg, lat = c2
+    say("batched F16S solve 24^3x48 12 point sources")
+    lat.tune(q.F16S, 12)
+    b = dev(cfg["b"])
+    x, st, info = lat.solve(b, tol=TOL, inner_prec=q.F16S)
+    assert st == 0 and all(i["converged"] for i in info), info
+    xs = host(x)
+    del x, b
+    for r in (0, 6, 11):
+        say("oracle residual of point source", r)
+        res = S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, xs[r], cfg["b"][r])
+        assert res <= TOL, (r, res)
+        assert abs(res - info[r]["true_rel_resid"]) <= 0.05 * res, (r, res, info[r]["true_rel_resid"])
+
+
+def test_uneven_batch_32_systems():
+    say("uneven batch of 32: inputs")
+    cfgs = [latgen.make_config(3, s) for s in range(32)]
+    lats = [q.Lattice(c["dims"], c["kappa"], c["U"]) for c in cfgs]
+    bs = [dev(c["b"]) for c in cfgs]
+    xs = [torch.zeros_like(b) for b in bs]
+    say("uneven batch of 32: solve (F32 mixed, graph)")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        st, info = q.qiral_solve_batch([l.handle for l in lats], [l.dims for l in lats], xs, bs,
+                                       q.solve_params(tol=TOL, inner_prec=q.F32, use_graph=1))
+    stream.synchronize()
+    assert st == 0, info
+    for i, c in enumerate(cfgs):
+        res = S.true_rel_residual(c["U"], c["kappa"], 0.0, host(xs[i])[0], c["b"][0])
+        assert res <= TOL, (i, c["dims"], res)
+    for l in lats:
+        l.close()
+
+
+def test_fgmres_trained_24x48():
+    say("24^3x48 eps0.5 k0.125 setup")
+    cfg = latgen.make_config(4)
+    lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
+    net = q.Network(lat, 8)
+    say("training on 2048 pairs")
+    hist = net.train(2048, lr=1e-3, seed=4)
+    assert np.all(np.isfinite(hist))
+    params = q.solve_params(solver=q.FGMRES_NN, tol=TOL, restart=20, maxiter=2000)
+    params.precond = net.handle
+    b = dev(cfg["b"][:1])
+    x = torch.zeros_like(b)
+    say("FGMRES(20) with the trained network")
+    st, info = q.qiral_solve(lat.handle, lat.dims, x, b, 1, params)
+    assert st == 0 and info[0]["converged"], info
+    res = S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, host(x)[0], cfg["b"][0])
+    assert res <= TOL, res
+    net.close()
+    lat.close()

@@ -10,8 +10,8 @@ small-lattice tests: FP64 within 1e-12 of the site's largest element; FP32 with
 reconstruct-12 links against the oracle applied to the same rounded inputs
 within 2e-6 of it; F16S within the FP16 quantisation of the output (2^-11 of
 the site's scale) plus FP32 rounding.  A mixed-precision solve is judged by
-the oracle's residual on sampled sites, each of which is at most the whole
-residual, tol * ||b||."""
+the oracle's full residual b - D x on two whole time slices, each held to a
+few times its share of the residual budget."""
 import numpy as np
 import pytest
 import torch
@@ -111,9 +111,23 @@ def test_hop_64x128_sampled(big, prec):
     del src_all
 
 
-def test_solve_64x128_f16s_sampled_residual(big):
+def _slab_links(cfg, t0):
+    """Links of the t-slices t0 - 1, t0, t0 + 1 of the tiled lattice, as a
+    lattice of 3 time slices [3][Lz][Ly][Lx][4][3][3]."""
+    cell, cd, reps = cfg["U_cell"], cfg["cell_dims"], cfg["reps"]
+    lt = cfg["dims"][3]
+    return np.stack([np.tile(cell[(t % lt) % cd[3]], (reps[2], reps[1], reps[0], 1, 1, 1))
+                     for t in (t0 - 1, t0, t0 + 1)])
+
+
+def test_solve_64x128_f16s_slab_residual(big):
     """F16S mixed-precision even-odd CGNR to 1e-10 on the whole lattice; the
-    oracle recomputes b - D x on sampled sites of both parities."""
+    oracle recomputes b - D x on two whole time slices (both parities).  On a
+    periodic lattice of the 3 slices t0 - 1, t0, t0 + 1 the hop at slice t0 is
+    exactly the full lattice's, so the residual there is exact.  A Gaussian
+    source spreads the residual over the lattice, so each slice's share of
+    ||b - D x||^2 is about 1/Lt of it: the bar is 16/Lt of the whole budget
+    (tol ||b||)^2 per slice, 4x the fair share in norm."""
     cfg, lat, b = big
     dims, kappa, tol = cfg["dims"], cfg["kappa"], 1e-10
     say("solve 64^3x128 f16s")
@@ -121,11 +135,15 @@ def test_solve_64x128_f16s_sampled_residual(big):
     torch.cuda.synchronize()
     assert st == 0 and info[0]["converged"] and info[0]["true_rel_resid"] <= tol, info[0]
     bnorm = float(torch.linalg.vector_norm(b).item())
-    Uo = Tiled(cfg["U_cell"], cfg["cell_dims"])
-    xs, bs = DevSites(x[0]), DevSites(b[0])
-    rng = np.random.default_rng(7)
-    for p in (0, 1):
-        for s in _sites(rng, dims, p, NSAMPLE):
-            t, z, y, xx = s[3], s[2], s[1], s[0]
-            r = bs[t, z, y, xx] - (xs[t, z, y, xx] - kappa * W.hop_site(Uo, xs, s))
-            assert np.sqrt(np.sum(np.abs(r) ** 2)) <= tol * bnorm, (s, r)
+    lt = dims[3]
+    for t0 in (0, 77):
+        say("oracle residual on slice", t0)
+        idx = [(t0 - 1) % lt, t0, (t0 + 1) % lt]
+        xs = x[0, idx].cpu().numpy()
+        bs = b[0, t0].cpu().numpy()
+        Hx = W.hop(_slab_links(cfg, t0), xs)[1]
+        r = bs - (xs[1] - kappa * Hx)
+        share = np.sqrt(np.sum(np.abs(r) ** 2)) / (tol * bnorm)
+        assert share <= np.sqrt(16.0 / lt), (t0, share)
+        # and not vacuous: the slice holds a real part of the residual budget
+        assert share > 0
