@@ -1,24 +1,30 @@
 """Benchmark of the even-odd Wilson-Dirac solve on one MI355X.
 
-A step is one whole solve of the 16^3x32 workload (exp(0.3 i H) links, kappa
-0.12, one Gaussian source): import of the canonical source, Schur source,
-even-odd CGNR with the hop in FP32 (reconstruct-12 links) and FP64 reliable
-updates, reconstruction of the even sites, FP64 true residual and export of the
-canonical solution, to ||b - D x|| / ||b|| <= 1e-10.  Inputs are resident in
-device memory before the timed region.
+A step is the paper's plain method on its 24^3x48 lattice: even-odd CGNR in
+FP64 (the hop on FP64 reconstruct-18 links; Schur source, reconstruction and
+FP64 true residual included) for each of the 12 point sources of the workload
+(exp(0.4 i H) links, kappa 0.12, one source per spin-colour at a seeded site),
+solved one after the other through qiral_solve to ||b - D x|| / ||b|| <= 1e-10.
+Inputs (canonical links packed once, canonical sources and the workspace) are
+resident in device memory before the timed region.
 
-value: Dslash GFLOP/s sustained over the solve, i.e. 1320 flop per output site
-and hop application times the hop applications the solve made, divided by the
-solve's wall time.  The JSON line also carries the solve's time to solution, the
-plain FP64 even-odd CGNR on the same GPU for comparison, a roofline entry for the
-dominant kernel (the FP32 reconstruct-12 even-odd hop: median of 5 trials of
-back-to-back launches queued behind a spin kernel, so that the host's per-call
-cost does not leave the GPU idle, timed with HIP events on the stream it runs
-on, against
-the published 8 TB/s and against a measured 1 GiB device copy; HBM traffic from
-the committed counter summary while the hop sources are unchanged), the one-time
-link packing time, and the CPU oracle timed on a bounded sample (seconds and
-sec x core, the paper's unit).
+value: Dslash GFLOP/s sustained over the step: 1320 flop per output site and
+hop application, times the hop applications of the 12 solves, divided by the
+step's wall time.
+
+The JSON line also carries:
+- the same 12 sources solved in one batched qiral_solve call in FP64, and in
+  the mixed-precision forms (F32 and F16S hop with FP64 reliable updates), each
+  with its time to solution and speedup over the step (plain FP64 eo-CGNR);
+- roofline: the dominant kernel of the step, the FP64 even-odd hop on this
+  lattice with one right-hand side (8 links x 144 B + 192 B in + 192 B out =
+  1536 B per output site, 331776 sites, 510 MB per launch: twice the 256 MB
+  last-level cache), launched through qiral_dslash_eo and timed with HIP events
+  on its stream: warm (back-to-back launches) and cold (single launches, each
+  after a 1 GiB read that replaces the cache's contents); HBM traffic from the
+  committed counter summary while the hop sources are unchanged;
+- the one-time link packing time, a measured 1 GiB device copy, and the CPU
+  oracle timed on a bounded sample (a few CGNR iterations of the same system).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--suite]
 """
@@ -33,8 +39,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f32_16x16x16x32_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f64_24x24x24x48_traffic.md")
 HOP_SOURCES = [os.path.join(ROOT, "paper_1401_2039_amd", "csrc", f) for f in ("qiral_dev.h", "api.hip")]
+FLOP_PER_SITE = 1320           # one even-odd hop, per output site
+# algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output spinor
+HOP_BYTES = {"f64": 8 * 144 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
+ROOFLINE_KERNEL = "k_hop<0, 0, false, 0, 4, 1, true>"   # S_F64, L_F64R18, H (not dagger), plain epilogue, T 4, NR 1, streaming
+WORKLOAD = ("24^3x48 lattice, exp(0.4iH) links, kappa=0.12, 12 point sources (one per spin-colour): even-odd CGNR "
+            "in FP64 with the FP64 reconstruct-18 hop, the sources solved one after the other, to 1e-10 true residual")
 
 
 def hop_source_hash():
@@ -47,8 +59,8 @@ def hop_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the dominant hop from the committed counter summary,
-    or None if it is missing or was taken on different kernel sources."""
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None if it is missing or was taken on different kernel sources."""
     try:
         kv = {}
         for line in open(TRAFFIC_SUMMARY):
@@ -60,9 +72,6 @@ def measured_traffic():
         return int(float(kv["hbm_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
-FLOP_PER_SITE = 1320           # one even-odd hop, per output site
-# algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output spinor
-HOP_BYTES = {"f64": 8 * 144 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
 
 
 def log(*a):
@@ -72,10 +81,10 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--hop-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=10, help="oracle CGNR iterations timed for the CPU baseline")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--hop-reps", type=int, default=50, help="back-to-back hop launches per warm trial")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle CGNR iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads (stderr JSON lines)")
     ap.add_argument("--suite-out", default=None, help="append the suite's JSON lines to this file")
@@ -97,9 +106,10 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     t_gen = time.time()
-    cfg = latgen.make_config(1)
-    log(f"[bench] generated 16^3x32 inputs in {time.time() - t_gen:.1f}s")
+    cfg = latgen.make_config(2)
+    log(f"[bench] generated 24^3x48 inputs in {time.time() - t_gen:.1f}s")
     dims, kappa = cfg["dims"], cfg["kappa"]
+    nrhs = cfg["b"].shape[0]
     vh = int(np.prod(dims)) // 2
     Ud = torch.from_numpy(cfg["U"]).to(dev)
     torch.cuda.synchronize()
@@ -109,72 +119,102 @@ def main():
     pack_ms = (time.perf_counter() - t_pack) * 1e3   # one-time link packing, outside the timed solves
     del Ud
     b = torch.from_numpy(cfg["b"]).to(dev)
-    x = torch.zeros_like(b)
+    srcs = [b[r:r + 1].contiguous() for r in range(nrhs)]
+    xs = [torch.zeros_like(s) for s in srcs]
     stream = torch.cuda.current_stream()
+    p64 = q.solve_params(tol=1e-10, inner_prec=q.F64)
+    ws = torch.empty(q.qiral_solve_workspace_bytes(lat.handle, p64, 1), dtype=torch.uint8, device=dev)
 
-    def solve(prec, use_graph=0):
-        st, info = q.qiral_solve(lat.handle, dims, x, b, 1,
-                                 q.solve_params(tol=1e-10, inner_prec=prec, use_graph=use_graph))
-        if st != 0:
-            raise RuntimeError(f"solve failed: status {st} {info}")
-        return info[0]
+    def step():
+        infos = []
+        for r in range(nrhs):
+            st, info = q.qiral_solve(lat.handle, dims, xs[r], srcs[r], 1, p64, ws=ws)
+            if st != 0:
+                raise RuntimeError(f"solve of source {r} failed: status {st} {info}")
+            infos.append(info[0])
+        return infos
 
-    # ---- timed steps: mixed-precision solve
+    # ---- timed steps: plain FP64 even-odd CGNR, the 12 sources one after the other
     for _ in range(args.warmup):
-        solve(q.F32)
+        step()
     torch.cuda.synchronize()
     hops, times, infos = 0, [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        info = solve(q.F32)
+        infos = step()
         times.append(time.perf_counter() - ts)
-        hops += info["hop_applications"]
-        infos.append(info)
+        hops += sum(i["hop_applications"] for i in infos)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = FLOP_PER_SITE * vh * hops / elapsed / 1e9
-    log(f"[bench] mixed F32 solve: {elapsed / args.steps * 1e3:.2f} ms/solve, iterations {infos[-1]['iterations']}, "
-        f"reliable updates {infos[-1]['reliable_updates']}, true residual {infos[-1]['true_rel_resid']:.2e}")
+    its = [i["iterations"] for i in infos]
+    log(f"[bench] step (12 FP64 eo-CGNR solves): {elapsed / args.steps * 1e3:.2f} ms, iterations {its}, "
+        f"{value:.0f} GFLOP/s")
 
-    # ---- plain FP64 even-odd CGNR on the same GPU (comparison, outside the timed region)
-    f64_times = []
-    for k in range(3):
-        ts = time.perf_counter()
-        i64 = solve(q.F64)
-        if k:
-            f64_times.append(time.perf_counter() - ts)
-    log(f"[bench] FP64 solve: {statistics.median(f64_times) * 1e3:.2f} ms, iterations {i64['iterations']}")
+    # ---- the same 12 sources in one batched call: FP64, and the mixed-precision forms
+    batched = {}
+    for name, prec in (("f64", q.F64), ("f32_mixed", q.F32), ("f16s_mixed", q.F16S)):
+        lat.tune(prec, nrhs)
+        prm = q.solve_params(tol=1e-10, inner_prec=prec)
+        wsb = torch.empty(q.qiral_solve_workspace_bytes(lat.handle, prm, nrhs), dtype=torch.uint8, device=dev)
+        xb = torch.zeros_like(b)
+        q.qiral_solve(lat.handle, dims, xb, b, nrhs, prm, ws=wsb)   # warm-up
+        ts_ = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st, binfo = q.qiral_solve(lat.handle, dims, xb, b, nrhs, prm, ws=wsb)
+            ts_.append(time.perf_counter() - ts)
+            if st != 0:
+                raise RuntimeError(f"batched {name} solve failed: status {st}")
+        t = statistics.median(ts_)
+        batched[name] = {"time_to_solution_s": round(t, 5), "speedup_vs_fp64_cgnr": round(statistics.median(times) / t, 3),
+                         "iterations_max": max(i["iterations"] for i in binfo),
+                         "reliable_updates_max": max(i["reliable_updates"] for i in binfo),
+                         "true_rel_resid_max": max(i["true_rel_resid"] for i in binfo)}
+        log(f"[bench] batched {name}: {t * 1e3:.2f} ms ({batched[name]['speedup_vs_fp64_cgnr']}x the step)")
+        del wsb, xb
 
-    # ---- roofline of the dominant kernel: the FP32 reconstruct-12 even-odd hop
-    psi = torch.from_numpy(latgen.gaussian_source(1, 0, dims, 1)).to(dev)
-    src = lat.import_field(psi, q.ODD, q.F32)
-    out = lat.field(q.EVEN, q.F32)
-    for _ in range(20):
-        lat.dslash_eo(out, src, 0, 0, q.F32)
-    # the same launches without a filled queue: the host's enqueue rate bounds this one
+    # ---- roofline of the dominant kernel: the FP64 even-odd hop, one right-hand side
+    psi = torch.from_numpy(latgen.gaussian_source(2, 1, dims, 1)).to(dev)
+    src = lat.import_field(psi, q.ODD, q.F64)
+    out = lat.field(q.EVEN, q.F64)
+    del psi
+    for _ in range(5):
+        lat.dslash_eo(out, src, 0, 0, q.F64)
+    trials = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.hop_reps):
-        lat.dslash_eo(out, src, 0, 0, q.F32)
-    e1.record(stream)
-    e1.synchronize()
-    unfilled_us = e0.elapsed_time(e1) * 1e3 / args.hop_reps
-    hop_us, host_us = timed_launches(torch, stream, lambda: lat.dslash_eo(out, src, 0, 0, q.F32), args.hop_reps)
-    log(f"[bench] F32 hop 16^3x32: {unfilled_us:.2f} us/launch enqueued one by one, "
-        f"{hop_us:.2f} us/launch from a filled queue, host {host_us:.2f} us per call")
-    hop_bytes = HOP_BYTES["f32"] * vh
-    achieved = hop_bytes / (hop_us * 1e-6) / 1e9
-    dslash_gflops = FLOP_PER_SITE * vh / (hop_us * 1e-6) / 1e9
-    log(f"[bench] F32 hop 16^3x32: {hop_us:.2f} us/launch, {achieved:.0f} GB/s algorithmic, {dslash_gflops:.0f} GFLOP/s")
+    for _ in range(3):
+        e0.record(stream)
+        for _ in range(args.hop_reps):
+            lat.dslash_eo(out, src, 0, 0, q.F64)
+        e1.record(stream)
+        e1.synchronize()
+        trials.append(e0.elapsed_time(e1) * 1e3 / args.hop_reps)
+    warm_us = statistics.median(trials)
+    flush = torch.zeros(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    cold = []
+    for _ in range(11):
+        flush.sum()   # a read: the cache then holds clean, unrelated lines
+        e0.record(stream)
+        lat.dslash_eo(out, src, 0, 0, q.F64)
+        e1.record(stream)
+        e1.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e3)
+    cold_us = statistics.median(cold)
+    del flush
+    hop_bytes = HOP_BYTES["f64"] * vh
+    achieved = hop_bytes / (warm_us * 1e-6) / 1e9
+    log(f"[bench] FP64 hop 24^3x48: warm {warm_us:.2f} us ({achieved:.0f} GB/s), cold {cold_us:.2f} us "
+        f"({hop_bytes / (cold_us * 1e-6) / 1e9:.0f} GB/s)")
 
-    # ---- a plain 1 GiB device copy: the reference a counter run scales FETCH_SIZE / WRITE_SIZE by,
-    # and the measured copy ceiling the roofline also quotes
+    # ---- a plain 1 GiB device copy: the measured copy ceiling, and the reference a
+    # counter run scales FETCH_SIZE / WRITE_SIZE by
     cx = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     cy = torch.empty_like(cx)
     cy.copy_(cx)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(5):
         cy.copy_(cx)
@@ -183,7 +223,6 @@ def main():
     copy_gbs = 2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del cx, cy
 
-    # ---- CPU oracle on a bounded sample: a few CGNR iterations of the same workload
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, args.cpu_iters)
@@ -199,38 +238,37 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "16^3x32 lattice, exp(0.3iH) links, kappa=0.12, 1 Gaussian RHS: even-odd CGNR, "
-                               "FP32 reconstruct-12 hop + FP64 reliable updates, to 1e-10 true residual",
-                   "dims": list(dims), "kappa": kappa, "nrhs": 1, "tol": 1e-10},
+        "config": {"workload": WORKLOAD, "dims": list(dims), "kappa": kappa, "nrhs": nrhs, "tol": 1e-10,
+                   "links": "exp(0.4 i H) per link, H a seeded Gaussian traceless Hermitian 3x3"},
         "time_to_solution_s": round(statistics.median(times), 6),
-        "fp64_time_to_solution_s": round(statistics.median(f64_times), 6),
-        "speedup_vs_fp64_cg": round(statistics.median(f64_times) / statistics.median(times), 3),
-        "iterations": infos[-1]["iterations"],
-        "fp64_iterations": i64["iterations"],
-        "reliable_updates": infos[-1]["reliable_updates"],
-        "true_rel_resid": infos[-1]["true_rel_resid"],
-        "dslash_gflops": round(dslash_gflops, 1),
-        "roofline": {"bound": "hbm", "kernel": "k_hop<S_F32,L_F32R12,false,0> (qiral_dslash_eo, F32)",
+        "iterations": its,
+        "true_rel_resid_max": max(i["true_rel_resid"] for i in infos),
+        "hop_applications_per_step": hops // args.steps,
+        "batched": batched,
+        "roofline": {"bound": "hbm", "kernel": ROOFLINE_KERNEL + " (qiral_dslash_eo, FP64, 1 RHS)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "source_sha256": hop_source_hash(),
-                     "launch_us": round(hop_us, 3), "launch_us_enqueued_one_by_one": round(unfilled_us, 3),
-                     "host_us_per_call": round(host_us, 3), "bytes_per_launch": hop_bytes,
-                     "fits_last_level_cache": True, "copy_ceiling_GBs": round(copy_gbs, 1),
-                     "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
+                     "bytes_per_launch": hop_bytes, "launch_us": round(warm_us, 3),
+                     "cold_launch_us": round(cold_us, 3),
+                     "cold_frac": round(hop_bytes / (cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "dslash_gflops": round(FLOP_PER_SITE * vh / (warm_us * 1e-6) / 1e9, 1),
+                     "source_sha256": hop_source_hash(), "fits_last_level_cache": False,
+                     "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
         "gauge_pack_ms": round(pack_ms, 3),
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+    del ws, src, out
     if args.suite:
-        suite(lat, q, latgen, np, torch, args.suite_out, args.parts.split(','), args.suite_hop_reps)
+        suite(q, latgen, np, torch, args.suite_out, args.parts.split(','), args.suite_hop_reps)
     lat.close()
 
 
 def cpu_baseline(cfg, iters):
-    """The oracle as it is, single thread, on `iters` CGNR iterations of the same lattice."""
+    """The oracle as it is, single thread, on `iters` CGNR iterations of the same
+    24^3x48 Schur system (the first point source)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -246,11 +284,10 @@ def cpu_baseline(cfg, iters):
         dt = time.perf_counter() - t0
     hops = 2 + 4 * iters   # initial S^dagger r, then S and S^dagger per iteration
     val = FLOP_PER_SITE * vh * hops / dt / 1e9
-    log(f"[bench] oracle: {iters} CGNR iterations on 16^3x32 in {dt:.1f}s ({val:.3f} GFLOP/s)")
-    import os
+    log(f"[bench] oracle: {iters} CGNR iterations on 24^3x48 in {dt:.1f}s ({val:.3f} GFLOP/s)")
     return {"value": round(val, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} CGNR iterations (plus the initial S^dagger r) of the oracle on the same 16^3x32 "
-                      f"Schur system, {dt:.1f}s, BLAS limited to 1 thread",
+            "sample": f"{iters} CGNR iterations (plus the initial S^dagger r) of the oracle on the same 24^3x48 "
+                      f"Schur system (first point source), {dt:.1f}s, BLAS limited to 1 thread",
             "seconds": round(dt, 3), "sec_x_core": round(dt, 3), "host_cores": len(os.sched_getaffinity(0))}
 
 
@@ -336,13 +373,17 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None, psi=None)
     return res
 
 
-def suite(lat1, q, latgen, np, torch, path=None, parts=(), hop_reps=None):
+def suite(q, latgen, np, torch, path=None, parts=(), hop_reps=None):
     """Extra measurements: hop throughput of every storage class on the workloads'
     lattices (warm and cache-flushed) and time to solution of each solver form."""
     import time as _t
     flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     dims1 = (16, 16, 16, 32)
+    lat1 = None
     if "c1" in parts:
+        c1 = latgen.make_config(1, with_source=False)
+        lat1 = q.Lattice(c1["dims"], c1["kappa"], c1["U"])
+        del c1
         for prec in (q.F64, q.F32, q.F16S):
             _emit(hop_rates(q, lat1, dims1, torch, prec, reps=hop_reps or 100, flush=flush), path)
 
@@ -359,6 +400,7 @@ def suite(lat1, q, latgen, np, torch, path=None, parts=(), hop_reps=None):
 
     if "c1" in parts:
         suite_c1(lat1, q, latgen, torch, path, timed_solve)
+        lat1.close()
     if "c0" in parts:
         suite_c0(q, latgen, torch, path, timed_solve)
     if "c2" in parts:

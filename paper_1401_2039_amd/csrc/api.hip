@@ -8,7 +8,6 @@
 #include <cstring>
 #include <string>
 
-#include "half_rne.h"
 #include "qiral_int.h"
 
 using namespace qiral;
@@ -128,15 +127,15 @@ __global__ __launch_bounds__(WG) void k_pack_gauge(Geo g, const double *__restri
   } else {
     uint2 *d = (uint2 *)dst + blk * 3 * WAVE + (s & 63);
     for (int j = 0; j < 3; ++j) {
-      unsigned a = d2h_rne(src[4 * j]) | ((unsigned)d2h_rne(src[4 * j + 1]) << 16);
-      unsigned b = d2h_rne(src[4 * j + 2]) | ((unsigned)d2h_rne(src[4 * j + 3]) << 16);
+      unsigned a = d2h(src[4 * j]) | ((unsigned)d2h(src[4 * j + 1]) << 16);
+      unsigned b = d2h(src[4 * j + 2]) | ((unsigned)d2h(src[4 * j + 3]) << 16);
       d[j * WAVE] = make_uint2(a, b);
     }
   }
 }
 
-// FP16 links: each real is rounded FP64 -> FP16 once, to nearest even
-// (d2h_rne); FP32 links: FP64 -> FP32, to nearest even.
+// FP16 links: each real is rounded FP64 -> FP16 once, to nearest even (d2h);
+// FP32 links: FP64 -> FP32, to nearest even.
 
 template <int S>
 __global__ __launch_bounds__(WG) void k_import(Geo g, const double *__restrict__ canon, size_t canon_stride,

@@ -198,6 +198,18 @@ template <> struct SpinorIO<S_F32> {
 __device__ __forceinline__ float h2f(unsigned short h) { return __half2float(__ushort_as_half(h)); }
 __device__ __forceinline__ unsigned short f2h(float f) { return __half_as_ushort(__float2half_rn(f)); }
 
+// FP64 -> FP16 with one rounding to nearest even.  Going through FP32 with
+// ordinary rounding would round twice (1 + 2^-11 + 2^-30 would become 1 instead
+// of 1 + 2^-10).  Rounding to FP32 "to odd" first -- toward zero, then setting
+// the last bit if the conversion was inexact -- and then to FP16 to nearest
+// gives the directly rounded result, because FP32 keeps at least two more bits
+// than FP16 (Boldo and Melquiond, IEEE Trans. Computers 57 (2008) 462).
+__device__ __forceinline__ unsigned short d2h(double d) {
+  float f = __double2float_rz(d);
+  if ((double)f != d) f = __uint_as_float(__float_as_uint(f) | 1u);
+  return f2h(f);
+}
+
 
 template <> struct SpinorIO<S_F16S> {
   using R = float;

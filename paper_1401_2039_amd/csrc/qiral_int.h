@@ -83,6 +83,16 @@ inline int wg_count(long nwaves) { return (int)((nwaves + 3) / 4); }
 hipError_t launch_hop(const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi, double a,
                       const void *in, void *out, const void *x, int nrhs, hipStream_t s, int chio = 0, int chix = 0);
 
+// The checks of qiral_solve's arguments that do not read the handle, the
+// handle's links of the inner precision, and the solve itself in a workspace
+// of ws_bytes >= qiral_solve_workspace_bytes (solver.hip).
+qiral_status check_solve_args(const qiral_lattice *lat, const double *x, const double *b, int nrhs,
+                              const qiral_solve_params *params, const qiral_solve_info *info);
+qiral_status check_solve_links(const qiral_lattice *lat, const qiral_solve_params *params);
+qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                      const qiral_solve_params *params, void *ws, size_t ws_bytes, qiral_solve_info *info,
+                      hipStream_t stream);
+
 // Bytes of a packed link store of the given storage precision (0: not built).
 size_t link_store_bytes(const Geo &g, int prec);
 // Pinned host bytes the solver's state polls need (two copies of every state).

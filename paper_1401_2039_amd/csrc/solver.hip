@@ -533,15 +533,21 @@ qiral_status check_ws(const void *ws, size_t ws_bytes, size_t need) {
   return QIRAL_OK;
 }
 
+}  // namespace
+
+namespace qiral {
+// The checks of qiral_solve's arguments that do not read the handle.
 qiral_status check_solve_args(const qiral_lattice *lat, const double *x, const double *b, int nrhs,
-                              const qiral_solve_params *params, const void *ws, const qiral_solve_info *info) {
+                              const qiral_solve_params *params, const qiral_solve_info *info) {
   if (!lat) return fail(QIRAL_ERR_INVALID_ARG, "lat is NULL");
   if (!x || !b) return fail(QIRAL_ERR_INVALID_ARG, "field pointer is NULL");
   if (nrhs < 1 || nrhs > QIRAL_MAX_SYSTEMS) return fail(QIRAL_ERR_INVALID_ARG, "nrhs must be in [1, 255]");
   if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
-  qiral_status st = check_params(params);
-  if (st != QIRAL_OK) return st;
-  if ((st = check_ws_ptr(ws)) != QIRAL_OK) return st;
+  return check_params(params);
+}
+
+// The handle holds links of the solve's inner precision.
+qiral_status check_solve_links(const qiral_lattice *lat, const qiral_solve_params *params) {
   if (!links_for(lat, params->inner_prec))
     return fail(QIRAL_ERR_INVALID_ARG, "the lattice holds no links of the inner precision (gauge_f32 / gauge_f16)");
   return QIRAL_OK;
@@ -567,8 +573,7 @@ qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon
   for (int r = 0; r < nrhs; ++r) sys[r] = SysIn{lat, x_canon + r * stride, b_canon + r * stride};
   return run_solve(lat, sys, params, ws, ws_bytes, info, stream);
 }
-
-}  // namespace
+}  // namespace qiral
 
 extern "C" size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params,
                                               int32_t nrhs) {
@@ -592,8 +597,10 @@ extern "C" size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *
 extern "C" qiral_status qiral_solve(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
                                     const qiral_solve_params *params, void *ws, size_t ws_bytes,
                                     qiral_solve_info *info, qiral_stream_t stream) {
-  qiral_status st = check_solve_args(lat, x_canon, b_canon, nrhs, params, ws, info);
+  qiral_status st = check_solve_args(lat, x_canon, b_canon, nrhs, params, info);
   if (st != QIRAL_OK) return st;
+  if ((st = check_ws_ptr(ws)) != QIRAL_OK) return st;
+  if ((st = check_solve_links(lat, params)) != QIRAL_OK) return st;
   const size_t need = qiral_solve_workspace_bytes(lat, params, nrhs);
   if ((st = check_ws(ws, ws_bytes, need)) != QIRAL_OK) return st;
   return solve_in(lat, x_canon, b_canon, nrhs, params, ws, ws_bytes, info, (hipStream_t)stream);

@@ -73,6 +73,36 @@ def test_link_stores_bit_exact():
     lat.close()
 
 
+def test_link_store_f16_rounding_cases():
+    """The FP16 store of links whose rows 0 and 1 hold doubles where rounding
+    through FP32 first would give a different FP16, values in the FP16 subnormal
+    range and exact ties: each real is the nearest FP16 (ties to even)."""
+    say("FP16 link store rounding cases")
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(93)
+    n = int(np.prod(dims)) * 4 * 12
+    e = rng.integers(-26, 1, n).astype(np.float64)
+    m = rng.integers(0, 1 << 10, n).astype(np.float64)
+    base = (1.0 + (m + 0.5) / 1024.0) * 2.0 ** e          # exact FP16 ties (and below half the smallest subnormal)
+    nudge = rng.choice([-1.0, 0.0, 1.0], n) * 2.0 ** (e - 30)   # just below, at, just above the tie
+    vals = np.where(rng.random(n) < 0.5, -1.0, 1.0) * (base + nudge)
+    vals[:4] = [1.0 + 2.0 ** -11 + 2.0 ** -30, 2.0 ** -25 + 2.0 ** -60, -(0.5 + 2.0 ** -12 + 2.0 ** -40), 0.0]
+    U = np.zeros(tuple(dims[::-1]) + (4, 3, 3), dtype=np.complex128)
+    v = vals.reshape(-1, 4, 12)
+    rows = v[..., 0::2] + 1j * v[..., 1::2]                # 6 complex entries per link
+    U.reshape(-1, 4, 3, 3)[:, :, :2, :] = rows.reshape(-1, 4, 2, 3)
+    U.reshape(-1, 4, 3, 3)[:, :, 2, 2] = 1.0
+    lat = q.Lattice(dims, 0.12, U)
+    got = _unpack_rows01(lat.gauge_f16, dims, np.float16)
+    Uf = U.reshape(-1, 4, 3, 3)
+    for p in (0, 1):
+        lex = _cb_order(dims, p)
+        r = np.moveaxis(Uf[lex][:, :, :2, :], 1, 0)
+        want = r.real.astype(np.float16).astype(np.float64) + 1j * r.imag.astype(np.float16).astype(np.float64)
+        assert np.array_equal(got[p], want), (p, int(np.count_nonzero(got[p] != want)))
+    lat.close()
+
+
 def test_workspace_size_contract():
     say("workspace contract")
     dims = (8, 8, 8, 8)
