@@ -240,6 +240,26 @@ qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *const *x_cano
                                int32_t nsys, const qiral_solve_params *params, void *ws, size_t ws_bytes,
                                qiral_solve_info *info, qiral_stream_t stream);
 
+/* Bytes of the library's static workspace (see qiral_solve_static). */
+#define QIRAL_STATIC_WORKSPACE_BYTES (32u << 20)
+
+/* qiral_solve for callers that cannot allocate device memory (code that must
+ * not call hipMalloc or a caching allocator: tight serving loops, harnesses
+ * that forbid allocation).  The same solve as qiral_solve, in a workspace that
+ * is a static array of QIRAL_STATIC_WORKSPACE_BYTES (32 MiB) in the library's
+ * device data: each GPU the library runs on holds its own copy from the
+ * library's load until the process ends.  The call allocates nothing on the
+ * device or the host's pinned heap.  Solves whose qiral_solve_workspace_bytes
+ * exceed 32 MiB (about 7 FP64 right-hand sides of an 8^4 lattice) return
+ * QIRAL_ERR_WORKSPACE before any HIP call; params->use_graph must be 0
+ * (QIRAL_ERR_UNSUPPORTED: instantiating a graph allocates).  The current device
+ * must be the lattice's.  Every call on a GPU uses that GPU's one array, which
+ * keeps the last call's contents (the solve initialises what it reads): calls
+ * that overlap in time on one GPU, from any thread or stream, race and must
+ * not be made. */
+qiral_status qiral_solve_static(qiral_lattice *lat, double *x_canon, const double *b_canon, int32_t nrhs,
+                                const qiral_solve_params *params, qiral_solve_info *info, qiral_stream_t stream);
+
 /* ---- Learned preconditioner (an addition to the paper's method) -----------
  * A 2-layer parallel-transport network 1 -> hidden -> 1 channels:
  *   psi_out^i(x) = sum_j sum_p W_p^{ij} [T_p psi_in^j](x),

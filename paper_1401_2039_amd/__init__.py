@@ -10,7 +10,7 @@ the C calls; nothing is computed in Python.
 """
 from .api import (  # noqa: F401
     Lattice, Network, qiral_field_bytes, qiral_gauge_bytes, qiral_lattice_create, qiral_solve_workspace_bytes,
-    qiral_solve_batch_workspace_bytes, qiral_lattice_destroy, qiral_field_import,
+    qiral_solve_batch_workspace_bytes, qiral_solve_static, qiral_lattice_destroy, qiral_field_import,
     qiral_field_export, qiral_dslash_eo, qiral_apply_M, qiral_tune, qiral_solve, qiral_solve_batch, solve_params,
 )
 from ._lib import (  # noqa: F401

@@ -24,6 +24,7 @@ CGNR_EO, BICGSTAB_EO, FGMRES_NN, CRNR_EO, FCG_NN = 0, 1, 2, 3, 4
 # binding-side choice: the C call takes one pointer per store)
 LINKS_F32, LINKS_F16 = 1 << F32, 1 << F16S
 MAX_SYSTEMS = 255
+STATIC_WORKSPACE_BYTES = 32 << 20
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_BAD_DIMS: "ERR_BAD_DIMS",
                 ERR_UNSUPPORTED: "ERR_UNSUPPORTED", ERR_HIP: "ERR_HIP", ERR_NOT_CONVERGED: "ERR_NOT_CONVERGED",
@@ -34,7 +35,7 @@ EXPORTS = [
     "qiral_status_string", "qiral_last_error", "qiral_gauge_bytes", "qiral_field_bytes", "qiral_lattice_create",
     "qiral_lattice_destroy", "qiral_lattice_query", "qiral_field_import", "qiral_field_export",
     "qiral_dslash_eo", "qiral_apply_M", "qiral_tune", "qiral_solve_workspace_bytes",
-    "qiral_solve_batch_workspace_bytes", "qiral_solve", "qiral_solve_batch",
+    "qiral_solve_batch_workspace_bytes", "qiral_solve", "qiral_solve_batch", "qiral_solve_static",
     "qiral_nn_bytes", "qiral_nn_create", "qiral_nn_destroy", "qiral_nn_num_weights", "qiral_nn_set_weights",
     "qiral_nn_get_weights", "qiral_nn_apply", "qiral_nn_apply_adjoint", "qiral_nn_sample", "qiral_nn_grad",
     "qiral_nn_train",
@@ -97,6 +98,7 @@ def load():
         "qiral_solve": (I, [P, P, P, I, ctypes.POINTER(SolveParams), P, S, ctypes.POINTER(SolveInfo), P]),
         "qiral_solve_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I,
                                   ctypes.POINTER(SolveParams), P, S, ctypes.POINTER(SolveInfo), P]),
+        "qiral_solve_static": (I, [P, P, P, I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), P]),
     }
     U64 = ctypes.c_uint64
     DP = ctypes.POINTER(ctypes.c_double)

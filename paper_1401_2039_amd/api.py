@@ -162,6 +162,19 @@ def qiral_solve(handle, dims, x_canon, b_canon, nrhs, params, ws="auto", stream=
     return st, [i.as_dict() for i in infos]
 
 
+def qiral_solve_static(handle, dims, x_canon, b_canon, nrhs, params, stream=None):
+    """qiral_solve in the library's static device workspace (no allocation)."""
+    n = _volume(dims) * 12 * 16 * nrhs
+    x = _need_cuda(x_canon, "x_canon", torch.complex128, n)
+    b = _need_cuda(b_canon, "b_canon", torch.complex128, n)
+    infos = (L.SolveInfo * nrhs)()
+    st = L.load().qiral_solve_static(ctypes.c_void_p(handle), x, b, nrhs, ctypes.byref(params), infos,
+                                     _stream(stream))
+    if st not in (L.OK, L.ERR_NOT_CONVERGED):
+        L.check(st, "qiral_solve_static")
+    return st, [i.as_dict() for i in infos]
+
+
 def qiral_solve_batch(handles, dims_list, xs, bs, params, ws="auto", stream=None):
     n = len(handles)
     hp = (ctypes.c_void_p * n)(*handles)
