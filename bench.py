@@ -418,6 +418,8 @@ def suite(q, latgen, np, torch, path=None, parts=(), hop_reps=None):
         suite_c4(q, latgen, torch, path, timed_solve)
     if "c64" in parts:
         suite_c64(q, latgen, torch, path, timed_solve, flush, hop_reps)
+    if "compose" in parts:
+        suite_compose(q, latgen, torch, path, timed_solve)
 
 
 def suite_c1(lat1, q, latgen, torch, path, timed_solve):
@@ -598,6 +600,36 @@ def suite_c4(q, latgen, torch, path, timed_solve):
     _emit({"kind": "summary", "workload": "24^3x48 eps0.5 k0.125", "training_s": round(t_train, 3),
            "fgmres_12rhs_s": round(t_nn, 4), "fcg_12rhs_s": round(t_fcg, 4), "cgnr_f64_12rhs_s": round(tseq, 4),
            "break_even_solves_of_12": (round(t_train / gain, 2) if gain > 0 else None)}, path)
+    net.close()
+    lat.close()
+
+
+def suite_compose(q, latgen, torch, path, timed_solve):
+    """Time per iteration against total time of every solver x system x
+    preconditioner composition (Sec. 5's comparison of its solvers), FP64, on the
+    24^3x48 exp(0.5 i H), kappa 0.125 lattice with one Gaussian source; the network
+    carries the Neumann-2 weights of 1 + kappa H + kappa^2 H^2."""
+    c4 = latgen.make_config(4)
+    lat = q.Lattice(c4["dims"], c4["kappa"], c4["U"])
+    b = torch.from_numpy(c4["b"][:1].copy()).cuda()
+    del c4
+    net = q.Network(lat, 8)
+    forms = [("cgnr", "schur", False), ("bicgstab", "schur", False), ("crnr", "schur", False),
+             ("cgnr", "full", False), ("bicgstab", "full", False), ("bicgstab", "schur", True),
+             ("bicgstab", "full", True), ("fgmres", "full", False), ("fgmres", "full", True),
+             ("fgmres", "schur", False), ("fgmres", "schur", True), ("fcg", "full", True), ("fcg", "schur", True)]
+    sol = {"cgnr": q.CGNR_EO, "bicgstab": q.BICGSTAB_EO, "crnr": q.CRNR_EO, "fgmres": q.FGMRES_NN, "fcg": q.FCG_NN}
+    sysd = {"schur": q.SYSTEM_SCHUR, "full": q.SYSTEM_FULL}
+    for solver, system, with_net in forms:
+        kw = dict(solver=sol[solver], system=sysd[system], restart=20, maxiter=20000, fallback_cg=0)
+        if with_net:
+            kw["precond"] = net.handle
+        t, st, info, _ = timed_solve(lat, b, reps=2, tol=1e-10, **kw)
+        it = info[0]["iterations"]
+        _emit({"kind": "compose", "workload": "24^3x48 eps0.5 k0.125 1 gaussian", "solver": solver, "system": system,
+               "preconditioner": "network" if with_net else "none", "status": st, "iterations": it,
+               "hops": info[0]["hop_applications"], "seconds": round(t, 5),
+               "ms_per_iteration": round(1e3 * t / max(it, 1), 4), "true_rel_resid": info[0]["true_rel_resid"]}, path)
     net.close()
     lat.close()
 

@@ -81,19 +81,43 @@ typedef enum {
   QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = A - kappa^2 H_oe A^-1 H_eo */
   QIRAL_OP_SCHUR_DAG = 3 /* S^dagger (see qiral_apply_M)                             */
 } qiral_op;
+/* The system a solver runs on (template chain "solver schur" or the solver on D
+ * itself, Sec. 2 and Sec. 3.1). */
+typedef enum {
+  QIRAL_SYSTEM_DEFAULT = 0, /* the solver's own: Schur for CGNR / BiCGStab / CRNR, D for FGMRES / FCG */
+  QIRAL_SYSTEM_SCHUR = 1,   /* S x_o = b_hat on the odd sites, then x_e = A^-1 (b_e + kappa H_eo x_o) */
+  QIRAL_SYSTEM_FULL = 2     /* D x = b on the whole lattice */
+} qiral_system;
+
 typedef enum {
   QIRAL_CGNR_EO = 0,     /* CGNR (Fig. "CG") on the Schur system ("schur" template) */
-  QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system      */
-  QIRAL_FGMRES_NN = 2,   /* FGMRES(m) on D with the learned preconditioner          */
+  QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system; with
+                            precond, BiCGStab with the network as right preconditioner
+                            (Schur: its restriction M_S v = P_o N (0 + v)), on the
+                            Schur system or (system FULL) on D                        */
+  QIRAL_FGMRES_NN = 2,   /* FGMRES(m) with the learned preconditioner on the right (or
+                            none: precond NULL), on D or (system SCHUR) on S          */
   QIRAL_CRNR_EO = 3,     /* conjugate residual (Saad, Alg. 6.20) on the Schur normal
                             equations S^dagger S x_o = S^dagger b_hat, stopping on the
                             Schur residual like CGNR; FP64 only (inner_prec F64,
                             otherwise QIRAL_ERR_UNSUPPORTED)                          */
   QIRAL_FCG_NN = 4       /* flexible CG (Notay, SIAM J. Sci. Comput. 22, 2000), FCG(1),
-                            on the normal equations D^dagger D x = D^dagger b with the
-                            preconditioner N N^dagger of the learned network N; stops
-                            on ||b - D x||; FP64 (inner_prec F64)                    */
+                            on the normal equations A^dagger A x = A^dagger b (A = D, or
+                            S with system SCHUR) with the preconditioner M M^dagger of
+                            the learned network (or none); stops on ||b - D x||; FP64 */
 } qiral_solver;
+/* Compositions (solver x system x preconditioner) that qiral_solve runs:
+ *   CGNR_EO, CRNR_EO:   system SCHUR (default), precond NULL: the grouped
+ *                       batched solver; CGNR_EO with system FULL is CGNR on the
+ *                       normal equations of D (run as FCG with no preconditioner,
+ *                       which takes CGNR's iterates).
+ *   BICGSTAB_EO:        SCHUR, precond NULL: the grouped solver; with precond,
+ *                       or with system FULL: right-preconditioned BiCGStab (FP64).
+ *   FGMRES_NN, FCG_NN:  FULL (default) or SCHUR, precond the network or NULL.
+ * Preconditioned and FULL-system forms run in FP64 (inner_prec F64), one
+ * right-hand side at a time, and are not taken by qiral_solve_batch;
+ * CRNR_EO with system FULL and CGNR_EO / CRNR_EO with precond give
+ * QIRAL_ERR_UNSUPPORTED. */
 
 /* The most systems (right-hand sides, or lattices of a batch) one solve takes. */
 #define QIRAL_MAX_SYSTEMS 255
@@ -188,12 +212,14 @@ typedef struct {
                           in (0, 1); 0.01 keeps the FP64 iteration counts on the workloads
                           tried (F32 and F16S) with 4-5 updates per 1e-10 solve           */
   int32_t restart;     /* FGMRES restart length m (FCG keeps one previous direction)           */
-  const qiral_nn *precond; /* learned preconditioner for QIRAL_FGMRES_NN and QIRAL_FCG_NN       */
+  const qiral_nn *precond; /* learned preconditioner (QIRAL_FGMRES_NN, QIRAL_FCG_NN,
+                              QIRAL_BICGSTAB_EO), or NULL                               */
   int32_t fallback_cg; /* FGMRES, FCG: on stagnation or breakdown continue with eo-CGNR from
                           the current x                                                    */
   int32_t x0_is_guess; /* start from the x passed in instead of 0                              */
   int32_t use_graph;   /* capture the iteration in a HIP graph and replay it                   */
   int32_t check_every; /* iterations enqueued between convergence checks (0: automatic)        */
+  int32_t system;      /* qiral_system: the system the solver runs on (0: the solver's own)     */
 } qiral_solve_params;
 
 typedef struct {

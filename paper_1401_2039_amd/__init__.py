@@ -15,5 +15,5 @@ from .api import (  # noqa: F401
 )
 from ._lib import (  # noqa: F401
     F64, F32, F16S, EVEN, ODD, FULL, OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG, CGNR_EO, BICGSTAB_EO,
-    FGMRES_NN, CRNR_EO, FCG_NN, LINKS_F32, LINKS_F16, RECON12, RECON18, QiralError,
+    FGMRES_NN, CRNR_EO, FCG_NN, SYSTEM_DEFAULT, SYSTEM_SCHUR, SYSTEM_FULL, LINKS_F32, LINKS_F16, RECON12, RECON18, QiralError,
 )

@@ -20,6 +20,7 @@ RECON18, RECON12 = 18, 12
 EVEN, ODD, FULL = 0, 1, 2
 OP_D, OP_DDAG, OP_SCHUR, OP_SCHUR_DAG = 0, 1, 2, 3
 CGNR_EO, BICGSTAB_EO, FGMRES_NN, CRNR_EO, FCG_NN = 0, 1, 2, 3, 4
+SYSTEM_DEFAULT, SYSTEM_SCHUR, SYSTEM_FULL = 0, 1, 2
 # which reduced-precision link stores the binding allocates for a lattice (a
 # binding-side choice: the C call takes one pointer per store)
 LINKS_F32, LINKS_F16 = 1 << F32, 1 << F16S
@@ -46,7 +47,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int), ("delta", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("precond", ctypes.c_void_p), ("fallback_cg", ctypes.c_int32), ("x0_is_guess", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32), ("system", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

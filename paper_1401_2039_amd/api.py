@@ -123,9 +123,9 @@ def qiral_tune(handle, dims, prec, inp, out, nrhs=1, stream=None):
 
 
 def solve_params(solver=L.CGNR_EO, tol=1e-10, maxiter=10000, inner_prec=L.F64, delta=0.01, restart=20, precond=None,
-                 fallback_cg=1, x0_is_guess=0, use_graph=0, check_every=0):
+                 fallback_cg=1, x0_is_guess=0, use_graph=0, check_every=0, system=L.SYSTEM_DEFAULT):
     return L.SolveParams(solver, tol, maxiter, inner_prec, delta, restart, precond, fallback_cg, x0_is_guess,
-                         use_graph, check_every)
+                         use_graph, check_every, system)
 
 
 def qiral_solve_workspace_bytes(handle, params, nrhs=1):

@@ -258,29 +258,46 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
 
 bool hop_stream(const Geo &g, int prec, long nrhs) {
   if (const char *e = getenv("QIRAL_HOP_NT")) return atoi(e) != 0;
+  if (nrhs > 1 && getenv("QIRAL_HOP_NT_MULTI")) return atoi(getenv("QIRAL_HOP_NT_MULTI")) != 0;
   const double link = prec == QIRAL_F64 ? 144 : prec == QIRAL_F32 ? 48 : 24;
   const double sp = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
   const double bytes = (double)g.vh * (8 * link + 2 * sp * nrhs);
   return bytes > 128e6;   // half the 256 MB last-level cache
 }
 
+// Planes per chunk of the z-tiled block order must make whole blocks.
+static int zb_quantum(const Geo &g) {
+  int q = 1;
+  while ((long)q * g.sz % WAVE != 0) ++q;   // at most 64
+  return q;
+}
+
+bool zb_valid(const Geo &g, int zb) {
+  return zb > 0 && zb < g.lz && g.lz % zb == 0 && (long)zb * g.sz % WAVE == 0 && g.st % WAVE == 0;
+}
+
 int hop_zb(const Geo &g, int prec) {
-  if (g.sz % WAVE != 0 || (long)g.nb * WAVE != g.vh) return 0;
+  if (g.st % WAVE != 0 || (long)g.nb * WAVE != g.vh) return 0;
   if (const char *e = getenv("QIRAL_HOP_ORDER")) {   // 0: plain order; n > 0: tiles of n planes
     const int n = atoi(e);
-    return (n > 0 && n < g.lz && g.lz % n == 0) ? n : 0;
+    return zb_valid(g, n) ? n : 0;
   }
   // keep zb planes of input spinors (the reuse distance of a t-neighbour) to
   // about 0.5 MB per XCD
   const long site_b = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
+  const int q = zb_quantum(g);
   int zb = 0;
-  for (int z = 1; z <= g.lz; ++z)
+  for (int z = q; z <= g.lz; z += q)
     if (g.lz % z == 0 && (long)z * g.sz * site_b <= (512l << 10)) zb = z;
-  return zb >= g.lz ? 0 : zb;   // a tile of every plane is the plain order
+  return zb_valid(g, zb) ? zb : 0;   // a tile of every plane is the plain order
 }
 
 int hop_tile(const Geo &g, int ngroups) {
   if (ngroups <= 1) return g.nb;   // one group: plain block order
+  if (const char *e = getenv("QIRAL_HOP_TILE")) {
+    const int n = atoi(e);
+    if (n > 0) return std::min(g.nb, n);
+  }
   const int slice = (g.st + WAVE - 1) / WAVE;   // blocks per t-slice
   return std::min(g.nb, std::max(64, 2 * slice));
 }

@@ -382,10 +382,13 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ part, in
 // layouts order a site's components differently within a 64-site block, so
 // the conversion goes through the spinor loaders).  One thread per padded
 // site of either parity; padding sites are copied too (they hold zeros).
-__global__ __launch_bounds__(256) void k_cvt64to32(Geo g, const void *__restrict__ a, void *__restrict__ b) {
+// Packed F64 <-> F32 conversion of nh consecutive half-fields (nh = 2: a full
+// field; nh = 1: one half), site by site (the two layouts order a site's
+// components differently inside a 64-site block).
+__global__ __launch_bounds__(256) void k_cvt64to32(Geo g, const void *__restrict__ a, void *__restrict__ b, int nh) {
   const size_t npad = (size_t)g.nb * WAVE;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 2 * npad) return;
+  if (gid >= nh * npad) return;
   const int par = (int)(gid / npad), s = (int)(gid % npad);
   cpx<double> v[12];
   SpinorIO<S_F64>::load((const char *)a + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, v);
@@ -393,16 +396,39 @@ __global__ __launch_bounds__(256) void k_cvt64to32(Geo g, const void *__restrict
   cvt12(v, w);
   SpinorIO<S_F32>::store((char *)b + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, w);
 }
-__global__ __launch_bounds__(256) void k_cvt32to64(Geo g, const void *__restrict__ a, void *__restrict__ b) {
+__global__ __launch_bounds__(256) void k_cvt32to64(Geo g, const void *__restrict__ a, void *__restrict__ b, int nh) {
   const size_t npad = (size_t)g.nb * WAVE;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 2 * npad) return;
+  if (gid >= nh * npad) return;
   const int par = (int)(gid / npad), s = (int)(gid % npad);
   cpx<float> v[12];
   SpinorIO<S_F32>::load((const char *)a + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, v);
   cpx<double> w[12];
   cvt12(v, w);
   SpinorIO<S_F64>::store((char *)b + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, w);
+}
+
+// out = C in on a packed F64 half-field, C the twisted-mass site factor `mode`
+// (CHI_*; a copy at mu = 0)
+__global__ __launch_bounds__(256) void k_chi64(Geo g, const void *__restrict__ in, void *__restrict__ out, int mode,
+                                               double tmu) {
+  const size_t npad = (size_t)g.nb * WAVE;
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= npad) return;
+  cpx<double> v[12];
+  SpinorIO<S_F64>::load(in, (int)s, npad, v);
+  apply_chi(v, mode, tmu);
+  SpinorIO<S_F64>::store(out, (int)s, npad, v);
+}
+
+// y = c[0] x + c[1] y (complex coefficients)
+__global__ __launch_bounds__(256) void k_zaxpby(const double2 *__restrict__ c, const double2 *__restrict__ x,
+                                                double2 *__restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = c[0], b = c[1], xv = x[i], yv = y[i];
+  y[i] = make_double2(a.x * xv.x - a.y * xv.y + b.x * yv.x - b.y * yv.y,
+                      a.x * xv.y + a.y * xv.x + b.x * yv.y + b.y * yv.x);
 }
 
 // Complex dots (V_i | w) for i < k, with partials per work-group.
@@ -892,105 +918,325 @@ extern "C" qiral_status qiral_nn_train(qiral_nn *nn, int32_t steps, double lr, u
 }
 
 // ---------------------------------------------------------------------------
-// FGMRES(m) on D with the network as right preconditioner.
+// Flexible solvers, composed with the system they run on and a right
+// preconditioner (the runtime counterpart of the right-to-left template chains
+// of Sec. 2 and Sec. 3.1):
+//   system: the full D x = b, or the odd-site Schur system S x_o = b_hat of the
+//           "schur" template (then x_e = A^-1 (b_e + kappa H_eo x_o));
+//   preconditioner M ~ A^-1: the network N (full system), its Schur
+//           restriction M_S v = P_o N (0 (+) v) (the odd part of D^-1 (0 (+) v)
+//           is S^-1 v), or the identity;
+//   solver: FGMRES(m) with M on the right, FCG(1) on the normal equations with
+//           M M^dagger, or BiCGStab with M on the right.
+// Krylov vectors are packed FP64 fields (both halves, or the odd half), handled
+// as flat complex arrays; the network runs in FP32.
 namespace qiral {
 qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
                                    void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
-
-// Workspace of FGMRES(m): V[m+1], Z[m], B, X, W, R (F64 full fields), two F32
-// full fields, partials and coefficients; of FCG: B X S W P Z R Q (F64 full), three
-// F32 full fields, partials.
-size_t fgmres_ws_bytes(const Geo &g, int m) {
-  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
-  const int nbk = nblk(f64 / 16);
-  return (size_t)(2 * m + 5) * f64 + 2 * f32 + sizeof(double) * ((size_t)2 * (m + 1) * nbk + 4 * 64 + nbk);
-}
-size_t fcg_ws_bytes(const Geo &g) {
-  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
-  const int nbk = nblk(f64 / 16);
-  return 8 * f64 + 3 * f32 + sizeof(double) * ((size_t)4 * nbk + 4 * 64 + nbk);
-}
-size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm) {
-  if (prm->solver == QIRAL_FGMRES_NN) return fgmres_ws_bytes(lat->geo, prm->restart > 0 ? prm->restart : 20);
-  return fcg_ws_bytes(lat->geo);
-}
 void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
 
+namespace {
+
+// Krylov vectors each flexible solver keeps (beyond the common fields)
+int flex_nvec(int solver, int m) {
+  return solver == QIRAL_FGMRES_NN ? 2 * m + 5 : solver == QIRAL_FCG_NN ? 8 : 10;
+}
+
+bool flex_schur(const qiral_solve_params *prm) {
+  if (prm->system == QIRAL_SYSTEM_SCHUR) return true;
+  if (prm->system == QIRAL_SYSTEM_FULL) return false;
+  return prm->solver == QIRAL_BICGSTAB_EO;   // default: BiCGStab on the Schur system, FGMRES / FCG on D
+}
+
+int flex_restart(const qiral_solve_params *prm) { return prm->restart > 0 ? prm->restart : 20; }
+
+// The system, its preconditioner and the workspace fields of one flexible solve.
+struct Flex {
+  qiral_lattice *lat;
+  qiral_nn *nn;        // NULL: the identity preconditioner
+  bool schur;
+  size_t hb64, hb32;   // bytes of an F64 / F32 half-field
+  size_t vb, n2;       // bytes and complex entries of a Krylov vector
+  int nbk;             // work-groups of the flat vector kernels
+  double2 *BF, *XF, *RF;        // F64 full fields: b, x, the true residual
+  void *tmpE;                   // F64 even half-field (Schur operator, source)
+  void *in32, *out32;           // F32 full fields for the network
+  double2 *vec;                 // the solver's Krylov vectors, vb bytes apart
+  double *part, *npart, *nrm;   // partial sums
+  double2 *coef;                // complex coefficients (device)
+  double2 *v(int i) const { return (double2 *)((char *)vec + (size_t)i * vb); }
+};
+
+size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex *f) {
+  const size_t hb64 = half_bytes(g, QIRAL_F64), hb32 = half_bytes(g, QIRAL_F32);
+  const size_t vb = schur ? hb64 : 2 * hb64;
+  const int m = flex_restart(prm);
+  const int nbk = nblk(vb / 16);
+  const int nv = flex_nvec(prm->solver, m);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += (bytes + 255) / 256 * 256; return at; };
+  const size_t oBF = take(2 * hb64), oXF = take(2 * hb64), oRF = take(2 * hb64), oT = take(hb64);
+  const size_t oin = take(2 * hb32), oout = take(2 * hb32);
+  const size_t ovec = o;
+  o += (size_t)nv * vb;
+  const size_t opart = take(sizeof(double) * 2 * (size_t)(m + 2) * nbk), onpart = take(sizeof(double) * nbk);
+  const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * 64);
+  if (f) {
+    f->hb64 = hb64;
+    f->hb32 = hb32;
+    f->vb = vb;
+    f->n2 = vb / 16;
+    f->nbk = nbk;
+    f->BF = (double2 *)oBF;   // offsets here; based by flex_setup
+    f->XF = (double2 *)oXF;
+    f->RF = (double2 *)oRF;
+    f->tmpE = (void *)oT;
+    f->in32 = (void *)oin;
+    f->out32 = (void *)oout;
+    f->vec = (double2 *)ovec;
+    f->part = (double *)opart;
+    f->npart = (double *)onpart;
+    f->nrm = (double *)onrm;
+    f->coef = (double2 *)ocoef;
+  }
+  return o;
+}
+
+qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void *ws, size_t ws_bytes, Flex &f) {
+  f.lat = lat;
+  f.nn = (qiral_nn *)prm->precond;
+  if (f.nn && f.nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
+  f.schur = flex_schur(prm);
+  const size_t need = flex_bytes(lat->geo, prm, f.schur, &f);
+  if (ws_bytes < need) return fail(QIRAL_ERR_WORKSPACE, "flexible-solver workspace too small");
+  char *b = (char *)ws;
+  f.BF = (double2 *)(b + (size_t)f.BF);
+  f.XF = (double2 *)(b + (size_t)f.XF);
+  f.RF = (double2 *)(b + (size_t)f.RF);
+  f.tmpE = b + (size_t)f.tmpE;
+  f.in32 = b + (size_t)f.in32;
+  f.out32 = b + (size_t)f.out32;
+  f.vec = (double2 *)(b + (size_t)f.vec);
+  f.part = (double *)(b + (size_t)f.part);
+  f.npart = (double *)(b + (size_t)f.npart);
+  f.nrm = (double *)(b + (size_t)f.nrm);
+  f.coef = (double2 *)(b + (size_t)f.coef);
+  return QIRAL_OK;
+}
+
+// y = A x or A^dagger x in FP64 (A = D, or S = A_oo - kappa^2 H_oe A_ee^-1 H_eo)
+hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s) {
+  const qiral_lattice *lat = f.lat;
+  if (!f.schur) return dag ? apply_Ddag_full(lat, QIRAL_F64, y, x, s) : apply_D_full(lat, QIRAL_F64, y, x, s);
+  const double k = lat->kappa;
+  hipError_t e = launch_hop(lat, QIRAL_F64, dag, 0, 0, 1.0, x, f.tmpE, nullptr, 1, s, dag ? CHI_AINVDAG : CHI_AINV,
+                            CHI_ONE);
+  if (e != hipSuccess) return e;
+  return launch_hop(lat, QIRAL_F64, dag, 1, 1, -k * k, f.tmpE, y, x, 1, s, CHI_ONE, dag ? CHI_ADAG : CHI_A);
+}
+
+// z = M v (or M^dagger v): the network in FP32 on v (full system) or on v placed
+// on the odd sites, keeping the odd part of the result (Schur system, whose
+// even half of in32 stays zero); the identity without a network.
+hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s) {
+  if (!f.nn) return hipMemcpyAsync(z, v, f.vb, hipMemcpyDeviceToDevice, s);
+  const Geo &g = f.lat->geo;
+  const int nh = f.schur ? 1 : 2;
+  char *in = (char *)f.in32 + (f.schur ? f.hb32 : 0);
+  char *out = (char *)f.out32 + (f.schur ? f.hb32 : 0);
+  const int nb = nblk((size_t)nh * npad_of(g));
+  hipLaunchKernelGGL(k_cvt64to32, dim3(nb), dim3(256), 0, s, g, v, in, nh);
+  hipError_t e = adj ? nn_apply_adjoint_dev(f.nn, f.out32, f.in32, s) : nn_apply_dev(f.nn, f.out32, f.in32, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cvt32to64, dim3(nb), dim3(256), 0, s, g, out, z, nh);
+  return hipGetLastError();
+}
+
+qiral_status flex_read(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  QIRAL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  QIRAL_HIP(hipStreamSynchronize(s));
+  return QIRAL_OK;
+}
+
+qiral_status flex_norm2(const Flex &f, const double2 *v, double &out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(f.nbk), dim3(256), 0, s, v, f.n2, f.npart);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, f.nbk, f.nrm, (const double *)nullptr);
+  return flex_read(&out, f.nrm, sizeof(double), s);
+}
+
+// (a | b) on the host
+qiral_status flex_dot(const Flex &f, const double2 *a, const double2 *b, std::complex<double> &out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot, dim3(f.nbk), dim3(256), 0, s, a, f.n2, 1, b, f.n2, f.part);
+  hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, f.part, f.nbk, f.coef + 32);
+  double2 c;
+  qiral_status st = flex_read(&c, f.coef + 32, sizeof c, s);
+  out = std::complex<double>(c.x, c.y);
+  return st;
+}
+
+qiral_status flex_set_coef(const Flex &f, const std::vector<double2> &c, hipStream_t s) {
+  QIRAL_HIP(hipMemcpyAsync(f.coef, c.data(), sizeof(double2) * c.size(), hipMemcpyHostToDevice, s));
+  return QIRAL_OK;
+}
+
+// Inputs: b (full) into BF, x into XF (guess or 0), and the system's right-hand
+// side into rhs (b itself, or b_hat = b_o + kappa H_oe A^-1 b_e) and its x.
+qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_canon, bool guess, double2 *rhs,
+                        double2 *X, double &bnorm, hipStream_t s) {
+  const qiral_lattice *lat = f.lat;
+  const Geo &g = lat->geo;
+  import_field(g, b_canon, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
+  if (guess) import_field(g, x_canon, f.XF, QIRAL_FULL, QIRAL_F64, 1, s);
+  else QIRAL_HIP(hipMemsetAsync(f.XF, 0, 2 * f.hb64, s));
+  // Hops and network layers write only the lattice's sites, while the flat
+  // vector kernels also sum the padding sites of the last 64-site block: every
+  // field whose padding they can reach starts at zero (the Krylov vectors are
+  // cleared by the solvers).  The network's input also keeps its even half at
+  // zero on the Schur system.
+  QIRAL_HIP(hipMemsetAsync(f.RF, 0, 2 * f.hb64, s));
+  QIRAL_HIP(hipMemsetAsync(f.in32, 0, 2 * f.hb32, s));
+  QIRAL_HIP(hipMemsetAsync(f.out32, 0, 2 * f.hb32, s));
+  const char *be = (const char *)f.BF, *bo = be + f.hb64;
+  if (!f.schur) {
+    QIRAL_HIP(hipMemcpyAsync(rhs, f.BF, 2 * f.hb64, hipMemcpyDeviceToDevice, s));
+    QIRAL_HIP(hipMemcpyAsync(X, f.XF, 2 * f.hb64, hipMemcpyDeviceToDevice, s));
+  } else {
+    hipLaunchKernelGGL(k_chi64, dim3(nblk(npad_of(g))), dim3(256), 0, s, g, be, f.tmpE, (int)CHI_AINV,
+                       2.0 * lat->kappa * lat->mu);
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 1, 1, lat->kappa, f.tmpE, rhs, bo, 1, s, CHI_ONE, CHI_ONE));
+    QIRAL_HIP(hipMemcpyAsync(X, (const char *)f.XF + f.hb64, f.hb64, hipMemcpyDeviceToDevice, s));
+  }
+  QIRAL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_norm, dim3(nblk(2 * f.hb64 / 16)), dim3(256), 0, s, f.BF, 2 * f.hb64 / 16, f.npart);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(2 * f.hb64 / 16), f.nrm, (const double *)nullptr);
+  double b2 = 0;
+  qiral_status st = flex_read(&b2, f.nrm, sizeof b2, s);
+  bnorm = std::sqrt(b2);
+  return st;
+}
+
+// x (full) from the system's solution X, its FP64 true residual ||b - D x||, export.
+qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &rn, hipStream_t s) {
+  const qiral_lattice *lat = f.lat;
+  const Geo &g = lat->geo;
+  if (!f.schur) {
+    QIRAL_HIP(hipMemcpyAsync(f.XF, X, 2 * f.hb64, hipMemcpyDeviceToDevice, s));
+  } else {
+    char *xe = (char *)f.XF, *xo = xe + f.hb64;
+    QIRAL_HIP(hipMemcpyAsync(xo, X, f.hb64, hipMemcpyDeviceToDevice, s));
+    // x_e = A^-1 (b_e + kappa H_eo x_o)
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 0, 1, lat->kappa, xo, xe, f.BF, 1, s, CHI_AINV, CHI_ONE));
+  }
+  QIRAL_HIP(apply_D_full(lat, QIRAL_F64, f.RF, f.XF, s));
+  const size_t nf = 2 * f.hb64 / 16;
+  hipLaunchKernelGGL(k_bminus, dim3(nblk(nf)), dim3(256), 0, s, f.BF, f.RF, nf);
+  hipLaunchKernelGGL(k_norm, dim3(nblk(nf)), dim3(256), 0, s, f.RF, nf, f.npart);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(nf), f.nrm, (const double *)nullptr);
+  double r2 = 0;
+  qiral_status st = flex_read(&r2, f.nrm, sizeof r2, s);
+  rn = std::sqrt(r2);
+  export_field(g, x_canon, f.XF, QIRAL_FULL, QIRAL_F64, 1, s);
+  QIRAL_HIP(hipGetLastError());
+  QIRAL_HIP(hipStreamSynchronize(s));
+  return st;
+}
+
+// R = rhs - A X; returns ||R||
+qiral_status flex_residual(const Flex &f, const double2 *rhs, const double2 *X, double2 *R, double &rn,
+                           hipStream_t s) {
+  QIRAL_HIP(flex_A(f, R, X, false, s));
+  hipLaunchKernelGGL(k_bminus, dim3(f.nbk), dim3(256), 0, s, rhs, R, f.n2);
+  double r2 = 0;
+  qiral_status st = flex_norm2(f, R, r2, s);
+  rn = std::sqrt(r2);
+  return st;
+}
+
+// Fill info, and continue with even-odd CGNR from the current x when asked.
+qiral_status flex_finish(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
+                         void *ws, size_t ws_bytes, qiral_solve_info *info, int steps, long long hops, double rn,
+                         double bn, bool broke, const char *name, std::chrono::steady_clock::time_point t0,
+                         hipStream_t s) {
+  const double target = prm->tol * bn;
+  qiral_status result = QIRAL_OK;
+  info->iterations = steps;
+  info->reliable_updates = 0;
+  info->fell_back = 0;
+  info->hop_applications = hops;
+  info->true_rel_resid = bn > 0 ? rn / bn : rn;
+  if (!std::isfinite(rn)) {
+    set_error(std::string("a NaN or Inf appeared in ") + name);
+    result = QIRAL_ERR_NONFINITE;
+  } else if (rn > target && prm->fallback_cg) {
+    qiral_solve_params cg = *prm;
+    cg.solver = QIRAL_CGNR_EO;
+    cg.system = QIRAL_SYSTEM_DEFAULT;
+    cg.precond = nullptr;
+    cg.x0_is_guess = 1;
+    qiral_solve_info ci;
+    memset(&ci, 0, sizeof ci);
+    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, ws, ws_bytes, &ci, s);
+    info->iterations = steps + ci.iterations;
+    info->reliable_updates = ci.reliable_updates;
+    info->true_rel_resid = ci.true_rel_resid;
+    info->hop_applications = hops + ci.hop_applications;
+    info->fell_back = 1;
+  } else if (rn > target) {
+    set_error(broke ? (std::string(name) + " broke down").c_str() : "tolerance not reached within maxiter");
+    result = QIRAL_ERR_NOT_CONVERGED;
+  }
+  info->converged = (result == QIRAL_OK);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+
+// hop applications (units of V/2 sites) of one application of A
+long long flex_hops(const Flex &f) { return 2; }
+
+}  // namespace
+
+size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm) {
+  return flex_bytes(lat->geo, prm, flex_schur(prm), nullptr);
+}
+
+// FGMRES(m) with M on the right: x = x0 + Z y, z_j = M v_j (Saad 1993).
 qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
                         void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
-  qiral_nn *nn = (qiral_nn *)prm->precond;
-  if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
-  const int m = prm->restart > 0 ? prm->restart : 20;
-  if (m > 64) return fail(QIRAL_ERR_INVALID_ARG, "restart must be <= 64");
-  const Geo &g = lat->geo;
-  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
-  const size_t n2 = f64 / 16;   // complex entries of a full F64 field (padding included, kept zero)
-  const int nbk = nblk(n2);
-  const int nsite_blk = nblk(2 * npad_of(g));   // one thread per padded site (layout conversions)
-  if (ws_bytes < fgmres_ws_bytes(g, m)) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace too small");
-  char *p = (char *)ws;
-  double2 *V = (double2 *)p; p += (size_t)(m + 1) * f64;
-  double2 *Z = (double2 *)p; p += (size_t)m * f64;
-  double2 *B = (double2 *)p; p += f64;
-  double2 *X = (double2 *)p; p += f64;
-  double2 *Wv = (double2 *)p; p += f64;
-  double2 *R = (double2 *)p; p += f64;
-  void *in32 = p; p += f32;
-  void *out32 = p; p += f32;
-  double *part = (double *)p; p += sizeof(double) * 2 * (m + 1) * nbk;
-  double2 *coef = (double2 *)p; p += sizeof(double) * 2 * 64;
-  double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
-  double *npart = (double *)p;
-  const size_t vs = n2;   // stride between vectors of V and Z in complex entries
-  if ((char *)(npart + nbk) > (char *)ws + ws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FGMRES workspace layout");
-
-  QIRAL_HIP(hipMemsetAsync(ws, 0, (size_t)(2 * m + 5) * f64 + 2 * f32, s));
-  import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
-  if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
-  auto norm = [&](const double2 *v, double &out) -> qiral_status {
-    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, v, n2, npart);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
-    QIRAL_HIP(hipMemcpyAsync(&out, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-    QIRAL_HIP(hipStreamSynchronize(s));
-    return QIRAL_OK;
-  };
-  auto residual = [&](double &rn) -> qiral_status {   // R = B - D X
-    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, R, X, s));
-    hipLaunchKernelGGL(k_bminus, dim3(nbk), dim3(256), 0, s, B, R, n2);
-    double r2 = 0;
-    qiral_status st = norm(R, r2);
-    rn = std::sqrt(r2);
-    return st;
-  };
-  double bn2 = 0;
-  qiral_status st = norm(B, bn2);
+  Flex f;
+  qiral_status st = flex_setup(lat, prm, ws, ws_bytes, f);
   if (st != QIRAL_OK) return st;
-  const double bn = std::sqrt(bn2), target = prm->tol * bn;
+  const int m = flex_restart(prm);
+  double2 *V = f.v(0), *Z = f.v(m + 1), *B = f.v(2 * m + 1), *X = f.v(2 * m + 2), *Wv = f.v(2 * m + 3),
+          *R = f.v(2 * m + 4);
+  const size_t vs = f.n2;   // stride between vectors of V and Z in complex entries
+  QIRAL_HIP(hipMemsetAsync(f.vec, 0, (size_t)(2 * m + 5) * f.vb, s));
+  double bn = 0;
+  if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
+  const double target = prm->tol * bn;
   double rn = 0;
-  if ((st = residual(rn)) != QIRAL_OK) return st;
-  int steps = 0, fell_back = 0;
-  long long hops = 2;
+  if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
+  int steps = 0;
+  long long hops = flex_hops(f);
   double prev_cycle = rn;
   typedef std::complex<double> C;
   std::vector<C> H((m + 1) * m), cs(m), sn(m), gv(m + 1);
+  bool broke = false;
   while (rn > target && steps < prm->maxiter) {
     // V0 = R / |R|
-    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, R, n2, npart);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
-    hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, s, R, nrm, V, n2);
+    hipLaunchKernelGGL(k_norm, dim3(f.nbk), dim3(256), 0, s, R, f.n2, f.npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, f.nbk, f.nrm, (const double *)nullptr);
+    hipLaunchKernelGGL(k_scale, dim3(f.nbk), dim3(256), 0, s, R, f.nrm, V, f.n2);
     std::fill(H.begin(), H.end(), C(0));
     std::fill(gv.begin(), gv.end(), C(0));
     gv[0] = rn;
     int k = 0;
     for (int j = 0; j < m && steps < prm->maxiter; ++j) {
-      // Z_j = N(V_j) in FP32, W = D Z_j in FP64
-      hipLaunchKernelGGL(k_cvt64to32, dim3(nsite_blk), dim3(256), 0, s, g, V + j * vs, in32);
-      QIRAL_HIP(nn_apply_dev(nn, out32, in32, s));
-      hipLaunchKernelGGL(k_cvt32to64, dim3(nsite_blk), dim3(256), 0, s, g, out32, Z + j * vs);
-      QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, Z + j * vs, s));
-      hops += 2;
+      // Z_j = M V_j, W = A Z_j
+      QIRAL_HIP(flex_M(f, Z + j * vs, V + j * vs, false, s));
+      QIRAL_HIP(flex_A(f, Wv, Z + j * vs, false, s));
+      hops += flex_hops(f);
       // classical Gram-Schmidt with selective reorthogonalisation (Daniel,
       // Gragg, Kaufman and Stewart 1976): a second pass only when the first
       // removed more than half of w's squared norm, i.e. when cancellation
@@ -998,22 +1244,21 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
       std::vector<C> h(j + 2, C(0));
       double w2 = 0;
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, Wv, n2, part);
-        hipLaunchKernelGGL(k_mdot_final, dim3(j + 1), dim3(256), 0, s, part, nbk, coef);
-        hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, V, vs, j + 1, coef, -1.0, Wv, n2);
+        hipLaunchKernelGGL(k_mdot, dim3(f.nbk), dim3(256), 0, s, V, vs, j + 1, Wv, f.n2, f.part);
+        hipLaunchKernelGGL(k_mdot_final, dim3(j + 1), dim3(256), 0, s, f.part, f.nbk, f.coef);
+        hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, V, vs, j + 1, f.coef, -1.0, Wv, f.n2);
         std::vector<double2> c(j + 1);
-        QIRAL_HIP(hipMemcpyAsync(c.data(), coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
-        QIRAL_HIP(hipStreamSynchronize(s));
+        if ((st = flex_read(c.data(), f.coef, sizeof(double2) * (j + 1), s)) != QIRAL_OK) return st;
         double c2 = 0;
         for (int i = 0; i <= j; ++i) {
           h[i] += C(c[i].x, c[i].y);
           c2 += c[i].x * c[i].x + c[i].y * c[i].y;
         }
-        if ((st = norm(Wv, w2)) != QIRAL_OK) return st;
+        if ((st = flex_norm2(f, Wv, w2, s)) != QIRAL_OK) return st;
         if (w2 > 0.5 * (w2 + c2)) break;   // ||w_after||^2 > ||w_before||^2 / 2
       }
       h[j + 1] = std::sqrt(w2);
-      hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, s, Wv, nrm, V + (j + 1) * vs, n2);
+      hipLaunchKernelGGL(k_scale, dim3(f.nbk), dim3(256), 0, s, Wv, f.nrm, V + (j + 1) * vs, f.n2);
       // Givens rotations on the new column
       for (int i = 0; i < j; ++i) {
         const C hi = h[i];
@@ -1043,153 +1288,81 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
     }
     std::vector<double2> yc(k);
     for (int i = 0; i < k; ++i) yc[i] = make_double2(y[i].real(), y[i].imag());
-    QIRAL_HIP(hipMemcpyAsync(coef, yc.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, Z, vs, k, coef, 1.0, X, n2);
-    if ((st = residual(rn)) != QIRAL_OK) return st;
-    hops += 2;
+    if ((st = flex_set_coef(f, yc, s)) != QIRAL_OK) return st;
+    hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, Z, vs, k, f.coef, 1.0, X, f.n2);
+    if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
+    hops += flex_hops(f);
     if (!std::isfinite(rn)) break;
-    if (rn > target && prm->fallback_cg && rn > 0.5 * prev_cycle) { fell_back = 1; break; }   // stagnation
+    if (rn > target && prm->fallback_cg && rn > 0.5 * prev_cycle) { broke = true; break; }   // stagnation
     prev_cycle = rn;
   }
-  // export and, if needed, continue with even-odd CGNR from the current x
-  export_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
-  QIRAL_HIP(hipStreamSynchronize(s));
-  qiral_status result = QIRAL_OK;
-  info->iterations = steps;
-  info->reliable_updates = 0;
-  info->fell_back = 0;
-  info->hop_applications = hops;
-  info->true_rel_resid = bn > 0 ? rn / bn : rn;
-  if (!std::isfinite(rn)) {
-    set_error("a NaN or Inf appeared in FGMRES");
-    result = QIRAL_ERR_NONFINITE;
-  } else if (rn > target && prm->fallback_cg) {
-    qiral_solve_params cg = *prm;
-    cg.solver = QIRAL_CGNR_EO;
-    cg.x0_is_guess = 1;
-    qiral_solve_info ci;
-    memset(&ci, 0, sizeof ci);
-    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, ws, ws_bytes, &ci, s);
-    info->iterations = steps + ci.iterations;
-    info->reliable_updates = ci.reliable_updates;
-    info->true_rel_resid = ci.true_rel_resid;
-    info->hop_applications = hops + ci.hop_applications;
-    info->fell_back = 1;
-    (void)fell_back;
-  } else if (rn > target) {
-    set_error("tolerance not reached within maxiter");
-    result = QIRAL_ERR_NOT_CONVERGED;
-  }
-  info->converged = (result == QIRAL_OK);
-  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return result;
+  double rt = 0;
+  if ((st = flex_end(f, X, x_canon, rt, s)) != QIRAL_OK) return st;
+  hops += 2;
+  if (std::isfinite(rn) && !std::isfinite(rt)) rn = rt;
+  return flex_finish(lat, x_canon, b_canon, prm, ws, ws_bytes, info, steps, hops, std::isfinite(rn) ? rt : rn, bn,
+                     broke, "FGMRES", t0, s);
 }
 
-// Flexible CG (Notay 2000), FCG(1), on D^dagger D x = D^dagger b with the
-// preconditioner z = N (N^dagger r) of the network (FP32).  The network is a
-// fixed linear map, so one previous direction is enough (as in preconditioned
-// CG); the flexible coefficient beta = (A p_prev | z) / (p_prev | A p_prev)
-// keeps the directions A-conjugate although z carries FP32 rounding.  The FP64
-// residual s = b - D x is updated alongside the normal residual r = D^dagger s
+// Flexible CG (Notay 2000), FCG(1), on the normal equations A^dagger A x =
+// A^dagger rhs with the preconditioner z = M (M^dagger r).  M is a fixed linear
+// map, so one previous direction is enough (as in preconditioned CG); the
+// flexible coefficient beta = (A^dagger A p_prev | z) / (p_prev | A^dagger A p_prev)
+// keeps the directions conjugate although z carries FP32 rounding.  The FP64
+// residual s = rhs - A x is updated alongside the normal residual r = A^dagger s
 // and decides convergence; the true residual is recomputed at the end.
 qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon, const qiral_solve_params *prm,
                      void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
-  qiral_nn *nn = (qiral_nn *)prm->precond;
-  if (!nn || nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
-  const Geo &g = lat->geo;
-  const size_t f64 = full_bytes64(g), f32 = full_bytes32(g);
-  const size_t n2 = f64 / 16;
-  const int nbk = nblk(n2);
-  const int nsite_blk = nblk(2 * npad_of(g));
-  if (ws_bytes < fcg_ws_bytes(g)) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace too small");
-  char *p = (char *)ws;
-  double2 *B = (double2 *)p; p += f64;
-  double2 *X = (double2 *)p; p += f64;
-  double2 *Sv = (double2 *)p; p += f64;
-  double2 *Wv = (double2 *)p; p += f64;
-  double2 *P = (double2 *)p; p += f64;
-  double2 *Z = (double2 *)p; p += f64;
-  double2 *R = (double2 *)p; p += f64;
-  double2 *Q = (double2 *)p; p += f64;
-  void *in32 = p; p += f32;
-  void *mid32 = p; p += f32;
-  void *out32 = p; p += f32;
-  double *part = (double *)p; p += sizeof(double) * 4 * nbk;
-  double2 *coef = (double2 *)p; p += sizeof(double) * 2 * 64;
-  double *nrm = (double *)p; p += sizeof(double) * 2 * 64;
-  double *npart = (double *)p;
-  if ((char *)(npart + nbk) > (char *)ws + ws_bytes) return fail(QIRAL_ERR_WORKSPACE, "FCG workspace layout");
-
-  QIRAL_HIP(hipMemsetAsync(ws, 0, 8 * f64 + 3 * f32, s));
-  import_field(g, b_canon, B, QIRAL_FULL, QIRAL_F64, 1, s);
-  if (prm->x0_is_guess) import_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
-  auto read = [&](void *dst, const void *src, size_t bytes) -> qiral_status {
-    QIRAL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
-    QIRAL_HIP(hipStreamSynchronize(s));
+  Flex f;
+  qiral_status st = flex_setup(lat, prm, ws, ws_bytes, f);
+  if (st != QIRAL_OK) return st;
+  double2 *B = f.v(0), *X = f.v(1), *Sv = f.v(2), *Wv = f.v(3), *P = f.v(4), *Z = f.v(5), *R = f.v(6), *Q = f.v(7);
+  QIRAL_HIP(hipMemsetAsync(f.vec, 0, 8 * f.vb, s));
+  double bn = 0;
+  if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
+  const double target = prm->tol * bn;
+  // S = B - A X, R = A^dagger S; returns ||S||
+  auto residuals = [&](double &sn) -> qiral_status {
+    qiral_status r = flex_residual(f, B, X, Sv, sn, s);
+    if (r != QIRAL_OK) return r;
+    QIRAL_HIP(flex_A(f, R, Sv, true, s));
     return QIRAL_OK;
   };
-  auto norm = [&](const double2 *v, double &out) -> qiral_status {
-    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, v, n2, npart);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
-    return read(&out, nrm, sizeof(double));
-  };
-  // S = B - D X, R = D^dagger S; returns ||S||
-  auto residuals = [&](double &sn) -> qiral_status {
-    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Sv, X, s));
-    hipLaunchKernelGGL(k_bminus, dim3(nbk), dim3(256), 0, s, B, Sv, n2);
-    QIRAL_HIP(apply_Ddag_full(lat, QIRAL_F64, R, Sv, s));
-    double s2 = 0;
-    qiral_status st = norm(Sv, s2);
-    sn = std::sqrt(s2);
-    return st;
-  };
-  double bn2 = 0;
-  qiral_status st = norm(B, bn2);
-  if (st != QIRAL_OK) return st;
-  const double bn = std::sqrt(bn2), target = prm->tol * bn;
   double sn = 0;
   if ((st = residuals(sn)) != QIRAL_OK) return st;
-  long long hops = 4;
+  long long hops = 2 * flex_hops(f);
   int it = 0, since_best = 0;
   bool broke = false;
   double best = sn, dprev = 0;
+  typedef std::complex<double> C;
   while (sn > target && it < prm->maxiter) {
-    // Z = N (N^dagger R) in FP32
-    hipLaunchKernelGGL(k_cvt64to32, dim3(nsite_blk), dim3(256), 0, s, g, R, in32);
-    QIRAL_HIP(nn_apply_adjoint_dev(nn, mid32, in32, s));
-    QIRAL_HIP(nn_apply_dev(nn, out32, mid32, s));
-    hipLaunchKernelGGL(k_cvt32to64, dim3(nsite_blk), dim3(256), 0, s, g, out32, Z);
+    // Z = M (M^dagger R)
+    QIRAL_HIP(flex_M(f, Q, R, true, s));   // Q is free until W = A P below
+    QIRAL_HIP(flex_M(f, Z, Q, false, s));
     if (it > 0) {
-      // Z -= ((Q | Z) / (P | Q)) P, then P <- Z
-      hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, Q, n2, 1, Z, n2, part);
-      hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, part, nbk, coef);
-      double2 c;
-      if ((st = read(&c, coef, sizeof c)) != QIRAL_OK) return st;
-      const double2 mb = make_double2(-c.x / dprev, -c.y / dprev);
-      QIRAL_HIP(hipMemcpyAsync(coef, &mb, sizeof mb, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_maxpy, dim3(nbk), dim3(256), 0, s, P, n2, 1, coef, 1.0, Z, n2);
+      // Z -= ((Q_prev | Z) / (P | Q_prev)) P, then P <- Z  (Q_prev = A^dagger A P_prev lives in Wv here)
+      C c;
+      if ((st = flex_dot(f, Wv, Z, c, s)) != QIRAL_OK) return st;
+      if ((st = flex_set_coef(f, {make_double2(-c.real() / dprev, -c.imag() / dprev)}, s)) != QIRAL_OK) return st;
+      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, P, f.n2, 1, f.coef, 1.0, Z, f.n2);
     }
     std::swap(P, Z);
-    // W = D P, Q = D^dagger W, (P | Q) = ||W||^2, (P | R) = conj((R | P))
-    QIRAL_HIP(apply_D_full(lat, QIRAL_F64, Wv, P, s));
-    QIRAL_HIP(apply_Ddag_full(lat, QIRAL_F64, Q, Wv, s));
-    hops += 4;
-    hipLaunchKernelGGL(k_mdot, dim3(nbk), dim3(256), 0, s, R, n2, 1, P, n2, part);
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, part, nbk, coef);
-    hipLaunchKernelGGL(k_norm, dim3(nbk), dim3(256), 0, s, Wv, n2, npart);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
-    double2 rp;
+    // Q = A P, Wv = A^dagger Q, (P | Wv) = ||Q||^2, (P | R) = conj((R | P))
+    QIRAL_HIP(flex_A(f, Q, P, false, s));
+    QIRAL_HIP(flex_A(f, Wv, Q, true, s));
+    hops += 2 * flex_hops(f);
+    C rp;
+    if ((st = flex_dot(f, R, P, rp, s)) != QIRAL_OK) return st;
     double d = 0;
-    if ((st = read(&rp, coef, sizeof rp)) != QIRAL_OK) return st;
-    if ((st = read(&d, nrm, sizeof d)) != QIRAL_OK) return st;
+    if ((st = flex_norm2(f, Q, d, s)) != QIRAL_OK) return st;
     if (!(d > 0) || !std::isfinite(d)) { broke = true; break; }   // P = 0: the preconditioner returned 0
-    const double2 al = make_double2(rp.x / d, -rp.y / d);
-    QIRAL_HIP(hipMemcpyAsync(coef, &al, sizeof al, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fcg_upd, dim3(nbk), dim3(256), 0, s, coef, P, Q, Wv, X, R, Sv, n2, npart);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, npart, nbk, nrm, (const double *)nullptr);
+    // alpha = (P | R) / (P | A^dagger A P); X += alpha P, R -= alpha Wv, S -= alpha Q
+    if ((st = flex_set_coef(f, {make_double2(rp.real() / d, -rp.imag() / d)}, s)) != QIRAL_OK) return st;
+    hipLaunchKernelGGL(k_fcg_upd, dim3(f.nbk), dim3(256), 0, s, f.coef, P, Wv, Q, X, R, Sv, f.n2, f.npart);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, f.nbk, f.nrm, (const double *)nullptr);
     double s2 = 0;
-    if ((st = read(&s2, nrm, sizeof s2)) != QIRAL_OK) return st;
+    if ((st = flex_read(&s2, f.nrm, sizeof s2, s)) != QIRAL_OK) return st;
     sn = std::sqrt(s2);
     dprev = d;
     ++it;
@@ -1197,37 +1370,100 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
     if (sn < 0.99 * best) { best = sn; since_best = 0; }
     else if (++since_best >= 50 && prm->fallback_cg) { broke = true; break; }   // stagnation
   }
-  // the true residual of the FCG iterate
-  if ((st = residuals(sn)) != QIRAL_OK) return st;
+  double rt = 0;
+  if ((st = flex_end(f, X, x_canon, rt, s)) != QIRAL_OK) return st;
   hops += 2;
-  export_field(g, x_canon, X, QIRAL_FULL, QIRAL_F64, 1, s);
-  QIRAL_HIP(hipStreamSynchronize(s));
-  qiral_status result = QIRAL_OK;
-  info->iterations = it;
-  info->reliable_updates = 0;
-  info->fell_back = 0;
-  info->hop_applications = hops;
-  info->true_rel_resid = bn > 0 ? sn / bn : sn;
-  if (!std::isfinite(sn)) {
-    set_error("a NaN or Inf appeared in FCG");
-    result = QIRAL_ERR_NONFINITE;
-  } else if (sn > target && prm->fallback_cg) {
-    qiral_solve_params cg = *prm;
-    cg.solver = QIRAL_CGNR_EO;
-    cg.x0_is_guess = 1;
-    qiral_solve_info ci;
-    memset(&ci, 0, sizeof ci);
-    result = run_solve_cg_fallback(lat, x_canon, b_canon, &cg, ws, ws_bytes, &ci, s);
-    info->iterations = it + ci.iterations;
-    info->true_rel_resid = ci.true_rel_resid;
-    info->hop_applications = hops + ci.hop_applications;
-    info->fell_back = 1;
-  } else if (sn > target) {
-    set_error(broke ? "FCG broke down (the preconditioner returned zero)" : "tolerance not reached within maxiter");
-    result = QIRAL_ERR_NOT_CONVERGED;
+  return flex_finish(lat, x_canon, b_canon, prm, ws, ws_bytes, info, it, hops, std::isfinite(sn) ? rt : sn, bn,
+                     broke, "FCG", t0, s);
+}
+
+// BiCGStab (van der Vorst 1992) with M on the right: the directions p and s are
+// preconditioned, p^ = M p, s^ = M s, and x moves along them (the preconditioned
+// BiCGStab of Barrett et al., Templates, SIAM 1994); with the identity these are
+// plain BiCGStab's iterates.  Scalars are formed on the host from FP64 dots.
+qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double *b_canon,
+                               const qiral_solve_params *prm, void *ws, size_t ws_bytes, qiral_solve_info *info,
+                               hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  Flex f;
+  qiral_status st = flex_setup(lat, prm, ws, ws_bytes, f);
+  if (st != QIRAL_OK) return st;
+  double2 *B = f.v(0), *X = f.v(1), *R = f.v(2), *RT = f.v(3), *P = f.v(4), *Vv = f.v(5), *Sv = f.v(6),
+          *T = f.v(7), *PH = f.v(8), *SH = f.v(9);   // PH and SH adjacent: one two-vector update of X
+  QIRAL_HIP(hipMemsetAsync(f.vec, 0, 10 * f.vb, s));
+  double bn = 0;
+  if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
+  const double target = prm->tol * bn;
+  typedef std::complex<double> C;
+  double rn = 0;
+  if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
+  long long hops = flex_hops(f);
+  int it = 0, restarts = 0;
+  bool broke = false;
+  while (rn > target && it < prm->maxiter && !broke) {
+    // (re)start: shadow residual r~ = r, rho = alpha = omega = 1, p = v = 0
+    QIRAL_HIP(hipMemcpyAsync(RT, R, f.vb, hipMemcpyDeviceToDevice, s));
+    QIRAL_HIP(hipMemsetAsync(P, 0, f.vb, s));
+    QIRAL_HIP(hipMemsetAsync(Vv, 0, f.vb, s));
+    C rho(1), alpha(1), omega(1);
+    bool restart = false;
+    while (rn > target && it < prm->maxiter) {
+      C rho1;
+      if ((st = flex_dot(f, RT, R, rho1, s)) != QIRAL_OK) return st;
+      if (rho1 == C(0)) { restart = true; break; }
+      const C beta = (rho1 / rho) * (alpha / omega);
+      // P = R + beta (P - omega V)
+      if ((st = flex_set_coef(f, {make_double2(omega.real(), omega.imag())}, s)) != QIRAL_OK) return st;
+      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, Vv, f.n2, 1, f.coef, -1.0, P, f.n2);
+      if ((st = flex_set_coef(f, {make_double2(1.0, 0.0), make_double2(beta.real(), beta.imag())}, s)) != QIRAL_OK)
+        return st;
+      hipLaunchKernelGGL(k_zaxpby, dim3(f.nbk), dim3(256), 0, s, f.coef, R, P, f.n2);
+      QIRAL_HIP(flex_M(f, PH, P, false, s));
+      QIRAL_HIP(flex_A(f, Vv, PH, false, s));
+      C rv;
+      if ((st = flex_dot(f, RT, Vv, rv, s)) != QIRAL_OK) return st;
+      if (rv == C(0)) { restart = true; break; }
+      alpha = rho1 / rv;
+      // S = R - alpha V
+      QIRAL_HIP(hipMemcpyAsync(Sv, R, f.vb, hipMemcpyDeviceToDevice, s));
+      if ((st = flex_set_coef(f, {make_double2(alpha.real(), alpha.imag())}, s)) != QIRAL_OK) return st;
+      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, Vv, f.n2, 1, f.coef, -1.0, Sv, f.n2);
+      QIRAL_HIP(flex_M(f, SH, Sv, false, s));
+      QIRAL_HIP(flex_A(f, T, SH, false, s));
+      hops += 2 * flex_hops(f);
+      C ts;
+      double tt = 0;
+      if ((st = flex_dot(f, T, Sv, ts, s)) != QIRAL_OK) return st;
+      if ((st = flex_norm2(f, T, tt, s)) != QIRAL_OK) return st;
+      omega = tt > 0 ? ts / tt : C(0);
+      // X += alpha PH + omega SH; R = S - omega T
+      if ((st = flex_set_coef(f, {make_double2(alpha.real(), alpha.imag()), make_double2(omega.real(), omega.imag())},
+                              s)) != QIRAL_OK)
+        return st;
+      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, PH, f.n2, 2, f.coef, 1.0, X, f.n2);
+      QIRAL_HIP(hipMemcpyAsync(R, Sv, f.vb, hipMemcpyDeviceToDevice, s));
+      if ((st = flex_set_coef(f, {make_double2(omega.real(), omega.imag())}, s)) != QIRAL_OK) return st;
+      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, T, f.n2, 1, f.coef, -1.0, R, f.n2);
+      double r2 = 0;
+      if ((st = flex_norm2(f, R, r2, s)) != QIRAL_OK) return st;
+      rn = std::sqrt(r2);
+      rho = rho1;
+      ++it;
+      if (!std::isfinite(rn)) break;
+      if (omega == C(0)) { restart = true; break; }
+    }
+    if (!std::isfinite(rn)) break;
+    if (restart) {
+      // breakdown: restart from the current x with the recomputed residual
+      if (++restarts > 5) { broke = true; break; }
+      if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
+      hops += flex_hops(f);
+    }
   }
-  info->converged = (result == QIRAL_OK);
-  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return result;
+  double rt = 0;
+  if ((st = flex_end(f, X, x_canon, rt, s)) != QIRAL_OK) return st;
+  hops += 2;
+  return flex_finish(lat, x_canon, b_canon, prm, ws, ws_bytes, info, it, hops, std::isfinite(rn) ? rt : rn, bn,
+                     broke, "BiCGStab", t0, s);
 }
 }  // namespace qiral

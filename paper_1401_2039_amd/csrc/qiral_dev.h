@@ -833,19 +833,19 @@ __device__ __forceinline__ int xcd_remap(int hw, int nblocks) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// Traversal order of the 64-site blocks of a hop.  With zb > 0 (a z-plane holds
-// a whole number of blocks and zb divides Lz) logical block L runs over
-// (z-tile of zb planes, t, z within the tile, block within the plane), so the
-// t-neighbours of a block were read zb planes earlier, not a whole t-slice
-// earlier, and are still in the L2 of the XCD that takes the range.  zb = 0 is
-// the plain lexicographic order.
+// Traversal order of the 64-site blocks of a hop.  With zb > 0 (a t-slice and a
+// chunk of zb z-planes are whole numbers of blocks, and zb divides Lz) logical
+// block L runs over (z-tile of zb planes, t, block within the chunk of the
+// tile's planes at that t), so the t-neighbours of a block were read one chunk
+// earlier, not a whole t-slice earlier, and are still in the L2 of the XCD that
+// takes the range.  zb = 0 is the plain lexicographic order.
 __host__ __device__ inline int block_order(const Geo &g, int L, int zb) {
   if (zb <= 0) return L;
-  const int B = g.sz / WAVE;   // blocks per z-plane
-  const int yb = L % B, L1 = L / B;
-  const int zi = L1 % zb, L2 = L1 / zb;
+  const int P = zb * g.sz / WAVE;    // blocks per chunk (zb planes of one t-slice)
+  const int Bt = g.st / WAVE;        // blocks per t-slice
+  const int j = L % P, L2 = L / P;
   const int t = L2 % g.lt, zt = L2 / g.lt;
-  return (t * g.lz + zt * zb + zi) * B + yb;
+  return t * Bt + zt * P + j;
 }
 
 }  // namespace qiral

@@ -38,6 +38,8 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qi
                         size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
 qiral_status run_fcg(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm, void *ws,
                      size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
+qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+                               void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
 size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm);
 }  // namespace qiral
 
@@ -82,6 +84,26 @@ SysSizes sys_sizes(const Geo &g, int prec, int nit) {
   // F64: BH T64, [BE|BO] full, [XE|XH] full
   z.bytes = nit * z.hb_it + z.hb_x + 2 * z.hb64 + 2 * (2 * z.hb64);
   return z;
+}
+
+// The forms run by the flexible (host-driven, one right-hand side at a time)
+// solvers: FGMRES, FCG, preconditioned or full-system BiCGStab, and CGNR on the
+// full system (FCG with no preconditioner takes CGNR's iterates there).
+bool is_flex(const qiral_solve_params *p) {
+  if (p->solver == QIRAL_FGMRES_NN || p->solver == QIRAL_FCG_NN) return true;
+  if (p->solver == QIRAL_BICGSTAB_EO) return p->precond || p->system == QIRAL_SYSTEM_FULL;
+  return p->solver == QIRAL_CGNR_EO && p->system == QIRAL_SYSTEM_FULL;
+}
+
+// The parameters the flexible solver runs with (CGNR on D as FCG without a preconditioner).
+qiral_solve_params flex_params(const qiral_solve_params *p) {
+  qiral_solve_params q = *p;
+  if (p->solver == QIRAL_CGNR_EO) {
+    q.solver = QIRAL_FCG_NN;
+    q.precond = nullptr;
+    q.system = QIRAL_SYSTEM_FULL;
+  }
+  return q;
 }
 
 int n_iterate_fields(const qiral_solve_params *prm) {
@@ -482,10 +504,16 @@ qiral_status check_params(const qiral_solve_params *p) {
   if (p->check_every < 0) return fail(QIRAL_ERR_INVALID_ARG, "check_every must be >= 0");
   if (p->solver == QIRAL_CRNR_EO && p->inner_prec != QIRAL_F64)
     return fail(QIRAL_ERR_UNSUPPORTED, "the conjugate residual solver runs in FP64 (inner_prec F64)");
-  if (p->solver == QIRAL_FGMRES_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FGMRES needs a precond network");
-  if (p->solver == QIRAL_FCG_NN && !p->precond) return fail(QIRAL_ERR_INVALID_ARG, "FCG needs a precond network");
-  if ((p->solver == QIRAL_FGMRES_NN || p->solver == QIRAL_FCG_NN) && p->inner_prec != QIRAL_F64)
-    return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES and FCG run in FP64 (inner_prec F64)");
+  if (p->system != QIRAL_SYSTEM_DEFAULT && p->system != QIRAL_SYSTEM_SCHUR && p->system != QIRAL_SYSTEM_FULL)
+    return fail(QIRAL_ERR_INVALID_ARG, "bad system");
+  if ((p->solver == QIRAL_CGNR_EO || p->solver == QIRAL_CRNR_EO) && p->precond)
+    return fail(QIRAL_ERR_UNSUPPORTED, "CGNR and CRNR take no preconditioner (FCG is the preconditioned CG on the "
+                                       "normal equations)");
+  if (p->solver == QIRAL_CRNR_EO && p->system == QIRAL_SYSTEM_FULL)
+    return fail(QIRAL_ERR_UNSUPPORTED, "the conjugate residual solver runs on the Schur system");
+  if (is_flex(p) && p->inner_prec != QIRAL_F64)
+    return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES, FCG and the preconditioned or full-system forms run in FP64 "
+                                       "(inner_prec F64)");
   if (p->solver == QIRAL_FGMRES_NN && p->restart > 64) return fail(QIRAL_ERR_INVALID_ARG, "restart must be <= 64");
   return QIRAL_OK;
 }
@@ -504,17 +532,18 @@ qiral_status run_solve_cg_fallback(qiral_lattice *lat, double *x, const double *
 
 namespace {
 
-bool is_flex(int solver) { return solver == QIRAL_FGMRES_NN || solver == QIRAL_FCG_NN; }
-
 // Workspace of a solve over these lattices (one system each; the right-hand
 // sides of qiral_solve are systems of one lattice).  FGMRES and FCG run one
 // right-hand side at a time in the same workspace and may continue with even-odd
 // CGNR (the fallback) in it.
 size_t ws_need(const std::vector<const qiral_lattice *> &lats, const qiral_solve_params *p) {
-  if (is_flex(p->solver)) {
+  if (is_flex(p)) {
     qiral_solve_params cg = *p;
     cg.solver = QIRAL_CGNR_EO;
-    return std::max(flex_ws_bytes(lats[0], p), solve_layout({lats[0]}, &cg).total);
+    cg.system = QIRAL_SYSTEM_DEFAULT;
+    cg.precond = nullptr;
+    const qiral_solve_params f = flex_params(p);
+    return std::max(flex_ws_bytes(lats[0], &f), solve_layout({lats[0]}, &cg).total);
   }
   return solve_layout(lats, p).total;
 }
@@ -558,12 +587,13 @@ qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon
                       const qiral_solve_params *params, void *ws, size_t ws_bytes, qiral_solve_info *info,
                       hipStream_t stream) {
   const size_t stride = (size_t)lat->geo.vh * 2 * 24;
-  if (is_flex(params->solver)) {
+  if (is_flex(params)) {
     // one right-hand side after the other
-    auto run = params->solver == QIRAL_FGMRES_NN ? run_fgmres : run_fcg;
+    const qiral_solve_params fp = flex_params(params);
+    auto run = fp.solver == QIRAL_FGMRES_NN ? run_fgmres : fp.solver == QIRAL_FCG_NN ? run_fcg : run_bicgstab_prec;
     qiral_status worst = QIRAL_OK;
     for (int r = 0; r < nrhs; ++r) {
-      qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, params, ws, ws_bytes, info + r, stream);
+      qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, &fp, ws, ws_bytes, info + r, stream);
       if (s != QIRAL_OK && s != QIRAL_ERR_NOT_CONVERGED) return s;
       if (s != QIRAL_OK) worst = s;
     }
@@ -578,14 +608,14 @@ qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon
 extern "C" size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params,
                                               int32_t nrhs) {
   if (!lat || nrhs < 1 || nrhs > QIRAL_MAX_SYSTEMS || check_params(params) != QIRAL_OK) return 0;
-  if (is_flex(params->solver)) return ws_need({lat}, params);
+  if (is_flex(params)) return ws_need({lat}, params);
   return ws_need(std::vector<const qiral_lattice *>(nrhs, lat), params);
 }
 
 extern "C" size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *lats, int32_t nsys,
                                                     const qiral_solve_params *params) {
   if (!lats || nsys < 1 || nsys > QIRAL_MAX_SYSTEMS || check_params(params) != QIRAL_OK) return 0;
-  if (is_flex(params->solver)) return 0;
+  if (is_flex(params)) return 0;
   std::vector<const qiral_lattice *> l(nsys);
   for (int i = 0; i < nsys; ++i) {
     if (!lats[i]) return 0;
@@ -615,8 +645,9 @@ extern "C" qiral_status qiral_solve_batch(qiral_lattice *const *lats, double *co
   if (!info) return fail(QIRAL_ERR_INVALID_ARG, "info is NULL");
   qiral_status st = check_params(params);
   if (st != QIRAL_OK) return st;
-  if (is_flex(params->solver))
-    return fail(QIRAL_ERR_UNSUPPORTED, "the learned-preconditioner solvers take one lattice (qiral_solve)");
+  if (is_flex(params))
+    return fail(QIRAL_ERR_UNSUPPORTED, "FGMRES, FCG and the preconditioned or full-system forms take one lattice "
+                                       "(qiral_solve)");
   if ((st = check_ws_ptr(ws)) != QIRAL_OK) return st;
   std::vector<SysIn> sys(nsys);
   for (int i = 0; i < nsys; ++i) {

@@ -128,11 +128,19 @@ def test_solve_params_validation():
     assert solve(solver=9) == L.ERR_INVALID_ARG
     assert solve(inner_prec=7) == L.ERR_INVALID_ARG
     assert solve(inner_prec=L.F32, delta=1.5) == L.ERR_INVALID_ARG
-    assert solve(solver=L.FGMRES_NN) == L.ERR_INVALID_ARG            # no network
     assert solve(solver=L.CRNR_EO, inner_prec=L.F32) == L.ERR_UNSUPPORTED
     assert b"conjugate residual" in lib.qiral_last_error()
-    assert solve(solver=L.FCG_NN) == L.ERR_INVALID_ARG                # no network
     assert solve(solver=L.FCG_NN, precond=1, inner_prec=L.F32) == L.ERR_UNSUPPORTED
+    # compositions: the system must be known; CGNR / CRNR take no preconditioner;
+    # CRNR runs on the Schur system; the flexible forms run in FP64
+    assert solve(system=3) == L.ERR_INVALID_ARG
+    assert solve(precond=1) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.CRNR_EO, precond=1) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.CRNR_EO, system=L.SYSTEM_FULL) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.BICGSTAB_EO, precond=1, inner_prec=L.F32) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.BICGSTAB_EO, system=L.SYSTEM_FULL, inner_prec=L.F16S) == L.ERR_UNSUPPORTED
+    assert solve(system=L.SYSTEM_FULL, inner_prec=L.F32) == L.ERR_UNSUPPORTED
+    assert solve(solver=L.FGMRES_NN, system=L.SYSTEM_SCHUR, inner_prec=L.F32) == L.ERR_UNSUPPORTED
     assert solve(solver=L.FGMRES_NN, precond=1, inner_prec=L.F16S) == L.ERR_UNSUPPORTED
     assert solve(solver=L.FGMRES_NN, precond=1, restart=65) == L.ERR_INVALID_ARG
     # an invalid parameter set has no workspace size
@@ -159,13 +167,14 @@ def test_workspace_pointer_checked_before_the_handle():
 
 
 def test_batch_rejects_learned_solvers():
-    """FGMRES and FCG take one lattice: the batch entry refuses them before it
-    reads the lattice table."""
+    """FGMRES, FCG and the preconditioned or full-system forms take one lattice:
+    the batch entry refuses them before it reads the lattice table."""
     lib = L.load()
     info = (L.SolveInfo * 1)()
     arr = (ctypes.c_void_p * 1)(1)
-    for solver in (L.FGMRES_NN, L.FCG_NN):
-        p = api.solve_params(solver=solver, precond=1)
+    for kw in (dict(solver=L.FGMRES_NN, precond=1), dict(solver=L.FCG_NN), dict(solver=L.BICGSTAB_EO, precond=1),
+               dict(solver=L.CGNR_EO, system=L.SYSTEM_FULL)):
+        p = api.solve_params(**kw)
         assert lib.qiral_solve_batch(arr, arr, arr, 1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 20, info,
                                      None) == L.ERR_UNSUPPORTED
         assert b"one lattice" in lib.qiral_last_error()

@@ -232,27 +232,31 @@ def test_f16s_tiny_scales():
 
 
 @pytest.mark.parametrize("prec", [q.F64, q.F32, q.F16S], ids=["f64", "f32", "f16s"])
-def test_block_order_bitwise(prec, monkeypatch):
-    """The z-tiled block order (tiles of 2 and 4 planes) visits every block once:
-    hop outputs equal those of the plain order bit for bit, for one and for three
-    right-hand sides (a last group with fewer), forward and dagger."""
-    dims = (8, 16, 8, 8)   # a z-plane is exactly one 64-site block
-    say("block order", prec)
+@pytest.mark.parametrize("dims,orders", [((8, 16, 8, 8), ("2", "4")), ((12, 4, 16, 4), ("8",))],
+                         ids=["planes", "chunks"])
+def test_block_order_bitwise(prec, monkeypatch, dims, orders):
+    """The z-tiled block order visits every block once: hop outputs equal those
+    of the plain order bit for bit, for one and for three right-hand sides (a
+    last group with fewer; traversal tiles of 5 blocks), forward and dagger.
+    8x16x8x8: a z-plane is one 64-site block (tiles of 2 and 4 planes);
+    12x4x16x4: a plane is 24 sites, so chunks of 8 planes (3 blocks)."""
+    say("block order", prec, dims)
     cfg = latgen.small_config(dims, seed=53, kind="expih", eps=0.4, nrhs=3)
     lat = q.Lattice(dims, 0.12, cfg["U"])
     src = lat.import_field(dev(cfg["b"]), q.ODD, prec)
+    monkeypatch.setenv("QIRAL_HOP_TILE", "5")
     for nrhs in (1, 3):
         for dag in (0, 1):
             outs = []
-            for order in ("0", "2", "4"):
+            for order in ("0",) + tuple(orders):
                 monkeypatch.setenv("QIRAL_HOP_ORDER", order)
                 out = lat.field(q.EVEN, prec, nrhs=nrhs)
                 out.fill_(0xFF)   # NaN patterns where a block were skipped
                 lat.dslash_eo(out, src[: out.numel()], 0, dag, prec, nrhs=nrhs)
                 outs.append(out)
-            assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2]), (nrhs, dag)
-    # and the plain order is the oracle's result
-    monkeypatch.setenv("QIRAL_HOP_ORDER", "2")
+            assert all(torch.equal(outs[0], o) for o in outs[1:]), (nrhs, dag)
+    # and the z-tiled order is the oracle's result
+    monkeypatch.setenv("QIRAL_HOP_ORDER", orders[0])
     out = lat.field(q.EVEN, q.F64, nrhs=1)
     lat.dslash_eo(out, lat.import_field(dev(cfg["b"][:1]), q.ODD, q.F64), 0, 0, q.F64)
     got = host(lat.export_field(out, 0, q.F64))[0]

@@ -196,16 +196,18 @@ def test_batched_point_sources_split2(nr, monkeypatch):
             assert S.true_rel_residual(U, 0.12, 0.0, xs[r], b[r]) <= 1e-10
 
 
-def test_block_order_solve_bitwise(monkeypatch):
+@pytest.mark.parametrize("dims,order", [((8, 16, 8, 8), "2"), ((12, 4, 16, 4), "8")], ids=["planes", "chunks"])
+def test_block_order_solve_bitwise(monkeypatch, dims, order):
     """Solves whose hops run in the z-tiled block order equal those in the plain
-    order bit for bit (partials are indexed by block, not by visit order)."""
-    dims = (8, 16, 8, 8)
-    say("block order solve")
+    order bit for bit (partials are indexed by block, not by visit order); also
+    where a z-plane is not a whole number of blocks (12x4x16x4: a plane is 24
+    sites, 8 planes make a chunk of 3 blocks)."""
+    say("block order solve", dims)
     cfg = latgen.small_config(dims, seed=54, kind="expih", eps=0.3, nrhs=3)
     lat = q.Lattice(dims, 0.12, cfg["U"])
     for prec, nrhs in ((q.F64, 1), (q.F32, 1), (q.F32, 3), (q.F16S, 3)):
         res = []
-        for order in ("0", "2"):
+        for order in ("0", order):
             monkeypatch.setenv("QIRAL_HOP_ORDER", order)
             x, st, info = lat.solve(dev(cfg["b"][:nrhs]), tol=1e-10, inner_prec=prec)
             assert st == 0, info
