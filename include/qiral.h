@@ -190,9 +190,11 @@ qiral_status qiral_apply_M(const qiral_lattice *lat, void *out, const void *in, 
 
 /* Autotune the hop's launch shape for this lattice, precision and number of
  * right-hand sides (waves per 64-site block 1 (F16S only), 2 or 4 (FP64: 4 only);
- * right-hand sides per lane 1..4, FP64 1..2, FP32 on 2 waves 1..2, 1 wave 1) by
- * timing each candidate on the stream; later hops and solves on this handle use
- * the fastest.  in and out are two distinct packed half-fields of precision prec
+ * right-hand sides per lane 1..4, FP64 1..2, FP32 on 2 waves 1..2, 1 wave 1; and,
+ * when that leaves several groups of right-hand sides, the traversal tile of
+ * 8, 16, 32 or 64 blocks that each group sweeps before the next one re-reads its
+ * links) by timing each candidate on the stream; later hops and solves on this
+ * handle use the fastest.  in and out are two distinct packed half-fields of precision prec
  * and nrhs fields (qiral_field_bytes(dims, QIRAL_EVEN, prec, nrhs) bytes each)
  * owned by the caller; in is zeroed, out overwritten.  If the environment
  * variable QIRAL_TUNE_CACHE names a file, the result is looked up there first
@@ -217,7 +219,9 @@ typedef struct {
   int32_t fallback_cg; /* FGMRES, FCG: on stagnation or breakdown continue with eo-CGNR from
                           the current x                                                    */
   int32_t x0_is_guess; /* start from the x passed in instead of 0                              */
-  int32_t use_graph;   /* capture the iteration in a HIP graph and replay it                   */
+  int32_t use_graph;   /* capture one iteration of the grouped solver in a HIP graph (once per
+                          solve) and replay it for every iteration; needs a stream other
+                          than the default one (ignored there)                              */
   int32_t check_every; /* iterations enqueued between convergence checks (0: automatic)        */
   int32_t system;      /* qiral_system: the system the solver runs on (0: the solver's own)     */
 } qiral_solve_params;

@@ -27,6 +27,7 @@ struct qiral_lattice {
   int device = 0;
   int tuned_nr[3][5] = {};   // autotuned right-hand sides per lane [prec][min(nrhs,4)], 0 = not tuned
   int tuned_t[3][5] = {};    // autotuned waves per site block, same index, 0 = not tuned
+  int tuned_tile[3][5] = {}; // autotuned traversal tile of multi-group hops (blocks), 0 = default
 };
 
 namespace qiral {
@@ -49,7 +50,7 @@ const void *links_for(const qiral_lattice *lat, int prec);
 // (enough waves to give every SIMD, 256 CUs x 4, a few); tuned_nr gives the
 // autotuned nr of a lattice (a heuristic until tuned).  QIRAL_HOP_SPLIT and
 // QIRAL_HOP_NR override.
-struct HopCfg { int t = 4, nr = 1; };
+struct HopCfg { int t = 4, nr = 1, tile = 0; };   // tile 0: hop_tile's default
 // Largest number of right-hand sides per lane that a hop of storage precision
 // S with T waves per site block keeps in registers; 0: the split is not built
 // (FP64 needs T = 4 and spills at 3 RHS; one wave per block fits only the F16S
@@ -59,14 +60,17 @@ constexpr int hop_nr_max(int S, int T) {
 }
 int hop_split(int prec, long nwork);
 // Streaming (non-temporal) link loads and output stores for hops whose working
-// set exceeds half the last-level cache.  QIRAL_HOP_NT=0|1 overrides.
-bool hop_stream(const Geo &g, int prec, long nrhs);
+// set exceeds half the last-level cache and whose links are read by one group
+// of right-hand sides (several groups re-read each tile's links from the cache).
+// QIRAL_HOP_NT=0|1 overrides.
+bool hop_stream(const Geo &g, int prec, long nrhs, long ngroups);
 // Planes per z-tile of the hop's block order (block_order), 0 for the plain
 // order.  QIRAL_HOP_ORDER=0 forces the plain order, QIRAL_HOP_ORDER=n tiles of
 // n planes where the lattice allows them.
 int hop_zb(const Geo &g, int prec);
-// Blocks per traversal tile of a multi-group hop (see k_hop).
-int hop_tile(const Geo &g, int ngroups);
+// Blocks per traversal tile of a multi-group hop (see k_hop); tuned > 0 is an
+// autotuned size.
+int hop_tile(const Geo &g, int ngroups, int tuned = 0);
 int tuned_nr(const qiral_lattice *lat, int prec, int nrhs);
 HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs);
 hipError_t launch_hop_cfg(const HopCfg &c, const qiral_lattice *lat, int prec, int dagger, int out_parity, int epi,

@@ -205,7 +205,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     // tile's blocks in turn
     const Geo &g = sys[0].lat->geo;
     const int nb = g.nb;
-    const int tile = hop_tile(g, nsys);
+    const int tile = hop_tile(g, (nsys + hc.nr - 1) / hc.nr, hc.tile);
     const int zb = hop_zb(g, prec), zb64 = hop_zb(g, QIRAL_F64);
     for (int b0 = 0; b0 < nb; b0 += tile) {
       const int b1 = std::min(nb, b0 + tile);
@@ -258,8 +258,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   L.prec = prec;
   L.T = hc.t;
   L.NR = hc.nr;
-  L.NT = hop_stream(sys[0].lat->geo, prec, same_lattice ? nsys : 1);
-  L.NT64 = hop_stream(sys[0].lat->geo, QIRAL_F64, 1);
+  L.NT = hop_stream(sys[0].lat->geo, prec, same_lattice ? nsys : 1, same_lattice ? (nsys + hc.nr - 1) / hc.nr : 1);
+  L.NT64 = hop_stream(sys[0].lat->geo, QIRAL_F64, 1, 1);
   L.stream = s;
 
   // ---- inputs
@@ -360,17 +360,21 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
   hipEvent_t *ev = owner->poll_ev;
   auto enqueue_chunk = [&](int n) -> qiral_status {
     if (use_graph) {
+      // one iteration captured once, replayed n times: the same launches as
+      // without the graph, enqueued by one call per iteration
       if (!gexec) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        for (int k = 0; k < chunk; ++k) iteration();
+        iteration();
         e = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipStreamEndCapture"); }
         e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphInstantiate"); }
       }
-      hipError_t e = hipGraphLaunch(gexec, s);
-      if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
+      for (int k = 0; k < n; ++k) {
+        hipError_t e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) { free_graph(); return hip_fail(e, "hipGraphLaunch"); }
+      }
     } else {
       for (int k = 0; k < n; ++k) iteration();
       hipError_t e = hipGetLastError();
@@ -397,13 +401,13 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     if ((st = enqueue_chunk(chunk)) != QIRAL_OK) return st;
     if ((st = post_copy(cur)) != QIRAL_OK) { free_graph(); return st; }
     long enqueued = chunk;
-    // With the automatic chunk and no graph, the chunk after the queued one is
+    // With the automatic chunk, the chunk after the queued one is
     // shortened when every running system is expected to stop within the
     // queued one: the CG-type residual norms fall about geometrically, so the
     // rate over the last checks predicts the iterations left.  This only
     // decides how many iterations the host queues ahead; the device decides
     // convergence, so the iterates do not change.
-    const bool adaptive = !use_graph && prm->check_every <= 0 && (!bicg);
+    const bool adaptive = prm->check_every <= 0 && (!bicg);
     std::vector<double> prev_nr(nsys, -1.0);
     std::vector<int> prev_it(nsys, -1);
     int next = chunk;

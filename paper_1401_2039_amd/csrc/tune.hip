@@ -1,5 +1,7 @@
 // Autotuner of the hop's launch shape: waves per 64-site block (1 (F16S), 2 or
-// 4) and right-hand sides per lane (1..4), timed with HIP events on the caller's stream for one
+// 4), right-hand sides per lane (1..4) and, when that leaves several groups of
+// right-hand sides, the traversal tile (8..64 blocks), timed with HIP events on
+// the caller's stream for one
 // lattice, precision and right-hand-side count.  Results live in the lattice
 // handle and, if QIRAL_TUNE_CACHE names a file, in a JSON cache keyed by
 // (architecture, precision, dims, nrhs) that later handles read.  The caller
@@ -22,13 +24,13 @@ namespace {
 
 std::string cache_key(const qiral_lattice *lat, int prec, int nrhs) {
   std::ostringstream k;
-  k << "gfx950/p" << prec << "/" << lat->dims[0] << "x" << lat->dims[1] << "x" << lat->dims[2] << "x" << lat->dims[3]
+  k << "gfx950/shape3/p" << prec << "/" << lat->dims[0] << "x" << lat->dims[1] << "x" << lat->dims[2] << "x" << lat->dims[3]
     << "/n" << nrhs;
   return k.str();
 }
 
-// The cache is a flat JSON object {"key": [t, nr, us], ...}, one entry per line.
-bool cache_lookup(const std::string &key, int &t, int &nr) {
+// The cache is a flat JSON object {"key": [t, nr, tile, us], ...}, one entry per line.
+bool cache_lookup(const std::string &key, int &t, int &nr, int &tile) {
   const char *path = getenv("QIRAL_TUNE_CACHE");
   if (!path) return false;
   std::ifstream f(path);
@@ -37,17 +39,19 @@ bool cache_lookup(const std::string &key, int &t, int &nr) {
   while (std::getline(f, line)) {
     const size_t i = line.find(pat);
     if (i == std::string::npos) continue;
-    int a = 0, b = 0;
-    if (sscanf(line.c_str() + i + pat.size(), "%d, %d", &a, &b) == 2 && (a == 1 || a == 2 || a == 4) && b >= 1 && b <= 4) {
+    int a = 0, b = 0, c = 0;
+    if (sscanf(line.c_str() + i + pat.size(), "%d, %d, %d", &a, &b, &c) == 3 && (a == 1 || a == 2 || a == 4) &&
+        b >= 1 && b <= 4 && c >= 0) {
       t = a;
       nr = b;
+      tile = c;
       return true;
     }
   }
   return false;
 }
 
-void cache_store(const std::string &key, int t, int nr, double us) {
+void cache_store(const std::string &key, int t, int nr, int tile, double us) {
   const char *path = getenv("QIRAL_TUNE_CACHE");
   if (!path) return;
   std::vector<std::string> lines;
@@ -62,7 +66,7 @@ void cache_store(const std::string &key, int t, int nr, double us) {
     }
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %.3f]", key.c_str(), t, nr, us);
+  snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %.3f]", key.c_str(), t, nr, tile, us);
   lines.push_back(buf);
   std::ofstream o(path);
   o << "{\n";
@@ -90,11 +94,12 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
   if (!links_for(lat, prec)) { set_error("the lattice holds no links of this precision"); return QIRAL_ERR_INVALID_ARG; }
   const int idx = nrhs < 4 ? nrhs : 4;
   const std::string key = cache_key(lat, prec, nrhs);
-  int t = 0, nr = 0;
+  int t = 0, nr = 0, tile = 0;
   double us = 0.0;
-  if (cache_lookup(key, t, nr) && (t == 1 || t == 2 || t == 4) && nr >= 1 && nr <= hop_nr_max(prec, t)) {
+  if (cache_lookup(key, t, nr, tile) && (t == 1 || t == 2 || t == 4) && nr >= 1 && nr <= hop_nr_max(prec, t)) {
     lat->tuned_t[prec][idx] = t;
     lat->tuned_nr[prec][idx] = nr;
+    lat->tuned_tile[prec][idx] = tile;
   } else {
     hipStream_t s = (hipStream_t)stream;
     const size_t fb = half_bytes(lat->geo, prec) * (size_t)nrhs;
@@ -105,28 +110,36 @@ extern "C" qiral_status qiral_tune(qiral_lattice *lat, qiral_prec prec, int32_t 
     double best = 1e30;
     const int nrmax = 4;   // further limited per shape by hop_nr_max
     for (int tt : {1, 2, 4}) {
-      for (int n = 1; n <= std::min(std::min(nrmax, hop_nr_max(prec, tt)), (int)nrhs); ++n) {
-        HopCfg c;
-        c.t = tt;
-        c.nr = n;
-        const int reps = 10;
-        for (int w = 0; w < 2; ++w) (void)launch_hop_cfg(c, lat, prec, 0, 0, 0, 1.0, in, out, nullptr, nrhs, s);
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps; ++r) (void)launch_hop_cfg(c, lat, prec, 0, 0, 0, 1.0, in, out, nullptr, nrhs, s);
-        (void)hipEventRecord(e1, s);
-        e = hipEventSynchronize(e1);
-        if (e != hipSuccess) break;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double u = 1e3 * ms / reps;
-        if (u < best) { best = u; t = tt; nr = n; }
+      for (int n = 1; n <= std::min(std::min(nrmax, hop_nr_max(prec, tt)), (int)nrhs) && e == hipSuccess; ++n) {
+        // several groups of right-hand sides: also the traversal tile (blocks
+        // each group sweeps before the next re-reads the tile's links)
+        const bool groups = (nrhs + n - 1) / n > 1;
+        for (int tl : {8, 16, 32, 64}) {
+          if (!groups && tl != 8) break;
+          HopCfg c;
+          c.t = tt;
+          c.nr = n;
+          c.tile = groups ? tl : 0;
+          const int reps = 10;
+          for (int w = 0; w < 2; ++w) (void)launch_hop_cfg(c, lat, prec, 0, 0, 0, 1.0, in, out, nullptr, nrhs, s);
+          (void)hipEventRecord(e0, s);
+          for (int r = 0; r < reps; ++r) (void)launch_hop_cfg(c, lat, prec, 0, 0, 0, 1.0, in, out, nullptr, nrhs, s);
+          (void)hipEventRecord(e1, s);
+          e = hipEventSynchronize(e1);
+          if (e != hipSuccess) break;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double u = 1e3 * ms / reps;
+          if (u < best) { best = u; t = tt; nr = n; tile = c.tile; }
+        }
       }
     }
     if (e != hipSuccess) return hip_fail(e, "tuning launch");
     lat->tuned_t[prec][idx] = t;
     lat->tuned_nr[prec][idx] = nr;
+    lat->tuned_tile[prec][idx] = tile;
     us = best;
-    cache_store(key, t, nr, us);
+    cache_store(key, t, nr, tile, us);
   }
   if (best_t) *best_t = t;
   if (best_nr) *best_nr = nr;

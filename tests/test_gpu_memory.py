@@ -10,7 +10,8 @@ stores it exposes.
   offset inside a larger buffer, gives the same solution as a fresh one.
 * The automatic convergence-check interval changes only how many iterations
   the host queues ahead: x and the iteration counts equal those of a fixed
-  interval of 4, for FP64, FP32 mixed and a batch of right-hand sides."""
+  interval of 4, for FP64, FP32 mixed and a batch of right-hand sides; so does
+  replaying the iteration from a HIP graph (twice, with eager solves between)."""
 import ctypes
 
 import numpy as np
@@ -148,8 +149,20 @@ def test_adaptive_check_interval_same_iterates(kw, nrhs):
     xa, sa, ia = lat.solve(b, tol=1e-10, check_every=0, **kw)
     xa = xa.clone()
     xf, sf, i_f = lat.solve(b, tol=1e-10, check_every=4, **kw)
+    xf = xf.clone()
     assert sa == 0 and sf == 0
     assert torch.equal(xa, xf)
     assert [i["iterations"] for i in ia] == [i["iterations"] for i in i_f]
     assert [i["reliable_updates"] for i in ia] == [i["reliable_updates"] for i in i_f]
+    # the iteration captured in a HIP graph and replayed (a side stream: the
+    # default stream is not captured), twice in a row with eager solves between
+    stream = torch.cuda.Stream()
+    for _ in range(2):
+        with torch.cuda.stream(stream):
+            xg, sg, ig = lat.solve(b, tol=1e-10, use_graph=1, **kw)
+        stream.synchronize()
+        assert sg == 0 and torch.equal(xa, xg)
+        assert [i["iterations"] for i in ia] == [i["iterations"] for i in ig]
+        xe, se, _ = lat.solve(b, tol=1e-10, **kw)
+        assert se == 0 and torch.equal(xa, xe)
     lat.close()
