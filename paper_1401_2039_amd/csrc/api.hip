@@ -266,31 +266,31 @@ bool hop_stream(const Geo &g, int prec, long nrhs, long ngroups) {
   return bytes > 128e6;   // half the 256 MB last-level cache
 }
 
-// Planes per chunk of the z-tiled block order must make whole blocks.
-static int zb_quantum(const Geo &g) {
-  int q = 1;
-  while ((long)q * g.sz % WAVE != 0) ++q;   // at most 64
-  return q;
-}
-
 bool zb_valid(const Geo &g, int zb) {
   return zb > 0 && zb < g.lz && g.lz % zb == 0 && (long)zb * g.sz % WAVE == 0 && g.st % WAVE == 0;
 }
 
-int hop_zb(const Geo &g, int prec) {
+int hop_zb(const Geo &g) {
   if (g.st % WAVE != 0 || (long)g.nb * WAVE != g.vh) return 0;
   if (const char *e = getenv("QIRAL_HOP_ORDER")) {   // 0: plain order; n > 0: tiles of n planes
     const int n = atoi(e);
     return zb_valid(g, n) ? n : 0;
   }
-  // keep zb planes of input spinors (the reuse distance of a t-neighbour) to
-  // about 0.5 MB per XCD
-  const long site_b = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
-  const int q = zb_quantum(g);
-  int zb = 0;
-  for (int z = q; z <= g.lz; z += q)
-    if (g.lz % z == 0 && (long)z * g.sz * site_b <= (512l << 10)) zb = z;
-  return zb_valid(g, zb) ? zb : 0;   // a tile of every plane is the plain order
+  // A lattice whose FP64 hop (1536 B per site) fits the 256 MB last-level
+  // cache keeps the plain order: its hops run from that cache, and tiling them
+  // cost up to 10% (FP32 at 16^3x32).
+  if ((double)g.vh * 1536.0 <= 256e6) return 0;
+  // As many z-tiles as XCDs (else half or a quarter as many), so that the
+  // contiguous range of blocks each XCD takes (xcd_remap) is one whole tile or
+  // a whole part of one: a tile's z-neighbour planes are then read twice only
+  // where two XCDs meet, and a block's t-neighbours were read one chunk earlier
+  // on the same XCD.  Measured on the 1-RHS hops at 64^3x128, tiles of Lz/8
+  // planes ran 21% (FP64), 15% (FP32) and 8% (F16S) faster than tiles of about
+  // 0.5 MB of input spinors (1, 2 and 4 planes); at 32^3x64 and 24^3x48 the
+  // best tiles were Lz/8 and Lz/4 planes as well.
+  for (int ntz : {NXCD, NXCD / 2, NXCD / 4})
+    if (g.lz % ntz == 0 && zb_valid(g, g.lz / ntz)) return g.lz / ntz;
+  return 0;   // the plain order
 }
 
 int hop_tile(const Geo &g, int ngroups, int tuned) {
@@ -330,7 +330,7 @@ static hipError_t launch_hop_ttt(const HopCfg &c, const qiral_lattice *lat, int 
   const size_t fstride = half_bytes(g, S);
   const void *gauge = links_for(lat, S);
   const int tile = hop_tile(g, (nrhs + NR - 1) / NR, c.tile);
-  const int zb = hop_zb(g, S);
+  const int zb = hop_zb(g);
   const long ntile = (g.nb + tile - 1) / tile;
   const long nitems = ntile * tile * ((nrhs + NR - 1) / NR);
   const int nwg = (int)((nitems * T + 3) / 4);

@@ -824,6 +824,7 @@ template <class R> __device__ __forceinline__ void dot12(const cpx<R> a[12], con
 // XCD-aware block order: the hardware hands consecutive work-group ids to the 8
 // XCDs in turn; this remap gives each XCD one contiguous range of logical
 // blocks, so neighbouring sites share an L2.
+constexpr int NXCD = 8;
 __device__ __forceinline__ int xcd_remap(int hw, int nblocks) {
 #ifdef QIRAL_NO_XCD_REMAP
   return hw;

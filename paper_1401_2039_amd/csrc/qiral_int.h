@@ -67,7 +67,7 @@ bool hop_stream(const Geo &g, int prec, long nrhs, long ngroups);
 // Planes per z-tile of the hop's block order (block_order), 0 for the plain
 // order.  QIRAL_HOP_ORDER=0 forces the plain order, QIRAL_HOP_ORDER=n tiles of
 // n planes where the lattice allows them.
-int hop_zb(const Geo &g, int prec);
+int hop_zb(const Geo &g);
 // Blocks per traversal tile of a multi-group hop (see k_hop); tuned > 0 is an
 // autotuned size.
 int hop_tile(const Geo &g, int ngroups, int tuned = 0);

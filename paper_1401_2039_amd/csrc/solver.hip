@@ -32,6 +32,7 @@
 #include "solver_kernels.h"
 
 namespace qiral {
+
 void import_field(const Geo &g, const double *src, void *dst, int subset, int prec, int nrhs, hipStream_t s);
 void export_field(const Geo &g, double *dst, const void *src, int subset, int prec, int nrhs, hipStream_t s);
 qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm, void *ws,
@@ -206,30 +207,22 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     const Geo &g = sys[0].lat->geo;
     const int nb = g.nb;
     const int tile = hop_tile(g, (nsys + hc.nr - 1) / hc.nr, hc.tile);
-    const int zb = hop_zb(g, prec), zb64 = hop_zb(g, QIRAL_F64);
+    const int zb = hop_zb(g);
     for (int b0 = 0; b0 < nb; b0 += tile) {
       const int b1 = std::min(nb, b0 + tile);
       for (int i = 0; i < nsys; ++i)
-        for (int b = b0; b < b1; ++b) work.push_back(work_item(i, 1, block_order(g, b, zb64)));
+        for (int b = b0; b < b1; ++b) work.push_back(work_item(i, 1, block_order(g, b, zb)));
       for (int i = 0; i < nsys; i += hc.nr)
         for (int b = b0; b < b1; ++b) work_hop.push_back(work_item(i, std::min(hc.nr, nsys - i), block_order(g, b, zb)));
     }
   } else {
-    // plain table: the block order of the FP64 hops; grouped: of the iterate's
+    // one item per (system, block), in each system's hop block order
     for (int i = 0; i < nsys; ++i) {
       const Geo &g = sys[i].lat->geo;
-      const int zb = hop_zb(g, QIRAL_F64);
+      const int zb = hop_zb(g);
       for (int b = 0; b < g.nb; ++b) work.push_back(work_item(i, 1, block_order(g, b, zb)));
     }
-    if (prec == QIRAL_F64) {
-      work_hop = work;
-    } else {
-      for (int i = 0; i < nsys; ++i) {
-        const Geo &g = sys[i].lat->geo;
-        const int zb = hop_zb(g, prec);
-        for (int b = 0; b < g.nb; ++b) work_hop.push_back(work_item(i, 1, block_order(g, b, zb)));
-      }
-    }
+    work_hop = work;
   }
   std::vector<SysState> hst(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -305,7 +298,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     } else if (!bicg) {
       hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
       hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_NZ_INIT, CHI_ONE, CHI_ADAG);
-      cg2(L, prec);   // p = z (beta = 0, p = 0)
+      cg2(L, prec, false);   // p = z (beta = 0)
     } else {
       copy_field(L, prec, F_R, F_RT, ST_RUN);
       bi_init(L, nsys);
@@ -323,7 +316,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
       if (mixed) { hop_sum(L, true); hop_upd(L, prec, false); }
       hop_sys(L, prec, true, 0, F_R, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINVDAG);
       hop_sys(L, prec, true, 1, F_TMP, F_Z, F_R, 1, A_MKAPPA2, ST_RUN, 1, SL_Z, FIN_BETA, CHI_ONE, CHI_ADAG);
-      cg2(L, prec);
+      cg2(L, prec, !mixed);   // a plain solve's x += alpha p comes here
     } else {
       bi_p(L, prec);
       hop_sys(L, prec, false, 0, F_P, F_TMP, 0, 0, A_ONE, ST_RUN, 0, 0, FIN_NONE, CHI_AINV);
@@ -442,6 +435,8 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
       }
       cur = 1 - cur;
     }
+    // a plain CGNR solve that stopped after k_cg1 still owes its last x += alpha p
+    if (!mixed && !bicg && !cr) cg_xfin(L);
     // reconstruct x_e, export, FP64 true residual
     hop_sys(L, S_F64, false, 1, F_XH, F_XE, F_BE, 0, A_KAPPA, ST_ANY, 0, 0, FIN_NONE, CHI_AINV);   // x_e
     hop_res(L, 0);
@@ -459,6 +454,7 @@ qiral_status run_solve(qiral_lattice *owner, const std::vector<SysIn> &sys, cons
     if (!again || restarts >= 2) break;
     ++restarts;
     for (int i = 0; i < nsys; ++i) {
+      hst[i].xpend = 0;   // k_cg_xfin has applied it
       if (!hst[i].nonfinite && true_rel[i] > prm->tol && hst[i].iter < prm->maxiter) {
         hst[i].status = ST_UPDATE;
         hst[i].final_update = 0;

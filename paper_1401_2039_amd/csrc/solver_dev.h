@@ -47,6 +47,7 @@ struct SysState {
   double rho_re, rho_im, rho0_re, rho0_im, al_re, al_im, om_re, om_im, be_re, be_im;
   double res[NSLOT][NV];
   int status, iter, maxiter, nupdates, nonfinite, mixed, final_update, solver;
+  int xpend;   // plain CGNR stopped after k_cg1: its last x += alpha p is still to be applied
   long long hops;
 };
 
@@ -94,7 +95,10 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
       if (!cfinite(nr)) { st->nonfinite = 1; st->status = ST_DONE; break; }
       const bool out_of_iters = st->iter >= st->maxiter;
       if (!st->mixed) {
-        if (nr <= st->thr2 || out_of_iters) st->status = ST_DONE;
+        if (nr <= st->thr2 || out_of_iters) {
+          st->status = ST_DONE;
+          if (st->solver == SOLVER_CG) st->xpend = 1;
+        }
       } else {
         if (nr > st->max_nr) st->max_nr = nr;
         if (nr <= st->thr2 || nr < st->delta2 * st->max_nr || out_of_iters) {
@@ -118,6 +122,7 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
       st->nr = nr;
       st->max_nr = nr;
       st->nupdates += 1;
+      st->xpend = 0;
       st->hops += 2;
       if (st->solver == SOLVER_BICG && st->iter > 0) {
         // keep the recurrence consistent with the replaced residual
@@ -209,6 +214,49 @@ __device__ inline void finalize(SysState *st, int fin, int slot, const double t[
     }
     default: break;
   }
+}
+
+// The fixed summation order of a reduction over the nb block partials of a
+// row: RED_WG threads; thread tid adds the pairs tid + RED_WG j (j = 0..3) +
+// 4 RED_WG k into four accumulators and combines them as (a0 + a1) + (a2 + a3),
+// thread 0 also adds an odd last partial; each wave adds its threads with
+// wave_sum, and the wave totals are added in wave order (k_reduce).
+constexpr int RED_WG = 1024;
+
+// Thread tid's share of N rows (`stride` doubles apart, 32-byte aligned).  The
+// loads of a step (4 pairs of every row) are independent, so the compiler can
+// issue them together: the partials were just written by other compute units,
+// and each round trip costs a full memory latency.
+template <int N>
+__device__ __forceinline__ void red_part(const double *p, size_t stride, int nb, int tid, double s[N]) {
+  const int npair = nb >> 1;
+  double a[N][4];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[i][j] = 0.0;
+  for (int k0 = tid; k0 < npair; k0 += 4 * RED_WG) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + j * RED_WG;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const double2 x = k < npair ? ((const double2 *)(p + (size_t)i * stride))[k] : make_double2(0.0, 0.0);
+        a[i][j] += x.x + x.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    s[i] = (a[i][0] + a[i][1]) + (a[i][2] + a[i][3]);
+    if (tid == 0 && (nb & 1)) s[i] += p[(size_t)i * stride + nb - 1];
+  }
+}
+
+// Row i of reduction slot `slot` of a system's partials.
+__device__ __forceinline__ const double *part_row(const SysDesc &d, int slot, int i) {
+  const size_t stride = (size_t)d.g.nb * 4;
+  return d.part + ((size_t)slot * NV + i) * stride;
 }
 
 // Per-wave context of a table-driven kernel.  A work item is one 64-site block

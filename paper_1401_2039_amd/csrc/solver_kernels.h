@@ -34,7 +34,8 @@ void hop_upd(const Launch &l, int prec, bool bicg);
 void hop_res(const Launch &l, int par);
 void bnorm(const Launch &l);
 void cg1(const Launch &l, int prec);
-void cg2(const Launch &l, int prec);
+void cg2(const Launch &l, int prec, bool xupd);
+void cg_xfin(const Launch &l);
 // Conjugate residual on S^dagger S (FP64): the x, r, z update with ||r||^2, and
 // the p, q, u update with ||q||^2 (init: p = z, q = w, u = v).
 void cr1(const Launch &l);

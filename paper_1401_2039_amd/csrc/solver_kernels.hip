@@ -195,10 +195,8 @@ __global__ __launch_bounds__(WG, 2) void k_hop_res(const SysDesc *__restrict__ s
 }
 
 // Sum a system's partials of one reduction slot and run the solver's scalar
-// step (one work-group of RED_WG threads per system).  Each thread adds a fixed
-// strided subset with independent 16-byte loads, then waves and the work-group
-// combine in a fixed order: the result does not depend on scheduling.
-constexpr int RED_WG = 1024;
+// step (one work-group of RED_WG threads per system), in the fixed order of
+// red_part: the result does not depend on scheduling.
 __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ sdesc, int slot, int fin,
                                                    int mask) {
   static_assert(sizeof(SysState) % 8 == 0 && sizeof(SysState) / 8 <= RED_WG, "state copy");
@@ -213,40 +211,13 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
   __shared__ SysState sst;
   const int tid = threadIdx.x, w = tid >> 6;
   if (tid < NW8) ((unsigned long long *)&sst)[tid] = ((const unsigned long long *)d.st)[tid];
-  const int np = d.g.nb;   // one partial per block
-  const double *p = d.part + (size_t)slot * NV * (d.g.nb * 4);
   __shared__ double red[NV][RED_WG / WAVE];
-  const int npair = np >> 1;
-  const double2 *q[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) q[i] = (const double2 *)(p + (size_t)i * d.g.nb * 4);   // 32-byte aligned rows
-  // Pairs k, k + RED_WG, ... of every row.  The loads of a step (4 pairs of all
-  // rows) are issued together: the partials were just written by other compute
-  // units, so each round trip costs a full memory latency.
-  double a[NV][4];
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) a[i][j] = 0.0;
-  for (int k0 = tid; k0 < npair; k0 += 4 * RED_WG) {
-    double2 x[NV][4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + j * RED_WG;
-#pragma unroll
-      for (int i = 0; i < NV; ++i) x[i][j] = k < npair ? q[i][k] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) a[i][j] += x[i][j].x + x[i][j].y;
-  }
+  double sp[NV];
+  red_part<NV>(part_row(d, slot, 0), (size_t)d.g.nb * 4, d.g.nb, tid, sp);
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    double s = (a[i][0] + a[i][1]) + (a[i][2] + a[i][3]);
-    if (tid == 0 && (np & 1)) s += ((const double *)q[i])[np - 1];
-    s = wave_sum(s);
-    if (lane_id() == 0) red[i][w] = s;
+    const double v = wave_sum(sp[i]);
+    if (lane_id() == 0) red[i][w] = v;
   }
   __syncthreads();
   if (!(sst.status & mask)) return;   // uniform over the work-group
@@ -254,9 +225,9 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const SysDesc *__restrict__ s
     double t[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int j = 0; j < RED_WG / WAVE; ++j) s += red[i][j];
-      t[i] = s;
+      double v = 0.0;
+      for (int j = 0; j < RED_WG / WAVE; ++j) v += red[i][j];
+      t[i] = v;
     }
     finalize(&sst, fin, slot, t);
   }
@@ -281,12 +252,16 @@ __global__ __launch_bounds__(WG) void k_bnorm(const SysDesc *__restrict__ sdesc,
   sys_partial(d, SL_B, it, v);
 }
 
-// CGNR: X += alpha P; R -= alpha AP; ||R||^2
+// CGNR: X += alpha P; R -= alpha AP; ||R||^2.  A plain (FP64) solve leaves X
+// to k_cg2, which reads P anyway: X += alpha P there, before P changes, is the
+// same arithmetic one pass over the vectors cheaper; k_cg_xfin applies the last
+// one when the solve stops here.
 template <int S, int XS>
 __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                             int nwork) {
   using R = typename SpinorIO<S>::R;
   using RX = typename SpinorIO<XS>::R;
+  constexpr bool xhere = S != S_F64;
   const Item it = fetch_item<1>(work, nwork);
   if (!it.active) return;
   const SysDesc &d = sdesc[it.sys];
@@ -294,13 +269,16 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
   double v[NV] = {0.0, 0.0, 0.0};
   if (it.s < d.g.vh) {
     const double al = d.st->alpha;
-    cpx<R> p[12], r[12], ap[12];
-    cpx<RX> x[12];
-    SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
-    SpinorIO<XS>::load(d.f[F_X], it.s, d.npad, x);
+    cpx<R> r[12], ap[12];
+    if (xhere) {
+      cpx<R> p[12];
+      cpx<RX> x[12];
+      SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+      SpinorIO<XS>::load(d.f[F_X], it.s, d.npad, x);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale((RX)al, cmake((RX)p[k].re, (RX)p[k].im)));
-    SpinorIO<XS>::store(d.f[F_X], it.s, d.npad, x);
+      for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale((RX)al, cmake((RX)p[k].re, (RX)p[k].im)));
+      SpinorIO<XS>::store(d.f[F_X], it.s, d.npad, x);
+    }
     SpinorIO<S>::load(d.f[F_R], it.s, d.npad, r);
     SpinorIO<S>::load(d.f[F_AP], it.s, d.npad, ap);
 #pragma unroll
@@ -309,6 +287,23 @@ __global__ __launch_bounds__(WG) void k_cg1(const SysDesc *__restrict__ sdesc, c
     v[0] = norm12(r);
   }
   sys_partial(d, SL_R, it, v);
+}
+
+// The x += alpha p that a plain CGNR solve stopped before (status done after
+// k_cg1, flag set by the residual check).
+__global__ __launch_bounds__(WG) void k_cg_xfin(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
+                                                int nwork) {
+  const Item it = fetch_item<1>(work, nwork);
+  if (!it.active) return;
+  const SysDesc &d = sdesc[it.sys];
+  if (!(d.st->status & ST_DONE) || !d.st->xpend || it.s >= d.g.vh) return;
+  const double al = d.st->alpha;
+  cpx<double> p[12], x[12];
+  SpinorIO<S_F64>::load(d.f[F_P], it.s, d.npad, p);
+  SpinorIO<S_F64>::load(d.f[F_X], it.s, d.npad, x);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale(al, cmake(p[k].re, p[k].im)));
+  SpinorIO<S_F64>::store(d.f[F_X], it.s, d.npad, x);
 }
 
 // Conjugate residual on S^dagger S: X += alpha P; R -= alpha U (U = S P);
@@ -376,8 +371,9 @@ __global__ __launch_bounds__(WG) void k_cr2(const SysDesc *__restrict__ sdesc, c
   sys_partial(d, SL_AP, it, v);
 }
 
-// CGNR: P = Z + beta P
-template <int S>
+// CGNR: P = Z + beta P; with XUPD (plain solves, in the iterations) first
+// X += alpha P with the old P (the update k_cg1 left).
+template <int S, bool XUPD>
 __global__ __launch_bounds__(WG) void k_cg2(const SysDesc *__restrict__ sdesc, const uint32_t *__restrict__ work,
                                             int nwork) {
   using R = typename SpinorIO<S>::R;
@@ -389,6 +385,14 @@ __global__ __launch_bounds__(WG) void k_cg2(const SysDesc *__restrict__ sdesc, c
   const R be = (R)d.st->beta;
   cpx<R> p[12], z[12];
   SpinorIO<S>::load(d.f[F_P], it.s, d.npad, p);
+  if (XUPD) {
+    const double al = d.st->alpha;
+    cpx<double> x[12];
+    SpinorIO<S_F64>::load(d.f[F_X], it.s, d.npad, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = cadd(x[k], cscale(al, cmake((double)p[k].re, (double)p[k].im)));
+    SpinorIO<S_F64>::store(d.f[F_X], it.s, d.npad, x);
+  }
   SpinorIO<S>::load(d.f[F_Z], it.s, d.npad, z);
 #pragma unroll
   for (int k = 0; k < 12; ++k) p[k] = cadd(z[k], cscale(be, p[k]));
@@ -599,11 +603,17 @@ void cg1(const Launch &l, int prec) {
   reduce(l, SL_R, FIN_NR, ST_RUN);
 }
 
-void cg2(const Launch &l, int prec) {
+void cg2(const Launch &l, int prec, bool xupd) {
   const dim3 g = grid_of(l.nwork), b(WG);
-  if (prec == S_F64) hipLaunchKernelGGL(k_cg2<S_F64>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
-  else if (prec == S_F32) hipLaunchKernelGGL(k_cg2<S_F32>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
-  else hipLaunchKernelGGL(k_cg2<S_F16S>, g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  if (prec == S_F64) {
+    if (xupd) hipLaunchKernelGGL((k_cg2<S_F64, true>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+    else hipLaunchKernelGGL((k_cg2<S_F64, false>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  } else if (prec == S_F32) hipLaunchKernelGGL((k_cg2<S_F32, false>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+  else hipLaunchKernelGGL((k_cg2<S_F16S, false>), g, b, 0, l.stream, l.desc, l.work, l.nwork);
+}
+
+void cg_xfin(const Launch &l) {
+  hipLaunchKernelGGL(k_cg_xfin, grid_of(l.nwork), dim3(WG), 0, l.stream, l.desc, l.work, l.nwork);
 }
 
 void cr1(const Launch &l) {

@@ -263,3 +263,21 @@ def test_255_right_hand_sides():
         q.qiral_solve(lat.handle, dims, torch.zeros((256,) + cfg["b"].shape[1:], dtype=torch.complex128, device="cuda"),
                       torch.zeros((256,) + cfg["b"].shape[1:], dtype=torch.complex128, device="cuda"), 256,
                       q.solve_params(tol=1e-10))
+
+
+@pytest.mark.parametrize("k", [1, 6])
+def test_fp64_cgnr_iterate_after_k_steps(c0, k):
+    """A plain FP64 solve stopped by maxiter = k returns the CGNR iterate after k
+    steps (the last x += alpha p applied after the loop): equal to the oracle's
+    CGNR stopped after k steps, reconstructed the same way, to FP64 rounding."""
+    cfg, lat, _, _ = c0
+    say("fp64 iterate after", k)
+    U, kap, b = cfg["U"], cfg["kappa"], cfg["b"][0]
+    bhat = W.schur_source(U, kap, 0.0, b)
+    xo, its, _ = S.cgnr(lambda v: W.schur(U, kap, 0.0, v), lambda v: W.schur(U, kap, 0.0, v, dagger=True), bhat,
+                        0.0, maxiter=k)
+    want = W.reconstruct_even(U, kap, 0.0, b, xo) + xo
+    x, st, info = lat.solve(dev(cfg["b"]), tol=1e-10, maxiter=k)
+    assert st == q._lib.ERR_NOT_CONVERGED and info[0]["iterations"] == k
+    got = host(x)[0]
+    assert np.sqrt(W.norm2(got - want) / W.norm2(want)) < 1e-13
