@@ -102,19 +102,26 @@ __device__ __forceinline__ void path_apply(const Geo &g, const void *links, cons
 // kernels
 
 // One layer, CI output channels per pass of each thread over the paths.
+// src_par >= 0: the input is zero off parity src_par, so a site of that parity
+// takes only the identity path and a site of the other parity only the 8 hops
+// (the paths left out would add exact zeros).  out_par >= 0: only outputs of
+// that parity are computed (the grid then covers one parity).
 template <int CIN, int COUT, int CI>
 __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict__ links,
                                                    const float2 *__restrict__ w, const void *__restrict__ in,
-                                                   void *__restrict__ out, size_t fstride) {
+                                                   void *__restrict__ out, size_t fstride, int src_par, int out_par) {
   __shared__ float2 sw[NPATH * COUT * CIN * 16];
   for (int i = threadIdx.x; i < NPATH * COUT * CIN * 16; i += blockDim.x) sw[i] = w[i];
   __syncthreads();
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 2 * npad) return;
-  const int par = (int)(gid / npad), s = (int)(gid % npad);
+  if (gid >= (out_par >= 0 ? 1 : 2) * npad) return;
+  const int par = out_par >= 0 ? out_par : (int)(gid / npad), s = (int)(gid % npad);
   if (s >= g.vh) return;
   const SiteC c = site_c(g, s, par);
+  // paths [p0, p1): all, or those that read the parity holding the input
+  const int p0 = (src_par >= 0 && par != src_par) ? 1 : 0;
+  const int p1 = (src_par >= 0 && par == src_par) ? 1 : NPATH;
   if constexpr (COUT == 1 && CIN > 1) {
     // Spin weights commute with the colour transport: per path, mix the CIN
     // input channels at the neighbour, then transport once.
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cmake(0.f, 0.f);
 #pragma unroll 1
-    for (int p = 0; p < NPATH; ++p) {
+    for (int p = p0; p < p1; ++p) {
       int mu = 0, n = s, lp = par;
       bool fwd = true;
       if (p > 0) {
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[ii][k] = cmake(0.f, 0.f);
 #pragma unroll 1
-    for (int p = 0; p < NPATH; ++p) {
+    for (int p = p0; p < p1; ++p) {
 #pragma unroll 1
       for (int j = 0; j < CIN; ++j) {
         cpx<float> t[12];
@@ -519,6 +526,86 @@ __global__ __launch_bounds__(256) void k_bminus(const double2 *__restrict__ b, d
   if (i < n) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
 }
 
+// out = y + c[0] x (complex c; out may not alias x)
+__global__ __launch_bounds__(256) void k_zaxpyz(const double2 *__restrict__ c, const double2 *__restrict__ x,
+                                                const double2 *y, double2 *out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = c[0], xv = x[i], yv = y[i];
+  out[i] = make_double2(yv.x + (a.x * xv.x - a.y * xv.y), yv.y + (a.x * xv.y + a.y * xv.x));
+}
+
+// Right-preconditioned BiCGStab's scalars, kept on the device in coef[] so that
+// an iteration needs one read by the host (||r||^2 and the breakdown flags).
+enum : int {
+  BQ_RHO = 40, BQ_ALPHA, BQ_OMEGA, BQ_RHO1, BQ_RV, BQ_TS, BQ_TT, BQ_RN2, BQ_FLAG,   // scalars; FLAG.x, .y below
+  BQ_C_OMEGA = 50, BQ_C_ZB, BQ_C_ZB2, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA      // coefficients of the vector kernels
+};
+// FLAG.x: the iteration broke down before x changed (rho_new or (r~, v) zero):
+// every later coefficient is 0, so x keeps its value and every vector stays
+// finite; FLAG.y: omega = 0, restart after this iteration.
+
+__device__ inline double2 zmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a / b by Smith's method (scaled by the larger part of b)
+__device__ inline double2 zdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  const double r = b.x / b.y, d = b.y + b.x * r;
+  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__device__ inline bool zzero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
+
+// (re)start: rho = alpha = omega = 1, no flags
+__global__ void k_bq_init(double2 *c) {
+  c[BQ_RHO] = c[BQ_ALPHA] = c[BQ_OMEGA] = make_double2(1.0, 0.0);
+  c[BQ_FLAG] = make_double2(0.0, 0.0);
+}
+
+// beta = (rho_new / rho) (alpha / omega); coefficients of p = r + beta (p - omega v)
+__global__ void k_bq_beta(double2 *c) {
+  const double2 rho1 = c[BQ_RHO1];
+  double2 beta = make_double2(0.0, 0.0), om = make_double2(0.0, 0.0);
+  if (zzero(rho1)) {
+    c[BQ_FLAG].x = 1.0;
+  } else {
+    beta = zmul(zdiv(rho1, c[BQ_RHO]), zdiv(c[BQ_ALPHA], c[BQ_OMEGA]));
+    om = c[BQ_OMEGA];
+    c[BQ_RHO] = rho1;
+  }
+  c[BQ_C_OMEGA] = om;
+  c[BQ_C_ZB] = make_double2(1.0, 0.0);
+  c[BQ_C_ZB2] = beta;
+}
+
+// alpha = rho_new / (r~, v); coefficient of s = r - alpha v
+__global__ void k_bq_alpha(double2 *c) {
+  double2 al = make_double2(0.0, 0.0);
+  if (c[BQ_FLAG].x == 0.0) {
+    if (zzero(c[BQ_RV])) c[BQ_FLAG].x = 1.0;
+    else al = zdiv(c[BQ_RHO], c[BQ_RV]);   // BQ_RHO holds rho_new by now
+  }
+  c[BQ_ALPHA] = al;
+  c[BQ_C_MALPHA] = make_double2(-al.x, -al.y);
+}
+
+// omega = (t, s) / (t, t); coefficients of x += alpha p^ + omega s^ and r = s - omega t
+__global__ void k_bq_omega(double2 *c) {
+  const double tt = c[BQ_TT].x;
+  double2 om = make_double2(0.0, 0.0), al = c[BQ_ALPHA];
+  if (c[BQ_FLAG].x == 0.0) {
+    if (tt > 0.0) om = make_double2(c[BQ_TS].x / tt, c[BQ_TS].y / tt);
+    if (zzero(om)) c[BQ_FLAG].y = 1.0;
+  } else {
+    al = make_double2(0.0, 0.0);
+  }
+  c[BQ_OMEGA] = om;
+  c[BQ_C_X] = al;
+  c[BQ_C_X2] = om;
+  c[BQ_C_MOMEGA] = make_double2(-om.x, -om.y);
+}
+
 // FCG step: x += alpha p, r -= alpha q, s -= alpha w (alpha = coef[0]); partial
 // sums of |s|^2 per work-group
 __global__ __launch_bounds__(256) void k_fcg_upd(const double2 *__restrict__ coef, const double2 *__restrict__ p,
@@ -576,23 +663,26 @@ size_t full_bytes32(const Geo &g) { return 2 * half_bytes(g, QIRAL_F32); }
 size_t full_bytes64(const Geo &g) { return 2 * half_bytes(g, QIRAL_F64); }
 
 hipError_t layer_launch(const qiral_nn *nn, const float2 *w, int cin, int cout, const void *in, void *out,
-                        hipStream_t s) {
+                        hipStream_t s, int src_par = -1, int out_par = -1) {
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
-  const int nb = nblk(2 * npad_of(g));
+  const int nb = nblk((out_par >= 0 ? 1 : 2) * npad_of(g));
   const void *links = nn->lat->g32;
+  const int sp = src_par, op = out_par;
+  // 1 -> 8 in two passes of 4 channels (184 VGPRs): one pass of 8 (256 VGPRs, one
+  // wave per SIMD) recomputes no transport but measured 12% slower
   if (cin == 1 && cout == 8)
-    hipLaunchKernelGGL((k_ptc_layer<1, 8, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<1, 8, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else if (cin == 8 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<8, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<8, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else if (cin == 1 && cout == 4)
-    hipLaunchKernelGGL((k_ptc_layer<1, 4, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<1, 4, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else if (cin == 4 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<4, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<4, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else if (cin == 1 && cout == 2)
-    hipLaunchKernelGGL((k_ptc_layer<1, 2, 2>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<1, 2, 2>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else if (cin == 2 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<2, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
+    hipLaunchKernelGGL((k_ptc_layer<2, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -616,11 +706,12 @@ hipError_t wgrad_launch(const qiral_nn *nn, int cin, int cout, const void *in, c
   return hipGetLastError();
 }
 
-// out = N(in), packed F32 full fields
-hipError_t nn_apply_dev(const qiral_nn *nn, void *out, const void *in, hipStream_t s) {
-  hipError_t e = layer_launch(nn, nn->w, 1, nn->hidden, in, nn->act, s);
+// out = N(in), packed F32 full fields.  par >= 0: in is zero off parity par and
+// only that parity of out is wanted (the rest of out is left as it was).
+hipError_t nn_apply_dev(const qiral_nn *nn, void *out, const void *in, hipStream_t s, int par = -1) {
+  hipError_t e = layer_launch(nn, nn->w, 1, nn->hidden, in, nn->act, s, par, -1);
   if (e != hipSuccess) return e;
-  return layer_launch(nn, nn->w + nn->nw1, nn->hidden, 1, nn->act, out, s);
+  return layer_launch(nn, nn->w + nn->nw1, nn->hidden, 1, nn->act, out, s, -1, par);
 }
 
 // D on a packed full field (out = A in - kappa H in, A = 1 + 2 i kappa mu gamma_5), precision prec
@@ -806,14 +897,14 @@ extern "C" qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void
 }
 
 // out = N^dagger(in) = L1^dagger L2^dagger in, packed F32 full fields (uses the
-// handle's adjoint-weight and activation buffers)
-hipError_t nn_apply_adjoint_dev(qiral_nn *nn, void *out, const void *in, hipStream_t s) {
+// handle's adjoint-weight and activation buffers); par as for nn_apply_dev.
+hipError_t nn_apply_adjoint_dev(qiral_nn *nn, void *out, const void *in, hipStream_t s, int par = -1) {
   const int H = nn->hidden;
   hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
-  hipError_t e = layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s);
+  hipError_t e = layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s, par, -1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w, nn->wadj, H, 1);
-  return layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s);
+  return layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s, -1, par);
 }
 
 extern "C" qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
@@ -1047,7 +1138,11 @@ hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s
   char *out = (char *)f.out32 + (f.schur ? f.hb32 : 0);
   const int nb = nblk((size_t)nh * npad_of(g));
   hipLaunchKernelGGL(k_cvt64to32, dim3(nb), dim3(256), 0, s, g, v, in, nh);
-  hipError_t e = adj ? nn_apply_adjoint_dev(f.nn, f.out32, f.in32, s) : nn_apply_dev(f.nn, f.out32, f.in32, s);
+  // the Schur restriction's input lives on the odd sites and only the odd part
+  // of the output is kept: the network skips the paths and sites that would
+  // only add zeros or be dropped
+  const int par = f.schur ? 1 : -1;
+  hipError_t e = adj ? nn_apply_adjoint_dev(f.nn, f.out32, f.in32, s, par) : nn_apply_dev(f.nn, f.out32, f.in32, s, par);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cvt32to64, dim3(nb), dim3(256), 0, s, g, out, z, nh);
   return hipGetLastError();
@@ -1073,6 +1168,17 @@ qiral_status flex_dot(const Flex &f, const double2 *a, const double2 *b, std::co
   qiral_status st = flex_read(&c, f.coef + 32, sizeof c, s);
   out = std::complex<double>(c.x, c.y);
   return st;
+}
+
+// (a | b) into coef[slot], ||v||^2 into coef[slot].x: on the device, no host read
+void flex_dot_dev(const Flex &f, const double2 *a, const double2 *b, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot, dim3(f.nbk), dim3(256), 0, s, a, f.n2, 1, b, f.n2, f.part);
+  hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(256), 0, s, f.part, f.nbk, f.coef + slot);
+}
+void flex_norm2_dev(const Flex &f, const double2 *v, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(f.nbk), dim3(256), 0, s, v, f.n2, f.npart);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, f.nbk, (double *)(f.coef + slot),
+                     (const double *)nullptr);
 }
 
 qiral_status flex_set_coef(const Flex &f, const std::vector<double2> &c, hipStream_t s) {
@@ -1394,63 +1500,50 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   double bn = 0;
   if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
   const double target = prm->tol * bn;
-  typedef std::complex<double> C;
   double rn = 0;
   if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
   long long hops = flex_hops(f);
   int it = 0, restarts = 0;
   bool broke = false;
+  const dim3 gv(f.nbk), bv(256);
   while (rn > target && it < prm->maxiter && !broke) {
     // (re)start: shadow residual r~ = r, rho = alpha = omega = 1, p = v = 0
     QIRAL_HIP(hipMemcpyAsync(RT, R, f.vb, hipMemcpyDeviceToDevice, s));
     QIRAL_HIP(hipMemsetAsync(P, 0, f.vb, s));
     QIRAL_HIP(hipMemsetAsync(Vv, 0, f.vb, s));
-    C rho(1), alpha(1), omega(1);
+    hipLaunchKernelGGL(k_bq_init, dim3(1), dim3(1), 0, s, f.coef);
     bool restart = false;
     while (rn > target && it < prm->maxiter) {
-      C rho1;
-      if ((st = flex_dot(f, RT, R, rho1, s)) != QIRAL_OK) return st;
-      if (rho1 == C(0)) { restart = true; break; }
-      const C beta = (rho1 / rho) * (alpha / omega);
+      // the scalars stay on the device (k_bq_*); the host reads ||r||^2 and the
+      // breakdown flags once per iteration
+      flex_dot_dev(f, RT, R, BQ_RHO1, s);
+      hipLaunchKernelGGL(k_bq_beta, dim3(1), dim3(1), 0, s, f.coef);
       // P = R + beta (P - omega V)
-      if ((st = flex_set_coef(f, {make_double2(omega.real(), omega.imag())}, s)) != QIRAL_OK) return st;
-      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, Vv, f.n2, 1, f.coef, -1.0, P, f.n2);
-      if ((st = flex_set_coef(f, {make_double2(1.0, 0.0), make_double2(beta.real(), beta.imag())}, s)) != QIRAL_OK)
-        return st;
-      hipLaunchKernelGGL(k_zaxpby, dim3(f.nbk), dim3(256), 0, s, f.coef, R, P, f.n2);
+      hipLaunchKernelGGL(k_maxpy, gv, bv, 0, s, Vv, f.n2, 1, f.coef + BQ_C_OMEGA, -1.0, P, f.n2);
+      hipLaunchKernelGGL(k_zaxpby, gv, bv, 0, s, f.coef + BQ_C_ZB, R, P, f.n2);
       QIRAL_HIP(flex_M(f, PH, P, false, s));
       QIRAL_HIP(flex_A(f, Vv, PH, false, s));
-      C rv;
-      if ((st = flex_dot(f, RT, Vv, rv, s)) != QIRAL_OK) return st;
-      if (rv == C(0)) { restart = true; break; }
-      alpha = rho1 / rv;
+      flex_dot_dev(f, RT, Vv, BQ_RV, s);
+      hipLaunchKernelGGL(k_bq_alpha, dim3(1), dim3(1), 0, s, f.coef);
       // S = R - alpha V
-      QIRAL_HIP(hipMemcpyAsync(Sv, R, f.vb, hipMemcpyDeviceToDevice, s));
-      if ((st = flex_set_coef(f, {make_double2(alpha.real(), alpha.imag())}, s)) != QIRAL_OK) return st;
-      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, Vv, f.n2, 1, f.coef, -1.0, Sv, f.n2);
+      hipLaunchKernelGGL(k_zaxpyz, gv, bv, 0, s, f.coef + BQ_C_MALPHA, Vv, R, Sv, f.n2);
       QIRAL_HIP(flex_M(f, SH, Sv, false, s));
       QIRAL_HIP(flex_A(f, T, SH, false, s));
-      hops += 2 * flex_hops(f);
-      C ts;
-      double tt = 0;
-      if ((st = flex_dot(f, T, Sv, ts, s)) != QIRAL_OK) return st;
-      if ((st = flex_norm2(f, T, tt, s)) != QIRAL_OK) return st;
-      omega = tt > 0 ? ts / tt : C(0);
+      flex_dot_dev(f, T, Sv, BQ_TS, s);
+      flex_norm2_dev(f, T, BQ_TT, s);
+      hipLaunchKernelGGL(k_bq_omega, dim3(1), dim3(1), 0, s, f.coef);
       // X += alpha PH + omega SH; R = S - omega T
-      if ((st = flex_set_coef(f, {make_double2(alpha.real(), alpha.imag()), make_double2(omega.real(), omega.imag())},
-                              s)) != QIRAL_OK)
-        return st;
-      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, PH, f.n2, 2, f.coef, 1.0, X, f.n2);
-      QIRAL_HIP(hipMemcpyAsync(R, Sv, f.vb, hipMemcpyDeviceToDevice, s));
-      if ((st = flex_set_coef(f, {make_double2(omega.real(), omega.imag())}, s)) != QIRAL_OK) return st;
-      hipLaunchKernelGGL(k_maxpy, dim3(f.nbk), dim3(256), 0, s, T, f.n2, 1, f.coef, -1.0, R, f.n2);
-      double r2 = 0;
-      if ((st = flex_norm2(f, R, r2, s)) != QIRAL_OK) return st;
-      rn = std::sqrt(r2);
-      rho = rho1;
+      hipLaunchKernelGGL(k_maxpy, gv, bv, 0, s, PH, f.n2, 2, f.coef + BQ_C_X, 1.0, X, f.n2);
+      hipLaunchKernelGGL(k_zaxpyz, gv, bv, 0, s, f.coef + BQ_C_MOMEGA, T, Sv, R, f.n2);
+      flex_norm2_dev(f, R, BQ_RN2, s);
+      double2 q[2];   // RN2, FLAG
+      if ((st = flex_read(q, f.coef + BQ_RN2, sizeof q, s)) != QIRAL_OK) return st;
+      if (q[1].x != 0.0) { restart = true; break; }   // broke down before x changed
+      hops += 2 * flex_hops(f);
+      rn = std::sqrt(q[0].x);
       ++it;
       if (!std::isfinite(rn)) break;
-      if (omega == C(0)) { restart = true; break; }
+      if (q[1].y != 0.0) { restart = true; break; }   // omega = 0
     }
     if (!std::isfinite(rn)) break;
     if (restart) {
