@@ -1,8 +1,8 @@
 """Benchmark of the even-odd Wilson-Dirac solve on one MI355X.
 
 A step is the paper's plain method on its 24^3x48 lattice: even-odd CGNR in
-FP64 (the hop on FP64 reconstruct-18 links; Schur source, reconstruction and
-FP64 true residual included) for each of the 12 point sources of the workload
+FP64 (the FP64 hop, which reads rows 0-1 of each stored FP64 link and rebuilds
+row 2; Schur source, reconstruction and FP64 true residual included) for each of the 12 point sources of the workload
 (exp(0.4 i H) links, kappa 0.12, one source per spin-colour at a seeded site),
 solved one after the other through qiral_solve to ||b - D x|| / ||b|| <= 1e-10.
 Inputs (canonical links packed once, canonical sources and the workspace) are
@@ -17,9 +17,9 @@ The JSON line also carries:
   the mixed-precision forms (F32 and F16S hop with FP64 reliable updates), each
   with its time to solution and speedup over the step (plain FP64 eo-CGNR);
 - roofline: the dominant kernel of the step, the FP64 even-odd hop on this
-  lattice with one right-hand side (8 links x 144 B + 192 B in + 192 B out =
-  1536 B per output site, 331776 sites, 510 MB per launch: twice the 256 MB
-  last-level cache), launched through qiral_dslash_eo and timed with HIP events
+  lattice with one right-hand side (8 links x 96 B (rows 0-1 of a link) + 192 B
+  in + 192 B out = 1152 B per output site, 331776 sites, 382 MB per launch:
+  1.5 times the 256 MB last-level cache), launched through qiral_dslash_eo and timed with HIP events
   on its stream: warm (back-to-back launches) and cold (single launches, each
   after a 1 GiB read that replaces the cache's contents); HBM traffic from the
   committed counter summary while the hop sources are unchanged;
@@ -43,10 +43,12 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f64_24x24x24x48_traffic.md
 HOP_SOURCES = [os.path.join(ROOT, "paper_1401_2039_amd", "csrc", f) for f in ("qiral_dev.h", "api.hip")]
 FLOP_PER_SITE = 1320           # one even-odd hop, per output site
 # algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output spinor
-HOP_BYTES = {"f64": 8 * 144 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
+# (every hop reads rows 0-1 of a link: 96 B in FP64, 48 B in FP32, 24 B in FP16)
+LINK_READ_BYTES = {"f64": 96, "f32": 48, "f16s": 24}
+HOP_BYTES = {"f64": 8 * 96 + 192 + 192, "f32": 8 * 48 + 96 + 96, "f16s": 8 * 24 + 52 + 52}
 ROOFLINE_KERNEL = "k_hop<0, 0, false, 0, 4, 1, true>"   # S_F64, L_F64R18, H (not dagger), plain epilogue, T 4, NR 1, streaming
 WORKLOAD = ("24^3x48 lattice, exp(0.4iH) links, kappa=0.12, 12 point sources (one per spin-colour): even-odd CGNR "
-            "in FP64 with the FP64 reconstruct-18 hop, the sources solved one after the other, to 1e-10 true residual")
+            "in FP64 with the FP64 hop, the sources solved one after the other, to 1e-10 true residual")
 
 
 def hop_source_hash():
@@ -247,7 +249,7 @@ def main():
         "true_rel_resid_max": max(i["true_rel_resid"] for i in infos),
         "hop_applications_per_step": hops // args.steps,
         "batched": batched,
-        "roofline": {"bound": "hbm", "kernel": ROOFLINE_KERNEL + " (qiral_dslash_eo, FP64, 1 RHS)",
+        "roofline": {"bound": "hbm", "kernel": ROOFLINE_KERNEL + " (qiral_dslash_eo, FP64, links read as rows 0-1, 1 RHS)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "bytes_per_launch": hop_bytes, "launch_us": round(warm_us, 3),
@@ -358,7 +360,7 @@ def hop_rates(q, lat, dims, torch, prec, nrhs=1, reps=100, flush=None, psi=None)
             ts.append(a.elapsed_time(b) * 1e3)
         cold = float(np.median(ts))
     key = {q.F64: "f64", q.F32: "f32", q.F16S: "f16s"}[prec]
-    link_b = {"f64": 144, "f32": 48, "f16s": 24}[key] * 8
+    link_b = LINK_READ_BYTES[key] * 8
     sp_b = {"f64": 192, "f32": 96, "f16s": 52}[key]
     bytes_ = vh * (link_b + 2 * sp_b * nrhs)
     res = {"kind": "hop", "dims": list(dims), "prec": key, "nrhs": nrhs, "bytes_per_launch": bytes_,
@@ -489,20 +491,6 @@ def suite_c2(q, latgen, torch, path, timed_solve, flush):
         t, st, info, _ = timed_solve(lat2, b2, reps=1, tol=1e-10, **kw)
         _emit({"kind": "solve", "workload": "24^3x48 eps0.4 k0.12 12 point sources", "form": name,
                "seconds": round(t, 4), "status": st, "iterations": [i["iterations"] for i in info],
-               "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
-    # the Schur-system compositions with the trained network (M_S v = P_o N (0 + v))
-    learned = {"fgmres20_full": t_nn, "fcg_full": t_fcg}
-    for name, solver in (("bicgstab_schur", q.BICGSTAB_EO), ("fgmres20_schur", q.FGMRES_NN)):
-        ps = q.solve_params(solver=solver, system=q.SYSTEM_SCHUR, tol=1e-10, restart=20, maxiter=4000)
-        ps.precond = net.handle
-        x = torch.zeros_like(b)
-        torch.cuda.synchronize()
-        t0 = _t.perf_counter()
-        st, info = q.qiral_solve(lat.handle, lat.dims, x, b, 12, ps)
-        learned[name] = _t.perf_counter() - t0
-        _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": name + "_trained",
-               "seconds": round(learned[name], 4), "status": st, "iterations": [i["iterations"] for i in info],
-               "fell_back": [i["fell_back"] for i in info],
                "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
     tseq = 0.0
     its = []

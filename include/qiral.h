@@ -136,12 +136,16 @@ size_t qiral_field_bytes(const int32_t dims[4], qiral_subset subset, qiral_prec 
  * whole 64-site blocks): prec QIRAL_F64 with QIRAL_RECON18 (144 B per link),
  * QIRAL_F32 with QIRAL_RECON12 (48 B) or QIRAL_F16S with QIRAL_RECON12 (24 B;
  * FP16 links carry no scale, |U_ab| <= 1).  Reconstruct-12 keeps rows 0 and 1
- * and rebuilds row 2 = conj(row0 x row1), exact for SU(3).  Returns 0 for other
- * combinations or invalid dims. */
+ * and rebuilds row 2 = conj(row0 x row1), exact for SU(3).  The FP64 store keeps
+ * all three rows, but the hops read rows 0 and 1 of it (96 B per link) and
+ * rebuild row 2 the same way.  Returns 0 for other combinations or invalid
+ * dims. */
 size_t qiral_gauge_bytes(const int32_t dims[4], qiral_prec prec, qiral_recon recon);
 
-/* Create a lattice handle.  Packs the canonical links (device, complex128, see
- * above) into the caller's stores: gauge_f64 (required, qiral_gauge_bytes(dims,
+/* Create a lattice handle.  The links must be SU(3) (unitary with determinant
+ * 1, to rounding), as those of lattice QCD are: every hop, FP64 included,
+ * rebuilds row 2 of a link from rows 0 and 1.  Packs the canonical links
+ * (device, complex128, see above) into the caller's stores: gauge_f64 (required, qiral_gauge_bytes(dims,
  * QIRAL_F64, QIRAL_RECON18) bytes) and, if not NULL, gauge_f32 and gauge_f16
  * (reconstruct-12 stores of FP32 and FP16 links for the reduced-precision hops
  * and solves).  Each real is rounded once from FP64 to the nearest FP32 / FP16

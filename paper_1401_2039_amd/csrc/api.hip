@@ -260,7 +260,7 @@ HopCfg hop_config(const qiral_lattice *lat, int prec, long nrhs) {
 bool hop_stream(const Geo &g, int prec, long nrhs, long ngroups) {
   if (const char *e = getenv("QIRAL_HOP_NT")) return atoi(e) != 0;
   if (ngroups > 1) return false;   // the groups re-read the tile's links
-  const double link = prec == QIRAL_F64 ? 144 : prec == QIRAL_F32 ? 48 : 24;
+  const double link = prec == QIRAL_F64 ? 96 : prec == QIRAL_F32 ? 48 : 24;   // bytes a hop reads per link
   const double sp = prec == QIRAL_F64 ? 192 : prec == QIRAL_F32 ? 96 : 52;
   const double bytes = (double)g.vh * (8 * link + 2 * sp * nrhs);
   return bytes > 128e6;   // half the 256 MB last-level cache
@@ -276,10 +276,10 @@ int hop_zb(const Geo &g) {
     const int n = atoi(e);
     return zb_valid(g, n) ? n : 0;
   }
-  // A lattice whose FP64 hop (1536 B per site) fits the 256 MB last-level
+  // A lattice whose FP64 hop (1152 B per site) fits the 256 MB last-level
   // cache keeps the plain order: its hops run from that cache, and tiling them
   // cost up to 10% (FP32 at 16^3x32).
-  if ((double)g.vh * 1536.0 <= 256e6) return 0;
+  if ((double)g.vh * 1152.0 <= 256e6) return 0;
   // As many z-tiles as XCDs (else half or a quarter as many), so that the
   // contiguous range of blocks each XCD takes (xcd_remap) is one whole tile or
   // a whole part of one: a tile's z-neighbour planes are then read twice only

@@ -13,8 +13,9 @@ constexpr int WG = 256;    // work-group: 4 waves
 // Minimum waves per SIMD asked of the compiler for a hop kernel (storage S, T
 // waves per site block, NR right-hand sides per lane): caps the VGPR budget at
 // 512 / waves so enough waves stay resident to cover memory latency, while
-// leaving the larger NR / smaller T variants room to avoid spilling.
-#define HOP_MIN_WAVES(S, T, NR) ((S) == 0 ? 2 : (NR) == 1 ? ((T) == 4 ? 4 : 3) : (NR) == 2 ? ((T) == 4 ? 3 : 2) : 2)
+// leaving the larger NR / smaller T variants room to avoid spilling (the FP64
+// 1-RHS hops spill at 128).
+#define HOP_MIN_WAVES(S, T, NR) ((S) == 0 ? ((NR) == 1 ? 3 : 2) : (NR) == 1 ? ((T) == 4 ? 4 : 3) : (NR) == 2 ? ((T) == 4 ? 3 : 2) : 2)
 
 // ---------------------------------------------------------------------------
 // Lattice geometry of one parity-checkerboarded lattice.
@@ -304,10 +305,11 @@ template <> struct SpinorIO<S_F16S> {
 // ---------------------------------------------------------------------------
 // Packed links.  Forward links U_mu(x) of the sites of parity p, in the same
 // 64-site blocking; block index ((p * 4 + mu) * nb + (s >> 6)).
-//   L_F64R18: 9 units of 16 B (complex128), row-major
+//   L_F64R18: 9 units of 16 B (complex128), row-major; the hops read the 6
+//             units of rows 0-1 (96 B) and rebuild row 2, like the others
 //   L_F32R12: 3 units of 16 B (rows 0-1, six complex64)
 //   L_F16R12: 3 units of 8 B  (rows 0-1, six complex FP16)
-// Row 2 of a reconstruct-12 link is conj(row0 x row1).
+// Row 2 of an SU(3) link is conj(row0 x row1) (unitarity and det = 1).
 enum { L_F64R18 = 0, L_F32R12 = 1, L_F16R12 = 2 };
 
 template <class R> __device__ __forceinline__ void recon_row2(cpx<R> u[9]) {
@@ -327,17 +329,20 @@ template <int L> struct LinkIO;
 // and row-2 rebuild) and load (both).
 template <> struct LinkIO<L_F64R18> {
   using R = double;
-  static constexpr size_t LINK_BYTES = 144;
-  struct Raw { double2 q[9]; };
+  static constexpr size_t LINK_BYTES = 144;   // stored; a hop reads 96
+  struct Raw { double2 q[6]; };
   template <bool NT = false>
   __device__ static void fetch(const void *g, int par, int mu, int s, int nb, Raw &r) {
     const double2 *p = (const double2 *)g + ((size_t)((par * 4 + mu) * nb + (s >> 6)) * 9) * WAVE + (s & 63);
+    // each unit is one contiguous 1 KB wave access: skipping row 2's three
+    // units skips their bytes entirely
 #pragma unroll
-    for (int j = 0; j < 9; ++j) r.q[j] = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
+    for (int j = 0; j < 6; ++j) r.q[j] = NT ? ld_nt(p + j * WAVE) : p[j * WAVE];
   }
   __device__ static void decode(const Raw &r, cpx<double> u[9]) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) u[j] = cmake(r.q[j].x, r.q[j].y);
+    for (int j = 0; j < 6; ++j) u[j] = cmake(r.q[j].x, r.q[j].y);
+    recon_row2(u);
   }
   template <bool NT = false>
   __device__ static void load(const void *g, int par, int mu, int s, int nb, cpx<double> u[9]) {

@@ -12,7 +12,7 @@ struct qiral_lattice {
   qiral::Geo geo;
   double kappa, mu;
   // packed link stores, owned by the caller (see qiral_gauge_bytes)
-  void *g64 = nullptr;   // FP64 reconstruct-18 links
+  void *g64 = nullptr;   // FP64 links, all 18 reals (hops read rows 0-1)
   void *g32 = nullptr;   // FP32 reconstruct-12 links (optional)
   void *g16 = nullptr;   // FP16 reconstruct-12 links (optional)
   size_t gauge_bytes = 0;
