@@ -30,6 +30,7 @@ struct qiral_nn {
   int nw1 = 0, nw2 = 0;     // complex weights per layer
   float2 *w = nullptr;      // [nw1 + nw2]
   float2 *wadj = nullptr;   // adjoint-layer weights (scratch)
+  float2 *kmat = nullptr;   // folded path-pair weights K, then K' (scratch)
   float *am = nullptr, *av = nullptr;   // Adam moments, [2 (nw1 + nw2)]
   double *grad = nullptr;   // dL/dRe, dL/dIm interleaved, [2 (nw1 + nw2)]
   double *part = nullptr;   // weight-gradient partials
@@ -101,27 +102,21 @@ __device__ __forceinline__ void path_apply(const Geo &g, const void *links, cons
 // ---------------------------------------------------------------------------
 // kernels
 
-// One layer, CI output channels per pass of each thread over the paths.
-// src_par >= 0: the input is zero off parity src_par, so a site of that parity
-// takes only the identity path and a site of the other parity only the 8 hops
-// (the paths left out would add exact zeros).  out_par >= 0: only outputs of
-// that parity are computed (the grid then covers one parity).
+// One layer (training), CI output channels per pass of each thread over the
+// paths.
 template <int CIN, int COUT, int CI>
 __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict__ links,
                                                    const float2 *__restrict__ w, const void *__restrict__ in,
-                                                   void *__restrict__ out, size_t fstride, int src_par, int out_par) {
+                                                   void *__restrict__ out, size_t fstride) {
   __shared__ float2 sw[NPATH * COUT * CIN * 16];
   for (int i = threadIdx.x; i < NPATH * COUT * CIN * 16; i += blockDim.x) sw[i] = w[i];
   __syncthreads();
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (out_par >= 0 ? 1 : 2) * npad) return;
-  const int par = out_par >= 0 ? out_par : (int)(gid / npad), s = (int)(gid % npad);
+  if (gid >= 2 * npad) return;
+  const int par = (int)(gid / npad), s = (int)(gid % npad);
   if (s >= g.vh) return;
   const SiteC c = site_c(g, s, par);
-  // paths [p0, p1): all, or those that read the parity holding the input
-  const int p0 = (src_par >= 0 && par != src_par) ? 1 : 0;
-  const int p1 = (src_par >= 0 && par == src_par) ? 1 : NPATH;
   if constexpr (COUT == 1 && CIN > 1) {
     // Spin weights commute with the colour transport: per path, mix the CIN
     // input channels at the neighbour, then transport once.
@@ -129,7 +124,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cmake(0.f, 0.f);
 #pragma unroll 1
-    for (int p = p0; p < p1; ++p) {
+    for (int p = 0; p < NPATH; ++p) {
       int mu = 0, n = s, lp = par;
       bool fwd = true;
       if (p > 0) {
@@ -177,7 +172,7 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geo g, const void *__restrict
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[ii][k] = cmake(0.f, 0.f);
 #pragma unroll 1
-    for (int p = p0; p < p1; ++p) {
+    for (int p = 0; p < NPATH; ++p) {
 #pragma unroll 1
       for (int j = 0; j < CIN; ++j) {
         cpx<float> t[12];
@@ -215,6 +210,150 @@ __global__ void k_adj_weights(const float2 *__restrict__ w, float2 *__restrict__
   const int r = e >> 2, q = e & 3;
   const float2 v = w[((p * cout + i) * cin + j) * 16 + 4 * q + r];
   wa[((pm * cin + j) * cout + i) * 16 + 4 * r + q] = make_float2(v.x, -v.y);
+}
+
+// ---------------------------------------------------------------------------
+// Inference with the two layers folded.  The layers are linear and a spin
+// matrix commutes with a colour transport, so
+//     N = sum_{p,p'} T_p K_{pp'} T_{p'},   K_{pp'} = sum_c W2_p^c W1_{p'}^c,
+// and N^dagger has the same form with K'_{pp'} = (K_{m(p') m(p)})^dagger, m the
+// mirror path (T_p^dagger = T_{m(p)}).  Pass A forms m_p(y) = sum_{p'} K_{pp'}
+// (T_{p'} v)(y) at every site, pass B sums out(x) = sum_p (T_p m_p)(x): one
+// transport per path and a spin product per path pair, where the layers take a
+// transport and H spin products per path in each layer and pass the H hidden
+// fields through memory nine times.
+
+__device__ __forceinline__ int mirror_path(int p) { return p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4); }
+
+// K (adj = 0) or K' (adj = 1) into k[p][p'][4][4], summed over the H channels
+// in FP64; one thread per entry.
+__global__ void k_nn_fold(const float2 *__restrict__ w1, const float2 *__restrict__ w2, int hidden, int adj,
+                          float2 *__restrict__ k) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NPATH * NPATH * 16) return;
+  const int e = idx & 15, pq = idx >> 4, p = pq / NPATH, q = pq % NPATH;
+  const int P = adj ? mirror_path(q) : p, Q = adj ? mirror_path(p) : q;
+  const int r = adj ? e & 3 : e >> 2, c = adj ? e >> 2 : e & 3;
+  double re = 0.0, im = 0.0;
+  for (int h = 0; h < hidden; ++h) {
+    const float2 *a = w2 + (P * hidden + h) * 16, *b = w1 + (Q * hidden + h) * 16;
+    for (int j = 0; j < 4; ++j) {
+      const float2 x = a[4 * r + j], y = b[4 * j + c];
+      re += (double)x.x * y.x - (double)x.y * y.y;
+      im += (double)x.x * y.y + (double)x.y * y.x;
+    }
+  }
+  k[idx] = make_float2((float)re, (float)(adj ? -im : im));
+}
+
+// A spinor of a field in storage class S (F32, or F64 rounded to F32).
+template <int S>
+__device__ __forceinline__ void load_as_f32(const void *half, int s, size_t npad, cpx<float> v[12]) {
+  if constexpr (S == S_F32) {
+    SpinorIO<S_F32>::load(half, s, npad, v);
+  } else {
+    cpx<double> d[12];
+    SpinorIO<S_F64>::load(half, s, npad, d);
+    cvt12(d, v);
+  }
+}
+
+// Pass A.  The input's half-fields are in0 (even) and in1 (odd), storage SIN;
+// src_par >= 0: the input is zero off that parity (the other pointer is never
+// read).  out_par >= 0: only outputs of that parity are wanted, so a site keeps
+// m_0 where it has that parity and m_1..m_8 where it has the other.  m_p is
+// written to the F32 half-field m + p * mstride + parity * (npad * 96 bytes),
+// and only where a pass B of the same out_par reads it.  Grid: (sites / 256,
+// 2 parities); PC output paths per sweep over the input paths.
+template <int SIN, int PC>
+__global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict__ links,
+                                                   const float2 *__restrict__ K, const void *__restrict__ in0,
+                                                   const void *__restrict__ in1, void *__restrict__ m,
+                                                   size_t mstride, int src_par, int out_par) {
+  const int ya = blockIdx.y;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.vh) return;
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  // input paths: the identity where y holds input, the hops where its
+  // neighbours do; output paths likewise for the wanted outputs
+  const int q0 = (src_par < 0 || ya == src_par) ? 0 : 1, q1 = (src_par < 0 || ya != src_par) ? NPATH : 1;
+  const int p0 = (out_par < 0 || ya == out_par) ? 0 : 1, p1 = (out_par < 0 || ya != out_par) ? NPATH : 1;
+  const void *here = ya ? in1 : in0, *there = ya ? in0 : in1;
+  const SiteC c = site_c(g, s, ya);
+#pragma unroll 1
+  for (int pc = p0; pc < p1; pc += PC) {
+    cpx<float> acc[PC][12];
+#pragma unroll
+    for (int j = 0; j < PC; ++j)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[j][k] = cmake(0.f, 0.f);
+#pragma unroll 1
+    for (int q = q0; q < q1; ++q) {
+      cpx<float> t[12];
+      if (q == 0) {
+        load_as_f32<SIN>(here, s, npad, t);
+      } else {
+        int mu;
+        bool fwd;
+        path_of(q, mu, fwd);
+        const int n = nbr(g, c, mu, fwd);
+        cpx<float> u[9], psi[12];
+        if (fwd) LinkIO<L_F32R12>::load(links, ya, mu, s, g.nb, u);
+        else LinkIO<L_F32R12>::load(links, 1 - ya, mu, n, g.nb, u);
+        load_as_f32<SIN>(there, n, npad, psi);
+        transport(u, psi, t, !fwd);
+      }
+#pragma unroll
+      for (int j = 0; j < PC; ++j) {
+        if (pc + j >= p1) break;
+        const float2 *Kp = K + ((pc + j) * NPATH + q) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const cpx<float> kr = cmake(Kp[4 * r + e].x, Kp[4 * r + e].y);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[j][4 * a + r] = cmac(kr, t[4 * a + e], acc[j][4 * a + r]);
+          }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+      if (pc + j >= p1) break;
+      SpinorIO<S_F32>::store((char *)m + (size_t)(pc + j) * mstride + ya * hb, s, npad, acc[j]);
+    }
+  }
+}
+
+// Pass B: out(x) = sum_p (T_p m_p)(x) at the sites of parity out_par (both if
+// negative; grid (sites / 256, 1 or 2)), written in storage SOUT to out0 (even
+// half) or out1 (odd half).
+template <int SOUT>
+__global__ __launch_bounds__(256) void k_nn_pass_b(Geo g, const void *__restrict__ links, const void *__restrict__ m,
+                                                   size_t mstride, void *__restrict__ out0, void *__restrict__ out1,
+                                                   int out_par) {
+  const int px = out_par >= 0 ? out_par : (int)blockIdx.y;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.vh) return;
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const SiteC c = site_c(g, s, px);
+  cpx<float> acc[12];
+  SpinorIO<S_F32>::load((const char *)m + px * hb, s, npad, acc);
+#pragma unroll 1
+  for (int p = 1; p < NPATH; ++p) {
+    cpx<float> t[12];
+    path_apply(g, links, (const char *)m + (size_t)p * mstride, hb, npad, c, px, p, t);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = cadd(acc[k], t[k]);
+  }
+  void *dst = px ? out1 : out0;
+  if constexpr (SOUT == S_F32) {
+    SpinorIO<S_F32>::store(dst, s, npad, acc);
+  } else {
+    cpx<double> d[12];
+    cvt12(acc, d);
+    SpinorIO<S_F64>::store(dst, s, npad, d);
+  }
 }
 
 // dL/d conj(W_p^{ij}) = sum_{x,c} g^i(x)[c][r] conj((T_p psi^j)(x)[c][s]); one
@@ -385,36 +524,6 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ part, in
 
 // ---------------------------------------------------------------------------
 // FP64 full-field vector kernels for FGMRES (both halves, padding stays zero)
-// Packed F64 full field <-> packed F32 full field, site by site (the two
-// layouts order a site's components differently within a 64-site block, so
-// the conversion goes through the spinor loaders).  One thread per padded
-// site of either parity; padding sites are copied too (they hold zeros).
-// Packed F64 <-> F32 conversion of nh consecutive half-fields (nh = 2: a full
-// field; nh = 1: one half), site by site (the two layouts order a site's
-// components differently inside a 64-site block).
-__global__ __launch_bounds__(256) void k_cvt64to32(Geo g, const void *__restrict__ a, void *__restrict__ b, int nh) {
-  const size_t npad = (size_t)g.nb * WAVE;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nh * npad) return;
-  const int par = (int)(gid / npad), s = (int)(gid % npad);
-  cpx<double> v[12];
-  SpinorIO<S_F64>::load((const char *)a + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, v);
-  cpx<float> w[12];
-  cvt12(v, w);
-  SpinorIO<S_F32>::store((char *)b + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, w);
-}
-__global__ __launch_bounds__(256) void k_cvt32to64(Geo g, const void *__restrict__ a, void *__restrict__ b, int nh) {
-  const size_t npad = (size_t)g.nb * WAVE;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nh * npad) return;
-  const int par = (int)(gid / npad), s = (int)(gid % npad);
-  cpx<float> v[12];
-  SpinorIO<S_F32>::load((const char *)a + par * npad * SpinorIO<S_F32>::SITE_BYTES, s, npad, v);
-  cpx<double> w[12];
-  cvt12(v, w);
-  SpinorIO<S_F64>::store((char *)b + par * npad * SpinorIO<S_F64>::SITE_BYTES, s, npad, w);
-}
-
 // out = C in on a packed F64 half-field, C the twisted-mass site factor `mode`
 // (CHI_*; a copy at mu = 0)
 __global__ __launch_bounds__(256) void k_chi64(Geo g, const void *__restrict__ in, void *__restrict__ out, int mode,
@@ -663,26 +772,25 @@ size_t full_bytes32(const Geo &g) { return 2 * half_bytes(g, QIRAL_F32); }
 size_t full_bytes64(const Geo &g) { return 2 * half_bytes(g, QIRAL_F64); }
 
 hipError_t layer_launch(const qiral_nn *nn, const float2 *w, int cin, int cout, const void *in, void *out,
-                        hipStream_t s, int src_par = -1, int out_par = -1) {
+                        hipStream_t s) {
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
-  const int nb = nblk((out_par >= 0 ? 1 : 2) * npad_of(g));
+  const int nb = nblk(2 * npad_of(g));
   const void *links = nn->lat->g32;
-  const int sp = src_par, op = out_par;
   // 1 -> 8 in two passes of 4 channels (184 VGPRs): one pass of 8 (256 VGPRs, one
   // wave per SIMD) recomputes no transport but measured 12% slower
   if (cin == 1 && cout == 8)
-    hipLaunchKernelGGL((k_ptc_layer<1, 8, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<1, 8, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else if (cin == 8 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<8, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<8, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else if (cin == 1 && cout == 4)
-    hipLaunchKernelGGL((k_ptc_layer<1, 4, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<1, 4, 4>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else if (cin == 4 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<4, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<4, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else if (cin == 1 && cout == 2)
-    hipLaunchKernelGGL((k_ptc_layer<1, 2, 2>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<1, 2, 2>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else if (cin == 2 && cout == 1)
-    hipLaunchKernelGGL((k_ptc_layer<2, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs, sp, op);
+    hipLaunchKernelGGL((k_ptc_layer<2, 1, 1>), dim3(nb), dim3(256), 0, s, g, links, w, in, out, fs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -706,12 +814,32 @@ hipError_t wgrad_launch(const qiral_nn *nn, int cin, int cout, const void *in, c
   return hipGetLastError();
 }
 
-// out = N(in), packed F32 full fields.  par >= 0: in is zero off parity par and
-// only that parity of out is wanted (the rest of out is left as it was).
-hipError_t nn_apply_dev(const qiral_nn *nn, void *out, const void *in, hipStream_t s, int par = -1) {
-  hipError_t e = layer_launch(nn, nn->w, 1, nn->hidden, in, nn->act, s, par, -1);
-  if (e != hipSuccess) return e;
-  return layer_launch(nn, nn->w + nn->nw1, nn->hidden, 1, nn->act, out, s, -1, par);
+// K and K' of the current weights into nn->kmat (before folded inference).
+hipError_t nn_fold(const qiral_nn *nn, hipStream_t s) {
+  const int n = NPATH * NPATH * 16;
+  for (int adj = 0; adj < 2; ++adj)
+    hipLaunchKernelGGL(k_nn_fold, dim3((n + 255) / 256), dim3(256), 0, s, nn->w, nn->w + nn->nw1, nn->hidden, adj,
+                       nn->kmat + adj * n);
+  return hipGetLastError();
+}
+
+// out = N(in) (adj = false) or N^dagger(in), folded, with the K of the last
+// nn_fold.  SIO: storage of in and out (packed F32 or F64 fields), given as
+// half-fields (in0, in1) and (out0, out1).  par >= 0: in is zero off parity par
+// (in0 or in1 is then not read) and only that parity of out is written.
+template <int SIO>
+hipError_t nn_apply_folded(const qiral_nn *nn, void *out0, void *out1, const void *in0, const void *in1, bool adj,
+                           hipStream_t s, int par = -1) {
+  const Geo &g = nn->lat->geo;
+  const size_t fs = full_bytes32(g);
+  const float2 *K = nn->kmat + (adj ? NPATH * NPATH * 16 : 0);
+  const unsigned gx = (unsigned)nblk(g.vh);
+  // four output paths per sweep: the eight hops of a Schur pass in two sweeps
+  hipLaunchKernelGGL((k_nn_pass_a<SIO, 4>), dim3(gx, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
+                     par, par);
+  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3(gx, par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
+                     (const void *)nn->act, fs, out0, out1, par);
+  return hipGetLastError();
 }
 
 // D on a packed full field (out = A in - kappa H in, A = 1 + 2 i kappa mu gamma_5), precision prec
@@ -779,7 +907,7 @@ void neumann2(int hidden, double kappa, std::vector<float2> &w) {
 namespace {
 // Offsets of the network's device memory (one caller-owned buffer).
 struct NnLayout {
-  size_t w, wadj, am, av, grad, part, scal, act, gact, fv, fb, fy, fg, loss, total;
+  size_t w, wadj, kmat, am, av, grad, part, scal, act, gact, pairx, fv, fb, fy, fg, loss, total;
 };
 inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 NnLayout nn_layout(const Geo &g, int hidden) {
@@ -791,6 +919,7 @@ NnLayout nn_layout(const Geo &g, int hidden) {
   auto take = [&](size_t bytes) { const size_t at = o; o = al256(o + bytes); return at; };
   l.w = take(sizeof(float2) * nw);
   l.wadj = take(sizeof(float2) * nw);
+  l.kmat = take(sizeof(float2) * 2 * NPATH * NPATH * 16);
   l.am = take(sizeof(float) * 2 * nw);
   l.av = take(sizeof(float) * 2 * nw);
   l.grad = take(sizeof(double) * 2 * nw);
@@ -798,6 +927,9 @@ NnLayout nn_layout(const Geo &g, int hidden) {
   l.scal = take(sizeof(double) * ((size_t)nblocks + 64));
   l.act = take(f32 * hidden);
   l.gact = take(f32 * hidden);
+  // f32 is a whole number of 256-byte units, so act, gact and pairx are
+  // adjacent: together they hold the nine F32 fields m_p of folded inference
+  l.pairx = take(f32 * (size_t)std::max(0, NPATH - 2 * hidden));
   l.fv = take(f32);
   l.fb = take(f32);
   l.fy = take(f32);
@@ -833,6 +965,7 @@ extern "C" qiral_status qiral_nn_create(qiral_nn **out, qiral_lattice *lat, int3
   char *m = (char *)mem;
   nn->w = (float2 *)(m + l.w);
   nn->wadj = (float2 *)(m + l.wadj);
+  nn->kmat = (float2 *)(m + l.kmat);
   nn->am = (float *)(m + l.am);
   nn->av = (float *)(m + l.av);
   nn->grad = (double *)(m + l.grad);
@@ -889,29 +1022,23 @@ extern "C" qiral_status qiral_nn_get_weights(const qiral_nn *nn, float *w, size_
   return QIRAL_OK;
 }
 
-extern "C" qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
+// Both network calls run the folded form on packed F32 full fields.
+static qiral_status nn_apply_api(const qiral_nn *nn, void *out, const void *in, bool adj, qiral_stream_t stream) {
   if (!nn || !out || !in) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
   if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
-  QIRAL_HIP(nn_apply_dev(nn, out, in, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t hb = half_bytes(nn->lat->geo, QIRAL_F32);
+  QIRAL_HIP(nn_fold(nn, s));
+  QIRAL_HIP(nn_apply_folded<S_F32>(nn, out, (char *)out + hb, in, (const char *)in + hb, adj, s));
   return QIRAL_OK;
 }
 
-// out = N^dagger(in) = L1^dagger L2^dagger in, packed F32 full fields (uses the
-// handle's adjoint-weight and activation buffers); par as for nn_apply_dev.
-hipError_t nn_apply_adjoint_dev(qiral_nn *nn, void *out, const void *in, hipStream_t s, int par = -1) {
-  const int H = nn->hidden;
-  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w + nn->nw1, nn->wadj, 1, H);
-  hipError_t e = layer_launch(nn, nn->wadj, 1, H, in, nn->gact, s, par, -1);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_weights, dim3((NPATH * H * 16 + 255) / 256), dim3(256), 0, s, nn->w, nn->wadj, H, 1);
-  return layer_launch(nn, nn->wadj, H, 1, nn->gact, out, s, -1, par);
+extern "C" qiral_status qiral_nn_apply(const qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
+  return nn_apply_api(nn, out, in, false, stream);
 }
 
 extern "C" qiral_status qiral_nn_apply_adjoint(qiral_nn *nn, void *out, const void *in, qiral_stream_t stream) {
-  if (!nn || !out || !in) return fail(QIRAL_ERR_INVALID_ARG, "NULL argument");
-  if (out == in) return fail(QIRAL_ERR_INVALID_ARG, "in and out must not alias");
-  QIRAL_HIP(nn_apply_adjoint_dev(nn, out, in, (hipStream_t)stream));
-  return QIRAL_OK;
+  return nn_apply_api(nn, out, in, true, stream);
 }
 
 extern "C" qiral_status qiral_nn_sample(qiral_nn *nn, void *out, uint64_t seed, uint64_t step, double *norm2,
@@ -1047,12 +1174,11 @@ struct Flex {
   qiral_lattice *lat;
   qiral_nn *nn;        // NULL: the identity preconditioner
   bool schur;
-  size_t hb64, hb32;   // bytes of an F64 / F32 half-field
+  size_t hb64;         // bytes of an F64 half-field
   size_t vb, n2;       // bytes and complex entries of a Krylov vector
   int nbk;             // work-groups of the flat vector kernels
   double2 *BF, *XF, *RF;        // F64 full fields: b, x, the true residual
   void *tmpE;                   // F64 even half-field (Schur operator, source)
-  void *in32, *out32;           // F32 full fields for the network
   double2 *vec;                 // the solver's Krylov vectors, vb bytes apart
   double *part, *npart, *nrm;   // partial sums
   double2 *coef;                // complex coefficients (device)
@@ -1060,7 +1186,7 @@ struct Flex {
 };
 
 size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex *f) {
-  const size_t hb64 = half_bytes(g, QIRAL_F64), hb32 = half_bytes(g, QIRAL_F32);
+  const size_t hb64 = half_bytes(g, QIRAL_F64);
   const size_t vb = schur ? hb64 : 2 * hb64;
   const int m = flex_restart(prm);
   const int nbk = nblk(vb / 16);
@@ -1068,14 +1194,12 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o += (bytes + 255) / 256 * 256; return at; };
   const size_t oBF = take(2 * hb64), oXF = take(2 * hb64), oRF = take(2 * hb64), oT = take(hb64);
-  const size_t oin = take(2 * hb32), oout = take(2 * hb32);
   const size_t ovec = o;
   o += (size_t)nv * vb;
   const size_t opart = take(sizeof(double) * 2 * (size_t)(m + 2) * nbk), onpart = take(sizeof(double) * nbk);
   const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * 64);
   if (f) {
     f->hb64 = hb64;
-    f->hb32 = hb32;
     f->vb = vb;
     f->n2 = vb / 16;
     f->nbk = nbk;
@@ -1083,8 +1207,6 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
     f->XF = (double2 *)oXF;
     f->RF = (double2 *)oRF;
     f->tmpE = (void *)oT;
-    f->in32 = (void *)oin;
-    f->out32 = (void *)oout;
     f->vec = (double2 *)ovec;
     f->part = (double *)opart;
     f->npart = (double *)onpart;
@@ -1106,8 +1228,6 @@ qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void 
   f.XF = (double2 *)(b + (size_t)f.XF);
   f.RF = (double2 *)(b + (size_t)f.RF);
   f.tmpE = b + (size_t)f.tmpE;
-  f.in32 = b + (size_t)f.in32;
-  f.out32 = b + (size_t)f.out32;
   f.vec = (double2 *)(b + (size_t)f.vec);
   f.part = (double *)(b + (size_t)f.part);
   f.npart = (double *)(b + (size_t)f.npart);
@@ -1127,25 +1247,15 @@ hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s
   return launch_hop(lat, QIRAL_F64, dag, 1, 1, -k * k, f.tmpE, y, x, 1, s, CHI_ONE, dag ? CHI_ADAG : CHI_A);
 }
 
-// z = M v (or M^dagger v): the network in FP32 on v (full system) or on v placed
-// on the odd sites, keeping the odd part of the result (Schur system, whose
-// even half of in32 stays zero); the identity without a network.
+// z = M v (or M^dagger v): the folded network in FP32 on v (full system) or on
+// v placed on the odd sites, keeping the odd part of the result (Schur system:
+// the passes skip the paths and sites that would only add zeros or be
+// dropped), reading and writing the FP64 Krylov vectors directly; the identity
+// without a network.
 hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s) {
   if (!f.nn) return hipMemcpyAsync(z, v, f.vb, hipMemcpyDeviceToDevice, s);
-  const Geo &g = f.lat->geo;
-  const int nh = f.schur ? 1 : 2;
-  char *in = (char *)f.in32 + (f.schur ? f.hb32 : 0);
-  char *out = (char *)f.out32 + (f.schur ? f.hb32 : 0);
-  const int nb = nblk((size_t)nh * npad_of(g));
-  hipLaunchKernelGGL(k_cvt64to32, dim3(nb), dim3(256), 0, s, g, v, in, nh);
-  // the Schur restriction's input lives on the odd sites and only the odd part
-  // of the output is kept: the network skips the paths and sites that would
-  // only add zeros or be dropped
-  const int par = f.schur ? 1 : -1;
-  hipError_t e = adj ? nn_apply_adjoint_dev(f.nn, f.out32, f.in32, s, par) : nn_apply_dev(f.nn, f.out32, f.in32, s, par);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cvt32to64, dim3(nb), dim3(256), 0, s, g, out, z, nh);
-  return hipGetLastError();
+  if (f.schur) return nn_apply_folded<S_F64>(f.nn, nullptr, z, nullptr, v, adj, s, 1);
+  return nn_apply_folded<S_F64>(f.nn, z, (char *)z + f.hb64, v, (const char *)v + f.hb64, adj, s);
 }
 
 qiral_status flex_read(void *dst, const void *src, size_t bytes, hipStream_t s) {
@@ -1198,11 +1308,9 @@ qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_ca
   // Hops and network layers write only the lattice's sites, while the flat
   // vector kernels also sum the padding sites of the last 64-site block: every
   // field whose padding they can reach starts at zero (the Krylov vectors are
-  // cleared by the solvers).  The network's input also keeps its even half at
-  // zero on the Schur system.
+  // cleared by the solvers).
   QIRAL_HIP(hipMemsetAsync(f.RF, 0, 2 * f.hb64, s));
-  QIRAL_HIP(hipMemsetAsync(f.in32, 0, 2 * f.hb32, s));
-  QIRAL_HIP(hipMemsetAsync(f.out32, 0, 2 * f.hb32, s));
+  if (f.nn) QIRAL_HIP(nn_fold(f.nn, s));   // the network's folded weights for this solve
   const char *be = (const char *)f.BF, *bo = be + f.hb64;
   if (!f.schur) {
     QIRAL_HIP(hipMemcpyAsync(rhs, f.BF, 2 * f.hb64, hipMemcpyDeviceToDevice, s));
