@@ -263,65 +263,68 @@ __device__ __forceinline__ void load_as_f32(const void *half, int s, size_t npad
 // read).  out_par >= 0: only outputs of that parity are wanted, so a site keeps
 // m_0 where it has that parity and m_1..m_8 where it has the other.  m_p is
 // written to the F32 half-field m + p * mstride + parity * (npad * 96 bytes),
-// and only where a pass B of the same out_par reads it.  Grid: (sites / 256,
-// 2 parities); PC output paths per sweep over the input paths.
+// and only where a pass B of the same out_par reads it.  Two waves share a
+// 64-site block, each sweeping the input paths for its own PC output paths, so
+// the second wave's neighbour loads hit the cache lines the first has just
+// brought in.  Grid: (ceil(nb / 2), 2 parities), 256 threads: two site blocks.
 template <int SIN, int PC>
 __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict__ links,
                                                    const float2 *__restrict__ K, const void *__restrict__ in0,
                                                    const void *__restrict__ in1, void *__restrict__ m,
                                                    size_t mstride, int src_par, int out_par) {
   const int ya = blockIdx.y;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = (blockIdx.x * 2 + (w >> 1)) * WAVE + (threadIdx.x & (WAVE - 1));
   if (s >= g.vh) return;
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   // input paths: the identity where y holds input, the hops where its
-  // neighbours do; output paths likewise for the wanted outputs
+  // neighbours do; output paths likewise for the wanted outputs, this wave's
+  // share of them
   const int q0 = (src_par < 0 || ya == src_par) ? 0 : 1, q1 = (src_par < 0 || ya != src_par) ? NPATH : 1;
-  const int p0 = (out_par < 0 || ya == out_par) ? 0 : 1, p1 = (out_par < 0 || ya != out_par) ? NPATH : 1;
+  const int pa = (out_par < 0 || ya == out_par) ? 0 : 1, pb = (out_par < 0 || ya != out_par) ? NPATH : 1;
+  const int p0 = pa + (w & 1) * PC, p1 = min(pb, p0 + PC);
+  if (p0 >= p1) return;
   const void *here = ya ? in1 : in0, *there = ya ? in0 : in1;
   const SiteC c = site_c(g, s, ya);
+  cpx<float> acc[PC][12];
+#pragma unroll
+  for (int j = 0; j < PC; ++j)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[j][k] = cmake(0.f, 0.f);
 #pragma unroll 1
-  for (int pc = p0; pc < p1; pc += PC) {
-    cpx<float> acc[PC][12];
-#pragma unroll
-    for (int j = 0; j < PC; ++j)
-#pragma unroll
-      for (int k = 0; k < 12; ++k) acc[j][k] = cmake(0.f, 0.f);
-#pragma unroll 1
-    for (int q = q0; q < q1; ++q) {
-      cpx<float> t[12];
-      if (q == 0) {
-        load_as_f32<SIN>(here, s, npad, t);
-      } else {
-        int mu;
-        bool fwd;
-        path_of(q, mu, fwd);
-        const int n = nbr(g, c, mu, fwd);
-        cpx<float> u[9], psi[12];
-        if (fwd) LinkIO<L_F32R12>::load(links, ya, mu, s, g.nb, u);
-        else LinkIO<L_F32R12>::load(links, 1 - ya, mu, n, g.nb, u);
-        load_as_f32<SIN>(there, n, npad, psi);
-        transport(u, psi, t, !fwd);
-      }
-#pragma unroll
-      for (int j = 0; j < PC; ++j) {
-        if (pc + j >= p1) break;
-        const float2 *Kp = K + ((pc + j) * NPATH + q) * 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const cpx<float> kr = cmake(Kp[4 * r + e].x, Kp[4 * r + e].y);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) acc[j][4 * a + r] = cmac(kr, t[4 * a + e], acc[j][4 * a + r]);
-          }
-      }
+  for (int q = q0; q < q1; ++q) {
+    cpx<float> t[12];
+    if (q == 0) {
+      load_as_f32<SIN>(here, s, npad, t);
+    } else {
+      int mu;
+      bool fwd;
+      path_of(q, mu, fwd);
+      const int n = nbr(g, c, mu, fwd);
+      cpx<float> u[9], psi[12];
+      if (fwd) LinkIO<L_F32R12>::load(links, ya, mu, s, g.nb, u);
+      else LinkIO<L_F32R12>::load(links, 1 - ya, mu, n, g.nb, u);
+      load_as_f32<SIN>(there, n, npad, psi);
+      transport(u, psi, t, !fwd);
     }
 #pragma unroll
     for (int j = 0; j < PC; ++j) {
-      if (pc + j >= p1) break;
-      SpinorIO<S_F32>::store((char *)m + (size_t)(pc + j) * mstride + ya * hb, s, npad, acc[j]);
+      if (p0 + j >= p1) break;
+      const float2 *Kp = K + ((p0 + j) * NPATH + q) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const cpx<float> kr = cmake(Kp[4 * r + e].x, Kp[4 * r + e].y);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) acc[j][4 * a + r] = cmac(kr, t[4 * a + e], acc[j][4 * a + r]);
+        }
     }
+  }
+#pragma unroll
+  for (int j = 0; j < PC; ++j) {
+    if (p0 + j >= p1) break;
+    SpinorIO<S_F32>::store((char *)m + (size_t)(p0 + j) * mstride + ya * hb, s, npad, acc[j]);
   }
 }
 
@@ -507,12 +510,36 @@ __global__ __launch_bounds__(256) void k_loss_grad(Geo g, const void *__restrict
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// out[0] = scale * sum(part[0..n)) in index order (one work-group).
+// Sum of x[i], i = tid, tid + 256, ... < n, as four interleaved chains (i / 256
+// mod 4) added at the end: a fixed order, with four loads in flight per thread
+// where one chain would wait out a memory latency per element.
+template <class T> __device__ __forceinline__ T zero_of();
+template <> __device__ __forceinline__ double zero_of<double>() { return 0.0; }
+template <> __device__ __forceinline__ double2 zero_of<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double add_of(double a, double b) { return a + b; }
+__device__ __forceinline__ double2 add_of(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+template <class T> __device__ __forceinline__ T strided_sum(const T *__restrict__ x, int n, int tid) {
+  T c0 = zero_of<T>(), c1 = c0, c2 = c0, c3 = c0;
+  int i = tid;
+  for (; i + 768 < n; i += 1024) {
+    const T a = x[i], b = x[i + 256], c = x[i + 512], d = x[i + 768];
+    c0 = add_of(c0, a);
+    c1 = add_of(c1, b);
+    c2 = add_of(c2, c);
+    c3 = add_of(c3, d);
+  }
+  if (i < n) c0 = add_of(c0, x[i]);
+  if (i + 256 < n) c1 = add_of(c1, x[i + 256]);
+  if (i + 512 < n) c2 = add_of(c2, x[i + 512]);
+  return add_of(add_of(c0, c1), add_of(c2, c3));
+}
+
+// out[0] = sum(part[0..n)) (divided by divisor[0] if given), in a fixed order
+// (one work-group).
 __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ part, int n, double *__restrict__ out,
                                              const double *__restrict__ divisor) {
   __shared__ double red[4];
-  double a = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  double a = strided_sum(part, n, (int)threadIdx.x);
   a = wave_sum(a);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
   __syncthreads();
@@ -577,15 +604,8 @@ __global__ __launch_bounds__(256) void k_mdot_final(const double *__restrict__ p
                                                     double2 *__restrict__ coef) {
   __shared__ double red[2][4];
   const int q = blockIdx.x;
-  const double *pq = part + (size_t)q * nblk * 2;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) {
-    const double2 v = ((const double2 *)pq)[b];
-    re += v.x;
-    im += v.y;
-  }
-  re = wave_sum(re);
-  im = wave_sum(im);
+  const double2 sum = strided_sum((const double2 *)(part + (size_t)q * nblk * 2), nblk, (int)threadIdx.x);
+  const double re = wave_sum(sum.x), im = wave_sum(sum.y);
   if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
   __syncthreads();
   if (threadIdx.x == 0)
@@ -833,10 +853,15 @@ hipError_t nn_apply_folded(const qiral_nn *nn, void *out0, void *out1, const voi
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
   const float2 *K = nn->kmat + (adj ? NPATH * NPATH * 16 : 0);
-  const unsigned gx = (unsigned)nblk(g.vh);
-  // four output paths per sweep: the eight hops of a Schur pass in two sweeps
-  hipLaunchKernelGGL((k_nn_pass_a<SIO, 4>), dim3(gx, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
-                     par, par);
+  const unsigned gx = (unsigned)nblk(g.vh), ga = (unsigned)((g.nb + 1) / 2);
+  // the output paths in two waves per site block: the eight hops of the Schur
+  // form four each, all nine paths five and four
+  if (par >= 0)
+    hipLaunchKernelGGL((k_nn_pass_a<SIO, 4>), dim3(ga, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
+                       par, par);
+  else
+    hipLaunchKernelGGL((k_nn_pass_a<SIO, 5>), dim3(ga, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
+                       par, par);
   hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3(gx, par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
                      (const void *)nn->act, fs, out0, out1, par);
   return hipGetLastError();
