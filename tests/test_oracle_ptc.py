@@ -1,7 +1,12 @@
 """The parallel-transport network: Neumann-series weights give 1 + kH + k^2 H^2
 exactly (ties the layer to the pinned hopping term), gauge equivariance, the
-adjoint identity, and the weight gradient against central finite differences."""
+adjoint identity, the weight gradient against central finite differences, and
+the identity behind the GPU's folded inference: two linear layers equal
+sum_{p,q} T_p K_pq T_q with K_pq = sum_c W2_p^c W1_q^c (its adjoint with
+K'_pq = K_{m(q) m(p)}^dagger), and on an odd-site input the odd output keeps
+only K_00 and the hop-hop pairs."""
 import numpy as np
+import pytest
 
 import latgen
 from oracle import ptc
@@ -67,3 +72,44 @@ def test_wgrad_finite_differences():
                 G = grads[layer][idx]
                 an = 2 * (G.real if part == "re" else G.imag)
                 assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (layer, idx, part, fd, an)
+
+
+def _fold(ws):
+    """K[p, q] = sum_c W2[p, 0, c] @ W1[q, c, 0] (4x4 spin matrices)."""
+    w1, w2 = ws
+    return np.einsum("pcrs,qcst->pqrt", w2[:, 0], w1[:, :, 0])
+
+
+def _apply_pairs(U, K, v, ps=range(9), qs=range(9)):
+    """sum_{p in ps} T_p sum_{q in qs} K[p, q] T_q v."""
+    t = {q: ptc.transport(U, v, q) for q in qs}
+    out = np.zeros_like(v)
+    for p in ps:
+        m = sum(t[q] @ K[p, q].T for q in qs)
+        out += ptc.transport(U, m, p)
+    return out
+
+
+@pytest.mark.parametrize("hidden", [2, 8])
+def test_two_layers_fold_into_path_pairs(hidden):
+    dims = (4, 2, 2, 4)
+    cfg = latgen.small_config(dims, seed=25, nrhs=1)
+    U, v = cfg["U"], cfg["b"][0]
+    rng = np.random.default_rng(3)
+    ws = [_rand_w(rng, hidden, 1), _rand_w(rng, 1, hidden)]
+    K = _fold(ws)
+    want = ptc.network(U, ws, v)
+    assert np.abs(_apply_pairs(U, K, v) - want).max() < 1e-12 * np.abs(want).max()
+    # adjoint: K'[p, q] = K[m(q), m(p)]^dagger
+    m = [ptc.mirror(p) for p in range(9)]
+    Ka = np.conj(np.swapaxes(K[np.ix_(m, m)].transpose(1, 0, 2, 3), 2, 3))
+    want_a = ptc.network_adjoint(U, ws, v)
+    assert np.abs(_apply_pairs(U, Ka, v) - want_a).max() < 1e-12 * np.abs(want_a).max()
+    # Schur restriction P_o N (0 + v_o): the identity pair on odd sites plus the
+    # hop-hop pairs through the even sites; every other pair adds zero
+    par = W.parity_field(dims)
+    vo = W.project(v, 1)
+    want_s = W.project(ptc.network(U, ws, vo), 1)
+    hops = range(1, 9)
+    got_s = W.project(vo @ K[0, 0].T + _apply_pairs(U, K, vo, hops, hops), 1)
+    assert par.any() and np.abs(got_s - want_s).max() < 1e-12 * np.abs(want_s).max()
