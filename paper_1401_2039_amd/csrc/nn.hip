@@ -31,6 +31,7 @@ struct qiral_nn {
   float2 *w = nullptr;      // [nw1 + nw2]
   float2 *wadj = nullptr;   // adjoint-layer weights (scratch)
   float2 *kmat = nullptr;   // folded path-pair weights K, then K' (scratch)
+  void *kfrag = nullptr;    // MFMA A fragments of K, then of K' (scratch)
   float *am = nullptr, *av = nullptr;   // Adam moments, [2 (nw1 + nw2)]
   double *grad = nullptr;   // dL/dRe, dL/dIm interleaved, [2 (nw1 + nw2)]
   double *part = nullptr;   // weight-gradient partials
@@ -258,32 +259,23 @@ __device__ __forceinline__ void load_as_f32(const void *half, int s, size_t npad
   }
 }
 
-// Pass A.  The input's half-fields are in0 (even) and in1 (odd), storage SIN;
-// src_par >= 0: the input is zero off that parity (the other pointer is never
-// read).  out_par >= 0: only outputs of that parity are wanted, so a site keeps
-// m_0 where it has that parity and m_1..m_8 where it has the other.  m_p is
-// written to the F32 half-field m + p * mstride + parity * (npad * 96 bytes),
-// and only where a pass B of the same out_par reads it.  Two waves share a
-// 64-site block, each sweeping the input paths for its own PC output paths, so
-// the second wave's neighbour loads hit the cache lines the first has just
+// Pass A over both parities and all nine paths (vector ALU, FP32): the input's
+// half-fields are in0 (even) and in1 (odd), storage SIN; m_p is written to the
+// F32 half-field m + p * mstride + parity * (npad * 96 bytes).  Two waves share
+// a 64-site block, each sweeping the input paths for its own PC output paths,
+// so the second wave's neighbour loads hit the cache lines the first has just
 // brought in.  Grid: (ceil(nb / 2), 2 parities), 256 threads: two site blocks.
 template <int SIN, int PC>
 __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict__ links,
                                                    const float2 *__restrict__ K, const void *__restrict__ in0,
                                                    const void *__restrict__ in1, void *__restrict__ m,
-                                                   size_t mstride, int src_par, int out_par) {
+                                                   size_t mstride) {
   const int ya = blockIdx.y;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = (blockIdx.x * 2 + (w >> 1)) * WAVE + (threadIdx.x & (WAVE - 1));
   if (s >= g.vh) return;
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
-  // input paths: the identity where y holds input, the hops where its
-  // neighbours do; output paths likewise for the wanted outputs, this wave's
-  // share of them
-  const int q0 = (src_par < 0 || ya == src_par) ? 0 : 1, q1 = (src_par < 0 || ya != src_par) ? NPATH : 1;
-  const int pa = (out_par < 0 || ya == out_par) ? 0 : 1, pb = (out_par < 0 || ya != out_par) ? NPATH : 1;
-  const int p0 = pa + (w & 1) * PC, p1 = min(pb, p0 + PC);
-  if (p0 >= p1) return;
+  const int p0 = (w & 1) * PC, p1 = min(NPATH, p0 + PC);
   const void *here = ya ? in1 : in0, *there = ya ? in0 : in1;
   const SiteC c = site_c(g, s, ya);
   cpx<float> acc[PC][12];
@@ -292,7 +284,7 @@ __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[j][k] = cmake(0.f, 0.f);
 #pragma unroll 1
-  for (int q = q0; q < q1; ++q) {
+  for (int q = 0; q < NPATH; ++q) {
     cpx<float> t[12];
     if (q == 0) {
       load_as_f32<SIN>(here, s, npad, t);
@@ -325,6 +317,147 @@ __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict
   for (int j = 0; j < PC; ++j) {
     if (p0 + j >= p1) break;
     SpinorIO<S_F32>::store((char *)m + (size_t)(p0 + j) * mstride + ya * hb, s, npad, acc[j]);
+  }
+}
+
+// Pass A of the one-parity form on the matrix cores.  With the input on
+// parity P and the output kept on P, a site y of the other parity needs
+// m_p(y) = sum_q K_pq t_q(y) for the eight hops p and q: per colour, a 32x32
+// complex (64x64 real) matrix applied to the 64-real vector of the t_q.  Over a
+// 64-site block that is a 64 x 64 x 192 product, done as 16x16x32 bf16 MFMAs
+// with FP32 accumulation: rows (p, spin, re/im), columns (site, colour),
+// k = (q, spin, re/im).  Each real is split into bf16 hi + lo parts and three
+// products are summed (hi*hi + hi*lo + lo*hi), about 1e-5 relative: used only
+// as the flexible solvers' preconditioner, which needs no exact arithmetic
+// (every recurrence uses the vector the preconditioner actually returned).
+//
+// Four waves per 64-site block.  Per K-step of four input paths, wave w makes
+// t_q for q = 1 + 4 ks + w at its lane's site and leaves its bf16 hi and lo
+// parts in LDS; after a barrier every wave reads the B fragments (8 k-values of
+// one column per lane) and multiplies them into its M-tile (output paths
+// 1 + 2w and 2 + 2w).  The accumulator rows of lane (g, n) are two complex
+// spin components of one colour of one site, which is exactly a float4 unit of
+// the F32 spinor layout, so the results are stored straight from the
+// accumulators.  Sites of parity P keep m_0 = K_00 v (vector ALU).  A
+// fragments come from k_nn_frag.  Grid: (nb, 2 parities), 256 threads.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// A fragments of the real form of K (or K') over the hop pairs, bf16 hi and lo:
+// f[(((mt * 2 + ks) * 2 + hl) * 64 + lane) * 8 + kk]; row lane % 16 of M-tile mt
+// is (p = 1 + 2 mt + row / 8, spin (row % 8) / 2, re/im row % 2); kk is (spin
+// kk / 2, re/im kk % 2) of input path q = 1 + 4 ks + lane / 16.
+__global__ void k_nn_frag(const float2 *__restrict__ K, __bf16 *__restrict__ f) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 4 * 2 * 2 * 64 * 8) return;
+  const int kk = idx & 7, lane = (idx >> 3) & 63, hl = (idx >> 9) & 1, ks = (idx >> 10) & 1, mt = idx >> 11;
+  const int row = lane & 15, r = (row & 7) >> 1, c = row & 1, e = kk >> 1, ci = kk & 1;
+  const int p = 1 + 2 * mt + (row >> 3), q = 1 + 4 * ks + (lane >> 4);
+  const float2 k = K[(p * NPATH + q) * 16 + 4 * r + e];
+  // (re, im) of the product k x: re = k.re x.re - k.im x.im, im = k.im x.re + k.re x.im
+  const float v = c == 0 ? (ci == 0 ? k.x : -k.y) : (ci == 0 ? k.y : k.x);
+  const __bf16 hi = (__bf16)v;
+  f[idx] = hl == 0 ? hi : (__bf16)(v - (float)hi);
+}
+
+template <int SIN>
+__global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__restrict__ links,
+                                                        const float2 *__restrict__ K, const bf16x8 *__restrict__ frag,
+                                                        const void *__restrict__ in, void *__restrict__ m,
+                                                        size_t mstride, int par) {
+  __shared__ uint4 lds_hi[4 * 3 * WAVE], lds_lo[4 * 3 * WAVE];   // [q in K-step][colour][site]
+  const int ya = blockIdx.y;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int sb = blockIdx.x, s = sb * WAVE + lane;
+  const bool live = s < g.vh;
+  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  if (ya == par) {
+    if (w != 0 || !live) return;
+    cpx<float> v[12], o[12];
+    load_as_f32<SIN>(in, s, npad, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] = cmake(0.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const cpx<float> kr = cmake(K[4 * r + e].x, K[4 * r + e].y);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[4 * a + r] = cmac(kr, v[4 * a + e], o[4 * a + r]);
+      }
+    SpinorIO<S_F32>::store((char *)m + ya * hb, s, npad, o);
+    return;
+  }
+  // every lane takes part in the matrix products; lanes past the last site
+  // carry zeros and store nothing
+  const SiteC c = site_c(g, live ? s : sb * WAVE, ya);
+  bf16x8 A[2][2];   // [ks][hi, lo] of M-tile w
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int hl = 0; hl < 2; ++hl) A[ks][hl] = frag[((w * 2 + ks) * 2 + hl) * WAVE + lane];
+  f32x4 D[4][3];   // [site tile][colour]
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) D[j][a] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int g4 = lane >> 4, n = lane & 15;
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    cpx<float> t[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = cmake(0.f, 0.f);
+    if (live) {
+      int mu;
+      bool fwd;
+      path_of(1 + 4 * ks + w, mu, fwd);
+      const int nb_ = nbr(g, c, mu, fwd);
+      cpx<float> u[9], psi[12];
+      if (fwd) LinkIO<L_F32R12>::load(links, ya, mu, s, g.nb, u);
+      else LinkIO<L_F32R12>::load(links, 1 - ya, mu, nb_, g.nb, u);
+      load_as_f32<SIN>(in, nb_, npad, psi);
+      transport(u, psi, t, !fwd);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float xr = t[4 * a + e].re, xi = t[4 * a + e].im;
+        const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
+        h[2 * e] = hr;
+        h[2 * e + 1] = hi;
+        l[2 * e] = (__bf16)(xr - (float)hr);
+        l[2 * e + 1] = (__bf16)(xi - (float)hi);
+      }
+      lds_hi[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, h);
+      lds_lo[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, l);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_hi[(g4 * 3 + a) * WAVE + 16 * j + n]);
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_lo[(g4 * 3 + a) * WAVE + 16 * j + n]);
+        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bh, D[j][a], 0, 0, 0);
+        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bl, D[j][a], 0, 0, 0);
+        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][1], bh, D[j][a], 0, 0, 0);
+      }
+    __syncthreads();   // the next K-step overwrites the LDS tiles
+  }
+  // lane (g4, n) holds rows 4 g4 .. 4 g4 + 3 of column (site 16 j + n, colour a):
+  // path 1 + 2w + g4 / 2, float4 unit 2a + g4 % 2 of the F32 spinor layout
+  float4 *base = (float4 *)((char *)m + (size_t)(1 + 2 * w + (g4 >> 1)) * mstride + ya * hb);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (sb * WAVE + 16 * j + n >= g.vh) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const f32x4 d = D[j][a];
+      base[((size_t)sb * 6 + 2 * a + (g4 & 1)) * WAVE + 16 * j + n] = make_float4(d[0], d[1], d[2], d[3]);
+    }
   }
 }
 
@@ -834,35 +967,37 @@ hipError_t wgrad_launch(const qiral_nn *nn, int cin, int cout, const void *in, c
   return hipGetLastError();
 }
 
-// K and K' of the current weights into nn->kmat (before folded inference).
+// K and K' of the current weights into nn->kmat, and their MFMA fragments into
+// nn->kfrag (before folded inference).
 hipError_t nn_fold(const qiral_nn *nn, hipStream_t s) {
-  const int n = NPATH * NPATH * 16;
-  for (int adj = 0; adj < 2; ++adj)
+  const int n = NPATH * NPATH * 16, nf = 4 * 2 * 2 * 64 * 8;
+  for (int adj = 0; adj < 2; ++adj) {
     hipLaunchKernelGGL(k_nn_fold, dim3((n + 255) / 256), dim3(256), 0, s, nn->w, nn->w + nn->nw1, nn->hidden, adj,
                        nn->kmat + adj * n);
+    hipLaunchKernelGGL(k_nn_frag, dim3(nf / 256), dim3(256), 0, s, (const float2 *)(nn->kmat + adj * n),
+                       (__bf16 *)nn->kfrag + adj * nf);
+  }
   return hipGetLastError();
 }
 
 // out = N(in) (adj = false) or N^dagger(in), folded, with the K of the last
 // nn_fold.  SIO: storage of in and out (packed F32 or F64 fields), given as
 // half-fields (in0, in1) and (out0, out1).  par >= 0: in is zero off parity par
-// (in0 or in1 is then not read) and only that parity of out is written.
+// (in0 or in1 is then not read) and only that parity of out is written, and
+// pass A runs on bf16 MFMA (about 1e-5 relative; the flexible solvers only).
 template <int SIO>
 hipError_t nn_apply_folded(const qiral_nn *nn, void *out0, void *out1, const void *in0, const void *in1, bool adj,
                            hipStream_t s, int par = -1) {
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
   const float2 *K = nn->kmat + (adj ? NPATH * NPATH * 16 : 0);
-  const unsigned gx = (unsigned)nblk(g.vh), ga = (unsigned)((g.nb + 1) / 2);
-  // the output paths in two waves per site block: the eight hops of the Schur
-  // form four each, all nine paths five and four
   if (par >= 0)
-    hipLaunchKernelGGL((k_nn_pass_a<SIO, 4>), dim3(ga, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
-                       par, par);
-  else
-    hipLaunchKernelGGL((k_nn_pass_a<SIO, 5>), dim3(ga, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1, nn->act, fs,
-                       par, par);
-  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3(gx, par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
+    hipLaunchKernelGGL((k_nn_pass_a_mfma<SIO>), dim3(g.nb, 2), dim3(256), 0, s, g, nn->lat->g32, K,
+                       (const bf16x8 *)nn->kfrag + (adj ? 4 * 2 * 2 * WAVE : 0), par ? in1 : in0, nn->act, fs, par);
+  else   // all nine output paths in two waves per site block, five and four
+    hipLaunchKernelGGL((k_nn_pass_a<SIO, 5>), dim3((g.nb + 1) / 2, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1,
+                       nn->act, fs);
+  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3(nblk(g.vh), par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
                      (const void *)nn->act, fs, out0, out1, par);
   return hipGetLastError();
 }
@@ -932,7 +1067,7 @@ void neumann2(int hidden, double kappa, std::vector<float2> &w) {
 namespace {
 // Offsets of the network's device memory (one caller-owned buffer).
 struct NnLayout {
-  size_t w, wadj, kmat, am, av, grad, part, scal, act, gact, pairx, fv, fb, fy, fg, loss, total;
+  size_t w, wadj, kmat, kfrag, am, av, grad, part, scal, act, gact, pairx, fv, fb, fy, fg, loss, total;
 };
 inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 NnLayout nn_layout(const Geo &g, int hidden) {
@@ -945,6 +1080,7 @@ NnLayout nn_layout(const Geo &g, int hidden) {
   l.w = take(sizeof(float2) * nw);
   l.wadj = take(sizeof(float2) * nw);
   l.kmat = take(sizeof(float2) * 2 * NPATH * NPATH * 16);
+  l.kfrag = take(2 * 4 * 2 * 2 * 64 * 8 * sizeof(__bf16));
   l.am = take(sizeof(float) * 2 * nw);
   l.av = take(sizeof(float) * 2 * nw);
   l.grad = take(sizeof(double) * 2 * nw);
@@ -991,6 +1127,7 @@ extern "C" qiral_status qiral_nn_create(qiral_nn **out, qiral_lattice *lat, int3
   nn->w = (float2 *)(m + l.w);
   nn->wadj = (float2 *)(m + l.wadj);
   nn->kmat = (float2 *)(m + l.kmat);
+  nn->kfrag = m + l.kfrag;
   nn->am = (float *)(m + l.am);
   nn->av = (float *)(m + l.av);
   nn->grad = (double *)(m + l.grad);
@@ -1275,8 +1412,8 @@ hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s
 // z = M v (or M^dagger v): the folded network in FP32 on v (full system) or on
 // v placed on the odd sites, keeping the odd part of the result (Schur system:
 // the passes skip the paths and sites that would only add zeros or be
-// dropped), reading and writing the FP64 Krylov vectors directly; the identity
-// without a network.
+// dropped, and the path-pair products run on bf16 MFMA), reading and writing
+// the FP64 Krylov vectors directly; the identity without a network.
 hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s) {
   if (!f.nn) return hipMemcpyAsync(z, v, f.vb, hipMemcpyDeviceToDevice, s);
   if (f.schur) return nn_apply_folded<S_F64>(f.nn, nullptr, z, nullptr, v, adj, s, 1);
