@@ -697,15 +697,6 @@ __global__ __launch_bounds__(256) void k_chi64(Geo g, const void *__restrict__ i
   SpinorIO<S_F64>::store(out, (int)s, npad, v);
 }
 
-// y = c[0] x + c[1] y (complex coefficients)
-__global__ __launch_bounds__(256) void k_zaxpby(const double2 *__restrict__ c, const double2 *__restrict__ x,
-                                                double2 *__restrict__ y, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double2 a = c[0], b = c[1], xv = x[i], yv = y[i];
-  y[i] = make_double2(a.x * xv.x - a.y * xv.y + b.x * yv.x - b.y * yv.y,
-                      a.x * xv.y + a.y * xv.x + b.x * yv.y + b.y * yv.x);
-}
 
 // Complex dots (V_i | w) for i < k, with partials per work-group.
 __global__ __launch_bounds__(256) void k_mdot(const double2 *__restrict__ V, size_t vstride, int k,
@@ -801,7 +792,7 @@ __global__ __launch_bounds__(256) void k_zaxpyz(const double2 *__restrict__ c, c
 // an iteration needs one read by the host (||r||^2 and the breakdown flags).
 enum : int {
   BQ_RHO = 40, BQ_ALPHA, BQ_OMEGA, BQ_RHO1, BQ_RV, BQ_TS, BQ_TT, BQ_RN2, BQ_FLAG,   // scalars; FLAG.x, .y below
-  BQ_C_OMEGA = 50, BQ_C_ZB, BQ_C_ZB2, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA      // coefficients of the vector kernels
+  BQ_C_OMEGA = 50, BQ_C_BETA, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA      // coefficients of the vector kernels
 };
 // FLAG.x: the iteration broke down before x changed (rho_new or (r~, v) zero):
 // every later coefficient is 0, so x keeps its value and every vector stays
@@ -837,8 +828,7 @@ __global__ void k_bq_beta(double2 *c) {
     c[BQ_RHO] = rho1;
   }
   c[BQ_C_OMEGA] = om;
-  c[BQ_C_ZB] = make_double2(1.0, 0.0);
-  c[BQ_C_ZB2] = beta;
+  c[BQ_C_BETA] = beta;
 }
 
 // alpha = rho_new / (r~, v); coefficient of s = r - alpha v
@@ -866,6 +856,80 @@ __global__ void k_bq_omega(double2 *c) {
   c[BQ_C_X] = al;
   c[BQ_C_X2] = om;
   c[BQ_C_MOMEGA] = make_double2(-om.x, -om.y);
+}
+
+// Fused BiCGStab vector steps (one pass each where the unfused steps took two).
+// Block partial pairs of a complex dot, (a | b) = sum conj(a) b, in the order
+// of k_mdot: wave sums, then (w0 + w1) + (w2 + w3).
+__device__ __forceinline__ void block_pair(double re, double im, double *__restrict__ dst) {
+  __shared__ double red[2][4];
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    dst[threadIdx.x] = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+}
+
+// P = R + beta[0] (P - omega[0] V)
+__global__ __launch_bounds__(256) void k_bq_p(const double2 *__restrict__ beta, const double2 *__restrict__ omega,
+                                              const double2 *__restrict__ R, const double2 *__restrict__ V,
+                                              double2 *__restrict__ P, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 be = beta[0], om = omega[0], r = R[i], v = V[i];
+  double2 p = P[i];
+  p.x -= om.x * v.x - om.y * v.y;
+  p.y -= om.x * v.y + om.y * v.x;
+  P[i] = make_double2(r.x + (be.x * p.x - be.y * p.y), r.y + (be.x * p.y + be.y * p.x));
+}
+
+// partial pairs of (a | b) and (c | d): part[(q * gridDim.x + block) * 2 + re/im]
+__global__ __launch_bounds__(256) void k_dot2(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                                              const double2 *__restrict__ c, const double2 *__restrict__ d, size_t n,
+                                              double *__restrict__ part) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 ab = make_double2(0.0, 0.0), cd = ab;
+  if (i < n) {
+    const double2 av = a[i], bv = b[i], cv = c[i], dv = d[i];
+    ab = make_double2(av.x * bv.x + av.y * bv.y, av.x * bv.y - av.y * bv.x);
+    cd = make_double2(cv.x * dv.x + cv.y * dv.y, cv.x * dv.y - cv.y * dv.x);
+  }
+  block_pair(ab.x, ab.y, part + (size_t)blockIdx.x * 2);
+  __syncthreads();
+  block_pair(cd.x, cd.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
+}
+
+// R = S + c[0] T, with the partial pairs of (RT | R) and (R | R) as k_dot2
+__global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ c, const double2 *__restrict__ S,
+                                              const double2 *__restrict__ T, const double2 *__restrict__ RT,
+                                              double2 *__restrict__ R, size_t n, double *__restrict__ part) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 rr = make_double2(0.0, 0.0), tr = rr;
+  if (i < n) {
+    const double2 a = c[0], sv = S[i], tv = T[i], rt = RT[i];
+    const double2 r = make_double2(sv.x + (a.x * tv.x - a.y * tv.y), sv.y + (a.x * tv.y + a.y * tv.x));
+    R[i] = r;
+    tr = make_double2(rt.x * r.x + rt.y * r.y, rt.x * r.y - rt.y * r.x);
+    rr = make_double2(r.x * r.x + r.y * r.y, 0.0);
+  }
+  block_pair(tr.x, tr.y, part + (size_t)blockIdx.x * 2);
+  __syncthreads();
+  block_pair(rr.x, rr.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
+}
+
+// coef[slot0] and coef[slot1] = the sums of the two partial-pair rows (grid 2)
+__global__ __launch_bounds__(256) void k_dot2_final(const double *__restrict__ part, int nblk,
+                                                    double2 *__restrict__ coef, int slot0, int slot1) {
+  __shared__ double red[2][4];
+  const int q = blockIdx.x;
+  const double2 sum = strided_sum((const double2 *)(part + (size_t)q * nblk * 2), nblk, (int)threadIdx.x);
+  const double re = wave_sum(sum.x), im = wave_sum(sum.y);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    coef[q == 0 ? slot0 : slot1] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                                                (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
 }
 
 // FCG step: x += alpha p, r -= alpha q, s -= alpha w (alpha = coef[0]); partial
@@ -1783,14 +1847,13 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
     QIRAL_HIP(hipMemsetAsync(Vv, 0, f.vb, s));
     hipLaunchKernelGGL(k_bq_init, dim3(1), dim3(1), 0, s, f.coef);
     bool restart = false;
+    flex_dot_dev(f, RT, R, BQ_RHO1, s);   // later iterations get it from k_bq_r
     while (rn > target && it < prm->maxiter) {
       // the scalars stay on the device (k_bq_*); the host reads ||r||^2 and the
       // breakdown flags once per iteration
-      flex_dot_dev(f, RT, R, BQ_RHO1, s);
       hipLaunchKernelGGL(k_bq_beta, dim3(1), dim3(1), 0, s, f.coef);
       // P = R + beta (P - omega V)
-      hipLaunchKernelGGL(k_maxpy, gv, bv, 0, s, Vv, f.n2, 1, f.coef + BQ_C_OMEGA, -1.0, P, f.n2);
-      hipLaunchKernelGGL(k_zaxpby, gv, bv, 0, s, f.coef + BQ_C_ZB, R, P, f.n2);
+      hipLaunchKernelGGL(k_bq_p, gv, bv, 0, s, f.coef + BQ_C_BETA, f.coef + BQ_C_OMEGA, R, Vv, P, f.n2);
       QIRAL_HIP(flex_M(f, PH, P, false, s));
       QIRAL_HIP(flex_A(f, Vv, PH, false, s));
       flex_dot_dev(f, RT, Vv, BQ_RV, s);
@@ -1799,13 +1862,15 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
       hipLaunchKernelGGL(k_zaxpyz, gv, bv, 0, s, f.coef + BQ_C_MALPHA, Vv, R, Sv, f.n2);
       QIRAL_HIP(flex_M(f, SH, Sv, false, s));
       QIRAL_HIP(flex_A(f, T, SH, false, s));
-      flex_dot_dev(f, T, Sv, BQ_TS, s);
-      flex_norm2_dev(f, T, BQ_TT, s);
+      // (T | S) and ||T||^2
+      hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, T, Sv, T, T, f.n2, f.part);
+      hipLaunchKernelGGL(k_dot2_final, dim3(2), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_TS, (int)BQ_TT);
       hipLaunchKernelGGL(k_bq_omega, dim3(1), dim3(1), 0, s, f.coef);
-      // X += alpha PH + omega SH; R = S - omega T
+      // X += alpha PH + omega SH; R = S - omega T with (RT | R) for the next
+      // iteration's rho and ||R||^2
       hipLaunchKernelGGL(k_maxpy, gv, bv, 0, s, PH, f.n2, 2, f.coef + BQ_C_X, 1.0, X, f.n2);
-      hipLaunchKernelGGL(k_zaxpyz, gv, bv, 0, s, f.coef + BQ_C_MOMEGA, T, Sv, R, f.n2);
-      flex_norm2_dev(f, R, BQ_RN2, s);
+      hipLaunchKernelGGL(k_bq_r, gv, bv, 0, s, f.coef + BQ_C_MOMEGA, Sv, T, RT, R, f.n2, f.part);
+      hipLaunchKernelGGL(k_dot2_final, dim3(2), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RHO1, (int)BQ_RN2);
       double2 q[2];   // RN2, FLAG
       if ((st = flex_read(q, f.coef + BQ_RN2, sizeof q, s)) != QIRAL_OK) return st;
       if (q[1].x != 0.0) { restart = true; break; }   // broke down before x changed
