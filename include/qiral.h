@@ -304,12 +304,19 @@ qiral_status qiral_solve_static(qiral_lattice *lat, double *x_canon, const doubl
  * runs in FP32 on the lattice's FP32 links, on packed FP32 FULL fields.  It is
  * created with the weights of 1 + kappa H + kappa^2 H^2 (channel 0 carries psi,
  * channel 1 carries H psi).  It is used by qiral_solve with solver
- * QIRAL_FGMRES_NN or QIRAL_FCG_NN and params.precond pointing to it. */
+ * QIRAL_FGMRES_NN, QIRAL_FCG_NN or QIRAL_BICGSTAB_EO and params.precond
+ * pointing to it.  The layers are linear, so applications use the folded form
+ * N = sum_{p,q} T_p K_pq T_q, K_pq = sum_c W2_p^c W1_q^c (equal up to rounding);
+ * on the Schur system the solvers run its path-pair products on bf16 matrix
+ * cores with hi/lo splitting (about 1e-5 relative), qiral_nn_apply in FP32. */
 
 /* Device bytes of a network with `hidden` channels (2, 4 or 8) on this lattice:
- * weights, adjoint weights, Adam moments, gradient, partial sums, the hidden
- * activations and their gradient (hidden FP32 full fields each), four FP32 full
- * fields for training pairs, and 256 training losses.  0 for invalid arguments. */
+ * weights, adjoint weights, the folded weights and their matrix-core fragments,
+ * Adam moments, gradient, partial sums, the hidden activations and their
+ * gradient (hidden FP32 full fields each; folded applications keep nine FP32
+ * full fields there, with 9 - 2 hidden more when hidden is 2 or 4), four FP32
+ * full fields for training pairs, and 256 training losses.  0 for invalid
+ * arguments.  Calls on one network use its memory: they must not overlap. */
 size_t qiral_nn_bytes(const qiral_lattice *lat, int32_t hidden);
 /* Create a network in the caller's device memory mem (256-byte aligned, at least
  * qiral_nn_bytes bytes, else QIRAL_ERR_WORKSPACE), which must outlive it; the
