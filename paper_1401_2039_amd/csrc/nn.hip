@@ -264,15 +264,18 @@ __device__ __forceinline__ void load_as_f32(const void *half, int s, size_t npad
 // F32 half-field m + p * mstride + parity * (npad * 96 bytes).  Two waves share
 // a 64-site block, each sweeping the input paths for its own PC output paths,
 // so the second wave's neighbour loads hit the cache lines the first has just
-// brought in.  Grid: (ceil(nb / 2), 2 parities), 256 threads: two site blocks.
+// brought in.  Site blocks in the hop's XCD-mapped order (zb as block_order).
+// Grid: (ceil(nb / 2), 2 parities), 256 threads: two site blocks.
 template <int SIN, int PC>
 __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict__ links,
                                                    const float2 *__restrict__ K, const void *__restrict__ in0,
                                                    const void *__restrict__ in1, void *__restrict__ m,
-                                                   size_t mstride) {
+                                                   size_t mstride, int zb) {
   const int ya = blockIdx.y;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int s = (blockIdx.x * 2 + (w >> 1)) * WAVE + (threadIdx.x & (WAVE - 1));
+  const int L = xcd_remap(blockIdx.x, gridDim.x) * 2 + (w >> 1);
+  if (L >= g.nb) return;
+  const int s = block_order(g, L, zb) * WAVE + (threadIdx.x & (WAVE - 1));
   if (s >= g.vh) return;
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   const int p0 = (w & 1) * PC, p1 = min(NPATH, p0 + PC);
@@ -339,7 +342,8 @@ __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict
 // spin components of one colour of one site, which is exactly a float4 unit of
 // the F32 spinor layout, so the results are stored straight from the
 // accumulators.  Sites of parity P keep m_0 = K_00 v (vector ALU).  A
-// fragments come from k_nn_frag.  Grid: (nb, 2 parities), 256 threads.
+// fragments come from k_nn_frag.  Site blocks in the hop's XCD-mapped order.
+// Grid: (nb, 2 parities), 256 threads.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -364,12 +368,12 @@ template <int SIN>
 __global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__restrict__ links,
                                                         const float2 *__restrict__ K, const bf16x8 *__restrict__ frag,
                                                         const void *__restrict__ in, void *__restrict__ m,
-                                                        size_t mstride, int par) {
+                                                        size_t mstride, int par, int zb) {
   __shared__ uint4 lds_hi[4 * 3 * WAVE], lds_lo[4 * 3 * WAVE];   // [q in K-step][colour][site]
   const int ya = blockIdx.y;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (WAVE - 1);
-  const int sb = blockIdx.x, s = sb * WAVE + lane;
+  const int sb = block_order(g, xcd_remap(blockIdx.x, gridDim.x), zb), s = sb * WAVE + lane;
   const bool live = s < g.vh;
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   if (ya == par) {
@@ -462,14 +466,17 @@ __global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__res
 }
 
 // Pass B: out(x) = sum_p (T_p m_p)(x) at the sites of parity out_par (both if
-// negative; grid (sites / 256, 1 or 2)), written in storage SOUT to out0 (even
-// half) or out1 (odd half).
+// negative; grid (ceil(nb / 4), 1 or 2), four site blocks in the hop's
+// XCD-mapped order), written in storage SOUT to out0 (even half) or out1 (odd
+// half).
 template <int SOUT>
 __global__ __launch_bounds__(256) void k_nn_pass_b(Geo g, const void *__restrict__ links, const void *__restrict__ m,
                                                    size_t mstride, void *__restrict__ out0, void *__restrict__ out1,
-                                                   int out_par) {
+                                                   int out_par, int zb) {
   const int px = out_par >= 0 ? out_par : (int)blockIdx.y;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+  if (L >= g.nb) return;
+  const int s = block_order(g, L, zb) * WAVE + (int)(threadIdx.x & (WAVE - 1));
   if (s >= g.vh) return;
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   const SiteC c = site_c(g, s, px);
@@ -1055,14 +1062,16 @@ hipError_t nn_apply_folded(const qiral_nn *nn, void *out0, void *out1, const voi
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
   const float2 *K = nn->kmat + (adj ? NPATH * NPATH * 16 : 0);
+  const int zb = hop_zb(g);   // the hops' z-tiles: neighbours stay in one XCD's L2
   if (par >= 0)
     hipLaunchKernelGGL((k_nn_pass_a_mfma<SIO>), dim3(g.nb, 2), dim3(256), 0, s, g, nn->lat->g32, K,
-                       (const bf16x8 *)nn->kfrag + (adj ? 4 * 2 * 2 * WAVE : 0), par ? in1 : in0, nn->act, fs, par);
+                       (const bf16x8 *)nn->kfrag + (adj ? 4 * 2 * 2 * WAVE : 0), par ? in1 : in0, nn->act, fs, par,
+                       zb);
   else   // all nine output paths in two waves per site block, five and four
     hipLaunchKernelGGL((k_nn_pass_a<SIO, 5>), dim3((g.nb + 1) / 2, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1,
-                       nn->act, fs);
-  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3(nblk(g.vh), par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
-                     (const void *)nn->act, fs, out0, out1, par);
+                       nn->act, fs, zb);
+  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3((g.nb + 3) / 4, par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
+                     (const void *)nn->act, fs, out0, out1, par, zb);
   return hipGetLastError();
 }
 
