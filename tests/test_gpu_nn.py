@@ -59,7 +59,7 @@ def _rand_weights(seed, H):
     return w1.astype(np.complex64), w2.astype(np.complex64)
 
 
-@pytest.mark.parametrize("H", [2, 8])
+@pytest.mark.parametrize("H", [2, 4, 8])
 def test_forward_and_adjoint(setup, H):
     cfg, lat, Ur = setup
     say("nn forward/adjoint", H)
