@@ -89,3 +89,26 @@ def test_cgnr_on_the_full_system(lattice):
     # it stops on the updated residual, the oracle here on the recomputed one
     assert abs(info[0]["iterations"] - io) <= 1, (info[0]["iterations"], io)
     assert S.true_rel_residual(U, k, mu, host(x)[0], b) <= 1e-10
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "fcg"])
+@pytest.mark.parametrize("steps", [1, 2])
+def test_schur_network_iterates(lattice, solver, steps):
+    """On the Schur system the network's path-pair products run on bf16 matrix
+    cores (hi and lo parts, three products); BiCGStab applies it, FCG applies it
+    and its adjoint.  Stopped after `steps` iterations, x equals the oracle
+    composition's iterate with the FP64 network to the precision of that split."""
+    L = lattice
+    U, k, mu, b = L["U"], L["k"], L["mu"], L["b"][0]
+    say("schur network iterates", solver, steps)
+    w = L["w"]
+    xo, io = C.solve(U, k, mu, b, solver, "schur", lambda v: ptc.network(U, w, v),
+                     lambda v: ptc.network_adjoint(U, w, v), tol=1e-10, m=20, maxiter=steps)
+    assert io["iterations"] == steps
+    x, st, info = L["lat"].solve(dev(L["b"]), tol=1e-10, solver=SOLVERS[solver], system=q.SYSTEM_SCHUR,
+                                 precond=L["net"].handle, restart=20, maxiter=steps, fallback_cg=0)
+    assert info[0]["iterations"] == steps and info[0]["converged"] == 0, info[0]
+    xg = host(x)[0]
+    rel = np.sqrt(np.vdot(xg - xo, xg - xo).real / np.vdot(xo, xo).real)
+    say("  relative difference", rel)
+    assert rel < 1e-5, rel
