@@ -422,6 +422,8 @@ def suite(q, latgen, np, torch, path=None, parts=(), hop_reps=None):
         suite_c64(q, latgen, torch, path, timed_solve, flush, hop_reps)
     if "compose" in parts:
         suite_compose(q, latgen, torch, path, timed_solve)
+    if "shard" in parts:
+        suite_shard(q, latgen, torch, path, flush, hop_reps)
 
 
 def suite_c1(lat1, q, latgen, torch, path, timed_solve):
@@ -714,6 +716,33 @@ def suite_c64(q, latgen, torch, path, timed_solve, flush, hop_reps=None):
                "device_gb": round(torch.cuda.max_memory_allocated() / 1e9, 1)}, path)
     lat.close()
 
+
+def suite_shard(q, latgen, torch, path, flush, hop_reps=None):
+    """One GPU's share of a lattice split along t over 8 GPUs, at its real shape:
+    the hop over the local volume, periodic (the exchange of boundary planes is
+    not built).  24^3x6 (24^3x48 / 8) takes the first 6 t-slices of the 24^3x48
+    links; 64^3x16 (64^3x128 / 8) the first 16 t-slices of the 32^3x64 links,
+    tiled twice along x, y and z."""
+    c2 = latgen.make_config(2, with_source=False)
+    dims = (24, 24, 24, 6)
+    lat = q.Lattice(dims, c2["kappa"], c2["U"][:6].copy())
+    del c2
+    for prec in (q.F64, q.F32, q.F16S):
+        rec = hop_rates(q, lat, dims, torch, prec, reps=hop_reps or 200, flush=flush)
+        rec["share_of"] = "24^3x48 over 8 GPUs (t split)"
+        _emit(rec, path)
+    lat.close()
+    cell = latgen.make_config(99, with_source=False)
+    dims = (64, 64, 64, 16)
+    U = torch.from_numpy(cell["U"][:16].copy()).cuda().repeat(1, 2, 2, 2, 1, 1, 1)
+    lat = q.Lattice(dims, cell["kappa"], U)
+    del U, cell
+    b = latgen.device_gaussian_source(101, 0, dims, 1)
+    for prec in (q.F64, q.F32, q.F16S):
+        rec = hop_rates(q, lat, dims, torch, prec, reps=hop_reps or 20, flush=flush, psi=b)
+        rec["share_of"] = "64^3x128 over 8 GPUs (t split)"
+        _emit(rec, path)
+    lat.close()
 
 if __name__ == "__main__":
     main()
