@@ -23,6 +23,10 @@ The JSON line also carries:
   on its stream: warm (back-to-back launches) and cold (single launches, each
   after a 1 GiB read that replaces the cache's contents); HBM traffic from the
   committed counter summary while the hop sources are unchanged;
+- learned: the learned preconditioner against plain FP64 eo-CGNR on the
+  24^3x48, exp(0.5 i H), kappa 0.125 lattice with 12 Gaussian sources (the
+  network trained on 2048 pairs (D v, v) first, training time reported apart,
+  with the break-even count of 12-source solves);
 - the one-time link packing time, a measured 1 GiB device copy, and the CPU
   oracle timed on a bounded sample (a few CGNR iterations of the same system).
 
@@ -88,6 +92,7 @@ def main():
     ap.add_argument("--hop-reps", type=int, default=50, help="back-to-back hop launches per warm trial")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle CGNR iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads (stderr JSON lines)")
     ap.add_argument("--suite-out", default=None, help="append the suite's JSON lines to this file")
     ap.add_argument("--parts", default="c1,c0,c2,c3,c99,c4", help="suite parts to run")
@@ -225,6 +230,8 @@ def main():
     copy_gbs = 2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del cx, cy
 
+    learned = None if args.no_learned else learned_vs_cgnr(q, latgen, torch, dev)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, args.cpu_iters)
@@ -249,6 +256,7 @@ def main():
         "true_rel_resid_max": max(i["true_rel_resid"] for i in infos),
         "hop_applications_per_step": hops // args.steps,
         "batched": batched,
+        "learned": learned,
         "roofline": {"bound": "hbm", "kernel": ROOFLINE_KERNEL + " (qiral_dslash_eo, FP64, links read as rows 0-1, 1 RHS)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
@@ -266,6 +274,71 @@ def main():
     if args.suite:
         suite(q, latgen, np, torch, args.suite_out, args.parts.split(','), args.suite_hop_reps)
     lat.close()
+
+
+def learned_vs_cgnr(q, latgen, torch, dev, steps=2048):
+    """The learned preconditioner against plain FP64 eo-CGNR on the 24^3x48,
+    exp(0.5 i H), kappa 0.125 lattice with 12 Gaussian sources: the 2-layer
+    network (8 hidden channels) trained on `steps` pairs (D v, v), then BiCGStab
+    on the Schur system with it as right preconditioner, all 12 sources in one
+    qiral_solve call, against the 12 sources solved one after the other by FP64
+    eo-CGNR; both to a 1e-10 true residual, each timed once after a warm-up."""
+    c4 = latgen.make_config(4)
+    lat = q.Lattice(c4["dims"], c4["kappa"], c4["U"])
+    b = torch.from_numpy(c4["b"]).to(dev)
+    n = b.shape[0]
+    del c4
+    net = q.Network(lat, 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(steps, lr=1e-3, seed=4)
+    t_train = time.perf_counter() - t0
+    pl = q.solve_params(solver=q.BICGSTAB_EO, system=q.SYSTEM_SCHUR, tol=1e-10, maxiter=4000)
+    pl.precond = net.handle
+    p64 = q.solve_params(tol=1e-10, inner_prec=q.F64)
+    wl = torch.empty(q.qiral_solve_workspace_bytes(lat.handle, pl, n), dtype=torch.uint8, device=dev)
+    w64 = torch.empty(q.qiral_solve_workspace_bytes(lat.handle, p64, 1), dtype=torch.uint8, device=dev)
+    x = torch.zeros_like(b)
+
+    def learned():
+        st, info = q.qiral_solve(lat.handle, lat.dims, x, b, n, pl, ws=wl)
+        if st != 0:
+            raise RuntimeError(f"learned solve failed: status {st}")
+        return info
+
+    def cgnr():
+        infos = []
+        for r in range(n):
+            st, info = q.qiral_solve(lat.handle, lat.dims, x[r:r + 1], b[r:r + 1], 1, p64, ws=w64)
+            if st != 0:
+                raise RuntimeError(f"FP64 eo-CGNR solve failed: status {st}")
+            infos.append(info[0])
+        return infos
+
+    out = {}
+    for name, fn in (("learned", learned), ("cgnr", cgnr)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0, info)
+    tl, il = out["learned"]
+    tc, ic = out["cgnr"]
+    res = {"workload": "24^3x48 lattice, exp(0.5iH) links, kappa=0.125, 12 Gaussian sources",
+           "form": "BiCGStab on the Schur system, trained 2-layer PTC network (8 hidden) as right preconditioner",
+           "time_to_solution_s": round(tl, 5), "fp64_cgnr_12_sequential_s": round(tc, 5),
+           "speedup_vs_fp64_cgnr": round(tc / tl, 3), "iterations": [i["iterations"] for i in il],
+           "cgnr_iterations": [i["iterations"] for i in ic],
+           "true_rel_resid_max": max(i["true_rel_resid"] for i in il),
+           "training_s": round(t_train, 3), "training_pairs": steps,
+           "loss_first64": round(float(sum(hist[:64]) / 64), 5), "loss_last64": round(float(sum(hist[-64:]) / 64), 5),
+           "break_even_solves_of_12": round(t_train / (tc - tl), 1) if tc > tl else None}
+    log(f"[bench] learned: {tl * 1e3:.1f} ms against FP64 eo-CGNR {tc * 1e3:.1f} ms "
+        f"({res['speedup_vs_fp64_cgnr']}x), training {t_train:.1f}s")
+    net.close()
+    lat.close()
+    return res
 
 
 def cpu_baseline(cfg, iters):
