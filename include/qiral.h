@@ -244,8 +244,11 @@ typedef struct {
  * nrhs right-hand sides needs on this lattice (0 for invalid arguments).  It
  * holds the Krylov vectors (5, 7 or 8 half-fields per right-hand side in the
  * iterate precision, plus 6 FP64 half-fields and, mixed, one FP32), the system
- * and work tables, per-system states and reduction partials; for FGMRES/FCG, the
- * flexible solver's FP64 full fields (the larger of that and its CGNR fallback). */
+ * and work tables, per-system states and reduction partials; for FGMRES/FCG and
+ * the preconditioned or full-system BiCGStab, the flexible solver's FP64 fields
+ * (the larger of that and its CGNR fallback): FGMRES and FCG solve the
+ * right-hand sides one after the other, BiCGStab all of them in lockstep (its
+ * Krylov vectors for each). */
 size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params, int32_t nrhs);
 /* The same for qiral_solve_batch over nsys lattices (0 for FGMRES/FCG). */
 size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *lats, int32_t nsys,

@@ -786,20 +786,14 @@ __global__ __launch_bounds__(256) void k_bminus(const double2 *__restrict__ b, d
   if (i < n) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
 }
 
-// out = y + c[0] x (complex c; out may not alias x)
-__global__ __launch_bounds__(256) void k_zaxpyz(const double2 *__restrict__ c, const double2 *__restrict__ x,
-                                                const double2 *y, double2 *out, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double2 a = c[0], xv = x[i], yv = y[i];
-  out[i] = make_double2(yv.x + (a.x * xv.x - a.y * xv.y), yv.y + (a.x * xv.y + a.y * xv.x));
-}
 
 // Right-preconditioned BiCGStab's scalars, kept on the device in coef[] so that
 // an iteration needs one read by the host (||r||^2 and the breakdown flags).
 enum : int {
   BQ_RHO = 40, BQ_ALPHA, BQ_OMEGA, BQ_RHO1, BQ_RV, BQ_TS, BQ_TT, BQ_RN2, BQ_FLAG,   // scalars; FLAG.x, .y below
-  BQ_C_OMEGA = 50, BQ_C_BETA, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA      // coefficients of the vector kernels
+  BQ_C_OMEGA = 50, BQ_C_BETA, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA,     // coefficients of the vector kernels
+  BQ_DONE = 56, BQ_TGT2,   // DONE.x != 0: converged (see k_bq_done); TGT2.x = (tol ||b||)^2
+  BQ_SLOTS = 64            // coefficient slots per system: system k's are coef[64 k ..]
 };
 // FLAG.x: the iteration broke down before x changed (rho_new or (r~, v) zero):
 // every later coefficient is 0, so x keeps its value and every vector stays
@@ -818,16 +812,27 @@ __device__ inline double2 zdiv(double2 a, double2 b) {
 __device__ inline bool zzero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
 
 // (re)start: rho = alpha = omega = 1, no flags
-__global__ void k_bq_init(double2 *c) {
+// The scalar steps run for nsys systems at once, one thread each, on system
+// k's slots coef[BQ_SLOTS k ..].  A system marked DONE gets coefficients that
+// leave x and r as they are (p = r, s = r, x += 0, r = s).
+__global__ void k_bq_init(double2 *coef, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  double2 *c = coef + (size_t)k * BQ_SLOTS;
   c[BQ_RHO] = c[BQ_ALPHA] = c[BQ_OMEGA] = make_double2(1.0, 0.0);
   c[BQ_FLAG] = make_double2(0.0, 0.0);
 }
 
 // beta = (rho_new / rho) (alpha / omega); coefficients of p = r + beta (p - omega v)
-__global__ void k_bq_beta(double2 *c) {
+__global__ void k_bq_beta(double2 *coef, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  double2 *c = coef + (size_t)k * BQ_SLOTS;
   const double2 rho1 = c[BQ_RHO1];
   double2 beta = make_double2(0.0, 0.0), om = make_double2(0.0, 0.0);
-  if (zzero(rho1)) {
+  if (c[BQ_DONE].x != 0.0) {
+    // p = r
+  } else if (zzero(rho1)) {
     c[BQ_FLAG].x = 1.0;
   } else {
     beta = zmul(zdiv(rho1, c[BQ_RHO]), zdiv(c[BQ_ALPHA], c[BQ_OMEGA]));
@@ -839,9 +844,12 @@ __global__ void k_bq_beta(double2 *c) {
 }
 
 // alpha = rho_new / (r~, v); coefficient of s = r - alpha v
-__global__ void k_bq_alpha(double2 *c) {
+__global__ void k_bq_alpha(double2 *coef, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  double2 *c = coef + (size_t)k * BQ_SLOTS;
   double2 al = make_double2(0.0, 0.0);
-  if (c[BQ_FLAG].x == 0.0) {
+  if (c[BQ_FLAG].x == 0.0 && c[BQ_DONE].x == 0.0) {
     if (zzero(c[BQ_RV])) c[BQ_FLAG].x = 1.0;
     else al = zdiv(c[BQ_RHO], c[BQ_RV]);   // BQ_RHO holds rho_new by now
   }
@@ -850,10 +858,15 @@ __global__ void k_bq_alpha(double2 *c) {
 }
 
 // omega = (t, s) / (t, t); coefficients of x += alpha p^ + omega s^ and r = s - omega t
-__global__ void k_bq_omega(double2 *c) {
+__global__ void k_bq_omega(double2 *coef, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  double2 *c = coef + (size_t)k * BQ_SLOTS;
   const double tt = c[BQ_TT].x;
   double2 om = make_double2(0.0, 0.0), al = c[BQ_ALPHA];
-  if (c[BQ_FLAG].x == 0.0) {
+  if (c[BQ_DONE].x != 0.0) {
+    al = make_double2(0.0, 0.0);
+  } else if (c[BQ_FLAG].x == 0.0) {
     if (tt > 0.0) om = make_double2(c[BQ_TS].x / tt, c[BQ_TS].y / tt);
     if (zzero(om)) c[BQ_FLAG].y = 1.0;
   } else {
@@ -865,7 +878,17 @@ __global__ void k_bq_omega(double2 *c) {
   c[BQ_C_MOMEGA] = make_double2(-om.x, -om.y);
 }
 
-// Fused BiCGStab vector steps (one pass each where the unfused steps took two).
+// DONE once ||r||^2 <= (tol ||b||)^2 (after the r update of an iteration)
+__global__ void k_bq_done(double2 *coef, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  double2 *c = coef + (size_t)k * BQ_SLOTS;
+  if (c[BQ_RN2].x <= c[BQ_TGT2].x) c[BQ_DONE].x = 1.0;
+}
+
+// Fused BiCGStab vector steps over the Krylov vectors of nsys systems, one
+// after the other (system k = element / n2; n2 is a whole number of 256-entry
+// work-groups, so a work-group never spans two systems).
 // Block partial pairs of a complex dot, (a | b) = sum conj(a) b, in the order
 // of k_mdot: wave sums, then (w0 + w1) + (w2 + w3).
 __device__ __forceinline__ void block_pair(double re, double im, double *__restrict__ dst) {
@@ -878,17 +901,60 @@ __device__ __forceinline__ void block_pair(double re, double im, double *__restr
     dst[threadIdx.x] = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
-// P = R + beta[0] (P - omega[0] V)
-__global__ __launch_bounds__(256) void k_bq_p(const double2 *__restrict__ beta, const double2 *__restrict__ omega,
-                                              const double2 *__restrict__ R, const double2 *__restrict__ V,
-                                              double2 *__restrict__ P, size_t n) {
+__device__ __forceinline__ const double2 *sys_coef(const double2 *coef, size_t i, size_t n2) {
+  return coef + (i / n2) * BQ_SLOTS;
+}
+
+// P = R + beta (P - omega V)
+__global__ __launch_bounds__(256) void k_bq_p(const double2 *__restrict__ coef, const double2 *__restrict__ R,
+                                              const double2 *__restrict__ V, double2 *__restrict__ P, size_t n2,
+                                              size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double2 be = beta[0], om = omega[0], r = R[i], v = V[i];
+  const double2 *c = sys_coef(coef, i, n2);
+  const double2 be = c[BQ_C_BETA], om = c[BQ_C_OMEGA], r = R[i], v = V[i];
   double2 p = P[i];
   p.x -= om.x * v.x - om.y * v.y;
   p.y -= om.x * v.y + om.y * v.x;
   P[i] = make_double2(r.x + (be.x * p.x - be.y * p.y), r.y + (be.x * p.y + be.y * p.x));
+}
+
+// S = R - alpha V
+__global__ __launch_bounds__(256) void k_bq_s(const double2 *__restrict__ coef, const double2 *__restrict__ V,
+                                              const double2 *__restrict__ R, double2 *__restrict__ S, size_t n2,
+                                              size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = sys_coef(coef, i, n2)[BQ_C_MALPHA], v = V[i], r = R[i];
+  S[i] = make_double2(r.x + (a.x * v.x - a.y * v.y), r.y + (a.x * v.y + a.y * v.x));
+}
+
+// X += alpha PH + omega SH
+__global__ __launch_bounds__(256) void k_bq_x(const double2 *__restrict__ coef, const double2 *__restrict__ PH,
+                                              const double2 *__restrict__ SH, double2 *__restrict__ X, size_t n2,
+                                              size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 *c = sys_coef(coef, i, n2);
+  const double2 al = c[BQ_C_X], om = c[BQ_C_X2], ph = PH[i], sh = SH[i];
+  double2 x = X[i];
+  x.x += al.x * ph.x - al.y * ph.y;
+  x.y += al.x * ph.y + al.y * ph.x;
+  x.x += om.x * sh.x - om.y * sh.y;
+  x.y += om.x * sh.y + om.y * sh.x;
+  X[i] = x;
+}
+
+// partial pairs of (a | b): part[block * 2 + re/im]
+__global__ __launch_bounds__(256) void k_dot1(const double2 *__restrict__ a, const double2 *__restrict__ b, size_t n,
+                                              double *__restrict__ part) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 ab = make_double2(0.0, 0.0);
+  if (i < n) {
+    const double2 av = a[i], bv = b[i];
+    ab = make_double2(av.x * bv.x + av.y * bv.y, av.x * bv.y - av.y * bv.x);
+  }
+  block_pair(ab.x, ab.y, part + (size_t)blockIdx.x * 2);
 }
 
 // partial pairs of (a | b) and (c | d): part[(q * gridDim.x + block) * 2 + re/im]
@@ -907,14 +973,14 @@ __global__ __launch_bounds__(256) void k_dot2(const double2 *__restrict__ a, con
   block_pair(cd.x, cd.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
 }
 
-// R = S + c[0] T, with the partial pairs of (RT | R) and (R | R) as k_dot2
-__global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ c, const double2 *__restrict__ S,
+// R = S - omega T, with the partial pairs of (RT | R) and (R | R) as k_dot2
+__global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ coef, const double2 *__restrict__ S,
                                               const double2 *__restrict__ T, const double2 *__restrict__ RT,
-                                              double2 *__restrict__ R, size_t n, double *__restrict__ part) {
+                                              double2 *__restrict__ R, size_t n2, size_t n, double *__restrict__ part) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double2 rr = make_double2(0.0, 0.0), tr = rr;
   if (i < n) {
-    const double2 a = c[0], sv = S[i], tv = T[i], rt = RT[i];
+    const double2 a = sys_coef(coef, i, n2)[BQ_C_MOMEGA], sv = S[i], tv = T[i], rt = RT[i];
     const double2 r = make_double2(sv.x + (a.x * tv.x - a.y * tv.y), sv.y + (a.x * tv.y + a.y * tv.x));
     R[i] = r;
     tr = make_double2(rt.x * r.x + rt.y * r.y, rt.x * r.y - rt.y * r.x);
@@ -925,18 +991,20 @@ __global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ c, con
   block_pair(rr.x, rr.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
 }
 
-// coef[slot0] and coef[slot1] = the sums of the two partial-pair rows (grid 2)
-__global__ __launch_bounds__(256) void k_dot2_final(const double *__restrict__ part, int nblk,
+// Sums of partial-pair rows: grid (nrow, nsys), row q of system k (its nbk
+// work-groups of a kernel that ran over nsys * nbk) into coef[BQ_SLOTS k + slot_q].
+__global__ __launch_bounds__(256) void k_pair_final(const double *__restrict__ part, int nbk,
                                                     double2 *__restrict__ coef, int slot0, int slot1) {
   __shared__ double red[2][4];
-  const int q = blockIdx.x;
-  const double2 sum = strided_sum((const double2 *)(part + (size_t)q * nblk * 2), nblk, (int)threadIdx.x);
+  const int q = blockIdx.x, k = blockIdx.y;
+  const size_t row = ((size_t)q * gridDim.y + k) * nbk;
+  const double2 sum = strided_sum((const double2 *)(part + row * 2), nbk, (int)threadIdx.x);
   const double re = wave_sum(sum.x), im = wave_sum(sum.y);
   if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
   __syncthreads();
   if (threadIdx.x == 0)
-    coef[q == 0 ? slot0 : slot1] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
-                                                (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+    coef[(size_t)k * BQ_SLOTS + (q == 0 ? slot0 : slot1)] =
+        make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]), (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
 }
 
 // FCG step: x += alpha p, r -= alpha q, s -= alpha w (alpha = coef[0]); partial
@@ -1417,10 +1485,20 @@ struct Flex {
   double2 *vec;                 // the solver's Krylov vectors, vb bytes apart
   double *part, *npart, *nrm;   // partial sums
   double2 *coef;                // complex coefficients (device)
+  int nsys = 1;                 // systems solved in lockstep (BiCGStab); their Krylov vectors follow one another
   double2 *v(int i) const { return (double2 *)((char *)vec + (size_t)i * vb); }
+  // vector i of system k; vector i of every system is one block of nsys vectors
+  double2 *slot(int i, int k) const { return (double2 *)((char *)vec + ((size_t)i * nsys + k) * vb); }
+  // system k alone: its coefficients, the shared full fields and scratch
+  Flex sys_view(int k) const {
+    Flex f = *this;
+    f.nsys = 1;
+    f.coef = coef + (size_t)k * BQ_SLOTS;
+    return f;
+  }
 };
 
-size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex *f) {
+size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex *f, int nsys = 1) {
   const size_t hb64 = half_bytes(g, QIRAL_F64);
   const size_t vb = schur ? hb64 : 2 * hb64;
   const int m = flex_restart(prm);
@@ -1428,12 +1506,17 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
   const int nv = flex_nvec(prm->solver, m);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o += (bytes + 255) / 256 * 256; return at; };
-  const size_t oBF = take(2 * hb64), oXF = take(2 * hb64), oRF = take(2 * hb64), oT = take(hb64);
+  // b, x and the true residual of the system being set up or finished, and the
+  // even half-fields of the Schur operator's first hop, one per system
+  const size_t oBF = take(2 * hb64), oXF = take(2 * hb64), oRF = take(2 * hb64), oT = take((size_t)nsys * hb64);
   const size_t ovec = o;
-  o += (size_t)nv * vb;
-  const size_t opart = take(sizeof(double) * 2 * (size_t)(m + 2) * nbk), onpart = take(sizeof(double) * nbk);
-  const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * 64);
+  o += (size_t)nv * nsys * vb;
+  const size_t opart = take(sizeof(double) * std::max<size_t>(2 * (size_t)(m + 2) * nbk, 4 * (size_t)nsys * nbk));
+  // norms of full fields (begin, end) take twice the blocks of a Schur vector
+  const size_t onpart = take(sizeof(double) * nblk(2 * hb64 / 16));
+  const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * BQ_SLOTS * nsys);
   if (f) {
+    f->nsys = nsys;
     f->hb64 = hb64;
     f->vb = vb;
     f->n2 = vb / 16;
@@ -1451,12 +1534,13 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
   return o;
 }
 
-qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void *ws, size_t ws_bytes, Flex &f) {
+qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void *ws, size_t ws_bytes, Flex &f,
+                        int nsys = 1) {
   f.lat = lat;
   f.nn = (qiral_nn *)prm->precond;
   if (f.nn && f.nn->lat != lat) return fail(QIRAL_ERR_INVALID_ARG, "precond must be a network made for this lattice");
   f.schur = flex_schur(prm);
-  const size_t need = flex_bytes(lat->geo, prm, f.schur, &f);
+  const size_t need = flex_bytes(lat->geo, prm, f.schur, &f, nsys);
   if (ws_bytes < need) return fail(QIRAL_ERR_WORKSPACE, "flexible-solver workspace too small");
   char *b = (char *)ws;
   f.BF = (double2 *)(b + (size_t)f.BF);
@@ -1472,14 +1556,23 @@ qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void 
 }
 
 // y = A x or A^dagger x in FP64 (A = D, or S = A_oo - kappa^2 H_oe A_ee^-1 H_eo)
-hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s) {
+// for nsys consecutive vectors (the Schur operator's hops take them together)
+hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s, int nsys = 1) {
   const qiral_lattice *lat = f.lat;
-  if (!f.schur) return dag ? apply_Ddag_full(lat, QIRAL_F64, y, x, s) : apply_D_full(lat, QIRAL_F64, y, x, s);
+  if (!f.schur) {
+    for (int k = 0; k < nsys; ++k) {
+      void *yk = (char *)y + (size_t)k * f.vb;
+      const void *xk = (const char *)x + (size_t)k * f.vb;
+      hipError_t e = dag ? apply_Ddag_full(lat, QIRAL_F64, yk, xk, s) : apply_D_full(lat, QIRAL_F64, yk, xk, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const double k = lat->kappa;
-  hipError_t e = launch_hop(lat, QIRAL_F64, dag, 0, 0, 1.0, x, f.tmpE, nullptr, 1, s, dag ? CHI_AINVDAG : CHI_AINV,
-                            CHI_ONE);
+  hipError_t e = launch_hop(lat, QIRAL_F64, dag, 0, 0, 1.0, x, f.tmpE, nullptr, nsys, s,
+                            dag ? CHI_AINVDAG : CHI_AINV, CHI_ONE);
   if (e != hipSuccess) return e;
-  return launch_hop(lat, QIRAL_F64, dag, 1, 1, -k * k, f.tmpE, y, x, 1, s, CHI_ONE, dag ? CHI_ADAG : CHI_A);
+  return launch_hop(lat, QIRAL_F64, dag, 1, 1, -k * k, f.tmpE, y, x, nsys, s, CHI_ONE, dag ? CHI_ADAG : CHI_A);
 }
 
 // z = M v (or M^dagger v): the folded network in FP32 on v (full system) or on
@@ -1645,8 +1738,9 @@ long long flex_hops(const Flex &f) { return 2; }
 
 }  // namespace
 
-size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm) {
-  return flex_bytes(lat->geo, prm, flex_schur(prm), nullptr);
+size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm, int nsys) {
+  // BiCGStab solves its right-hand sides in lockstep, FGMRES and FCG one after the other
+  return flex_bytes(lat->geo, prm, flex_schur(prm), nullptr, prm->solver == QIRAL_BICGSTAB_EO ? nsys : 1);
 }
 
 // FGMRES(m) with M on the right: x = x0 + Z y, z_j = M v_j (Saad 1993).
@@ -1829,78 +1923,136 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
 // BiCGStab (van der Vorst 1992) with M on the right: the directions p and s are
 // preconditioned, p^ = M p, s^ = M s, and x moves along them (the preconditioned
 // BiCGStab of Barrett et al., Templates, SIAM 1994); with the identity these are
-// plain BiCGStab's iterates.  Scalars are formed on the host from FP64 dots.
-qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double *b_canon,
+// plain BiCGStab's iterates.  The nsys right-hand sides run in lockstep: one
+// launch of each vector step and dot for all of them, the Schur operator's hops
+// on all of them at once, the preconditioner on each system still iterating.
+// The scalars of each system stay on the device (k_bq_*); the host reads them
+// once per iteration, retires the systems that converged (their coefficients
+// then leave x and r unchanged) and restarts those that broke down.  Every
+// system takes the iterates it would take alone.
+qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double *b_canon, int nsys,
                                const qiral_solve_params *prm, void *ws, size_t ws_bytes, qiral_solve_info *info,
                                hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   Flex f;
-  qiral_status st = flex_setup(lat, prm, ws, ws_bytes, f);
+  qiral_status st = flex_setup(lat, prm, ws, ws_bytes, f, nsys);
   if (st != QIRAL_OK) return st;
-  double2 *B = f.v(0), *X = f.v(1), *R = f.v(2), *RT = f.v(3), *P = f.v(4), *Vv = f.v(5), *Sv = f.v(6),
-          *T = f.v(7), *PH = f.v(8), *SH = f.v(9);   // PH and SH adjacent: one two-vector update of X
-  QIRAL_HIP(hipMemsetAsync(f.vec, 0, 10 * f.vb, s));
-  double bn = 0;
-  if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
-  const double target = prm->tol * bn;
-  double rn = 0;
-  if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
-  long long hops = flex_hops(f);
-  int it = 0, restarts = 0;
-  bool broke = false;
-  const dim3 gv(f.nbk), bv(256);
-  while (rn > target && it < prm->maxiter && !broke) {
-    // (re)start: shadow residual r~ = r, rho = alpha = omega = 1, p = v = 0
-    QIRAL_HIP(hipMemcpyAsync(RT, R, f.vb, hipMemcpyDeviceToDevice, s));
-    QIRAL_HIP(hipMemsetAsync(P, 0, f.vb, s));
-    QIRAL_HIP(hipMemsetAsync(Vv, 0, f.vb, s));
-    hipLaunchKernelGGL(k_bq_init, dim3(1), dim3(1), 0, s, f.coef);
-    bool restart = false;
-    flex_dot_dev(f, RT, R, BQ_RHO1, s);   // later iterations get it from k_bq_r
-    while (rn > target && it < prm->maxiter) {
-      // the scalars stay on the device (k_bq_*); the host reads ||r||^2 and the
-      // breakdown flags once per iteration
-      hipLaunchKernelGGL(k_bq_beta, dim3(1), dim3(1), 0, s, f.coef);
-      // P = R + beta (P - omega V)
-      hipLaunchKernelGGL(k_bq_p, gv, bv, 0, s, f.coef + BQ_C_BETA, f.coef + BQ_C_OMEGA, R, Vv, P, f.n2);
-      QIRAL_HIP(flex_M(f, PH, P, false, s));
-      QIRAL_HIP(flex_A(f, Vv, PH, false, s));
-      flex_dot_dev(f, RT, Vv, BQ_RV, s);
-      hipLaunchKernelGGL(k_bq_alpha, dim3(1), dim3(1), 0, s, f.coef);
-      // S = R - alpha V
-      hipLaunchKernelGGL(k_zaxpyz, gv, bv, 0, s, f.coef + BQ_C_MALPHA, Vv, R, Sv, f.n2);
-      QIRAL_HIP(flex_M(f, SH, Sv, false, s));
-      QIRAL_HIP(flex_A(f, T, SH, false, s));
-      // (T | S) and ||T||^2
-      hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, T, Sv, T, T, f.n2, f.part);
-      hipLaunchKernelGGL(k_dot2_final, dim3(2), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_TS, (int)BQ_TT);
-      hipLaunchKernelGGL(k_bq_omega, dim3(1), dim3(1), 0, s, f.coef);
-      // X += alpha PH + omega SH; R = S - omega T with (RT | R) for the next
-      // iteration's rho and ||R||^2
-      hipLaunchKernelGGL(k_maxpy, gv, bv, 0, s, PH, f.n2, 2, f.coef + BQ_C_X, 1.0, X, f.n2);
-      hipLaunchKernelGGL(k_bq_r, gv, bv, 0, s, f.coef + BQ_C_MOMEGA, Sv, T, RT, R, f.n2, f.part);
-      hipLaunchKernelGGL(k_dot2_final, dim3(2), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RHO1, (int)BQ_RN2);
-      double2 q[2];   // RN2, FLAG
-      if ((st = flex_read(q, f.coef + BQ_RN2, sizeof q, s)) != QIRAL_OK) return st;
-      if (q[1].x != 0.0) { restart = true; break; }   // broke down before x changed
-      hops += 2 * flex_hops(f);
-      rn = std::sqrt(q[0].x);
-      ++it;
-      if (!std::isfinite(rn)) break;
-      if (q[1].y != 0.0) { restart = true; break; }   // omega = 0
-    }
-    if (!std::isfinite(rn)) break;
-    if (restart) {
-      // breakdown: restart from the current x with the recomputed residual
-      if (++restarts > 5) { broke = true; break; }
-      if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
-      hops += flex_hops(f);
+  const Geo &g = lat->geo;
+  const size_t stride = (size_t)g.vh * 2 * 24;   // doubles of one canonical field
+  enum { B, X, R, RT, P, V, S, T, PH, SH };
+  auto blk = [&](int i) { return f.slot(i, 0); };   // vector i of every system
+  QIRAL_HIP(hipMemsetAsync(f.vec, 0, 10 * (size_t)nsys * f.vb, s));
+  std::vector<double> bn(nsys), rn(nsys), target(nsys), rt(nsys);
+  std::vector<int> it(nsys, 0), restarts(nsys, 0);
+  std::vector<long long> hops(nsys, 0);
+  std::vector<char> active(nsys, 1), broke(nsys, 0);
+  const std::vector<double2> one(nsys, make_double2(1.0, 0.0)), zero(nsys, make_double2(0.0, 0.0));
+  for (int k = 0; k < nsys; ++k) {
+    const Flex fk = f.sys_view(k);
+    if ((st = flex_begin(fk, x_canon + k * stride, b_canon + k * stride, prm->x0_is_guess != 0, f.slot(B, k),
+                         f.slot(X, k), bn[k], s)) != QIRAL_OK)
+      return st;
+    target[k] = prm->tol * bn[k];
+    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s)) != QIRAL_OK) return st;
+    hops[k] = flex_hops(f);
+    active[k] = rn[k] > target[k] && prm->maxiter > 0;
+    QIRAL_HIP(hipMemcpyAsync(f.coef + (size_t)k * BQ_SLOTS + BQ_DONE, active[k] ? &zero[k] : &one[k], sizeof(double2),
+                             hipMemcpyHostToDevice, s));
+  }
+  auto retire = [&](int k) -> qiral_status {   // x and r of system k stay as they are from now on
+    active[k] = 0;
+    QIRAL_HIP(hipMemcpyAsync(f.coef + (size_t)k * BQ_SLOTS + BQ_DONE, &one[k], sizeof(double2),
+                             hipMemcpyHostToDevice, s));
+    return QIRAL_OK;
+  };
+  auto restart = [&](int k) -> qiral_status {   // shadow residual r~ = r, rho = alpha = omega = 1, p = v = 0
+    QIRAL_HIP(hipMemcpyAsync(f.slot(RT, k), f.slot(R, k), f.vb, hipMemcpyDeviceToDevice, s));
+    QIRAL_HIP(hipMemsetAsync(f.slot(P, k), 0, f.vb, s));
+    QIRAL_HIP(hipMemsetAsync(f.slot(V, k), 0, f.vb, s));
+    hipLaunchKernelGGL(k_bq_init, dim3(1), dim3(1), 0, s, f.coef + (size_t)k * BQ_SLOTS, 1);
+    flex_dot_dev(f.sys_view(k), f.slot(RT, k), f.slot(R, k), BQ_RHO1, s);
+    return QIRAL_OK;
+  };
+  const size_t ntot = (size_t)nsys * f.n2;
+  const dim3 gv((unsigned)(nsys * f.nbk)), bv(256), gs((unsigned)((nsys + 63) / 64)), bs(64);
+  auto any_active = [&]() { return std::find(active.begin(), active.end(), 1) != active.end(); };
+  if (any_active()) {
+    QIRAL_HIP(hipMemcpyAsync(blk(RT), blk(R), (size_t)nsys * f.vb, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_bq_init, gs, bs, 0, s, f.coef, nsys);
+    hipLaunchKernelGGL(k_dot1, gv, bv, 0, s, blk(RT), blk(R), ntot, f.part);
+    hipLaunchKernelGGL(k_pair_final, dim3(1, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RHO1,
+                       (int)BQ_RHO1);
+  }
+  std::vector<double2> hc((size_t)nsys * BQ_SLOTS);
+  while (any_active()) {
+    hipLaunchKernelGGL(k_bq_beta, gs, bs, 0, s, f.coef, nsys);
+    hipLaunchKernelGGL(k_bq_p, gv, bv, 0, s, f.coef, blk(R), blk(V), blk(P), f.n2, ntot);   // p = r + beta (p - omega v)
+    for (int k = 0; k < nsys; ++k)
+      if (active[k]) QIRAL_HIP(flex_M(f, f.slot(PH, k), f.slot(P, k), false, s));
+    QIRAL_HIP(flex_A(f, blk(V), blk(PH), false, s, nsys));
+    hipLaunchKernelGGL(k_dot1, gv, bv, 0, s, blk(RT), blk(V), ntot, f.part);
+    hipLaunchKernelGGL(k_pair_final, dim3(1, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RV, (int)BQ_RV);
+    hipLaunchKernelGGL(k_bq_alpha, gs, bs, 0, s, f.coef, nsys);
+    hipLaunchKernelGGL(k_bq_s, gv, bv, 0, s, f.coef, blk(V), blk(R), blk(S), f.n2, ntot);   // s = r - alpha v
+    for (int k = 0; k < nsys; ++k)
+      if (active[k]) QIRAL_HIP(flex_M(f, f.slot(SH, k), f.slot(S, k), false, s));
+    QIRAL_HIP(flex_A(f, blk(T), blk(SH), false, s, nsys));
+    hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, blk(T), blk(S), blk(T), blk(T), ntot, f.part);   // (t|s), ||t||^2
+    hipLaunchKernelGGL(k_pair_final, dim3(2, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_TS, (int)BQ_TT);
+    hipLaunchKernelGGL(k_bq_omega, gs, bs, 0, s, f.coef, nsys);
+    // x += alpha p^ + omega s^; r = s - omega t with (r~|r), the next rho, and ||r||^2
+    hipLaunchKernelGGL(k_bq_x, gv, bv, 0, s, f.coef, blk(PH), blk(SH), blk(X), f.n2, ntot);
+    hipLaunchKernelGGL(k_bq_r, gv, bv, 0, s, f.coef, blk(S), blk(T), blk(RT), blk(R), f.n2, ntot, f.part);
+    hipLaunchKernelGGL(k_pair_final, dim3(2, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RHO1,
+                       (int)BQ_RN2);
+    if ((st = flex_read(hc.data(), f.coef, sizeof(double2) * hc.size(), s)) != QIRAL_OK) return st;
+    for (int k = 0; k < nsys; ++k) {
+      if (!active[k]) continue;
+      const double2 *c = hc.data() + (size_t)k * BQ_SLOTS;
+      bool again = c[BQ_FLAG].x != 0.0;   // broke down before x changed: the iteration does not count
+      if (!again) {
+        hops[k] += 2 * flex_hops(f);
+        rn[k] = std::sqrt(c[BQ_RN2].x);
+        ++it[k];
+        if (!std::isfinite(rn[k]) || rn[k] <= target[k]) {
+          if ((st = retire(k)) != QIRAL_OK) return st;
+          continue;
+        }
+        again = c[BQ_FLAG].y != 0.0;   // omega = 0
+      }
+      if (it[k] >= prm->maxiter) {
+        if ((st = retire(k)) != QIRAL_OK) return st;
+      } else if (again) {
+        // breakdown: restart from the current x with the recomputed residual
+        if (++restarts[k] > 5) {
+          broke[k] = 1;
+          if ((st = retire(k)) != QIRAL_OK) return st;
+          continue;
+        }
+        if ((st = flex_residual(f.sys_view(k), f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s)) != QIRAL_OK)
+          return st;
+        hops[k] += flex_hops(f);
+        if (rn[k] <= target[k]) {
+          if ((st = retire(k)) != QIRAL_OK) return st;
+        } else if ((st = restart(k)) != QIRAL_OK) {
+          return st;
+        }
+      }
     }
   }
-  double rt = 0;
-  if ((st = flex_end(f, X, x_canon, rt, s)) != QIRAL_OK) return st;
-  hops += 2;
-  return flex_finish(lat, x_canon, b_canon, prm, ws, ws_bytes, info, it, hops, std::isfinite(rn) ? rt : rn, bn,
-                     broke, "BiCGStab", t0, s);
+  // every solution out first: a CG fallback below reuses the workspace
+  for (int k = 0; k < nsys; ++k) {
+    import_field(g, b_canon + k * stride, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
+    if ((st = flex_end(f.sys_view(k), f.slot(X, k), x_canon + k * stride, rt[k], s)) != QIRAL_OK) return st;
+    hops[k] += 2;
+  }
+  qiral_status worst = QIRAL_OK;
+  for (int k = 0; k < nsys; ++k) {
+    st = flex_finish(lat, x_canon + k * stride, b_canon + k * stride, prm, ws, ws_bytes, info + k, it[k], hops[k],
+                     std::isfinite(rn[k]) ? rt[k] : rn[k], bn[k], broke[k] != 0, "BiCGStab", t0, s);
+    if (st != QIRAL_OK && st != QIRAL_ERR_NOT_CONVERGED) return st;
+    if (st != QIRAL_OK) worst = st;
+  }
+  return worst;
 }
 }  // namespace qiral

@@ -39,9 +39,9 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x, const double *b, const qi
                         size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
 qiral_status run_fcg(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm, void *ws,
                      size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
-qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x, const double *b, const qiral_solve_params *prm,
+qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x, const double *b, int nsys, const qiral_solve_params *prm,
                                void *ws, size_t ws_bytes, qiral_solve_info *info, hipStream_t s);
-size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm);
+size_t flex_ws_bytes(const qiral_lattice *lat, const qiral_solve_params *prm, int nsys);
 }  // namespace qiral
 
 using namespace qiral;
@@ -534,8 +534,8 @@ namespace {
 
 // Workspace of a solve over these lattices (one system each; the right-hand
 // sides of qiral_solve are systems of one lattice).  FGMRES and FCG run one
-// right-hand side at a time in the same workspace and may continue with even-odd
-// CGNR (the fallback) in it.
+// right-hand side at a time in the same workspace, the flexible BiCGStab all of
+// them in lockstep, and each may continue with even-odd CGNR (the fallback) in it.
 size_t ws_need(const std::vector<const qiral_lattice *> &lats, const qiral_solve_params *p) {
   if (is_flex(p)) {
     qiral_solve_params cg = *p;
@@ -543,7 +543,7 @@ size_t ws_need(const std::vector<const qiral_lattice *> &lats, const qiral_solve
     cg.system = QIRAL_SYSTEM_DEFAULT;
     cg.precond = nullptr;
     const qiral_solve_params f = flex_params(p);
-    return std::max(flex_ws_bytes(lats[0], &f), solve_layout({lats[0]}, &cg).total);
+    return std::max(flex_ws_bytes(lats[0], &f, (int)lats.size()), solve_layout({lats[0]}, &cg).total);
   }
   return solve_layout(lats, p).total;
 }
@@ -588,9 +588,11 @@ qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon
                       hipStream_t stream) {
   const size_t stride = (size_t)lat->geo.vh * 2 * 24;
   if (is_flex(params)) {
-    // one right-hand side after the other
     const qiral_solve_params fp = flex_params(params);
-    auto run = fp.solver == QIRAL_FGMRES_NN ? run_fgmres : fp.solver == QIRAL_FCG_NN ? run_fcg : run_bicgstab_prec;
+    if (fp.solver == QIRAL_BICGSTAB_EO)   // the right-hand sides in lockstep
+      return run_bicgstab_prec(lat, x_canon, b_canon, nrhs, &fp, ws, ws_bytes, info, stream);
+    // one right-hand side after the other
+    auto run = fp.solver == QIRAL_FGMRES_NN ? run_fgmres : run_fcg;
     qiral_status worst = QIRAL_OK;
     for (int r = 0; r < nrhs; ++r) {
       qiral_status s = run(lat, x_canon + r * stride, b_canon + r * stride, &fp, ws, ws_bytes, info + r, stream);
@@ -608,7 +610,6 @@ qiral_status solve_in(qiral_lattice *lat, double *x_canon, const double *b_canon
 extern "C" size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params,
                                               int32_t nrhs) {
   if (!lat || nrhs < 1 || nrhs > QIRAL_MAX_SYSTEMS || check_params(params) != QIRAL_OK) return 0;
-  if (is_flex(params)) return ws_need({lat}, params);
   return ws_need(std::vector<const qiral_lattice *>(nrhs, lat), params);
 }
 

@@ -112,3 +112,51 @@ def test_schur_network_iterates(lattice, solver, steps):
     rel = np.sqrt(np.vdot(xg - xo, xg - xo).real / np.vdot(xo, xo).real)
     say("  relative difference", rel)
     assert rel < 1e-5, rel
+
+
+@pytest.mark.parametrize("system,with_net", [("full", False), ("full", True), ("schur", True)],
+                         ids=["full-none", "full-net", "schur-net"])
+def test_bicgstab_lockstep_equals_one_by_one(lattice, system, with_net):
+    """The preconditioned and the full-system BiCGStab solve several right-hand
+    sides in lockstep (one launch of each vector step for all, the Schur
+    operator's hops on all at once); each takes the iterates it takes alone, bit
+    for bit."""
+    import torch
+    L = lattice
+    say("bicgstab lockstep", system, with_net)
+    b1 = L["b"][0]
+    rng = np.random.default_rng(7)
+    extra = rng.standard_normal((2,) + b1.shape) + 1j * rng.standard_normal((2,) + b1.shape)
+    B = np.concatenate([b1[None], extra])
+    kw = dict(tol=1e-10, solver=q.BICGSTAB_EO, system=SYSTEMS[system],
+              precond=L["net"].handle if with_net else None, restart=20, maxiter=2000, fallback_cg=0)
+    x3, st3, info3 = L["lat"].solve(dev(B), **kw)
+    x3 = x3.clone()
+    assert st3 == 0 and all(i["converged"] == 1 for i in info3), info3
+    for r in range(3):
+        x1, st1, info1 = L["lat"].solve(dev(B[r:r + 1]), **kw)
+        assert st1 == 0
+        assert info1[0]["iterations"] == info3[r]["iterations"], (r, info1[0], info3[r])
+        assert torch.equal(x3[r:r + 1], x1), r
+
+
+def test_bicgstab_lockstep_larger_lattice():
+    """The same on 12^3x16 (216 site blocks): large enough that the per-system
+    state sits past the partial sums of a full-field norm."""
+    import torch
+    dims = (12, 12, 12, 16)
+    say("bicgstab lockstep", dims)
+    cfg = latgen.small_config(dims, seed=41, kind="expih", eps=0.4, nrhs=3)
+    lat = q.Lattice(dims, 0.12, cfg["U"])
+    net = q.Network(lat, 8)
+    kw = dict(tol=1e-10, solver=q.BICGSTAB_EO, system=q.SYSTEM_SCHUR, precond=net.handle, maxiter=2000, fallback_cg=0)
+    x3, st3, info3 = lat.solve(dev(cfg["b"]), **kw)
+    x3 = x3.clone()
+    assert st3 == 0, info3
+    for r in range(3):
+        x1, st1, info1 = lat.solve(dev(cfg["b"][r:r + 1]), **kw)
+        assert st1 == 0 and info1[0]["iterations"] == info3[r]["iterations"]
+        assert torch.equal(x3[r:r + 1], x1), r
+        assert S.true_rel_residual(cfg["U"], 0.12, 0.0, host(x3)[r], cfg["b"][r]) <= 1e-10
+    net.close()
+    lat.close()
