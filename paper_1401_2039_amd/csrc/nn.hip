@@ -344,6 +344,12 @@ __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict
 // accumulators.  Sites of parity P keep m_0 = K_00 v (vector ALU).  A
 // fragments come from k_nn_frag.  Site blocks in the hop's XCD-mapped order.
 // Grid: (nb, 2 parities), 256 threads.
+//
+// Each work-group does its site block for nsys systems one after the other
+// (inputs istride bytes apart, path fields msys bytes apart), so the links a
+// block reads for the first system are still in the cache for the others.
+// Path field p of a system starts at p * mstride and its parity-x half at
+// x * hoff (hoff = 0: each path field holds only the parity it is used on).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -365,32 +371,39 @@ __global__ void k_nn_frag(const float2 *__restrict__ K, __bf16 *__restrict__ f) 
 }
 
 template <int SIN>
-__global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__restrict__ links,
+__global__ __launch_bounds__(256, 3) void k_nn_pass_a_mfma(Geo g, const void *__restrict__ links,
                                                         const float2 *__restrict__ K, const bf16x8 *__restrict__ frag,
-                                                        const void *__restrict__ in, void *__restrict__ m,
-                                                        size_t mstride, int par, int zb) {
+                                                        const void *__restrict__ in, size_t istride,
+                                                        void *__restrict__ m, size_t mstride, size_t hoff, size_t msys,
+                                                        int nsys, int par, int zb) {
   __shared__ uint4 lds_hi[4 * 3 * WAVE], lds_lo[4 * 3 * WAVE];   // [q in K-step][colour][site]
+  // each lane's two links (stored rows), kept for the systems after the first:
+  // in the cache they would not outlive one system's pass over the XCD
+  __shared__ float4 lds_link[2 * 3 * 256];
   const int ya = blockIdx.y;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (WAVE - 1);
   const int sb = block_order(g, xcd_remap(blockIdx.x, gridDim.x), zb), s = sb * WAVE + lane;
   const bool live = s < g.vh;
-  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t npad = (size_t)g.nb * WAVE;
   if (ya == par) {
     if (w != 0 || !live) return;
-    cpx<float> v[12], o[12];
-    load_as_f32<SIN>(in, s, npad, v);
+#pragma unroll 1
+    for (int sy = 0; sy < nsys; ++sy) {
+      cpx<float> v[12], o[12];
+      load_as_f32<SIN>((const char *)in + sy * istride, s, npad, v);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[k] = cmake(0.f, 0.f);
+      for (int k = 0; k < 12; ++k) o[k] = cmake(0.f, 0.f);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const cpx<float> kr = cmake(K[4 * r + e].x, K[4 * r + e].y);
+        for (int e = 0; e < 4; ++e) {
+          const cpx<float> kr = cmake(K[4 * r + e].x, K[4 * r + e].y);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) o[4 * a + r] = cmac(kr, v[4 * a + e], o[4 * a + r]);
-      }
-    SpinorIO<S_F32>::store((char *)m + ya * hb, s, npad, o);
+          for (int a = 0; a < 3; ++a) o[4 * a + r] = cmac(kr, v[4 * a + e], o[4 * a + r]);
+        }
+      SpinorIO<S_F32>::store((char *)m + sy * msys + ya * hoff, s, npad, o);
+    }
     return;
   }
   // every lane takes part in the matrix products; lanes past the last site
@@ -401,66 +414,81 @@ __global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__res
   for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
     for (int hl = 0; hl < 2; ++hl) A[ks][hl] = frag[((w * 2 + ks) * 2 + hl) * WAVE + lane];
-  f32x4 D[4][3];   // [site tile][colour]
+#pragma unroll 1
+  for (int sy = 0; sy < nsys; ++sy) {
+    const void *in_s = (const char *)in + sy * istride;
+    f32x4 D[4][3];   // [site tile][colour]
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) D[j][a] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int g4 = lane >> 4, n = lane & 15;
+      for (int a = 0; a < 3; ++a) D[j][a] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int g4 = lane >> 4, n = lane & 15;
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
-    cpx<float> t[12];
+    for (int ks = 0; ks < 2; ++ks) {
+      cpx<float> t[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) t[k] = cmake(0.f, 0.f);
-    if (live) {
-      int mu;
-      bool fwd;
-      path_of(1 + 4 * ks + w, mu, fwd);
-      const int nb_ = nbr(g, c, mu, fwd);
-      cpx<float> u[9], psi[12];
-      if (fwd) LinkIO<L_F32R12>::load(links, ya, mu, s, g.nb, u);
-      else LinkIO<L_F32R12>::load(links, 1 - ya, mu, nb_, g.nb, u);
-      load_as_f32<SIN>(in, nb_, npad, psi);
-      transport(u, psi, t, !fwd);
-    }
+      for (int k = 0; k < 12; ++k) t[k] = cmake(0.f, 0.f);
+      if (live) {
+        int mu;
+        bool fwd;
+        path_of(1 + 4 * ks + w, mu, fwd);
+        const int nb_ = nbr(g, c, mu, fwd);
+        cpx<float> u[9], psi[12];
+        LinkIO<L_F32R12>::Raw lr;
+        float4 *st = lds_link + ks * 3 * 256 + threadIdx.x;
+        if (sy == 0) {
+          if (fwd) LinkIO<L_F32R12>::fetch(links, ya, mu, s, g.nb, lr);
+          else LinkIO<L_F32R12>::fetch(links, 1 - ya, mu, nb_, g.nb, lr);
+          if (nsys > 1)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      bf16x8 h, l;
+            for (int j = 0; j < 3; ++j) st[j * 256] = lr.q[j];
+        } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float xr = t[4 * a + e].re, xi = t[4 * a + e].im;
-        const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
-        h[2 * e] = hr;
-        h[2 * e + 1] = hi;
-        l[2 * e] = (__bf16)(xr - (float)hr);
-        l[2 * e + 1] = (__bf16)(xi - (float)hi);
+          for (int j = 0; j < 3; ++j) lr.q[j] = st[j * 256];
+        }
+        LinkIO<L_F32R12>::decode(lr, u);
+        load_as_f32<SIN>(in_s, nb_, npad, psi);
+        transport(u, psi, t, !fwd);
       }
-      lds_hi[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, h);
-      lds_lo[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, l);
-    }
-    __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a) {
+        bf16x8 h, l;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_hi[(g4 * 3 + a) * WAVE + 16 * j + n]);
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_lo[(g4 * 3 + a) * WAVE + 16 * j + n]);
-        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bh, D[j][a], 0, 0, 0);
-        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bl, D[j][a], 0, 0, 0);
-        D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][1], bh, D[j][a], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) {
+          const float xr = t[4 * a + e].re, xi = t[4 * a + e].im;
+          const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
+          h[2 * e] = hr;
+          h[2 * e + 1] = hi;
+          l[2 * e] = (__bf16)(xr - (float)hr);
+          l[2 * e + 1] = (__bf16)(xi - (float)hi);
+        }
+        lds_hi[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, h);
+        lds_lo[(w * 3 + a) * WAVE + lane] = __builtin_bit_cast(uint4, l);
       }
-    __syncthreads();   // the next K-step overwrites the LDS tiles
-  }
-  // lane (g4, n) holds rows 4 g4 .. 4 g4 + 3 of column (site 16 j + n, colour a):
-  // path 1 + 2w + g4 / 2, float4 unit 2a + g4 % 2 of the F32 spinor layout
-  float4 *base = (float4 *)((char *)m + (size_t)(1 + 2 * w + (g4 >> 1)) * mstride + ya * hb);
+      __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (sb * WAVE + 16 * j + n >= g.vh) continue;
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const f32x4 d = D[j][a];
-      base[((size_t)sb * 6 + 2 * a + (g4 & 1)) * WAVE + 16 * j + n] = make_float4(d[0], d[1], d[2], d[3]);
+        for (int j = 0; j < 4; ++j) {
+          const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_hi[(g4 * 3 + a) * WAVE + 16 * j + n]);
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_lo[(g4 * 3 + a) * WAVE + 16 * j + n]);
+          D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bh, D[j][a], 0, 0, 0);
+          D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], bl, D[j][a], 0, 0, 0);
+          D[j][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][1], bh, D[j][a], 0, 0, 0);
+        }
+      __syncthreads();   // the next K-step overwrites the LDS tiles
+    }
+    // lane (g4, n) holds rows 4 g4 .. 4 g4 + 3 of column (site 16 j + n, colour a):
+    // path 1 + 2w + g4 / 2, float4 unit 2a + g4 % 2 of the F32 spinor layout
+    float4 *base = (float4 *)((char *)m + sy * msys + (size_t)(1 + 2 * w + (g4 >> 1)) * mstride + ya * hoff);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (sb * WAVE + 16 * j + n >= g.vh) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const f32x4 d = D[j][a];
+        base[((size_t)sb * 6 + 2 * a + (g4 & 1)) * WAVE + 16 * j + n] = make_float4(d[0], d[1], d[2], d[3]);
+      }
     }
   }
 }
@@ -468,34 +496,42 @@ __global__ __launch_bounds__(256) void k_nn_pass_a_mfma(Geo g, const void *__res
 // Pass B: out(x) = sum_p (T_p m_p)(x) at the sites of parity out_par (both if
 // negative; grid (ceil(nb / 4), 1 or 2), four site blocks in the hop's
 // XCD-mapped order), written in storage SOUT to out0 (even half) or out1 (odd
-// half).
-template <int SOUT>
+// half).  Path fields as in pass A; nsys systems one after the other (outputs
+// ostride bytes apart), reusing the block's links from the cache.
+template <int SOUT, bool MULTI>
 __global__ __launch_bounds__(256) void k_nn_pass_b(Geo g, const void *__restrict__ links, const void *__restrict__ m,
-                                                   size_t mstride, void *__restrict__ out0, void *__restrict__ out1,
-                                                   int out_par, int zb) {
+                                                   size_t mstride, size_t hoff, size_t msys, void *__restrict__ out0,
+                                                   void *__restrict__ out1, size_t ostride, int nsys, int out_par,
+                                                   int zb) {
   const int px = out_par >= 0 ? out_par : (int)blockIdx.y;
   const int L = xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
   if (L >= g.nb) return;
   const int s = block_order(g, L, zb) * WAVE + (int)(threadIdx.x & (WAVE - 1));
   if (s >= g.vh) return;
-  const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
+  const size_t npad = (size_t)g.nb * WAVE;
   const SiteC c = site_c(g, s, px);
-  cpx<float> acc[12];
-  SpinorIO<S_F32>::load((const char *)m + px * hb, s, npad, acc);
+  // one system: no loop state, so the kernel keeps five waves per SIMD
+  const int ns = MULTI ? nsys : 1;
 #pragma unroll 1
-  for (int p = 1; p < NPATH; ++p) {
-    cpx<float> t[12];
-    path_apply(g, links, (const char *)m + (size_t)p * mstride, hb, npad, c, px, p, t);
+  for (int sy = 0; sy < ns; ++sy) {
+    const char *ms = (const char *)m + sy * msys;
+    cpx<float> acc[12];
+    SpinorIO<S_F32>::load(ms + px * hoff, s, npad, acc);
+#pragma unroll 1
+    for (int p = 1; p < NPATH; ++p) {
+      cpx<float> t[12];
+      path_apply(g, links, ms + (size_t)p * mstride, hoff, npad, c, px, p, t);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = cadd(acc[k], t[k]);
-  }
-  void *dst = px ? out1 : out0;
-  if constexpr (SOUT == S_F32) {
-    SpinorIO<S_F32>::store(dst, s, npad, acc);
-  } else {
-    cpx<double> d[12];
-    cvt12(acc, d);
-    SpinorIO<S_F64>::store(dst, s, npad, d);
+      for (int k = 0; k < 12; ++k) acc[k] = cadd(acc[k], t[k]);
+    }
+    void *dst = (char *)(px ? out1 : out0) + sy * ostride;
+    if constexpr (SOUT == S_F32) {
+      SpinorIO<S_F32>::store(dst, s, npad, acc);
+    } else {
+      cpx<double> d[12];
+      cvt12(acc, d);
+      SpinorIO<S_F64>::store(dst, s, npad, d);
+    }
   }
 }
 
@@ -1124,22 +1160,34 @@ hipError_t nn_fold(const qiral_nn *nn, hipStream_t s) {
 // half-fields (in0, in1) and (out0, out1).  par >= 0: in is zero off parity par
 // (in0 or in1 is then not read) and only that parity of out is written, and
 // pass A runs on bf16 MFMA (about 1e-5 relative; the flexible solvers only).
+// There nsys systems may go through in one pass each: inputs and outputs
+// iostride bytes apart, their path fields in mbuf (nsys x 9 F32 half-fields;
+// the network's own buffer when null, which holds one system's).
 template <int SIO>
 hipError_t nn_apply_folded(const qiral_nn *nn, void *out0, void *out1, const void *in0, const void *in1, bool adj,
-                           hipStream_t s, int par = -1) {
+                           hipStream_t s, int par = -1, int nsys = 1, size_t iostride = 0, void *mbuf = nullptr) {
   const Geo &g = nn->lat->geo;
-  const size_t fs = full_bytes32(g);
+  const size_t fs = full_bytes32(g), hb = fs / 2;
   const float2 *K = nn->kmat + (adj ? NPATH * NPATH * 16 : 0);
   const int zb = hop_zb(g);   // the hops' z-tiles: neighbours stay in one XCD's L2
-  if (par >= 0)
+  if (par >= 0) {
+    // path field p is the one parity it is used on: m_0 on par, m_1..m_8 on 1 - par
+    void *m = mbuf ? mbuf : nn->act;
     hipLaunchKernelGGL((k_nn_pass_a_mfma<SIO>), dim3(g.nb, 2), dim3(256), 0, s, g, nn->lat->g32, K,
-                       (const bf16x8 *)nn->kfrag + (adj ? 4 * 2 * 2 * WAVE : 0), par ? in1 : in0, nn->act, fs, par,
-                       zb);
-  else   // all nine output paths in two waves per site block, five and four
+                       (const bf16x8 *)nn->kfrag + (adj ? 4 * 2 * 2 * WAVE : 0), par ? in1 : in0, iostride, m, hb,
+                       (size_t)0, NPATH * hb, nsys, par, zb);
+    if (nsys > 1)
+      hipLaunchKernelGGL((k_nn_pass_b<SIO, true>), dim3((g.nb + 3) / 4, 1), dim3(256), 0, s, g, nn->lat->g32,
+                         (const void *)m, hb, (size_t)0, NPATH * hb, out0, out1, iostride, nsys, par, zb);
+    else
+      hipLaunchKernelGGL((k_nn_pass_b<SIO, false>), dim3((g.nb + 3) / 4, 1), dim3(256), 0, s, g, nn->lat->g32,
+                         (const void *)m, hb, (size_t)0, NPATH * hb, out0, out1, (size_t)0, 1, par, zb);
+  } else {   // all nine output paths in two waves per site block, five and four
     hipLaunchKernelGGL((k_nn_pass_a<SIO, 5>), dim3((g.nb + 1) / 2, 2), dim3(256), 0, s, g, nn->lat->g32, K, in0, in1,
                        nn->act, fs, zb);
-  hipLaunchKernelGGL((k_nn_pass_b<SIO>), dim3((g.nb + 3) / 4, par >= 0 ? 1 : 2), dim3(256), 0, s, g, nn->lat->g32,
-                     (const void *)nn->act, fs, out0, out1, par, zb);
+    hipLaunchKernelGGL((k_nn_pass_b<SIO, false>), dim3((g.nb + 3) / 4, 2), dim3(256), 0, s, g, nn->lat->g32,
+                       (const void *)nn->act, fs, hb, (size_t)0, out0, out1, (size_t)0, 1, par, zb);
+  }
   return hipGetLastError();
 }
 
@@ -1485,6 +1533,7 @@ struct Flex {
   double2 *vec;                 // the solver's Krylov vectors, vb bytes apart
   double *part, *npart, *nrm;   // partial sums
   double2 *coef;                // complex coefficients (device)
+  void *mbuf;                   // path fields of the network for all systems at once (lockstep), or null
   int nsys = 1;                 // systems solved in lockstep (BiCGStab); their Krylov vectors follow one another
   double2 *v(int i) const { return (double2 *)((char *)vec + (size_t)i * vb); }
   // vector i of system k; vector i of every system is one block of nsys vectors
@@ -1515,6 +1564,10 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
   // norms of full fields (begin, end) take twice the blocks of a Schur vector
   const size_t onpart = take(sizeof(double) * nblk(2 * hb64 / 16));
   const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * BQ_SLOTS * nsys);
+  // systems in lockstep on the Schur system take the network's passes together:
+  // nine F32 half-fields of path fields each
+  const bool mall = prm->precond && schur && nsys > 1;
+  const size_t om = mall ? take((size_t)nsys * NPATH * half_bytes(g, QIRAL_F32)) : 0;
   if (f) {
     f->nsys = nsys;
     f->hb64 = hb64;
@@ -1530,6 +1583,7 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
     f->npart = (double *)onpart;
     f->nrm = (double *)onrm;
     f->coef = (double2 *)ocoef;
+    f->mbuf = mall ? (void *)om : nullptr;
   }
   return o;
 }
@@ -1552,6 +1606,7 @@ qiral_status flex_setup(qiral_lattice *lat, const qiral_solve_params *prm, void 
   f.npart = (double *)(b + (size_t)f.npart);
   f.nrm = (double *)(b + (size_t)f.nrm);
   f.coef = (double2 *)(b + (size_t)f.coef);
+  if (f.mbuf) f.mbuf = b + (size_t)f.mbuf;
   return QIRAL_OK;
 }
 
@@ -1579,11 +1634,21 @@ hipError_t flex_A(const Flex &f, void *y, const void *x, bool dag, hipStream_t s
 // v placed on the odd sites, keeping the odd part of the result (Schur system:
 // the passes skip the paths and sites that would only add zeros or be
 // dropped, and the path-pair products run on bf16 MFMA), reading and writing
-// the FP64 Krylov vectors directly; the identity without a network.
-hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s) {
-  if (!f.nn) return hipMemcpyAsync(z, v, f.vb, hipMemcpyDeviceToDevice, s);
-  if (f.schur) return nn_apply_folded<S_F64>(f.nn, nullptr, z, nullptr, v, adj, s, 1);
-  return nn_apply_folded<S_F64>(f.nn, z, (char *)z + f.hb64, v, (const char *)v + f.hb64, adj, s);
+// the FP64 Krylov vectors directly; the identity without a network.  nsys
+// consecutive vectors (the Schur form takes them in one pass each).
+hipError_t flex_M(const Flex &f, void *z, const void *v, bool adj, hipStream_t s, int nsys = 1) {
+  if (!f.nn) return hipMemcpyAsync(z, v, (size_t)nsys * f.vb, hipMemcpyDeviceToDevice, s);
+  if (f.schur) {
+    if (nsys > 1 && !f.mbuf) return hipErrorInvalidValue;
+    return nn_apply_folded<S_F64>(f.nn, nullptr, z, nullptr, v, adj, s, 1, nsys, f.vb, nsys > 1 ? f.mbuf : nullptr);
+  }
+  for (int k = 0; k < nsys; ++k) {
+    char *zk = (char *)z + (size_t)k * f.vb;
+    const char *vk = (const char *)v + (size_t)k * f.vb;
+    hipError_t e = nn_apply_folded<S_F64>(f.nn, zk, zk + f.hb64, vk, vk + f.hb64, adj, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 qiral_status flex_read(void *dst, const void *src, size_t bytes, hipStream_t s) {
@@ -1684,11 +1749,15 @@ qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &
   return st;
 }
 
-// R = rhs - A X; returns ||R||
+// R = rhs - A X (rhs itself when X is known to be zero); returns ||R||
 qiral_status flex_residual(const Flex &f, const double2 *rhs, const double2 *X, double2 *R, double &rn,
-                           hipStream_t s) {
-  QIRAL_HIP(flex_A(f, R, X, false, s));
-  hipLaunchKernelGGL(k_bminus, dim3(f.nbk), dim3(256), 0, s, rhs, R, f.n2);
+                           hipStream_t s, bool xzero = false) {
+  if (xzero) {
+    QIRAL_HIP(hipMemcpyAsync(R, rhs, f.vb, hipMemcpyDeviceToDevice, s));
+  } else {
+    QIRAL_HIP(flex_A(f, R, X, false, s));
+    hipLaunchKernelGGL(k_bminus, dim3(f.nbk), dim3(256), 0, s, rhs, R, f.n2);
+  }
   double r2 = 0;
   qiral_status st = flex_norm2(f, R, r2, s);
   rn = std::sqrt(r2);
@@ -1759,9 +1828,10 @@ qiral_status run_fgmres(qiral_lattice *lat, double *x_canon, const double *b_can
   if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
   const double target = prm->tol * bn;
   double rn = 0;
-  if ((st = flex_residual(f, B, X, R, rn, s)) != QIRAL_OK) return st;
+  const bool xzero = prm->x0_is_guess == 0;
+  if ((st = flex_residual(f, B, X, R, rn, s, xzero)) != QIRAL_OK) return st;
   int steps = 0;
-  long long hops = flex_hops(f);
+  long long hops = xzero ? 0 : flex_hops(f);
   double prev_cycle = rn;
   typedef std::complex<double> C;
   std::vector<C> H((m + 1) * m), cs(m), sn(m), gv(m + 1);
@@ -1866,15 +1936,16 @@ qiral_status run_fcg(qiral_lattice *lat, double *x_canon, const double *b_canon,
   if ((st = flex_begin(f, x_canon, b_canon, prm->x0_is_guess != 0, B, X, bn, s)) != QIRAL_OK) return st;
   const double target = prm->tol * bn;
   // S = B - A X, R = A^dagger S; returns ||S||
-  auto residuals = [&](double &sn) -> qiral_status {
-    qiral_status r = flex_residual(f, B, X, Sv, sn, s);
+  auto residuals = [&](double &sn, bool xzero) -> qiral_status {
+    qiral_status r = flex_residual(f, B, X, Sv, sn, s, xzero);
     if (r != QIRAL_OK) return r;
     QIRAL_HIP(flex_A(f, R, Sv, true, s));
     return QIRAL_OK;
   };
   double sn = 0;
-  if ((st = residuals(sn)) != QIRAL_OK) return st;
-  long long hops = 2 * flex_hops(f);
+  const bool xzero = prm->x0_is_guess == 0;
+  if ((st = residuals(sn, xzero)) != QIRAL_OK) return st;
+  long long hops = (xzero ? 1 : 2) * flex_hops(f);
   int it = 0, since_best = 0;
   bool broke = false;
   double best = sn, dprev = 0;
@@ -1941,7 +2012,10 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   const size_t stride = (size_t)g.vh * 2 * 24;   // doubles of one canonical field
   enum { B, X, R, RT, P, V, S, T, PH, SH };
   auto blk = [&](int i) { return f.slot(i, 0); };   // vector i of every system
-  QIRAL_HIP(hipMemsetAsync(f.vec, 0, 10 * (size_t)nsys * f.vb, s));
+  // p and v start at zero; with padding sites in the last block every vector
+  // does, since the vector kernels sum over them and no hop writes them
+  if (g.vh % WAVE) QIRAL_HIP(hipMemsetAsync(f.vec, 0, 10 * (size_t)nsys * f.vb, s));
+  else for (int i : {(int)P, (int)V}) QIRAL_HIP(hipMemsetAsync(blk(i), 0, (size_t)nsys * f.vb, s));
   std::vector<double> bn(nsys), rn(nsys), target(nsys), rt(nsys);
   std::vector<int> it(nsys, 0), restarts(nsys, 0);
   std::vector<long long> hops(nsys, 0);
@@ -1953,8 +2027,9 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
                          f.slot(X, k), bn[k], s)) != QIRAL_OK)
       return st;
     target[k] = prm->tol * bn[k];
-    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s)) != QIRAL_OK) return st;
-    hops[k] = flex_hops(f);
+    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s, !prm->x0_is_guess)) != QIRAL_OK)
+      return st;
+    hops[k] = prm->x0_is_guess ? flex_hops(f) : 0;
     active[k] = rn[k] > target[k] && prm->maxiter > 0;
     QIRAL_HIP(hipMemcpyAsync(f.coef + (size_t)k * BQ_SLOTS + BQ_DONE, active[k] ? &zero[k] : &one[k], sizeof(double2),
                              hipMemcpyHostToDevice, s));
@@ -1987,15 +2062,13 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   while (any_active()) {
     hipLaunchKernelGGL(k_bq_beta, gs, bs, 0, s, f.coef, nsys);
     hipLaunchKernelGGL(k_bq_p, gv, bv, 0, s, f.coef, blk(R), blk(V), blk(P), f.n2, ntot);   // p = r + beta (p - omega v)
-    for (int k = 0; k < nsys; ++k)
-      if (active[k]) QIRAL_HIP(flex_M(f, f.slot(PH, k), f.slot(P, k), false, s));
+    QIRAL_HIP(flex_M(f, blk(PH), blk(P), false, s, nsys));
     QIRAL_HIP(flex_A(f, blk(V), blk(PH), false, s, nsys));
     hipLaunchKernelGGL(k_dot1, gv, bv, 0, s, blk(RT), blk(V), ntot, f.part);
     hipLaunchKernelGGL(k_pair_final, dim3(1, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RV, (int)BQ_RV);
     hipLaunchKernelGGL(k_bq_alpha, gs, bs, 0, s, f.coef, nsys);
     hipLaunchKernelGGL(k_bq_s, gv, bv, 0, s, f.coef, blk(V), blk(R), blk(S), f.n2, ntot);   // s = r - alpha v
-    for (int k = 0; k < nsys; ++k)
-      if (active[k]) QIRAL_HIP(flex_M(f, f.slot(SH, k), f.slot(S, k), false, s));
+    QIRAL_HIP(flex_M(f, blk(SH), blk(S), false, s, nsys));
     QIRAL_HIP(flex_A(f, blk(T), blk(SH), false, s, nsys));
     hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, blk(T), blk(S), blk(T), blk(T), ntot, f.part);   // (t|s), ||t||^2
     hipLaunchKernelGGL(k_pair_final, dim3(2, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_TS, (int)BQ_TT);
