@@ -828,7 +828,8 @@ __global__ __launch_bounds__(256) void k_bminus(const double2 *__restrict__ b, d
 enum : int {
   BQ_RHO = 40, BQ_ALPHA, BQ_OMEGA, BQ_RHO1, BQ_RV, BQ_TS, BQ_TT, BQ_RN2, BQ_FLAG,   // scalars; FLAG.x, .y below
   BQ_C_OMEGA = 50, BQ_C_BETA, BQ_C_MALPHA, BQ_C_X, BQ_C_X2, BQ_C_MOMEGA,     // coefficients of the vector kernels
-  BQ_DONE = 56, BQ_TGT2,   // DONE.x != 0: converged (see k_bq_done); TGT2.x = (tol ||b||)^2
+  BQ_DONE = 56,            // DONE.x != 0: the system is retired; its x and r stay as they are
+  BQ_BN2, BQ_TR2,          // .x: ||b||^2 of the full source, ||b - D x||^2 of the final x
   BQ_SLOTS = 64            // coefficient slots per system: system k's are coef[64 k ..]
 };
 // FLAG.x: the iteration broke down before x changed (rho_new or (r~, v) zero):
@@ -914,14 +915,6 @@ __global__ void k_bq_omega(double2 *coef, int nsys) {
   c[BQ_C_MOMEGA] = make_double2(-om.x, -om.y);
 }
 
-// DONE once ||r||^2 <= (tol ||b||)^2 (after the r update of an iteration)
-__global__ void k_bq_done(double2 *coef, int nsys) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nsys) return;
-  double2 *c = coef + (size_t)k * BQ_SLOTS;
-  if (c[BQ_RN2].x <= c[BQ_TGT2].x) c[BQ_DONE].x = 1.0;
-}
-
 // Fused BiCGStab vector steps over the Krylov vectors of nsys systems, one
 // after the other (system k = element / n2; n2 is a whole number of 256-entry
 // work-groups, so a work-group never spans two systems).
@@ -993,23 +986,22 @@ __global__ __launch_bounds__(256) void k_dot1(const double2 *__restrict__ a, con
   block_pair(ab.x, ab.y, part + (size_t)blockIdx.x * 2);
 }
 
-// partial pairs of (a | b) and (c | d): part[(q * gridDim.x + block) * 2 + re/im]
-__global__ __launch_bounds__(256) void k_dot2(const double2 *__restrict__ a, const double2 *__restrict__ b,
-                                              const double2 *__restrict__ c, const double2 *__restrict__ d, size_t n,
+// partial pairs of (a | b) and (a | a): part[(q * gridDim.x + block) * 2 + re/im]
+__global__ __launch_bounds__(256) void k_dot2(const double2 *__restrict__ a, const double2 *__restrict__ b, size_t n,
                                               double *__restrict__ part) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double2 ab = make_double2(0.0, 0.0), cd = ab;
+  double2 ab = make_double2(0.0, 0.0), aa = ab;
   if (i < n) {
-    const double2 av = a[i], bv = b[i], cv = c[i], dv = d[i];
+    const double2 av = a[i], bv = b[i];
     ab = make_double2(av.x * bv.x + av.y * bv.y, av.x * bv.y - av.y * bv.x);
-    cd = make_double2(cv.x * dv.x + cv.y * dv.y, cv.x * dv.y - cv.y * dv.x);
+    aa = make_double2(av.x * av.x + av.y * av.y, av.x * av.y - av.y * av.x);
   }
   block_pair(ab.x, ab.y, part + (size_t)blockIdx.x * 2);
   __syncthreads();
-  block_pair(cd.x, cd.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
+  block_pair(aa.x, aa.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
 }
 
-// R = S - omega T, with the partial pairs of (RT | R) and (R | R) as k_dot2
+// R = S - omega T, with the partial pairs of (RT | R) and (R | R), laid out as k_dot2's
 __global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ coef, const double2 *__restrict__ S,
                                               const double2 *__restrict__ T, const double2 *__restrict__ RT,
                                               double2 *__restrict__ R, size_t n2, size_t n, double *__restrict__ part) {
@@ -1692,7 +1684,7 @@ qiral_status flex_set_coef(const Flex &f, const std::vector<double2> &c, hipStre
 // Inputs: b (full) into BF, x into XF (guess or 0), and the system's right-hand
 // side into rhs (b itself, or b_hat = b_o + kappa H_oe A^-1 b_e) and its x.
 qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_canon, bool guess, double2 *rhs,
-                        double2 *X, double &bnorm, hipStream_t s) {
+                        double2 *X, double &bnorm, hipStream_t s, int bn2_slot = -1, bool fold = true) {
   const qiral_lattice *lat = f.lat;
   const Geo &g = lat->geo;
   import_field(g, b_canon, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
@@ -1703,7 +1695,7 @@ qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_ca
   // field whose padding they can reach starts at zero (the Krylov vectors are
   // cleared by the solvers).
   QIRAL_HIP(hipMemsetAsync(f.RF, 0, 2 * f.hb64, s));
-  if (f.nn) QIRAL_HIP(nn_fold(f.nn, s));   // the network's folded weights for this solve
+  if (f.nn && fold) QIRAL_HIP(nn_fold(f.nn, s));   // the network's folded weights for this solve
   const char *be = (const char *)f.BF, *bo = be + f.hb64;
   if (!f.schur) {
     QIRAL_HIP(hipMemcpyAsync(rhs, f.BF, 2 * f.hb64, hipMemcpyDeviceToDevice, s));
@@ -1716,7 +1708,9 @@ qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_ca
   }
   QIRAL_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_norm, dim3(nblk(2 * f.hb64 / 16)), dim3(256), 0, s, f.BF, 2 * f.hb64 / 16, f.npart);
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(2 * f.hb64 / 16), f.nrm, (const double *)nullptr);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(2 * f.hb64 / 16),
+                     bn2_slot >= 0 ? (double *)(f.coef + bn2_slot) : f.nrm, (const double *)nullptr);
+  if (bn2_slot >= 0) return QIRAL_OK;   // ||b||^2 left in coef[bn2_slot].x
   double b2 = 0;
   qiral_status st = flex_read(&b2, f.nrm, sizeof b2, s);
   bnorm = std::sqrt(b2);
@@ -1724,7 +1718,8 @@ qiral_status flex_begin(const Flex &f, const double *x_canon, const double *b_ca
 }
 
 // x (full) from the system's solution X, its FP64 true residual ||b - D x||, export.
-qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &rn, hipStream_t s) {
+qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &rn, hipStream_t s,
+                      int rn2_slot = -1) {
   const qiral_lattice *lat = f.lat;
   const Geo &g = lat->geo;
   if (!f.schur) {
@@ -1739,7 +1734,13 @@ qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &
   const size_t nf = 2 * f.hb64 / 16;
   hipLaunchKernelGGL(k_bminus, dim3(nblk(nf)), dim3(256), 0, s, f.BF, f.RF, nf);
   hipLaunchKernelGGL(k_norm, dim3(nblk(nf)), dim3(256), 0, s, f.RF, nf, f.npart);
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(nf), f.nrm, (const double *)nullptr);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, f.npart, nblk(nf),
+                     rn2_slot >= 0 ? (double *)(f.coef + rn2_slot) : f.nrm, (const double *)nullptr);
+  if (rn2_slot >= 0) {   // ||b - D x||^2 left in coef[rn2_slot].x; the caller reads it later
+    export_field(g, x_canon, f.XF, QIRAL_FULL, QIRAL_F64, 1, s);
+    QIRAL_HIP(hipGetLastError());
+    return QIRAL_OK;
+  }
   double r2 = 0;
   qiral_status st = flex_read(&r2, f.nrm, sizeof r2, s);
   rn = std::sqrt(r2);
@@ -1751,12 +1752,16 @@ qiral_status flex_end(const Flex &f, const double2 *X, double *x_canon, double &
 
 // R = rhs - A X (rhs itself when X is known to be zero); returns ||R||
 qiral_status flex_residual(const Flex &f, const double2 *rhs, const double2 *X, double2 *R, double &rn,
-                           hipStream_t s, bool xzero = false) {
+                           hipStream_t s, bool xzero = false, int rn2_slot = -1) {
   if (xzero) {
     QIRAL_HIP(hipMemcpyAsync(R, rhs, f.vb, hipMemcpyDeviceToDevice, s));
   } else {
     QIRAL_HIP(flex_A(f, R, X, false, s));
     hipLaunchKernelGGL(k_bminus, dim3(f.nbk), dim3(256), 0, s, rhs, R, f.n2);
+  }
+  if (rn2_slot >= 0) {   // ||R||^2 left in coef[rn2_slot].x
+    flex_norm2_dev(f, R, rn2_slot, s);
+    return QIRAL_OK;
   }
   double r2 = 0;
   qiral_status st = flex_norm2(f, R, r2, s);
@@ -2021,14 +2026,23 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   std::vector<long long> hops(nsys, 0);
   std::vector<char> active(nsys, 1), broke(nsys, 0);
   const std::vector<double2> one(nsys, make_double2(1.0, 0.0)), zero(nsys, make_double2(0.0, 0.0));
+  // every system's source, x and residual, with ||b||^2 and ||r||^2 left in
+  // its coefficient slots: one host read for all of them
   for (int k = 0; k < nsys; ++k) {
     const Flex fk = f.sys_view(k);
     if ((st = flex_begin(fk, x_canon + k * stride, b_canon + k * stride, prm->x0_is_guess != 0, f.slot(B, k),
-                         f.slot(X, k), bn[k], s)) != QIRAL_OK)
+                         f.slot(X, k), bn[k], s, BQ_BN2, k == 0)) != QIRAL_OK)
       return st;
+    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s, !prm->x0_is_guess, BQ_RN2)) !=
+        QIRAL_OK)
+      return st;
+  }
+  std::vector<double2> hc((size_t)nsys * BQ_SLOTS);
+  if ((st = flex_read(hc.data(), f.coef, sizeof(double2) * hc.size(), s)) != QIRAL_OK) return st;
+  for (int k = 0; k < nsys; ++k) {
+    bn[k] = std::sqrt(hc[(size_t)k * BQ_SLOTS + BQ_BN2].x);
+    rn[k] = std::sqrt(hc[(size_t)k * BQ_SLOTS + BQ_RN2].x);
     target[k] = prm->tol * bn[k];
-    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s, !prm->x0_is_guess)) != QIRAL_OK)
-      return st;
     hops[k] = prm->x0_is_guess ? flex_hops(f) : 0;
     active[k] = rn[k] > target[k] && prm->maxiter > 0;
     QIRAL_HIP(hipMemcpyAsync(f.coef + (size_t)k * BQ_SLOTS + BQ_DONE, active[k] ? &zero[k] : &one[k], sizeof(double2),
@@ -2058,7 +2072,6 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
     hipLaunchKernelGGL(k_pair_final, dim3(1, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RHO1,
                        (int)BQ_RHO1);
   }
-  std::vector<double2> hc((size_t)nsys * BQ_SLOTS);
   while (any_active()) {
     hipLaunchKernelGGL(k_bq_beta, gs, bs, 0, s, f.coef, nsys);
     hipLaunchKernelGGL(k_bq_p, gv, bv, 0, s, f.coef, blk(R), blk(V), blk(P), f.n2, ntot);   // p = r + beta (p - omega v)
@@ -2070,7 +2083,7 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
     hipLaunchKernelGGL(k_bq_s, gv, bv, 0, s, f.coef, blk(V), blk(R), blk(S), f.n2, ntot);   // s = r - alpha v
     QIRAL_HIP(flex_M(f, blk(SH), blk(S), false, s, nsys));
     QIRAL_HIP(flex_A(f, blk(T), blk(SH), false, s, nsys));
-    hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, blk(T), blk(S), blk(T), blk(T), ntot, f.part);   // (t|s), ||t||^2
+    hipLaunchKernelGGL(k_dot2, gv, bv, 0, s, blk(T), blk(S), ntot, f.part);   // (t|s), ||t||^2
     hipLaunchKernelGGL(k_pair_final, dim3(2, nsys), dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_TS, (int)BQ_TT);
     hipLaunchKernelGGL(k_bq_omega, gs, bs, 0, s, f.coef, nsys);
     // x += alpha p^ + omega s^; r = s - omega t with (r~|r), the next rho, and ||r||^2
@@ -2113,12 +2126,15 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
       }
     }
   }
-  // every solution out first: a CG fallback below reuses the workspace
+  // every solution out first (a CG fallback below reuses the workspace), with
+  // ||b - D x||^2 in the coefficient slots: one host read for all systems
   for (int k = 0; k < nsys; ++k) {
     import_field(g, b_canon + k * stride, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
-    if ((st = flex_end(f.sys_view(k), f.slot(X, k), x_canon + k * stride, rt[k], s)) != QIRAL_OK) return st;
+    if ((st = flex_end(f.sys_view(k), f.slot(X, k), x_canon + k * stride, rt[k], s, BQ_TR2)) != QIRAL_OK) return st;
     hops[k] += 2;
   }
+  if ((st = flex_read(hc.data(), f.coef, sizeof(double2) * hc.size(), s)) != QIRAL_OK) return st;
+  for (int k = 0; k < nsys; ++k) rt[k] = std::sqrt(hc[(size_t)k * BQ_SLOTS + BQ_TR2].x);
   qiral_status worst = QIRAL_OK;
   for (int k = 0; k < nsys; ++k) {
     st = flex_finish(lat, x_canon + k * stride, b_canon + k * stride, prm, ws, ws_bytes, info + k, it[k], hops[k],
