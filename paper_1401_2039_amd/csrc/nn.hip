@@ -807,6 +807,24 @@ __global__ __launch_bounds__(256) void k_norm(const double2 *__restrict__ w, siz
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// k_norm for nsys vectors of n2 entries each (a whole number of nbk 256-entry
+// blocks), optionally as two halves a and b of one field per system: grid
+// (nsys * nbk, 1 or 2); part[(k * halves + half) * nbk + block], so that system
+// k's partials are those k_norm gives for its field a (then b) alone.
+__global__ __launch_bounds__(256) void k_norm_sys(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                                                  size_t n2, int nbk, double *__restrict__ part) {
+  __shared__ double red[4];
+  const int k = blockIdx.x / nbk, j = blockIdx.x - k * nbk, half = blockIdx.y;
+  const double2 *w = (half ? b : a) + (size_t)k * n2;
+  const size_t i = (size_t)j * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n2) v = w[i].x * w[i].x + w[i].y * w[i].y;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[((size_t)k * gridDim.y + half) * nbk + j] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // v = w / sqrt(nrm2[0])  (zero if the norm is zero)
 __global__ __launch_bounds__(256) void k_scale(const double2 *__restrict__ w, const double *__restrict__ nrm2,
                                                double2 *__restrict__ v, size_t n) {
@@ -832,6 +850,18 @@ enum : int {
   BQ_BN2, BQ_TR2,          // .x: ||b||^2 of the full source, ||b - D x||^2 of the final x
   BQ_SLOTS = 64            // coefficient slots per system: system k's are coef[64 k ..]
 };
+
+// k_sum per system: coef[BQ_SLOTS k + slot].x = the sum of part[n k .. n k + n)
+// in k_sum's order; one work-group per system
+__global__ __launch_bounds__(256) void k_sum_sys(const double *__restrict__ part, int n, double2 *__restrict__ coef,
+                                                 int slot) {
+  __shared__ double red[4];
+  double a = strided_sum(part + (size_t)blockIdx.x * n, n, (int)threadIdx.x);
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) coef[(size_t)blockIdx.x * BQ_SLOTS + slot].x = (red[0] + red[1]) + (red[2] + red[3]);
+}
 // FLAG.x: the iteration broke down before x changed (rho_new or (r~, v) zero):
 // every later coefficient is 0, so x keeps its value and every vector stays
 // finite; FLAG.y: omega = 0, restart after this iteration.
@@ -2028,14 +2058,43 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   const std::vector<double2> one(nsys, make_double2(1.0, 0.0)), zero(nsys, make_double2(0.0, 0.0));
   // every system's source, x and residual, with ||b||^2 and ||r||^2 left in
   // its coefficient slots: one host read for all of them
-  for (int k = 0; k < nsys; ++k) {
-    const Flex fk = f.sys_view(k);
-    if ((st = flex_begin(fk, x_canon + k * stride, b_canon + k * stride, prm->x0_is_guess != 0, f.slot(B, k),
-                         f.slot(X, k), bn[k], s, BQ_BN2, k == 0)) != QIRAL_OK)
-      return st;
-    if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s, !prm->x0_is_guess, BQ_RN2)) !=
-        QIRAL_OK)
-      return st;
+  const bool guess = prm->x0_is_guess != 0;
+  const dim3 gn1((unsigned)(nsys * f.nbk), 1), gn2((unsigned)(nsys * f.nbk), 2), gk((unsigned)nsys);
+  if (f.schur) {
+    // all systems at once, with the same arithmetic as flex_begin and
+    // flex_residual system by system: b_e in PH and b_o in SH for now (p and v
+    // stay zero for the first iteration)
+    if (f.nn) QIRAL_HIP(nn_fold(f.nn, s));
+    import_field(g, b_canon, blk(PH), QIRAL_EVEN, QIRAL_F64, nsys, s);
+    import_field(g, b_canon, blk(SH), QIRAL_ODD, QIRAL_F64, nsys, s);
+    if (guess) import_field(g, x_canon, blk(X), QIRAL_ODD, QIRAL_F64, nsys, s);
+    else QIRAL_HIP(hipMemsetAsync(blk(X), 0, (size_t)nsys * f.vb, s));
+    for (int k = 0; k < nsys; ++k)
+      hipLaunchKernelGGL(k_chi64, dim3(nblk(npad_of(g))), dim3(256), 0, s, g, f.slot(PH, k),
+                         (char *)f.tmpE + (size_t)k * f.hb64, (int)CHI_AINV, 2.0 * lat->kappa * lat->mu);
+    // b^ = b_o + kappa H_oe A_ee^-1 b_e
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 1, 1, lat->kappa, f.tmpE, blk(B), blk(SH), nsys, s, CHI_ONE, CHI_ONE));
+    hipLaunchKernelGGL(k_norm_sys, gn2, dim3(256), 0, s, blk(PH), blk(SH), f.n2, f.nbk, f.part);
+    hipLaunchKernelGGL(k_sum_sys, gk, dim3(256), 0, s, f.part, 2 * f.nbk, f.coef, (int)BQ_BN2);
+    if (guess) {
+      QIRAL_HIP(flex_A(f, blk(R), blk(X), false, s, nsys));
+      hipLaunchKernelGGL(k_bminus, dim3((unsigned)(nsys * f.nbk)), dim3(256), 0, s, blk(B), blk(R),
+                         (size_t)nsys * f.n2);
+    } else {
+      QIRAL_HIP(hipMemcpyAsync(blk(R), blk(B), (size_t)nsys * f.vb, hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_norm_sys, gn1, dim3(256), 0, s, blk(R), (const double2 *)nullptr, f.n2, f.nbk, f.part);
+    hipLaunchKernelGGL(k_sum_sys, gk, dim3(256), 0, s, f.part, f.nbk, f.coef, (int)BQ_RN2);
+    QIRAL_HIP(hipGetLastError());
+  } else {
+    for (int k = 0; k < nsys; ++k) {
+      const Flex fk = f.sys_view(k);
+      if ((st = flex_begin(fk, x_canon + k * stride, b_canon + k * stride, guess, f.slot(B, k), f.slot(X, k), bn[k],
+                           s, BQ_BN2, k == 0)) != QIRAL_OK)
+        return st;
+      if ((st = flex_residual(fk, f.slot(B, k), f.slot(X, k), f.slot(R, k), rn[k], s, !guess, BQ_RN2)) != QIRAL_OK)
+        return st;
+    }
   }
   std::vector<double2> hc((size_t)nsys * BQ_SLOTS);
   if ((st = flex_read(hc.data(), f.coef, sizeof(double2) * hc.size(), s)) != QIRAL_OK) return st;
@@ -2128,10 +2187,32 @@ qiral_status run_bicgstab_prec(qiral_lattice *lat, double *x_canon, const double
   }
   // every solution out first (a CG fallback below reuses the workspace), with
   // ||b - D x||^2 in the coefficient slots: one host read for all systems
-  for (int k = 0; k < nsys; ++k) {
-    import_field(g, b_canon + k * stride, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
-    if ((st = flex_end(f.sys_view(k), f.slot(X, k), x_canon + k * stride, rt[k], s, BQ_TR2)) != QIRAL_OK) return st;
-    hops[k] += 2;
+  if (f.schur) {
+    // all systems at once, with flex_end's arithmetic: b_e in V, b_o in S,
+    // x_e in P, D x in T (even) and PH (odd), then b - D x there
+    const double k1 = lat->kappa;
+    import_field(g, b_canon, blk(V), QIRAL_EVEN, QIRAL_F64, nsys, s);
+    import_field(g, b_canon, blk(S), QIRAL_ODD, QIRAL_F64, nsys, s);
+    // x_e = A_ee^-1 (b_e + kappa H_eo x_o)
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 0, 1, k1, blk(X), blk(P), blk(V), nsys, s, CHI_AINV, CHI_ONE));
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 0, 1, -k1, blk(X), blk(T), blk(P), nsys, s, CHI_ONE, CHI_A));
+    QIRAL_HIP(launch_hop(lat, QIRAL_F64, 0, 1, 1, -k1, blk(P), blk(PH), blk(X), nsys, s, CHI_ONE, CHI_A));
+    const dim3 gb((unsigned)(nsys * f.nbk));
+    hipLaunchKernelGGL(k_bminus, gb, dim3(256), 0, s, blk(V), blk(T), (size_t)nsys * f.n2);
+    hipLaunchKernelGGL(k_bminus, gb, dim3(256), 0, s, blk(S), blk(PH), (size_t)nsys * f.n2);
+    hipLaunchKernelGGL(k_norm_sys, gn2, dim3(256), 0, s, blk(T), blk(PH), f.n2, f.nbk, f.part);
+    hipLaunchKernelGGL(k_sum_sys, gk, dim3(256), 0, s, f.part, 2 * f.nbk, f.coef, (int)BQ_TR2);
+    export_field(g, x_canon, blk(P), QIRAL_EVEN, QIRAL_F64, nsys, s);
+    export_field(g, x_canon, blk(X), QIRAL_ODD, QIRAL_F64, nsys, s);
+    QIRAL_HIP(hipGetLastError());
+    for (int k = 0; k < nsys; ++k) hops[k] += 2;
+  } else {
+    for (int k = 0; k < nsys; ++k) {
+      import_field(g, b_canon + k * stride, f.BF, QIRAL_FULL, QIRAL_F64, 1, s);
+      if ((st = flex_end(f.sys_view(k), f.slot(X, k), x_canon + k * stride, rt[k], s, BQ_TR2)) != QIRAL_OK)
+        return st;
+      hops[k] += 2;
+    }
   }
   if ((st = flex_read(hc.data(), f.coef, sizeof(double2) * hc.size(), s)) != QIRAL_OK) return st;
   for (int k = 0; k < nsys; ++k) rt[k] = std::sqrt(hc[(size_t)k * BQ_SLOTS + BQ_TR2].x);
