@@ -960,6 +960,31 @@ __device__ __forceinline__ void block_pair(double re, double im, double *__restr
     dst[threadIdx.x] = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
+// Two block partial pairs at once, each summed as block_pair sums it, with one
+// barrier: p0 = (re0, im0) to dst0, p1 = (re1, im1) to dst1.
+__device__ __forceinline__ void block_pair2(double re0, double im0, double re1, double im1, double *__restrict__ dst0,
+                                            double *__restrict__ dst1) {
+  __shared__ double red[4][4];
+  re0 = wave_sum(re0);
+  im0 = wave_sum(im0);
+  re1 = wave_sum(re1);
+  im1 = wave_sum(im1);
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    red[0][w] = re0;
+    red[1][w] = im0;
+    red[2][w] = re1;
+    red[3][w] = im1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int t = threadIdx.x;
+    const double v = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+    if (t < 2) dst0[t] = v;
+    else dst1[t - 2] = v;
+  }
+}
+
 __device__ __forceinline__ const double2 *sys_coef(const double2 *coef, size_t i, size_t n2) {
   return coef + (i / n2) * BQ_SLOTS;
 }
@@ -1026,9 +1051,7 @@ __global__ __launch_bounds__(256) void k_dot2(const double2 *__restrict__ a, con
     ab = make_double2(av.x * bv.x + av.y * bv.y, av.x * bv.y - av.y * bv.x);
     aa = make_double2(av.x * av.x + av.y * av.y, av.x * av.y - av.y * av.x);
   }
-  block_pair(ab.x, ab.y, part + (size_t)blockIdx.x * 2);
-  __syncthreads();
-  block_pair(aa.x, aa.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
+  block_pair2(ab.x, ab.y, aa.x, aa.y, part + (size_t)blockIdx.x * 2, part + ((size_t)gridDim.x + blockIdx.x) * 2);
 }
 
 // R = S - omega T, with the partial pairs of (RT | R) and (R | R), laid out as k_dot2's
@@ -1044,9 +1067,7 @@ __global__ __launch_bounds__(256) void k_bq_r(const double2 *__restrict__ coef, 
     tr = make_double2(rt.x * r.x + rt.y * r.y, rt.x * r.y - rt.y * r.x);
     rr = make_double2(r.x * r.x + r.y * r.y, 0.0);
   }
-  block_pair(tr.x, tr.y, part + (size_t)blockIdx.x * 2);
-  __syncthreads();
-  block_pair(rr.x, rr.y, part + ((size_t)gridDim.x + blockIdx.x) * 2);
+  block_pair2(tr.x, tr.y, rr.x, rr.y, part + (size_t)blockIdx.x * 2, part + ((size_t)gridDim.x + blockIdx.x) * 2);
 }
 
 // Sums of partial-pair rows: grid (nrow, nsys), row q of system k (its nbk
