@@ -687,6 +687,16 @@ def suite_c4(q, latgen, torch, path, timed_solve):
     _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "batched12_cgnr_f16s",
            "seconds": round(t, 4), "iterations": [i["iterations"] for i in info],
            "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    # plain FP64 methods batched the same way as the learned form: eo-CGNR, and
+    # BiCGStab on the Schur system, the strongest of them here
+    t, st, info, _ = timed_solve(lat, b, reps=1, tol=1e-10, inner_prec=q.F64)
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "batched12_cgnr_f64",
+           "seconds": round(t, 4), "status": st, "iterations": [i["iterations"] for i in info],
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
+    t, st, info, _ = timed_solve(lat, b, reps=1, tol=1e-10, solver=q.BICGSTAB_EO, inner_prec=q.F64)
+    _emit({"kind": "solve", "workload": "24^3x48 eps0.5 k0.125 12 gaussian", "form": "batched12_bicgstab_f64",
+           "seconds": round(t, 4), "status": st, "iterations": [i["iterations"] for i in info],
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}, path)
     best = min(learned, key=learned.get)
     gain = tseq - learned[best]
     _emit({"kind": "summary", "workload": "24^3x48 eps0.5 k0.125", "training_s": round(t_train, 3),
