@@ -346,8 +346,8 @@ __global__ __launch_bounds__(256) void k_nn_pass_a(Geo g, const void *__restrict
 // Grid: (nb, 2 parities), 256 threads.
 //
 // Each work-group does its site block for nsys systems one after the other
-// (inputs istride bytes apart, path fields msys bytes apart), so the links a
-// block reads for the first system are still in the cache for the others.
+// (inputs istride bytes apart, path fields msys bytes apart); the links it
+// reads for the first system are kept in LDS for the others.
 // Path field p of a system starts at p * mstride and its parity-x half at
 // x * hoff (hoff = 0: each path field holds only the parity it is used on).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
