@@ -248,7 +248,9 @@ typedef struct {
  * the preconditioned or full-system BiCGStab, the flexible solver's FP64 fields
  * (the larger of that and its CGNR fallback): FGMRES and FCG solve the
  * right-hand sides one after the other, BiCGStab all of them in lockstep (its
- * Krylov vectors for each). */
+ * Krylov vectors for each and, on the Schur system with a network and more than
+ * one right-hand side, nine FP32 half-fields of the network's path fields for
+ * each). */
 size_t qiral_solve_workspace_bytes(const qiral_lattice *lat, const qiral_solve_params *params, int32_t nrhs);
 /* The same for qiral_solve_batch over nsys lattices (0 for FGMRES/FCG). */
 size_t qiral_solve_batch_workspace_bytes(const qiral_lattice *const *lats, int32_t nsys,
