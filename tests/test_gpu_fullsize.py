@@ -10,7 +10,10 @@
   FP32/FP64 mixed in one HIP-graph-replayed batch: every system's residual
   under the oracle's D.
 * 24^3x48 with exp(0.5 i H), kappa 0.125: the network trained on 2048 pairs,
-  FGMRES(20) on one of the 12 Gaussian sources, judged by the oracle's D.
+  FGMRES(20) on one of the 12 Gaussian sources, and BiCGStab on the Schur
+  system with it for all 12 sources in lockstep (the learned form the bench
+  times), 3 of them judged by the oracle's D and one equal bit for bit to its
+  solve alone.
 
 Bars: hops as in the small-lattice tests (FP32 2e-6 of the site's largest
 element; F16S the FP16 quantum of the site's scale); solves 1e-10 true
@@ -114,7 +117,7 @@ def test_uneven_batch_32_systems():
         l.close()
 
 
-def test_fgmres_trained_24x48():
+def test_learned_solves_24x48():
     say("24^3x48 eps0.5 k0.125 setup")
     cfg = latgen.make_config(4)
     lat = q.Lattice(cfg["dims"], cfg["kappa"], cfg["U"])
@@ -131,5 +134,21 @@ def test_fgmres_trained_24x48():
     assert st == 0 and info[0]["converged"], info
     res = S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, host(x)[0], cfg["b"][0])
     assert res <= TOL, res
+    say("BiCGStab on the Schur system with the trained network, 12 sources in lockstep")
+    pl = q.solve_params(solver=q.BICGSTAB_EO, system=q.SYSTEM_SCHUR, tol=TOL, maxiter=2000, fallback_cg=0)
+    pl.precond = net.handle
+    b12 = dev(cfg["b"])
+    x12 = torch.zeros_like(b12)
+    st, info = q.qiral_solve(lat.handle, lat.dims, x12, b12, 12, pl)
+    assert st == 0 and all(i["converged"] for i in info), info
+    x1 = torch.zeros_like(b12[5:6])
+    st1, info1 = q.qiral_solve(lat.handle, lat.dims, x1, b12[5:6].contiguous(), 1, pl)
+    assert st1 == 0 and info1[0]["iterations"] == info[5]["iterations"], (info1, info[5])
+    assert torch.equal(x1, x12[5:6])
+    xs = host(x12)
+    for r in (0, 5, 11):
+        res = S.true_rel_residual(cfg["U"], cfg["kappa"], 0.0, xs[r], cfg["b"][r])
+        say("  source", r, "iterations", info[r]["iterations"], "oracle residual", res)
+        assert res <= TOL, (r, res)
     net.close()
     lat.close()
