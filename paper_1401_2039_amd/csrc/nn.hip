@@ -535,46 +535,87 @@ __global__ __launch_bounds__(256) void k_nn_pass_b(Geo g, const void *__restrict
   }
 }
 
-// dL/d conj(W_p^{ij}) = sum_{x,c} g^i(x)[c][r] conj((T_p psi^j)(x)[c][s]); one
-// block row per (p, i, j), WG_CHUNKS site chunks, partials in FP64.
-template <int CIN, int COUT>
+// dL/d conj(W_p^{ij}) = sum_{x,c} g^i(x)[c][r] conj((T_p psi^j)(x)[c][s]).  One
+// block row per path p and chunk of JC inputs j and IC outputs i (the link of
+// p is loaded once per site for the JC transports, each g^i once for the JC
+// inputs), WG_CHUNKS site chunks, partials in FP64 per (p, i, j), each over the
+// same sites in the same order as with one row per pair.
+template <int CIN, int COUT, int JC, int IC>
 __global__ __launch_bounds__(256) void k_ptc_wgrad(Geo g, const void *__restrict__ links, const void *__restrict__ in,
                                                    const void *__restrict__ gout, size_t fstride,
                                                    double *__restrict__ part) {
-  const int combo = blockIdx.y;   // (p * COUT + i) * CIN + j
-  const int j = combo % CIN, i = (combo / CIN) % COUT, p = combo / (CIN * COUT);
+  static_assert(CIN % JC == 0 && COUT % IC == 0, "k_ptc_wgrad: whole chunks");
+  constexpr int NJ = CIN / JC, NI = COUT / IC;
+  const int row = blockIdx.y;   // (p * NI + ib) * NJ + jb
+  const int jb = row % NJ, ib = (row / NJ) % NI, p = row / (NJ * NI);
   const size_t npad = (size_t)g.nb * WAVE, hb = npad * SpinorIO<S_F32>::SITE_BYTES;
   const size_t nsite = 2 * npad;
-  cpx<float> acc[16];
+  cpx<float> acc[IC][JC][16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = cmake(0.f, 0.f);
+  for (int ii = 0; ii < IC; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[ii][jj][k] = cmake(0.f, 0.f);
   for (size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x; gid < nsite; gid += (size_t)gridDim.x * blockDim.x) {
     const int par = (int)(gid / npad), s = (int)(gid % npad);
     if (s >= g.vh) continue;
     const SiteC c = site_c(g, s, par);
-    cpx<float> t[12], gg[12];
-    path_apply(g, links, (const char *)in + j * fstride, hb, npad, c, par, p, t);
-    SpinorIO<S_F32>::load((const char *)gout + i * fstride + par * hb, s, npad, gg);
+    cpx<float> t[JC][12];
+    if (p == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int jj = 0; jj < JC; ++jj)
+        SpinorIO<S_F32>::load((const char *)in + (size_t)(jb * JC + jj) * fstride + par * hb, s, npad, t[jj]);
+    } else {
+      int mu;
+      bool fwd;
+      path_of(p, mu, fwd);
+      const int n = nbr(g, c, mu, fwd);
+      cpx<float> u[9];
+      if (fwd) LinkIO<L_F32R12>::load(links, par, mu, c.s, g.nb, u);
+      else LinkIO<L_F32R12>::load(links, 1 - par, mu, n, g.nb, u);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int jj = 0; jj < JC; ++jj) {
+        cpx<float> psi[12];
+        SpinorIO<S_F32>::load((const char *)in + (size_t)(jb * JC + jj) * fstride + (1 - par) * hb, n, npad, psi);
+        transport(u, psi, t[jj], !fwd);
+      }
+    }
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[4 * r + q] = cjmac(t[4 * a + q], gg[4 * a + r], acc[4 * r + q]);
+    for (int ii = 0; ii < IC; ++ii) {
+      cpx<float> gg[12];
+      SpinorIO<S_F32>::load((const char *)gout + (size_t)(ib * IC + ii) * fstride + par * hb, s, npad, gg);
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              acc[ii][jj][4 * r + q] = cjmac(t[jj][4 * a + q], gg[4 * a + r], acc[ii][jj][4 * r + q]);
+    }
   }
-  // fixed-order block reduction
+  // fixed-order block reduction, one (i, j) pair after the other
   __shared__ double red[32][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    double re = wave_sum((double)acc[k].re), im = wave_sum((double)acc[k].im);
-    if (lane == 0) { red[2 * k][wv] = re; red[2 * k + 1][wv] = im; }
-  }
-  __syncthreads();
-  if (threadIdx.x < 32) {
-    const double v = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
-    part[((size_t)combo * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
-  }
+  for (int ii = 0; ii < IC; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        double re = wave_sum((double)acc[ii][jj][k].re), im = wave_sum((double)acc[ii][jj][k].im);
+        if (lane == 0) { red[2 * k][wv] = re; red[2 * k + 1][wv] = im; }
+      }
+      __syncthreads();
+      if (threadIdx.x < 32) {
+        const int combo = (p * COUT + ib * IC + ii) * CIN + jb * JC + jj;
+        const double v = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+        part[((size_t)combo * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
+      }
+      __syncthreads();   // red is written again for the next pair
+    }
 }
 
 // grad[2 k] = dL/dRe W_k = 2 Re G_k, grad[2 k + 1] = dL/dIm W_k = 2 Im G_k.
@@ -583,6 +624,7 @@ __global__ void k_wgrad_final(const double *__restrict__ part, double *__restric
   if (idx >= ncombo * 32) return;
   const int combo = idx >> 5, k = idx & 31;
   double s = 0.0;
+#pragma unroll 8
   for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)combo * nchunk + ch) * 32 + k];
   grad[(size_t)combo * 32 + k] = 2.0 * s;
 }
@@ -1172,14 +1214,15 @@ hipError_t wgrad_launch(const qiral_nn *nn, int cin, int cout, const void *in, c
   const Geo &g = nn->lat->geo;
   const size_t fs = full_bytes32(g);
   const int ncombo = NPATH * cin * cout;
-  dim3 grid(WG_CHUNKS, ncombo);
+  // rows of 2 (p, i, j) pairs: one transport or one g^i serves both
+  dim3 grid(WG_CHUNKS, ncombo / 2);
   const void *links = nn->lat->g32;
-  if (cin == 1 && cout == 8) hipLaunchKernelGGL((k_ptc_wgrad<1, 8>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
-  else if (cin == 8 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<8, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
-  else if (cin == 1 && cout == 4) hipLaunchKernelGGL((k_ptc_wgrad<1, 4>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
-  else if (cin == 4 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<4, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
-  else if (cin == 1 && cout == 2) hipLaunchKernelGGL((k_ptc_wgrad<1, 2>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
-  else if (cin == 2 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<2, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  if (cin == 1 && cout == 8) hipLaunchKernelGGL((k_ptc_wgrad<1, 8, 1, 2>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 8 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<8, 1, 2, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 1 && cout == 4) hipLaunchKernelGGL((k_ptc_wgrad<1, 4, 1, 2>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 4 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<4, 1, 2, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 1 && cout == 2) hipLaunchKernelGGL((k_ptc_wgrad<1, 2, 1, 2>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
+  else if (cin == 2 && cout == 1) hipLaunchKernelGGL((k_ptc_wgrad<2, 1, 2, 1>), grid, dim3(256), 0, s, g, links, in, gout, fs, nn->part);
   else return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_wgrad_final, dim3((ncombo * 32 + 255) / 256), dim3(256), 0, s, nn->part, grad, ncombo, WG_CHUNKS);
   return hipGetLastError();
