@@ -46,7 +46,7 @@ struct qiral_nn {
 namespace {
 
 constexpr int NPATH = 9;
-constexpr int WG_CHUNKS = 128;   // site chunks of the weight-gradient reduction
+constexpr int WG_CHUNKS = 64;   // site chunks of the weight-gradient reduction
 constexpr int LOSS_CAP = 256;    // training losses kept on the device between copies to the host
 
 qiral_status fail(qiral_status s, const char *m) {
