@@ -1652,8 +1652,8 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
   const size_t onrm = take(sizeof(double) * 2 * 64), ocoef = take(sizeof(double2) * BQ_SLOTS * nsys);
   // systems in lockstep on the Schur system take the network's passes together:
   // nine F32 half-fields of path fields each
-  const bool mall = prm->precond && schur && nsys > 1;
-  const size_t om = mall ? take((size_t)nsys * NPATH * half_bytes(g, QIRAL_F32)) : 0;
+  const bool batched_net = prm->precond && schur && nsys > 1;
+  const size_t om = batched_net ? take((size_t)nsys * NPATH * half_bytes(g, QIRAL_F32)) : 0;
   if (f) {
     f->nsys = nsys;
     f->hb64 = hb64;
@@ -1669,7 +1669,7 @@ size_t flex_bytes(const Geo &g, const qiral_solve_params *prm, bool schur, Flex 
     f->npart = (double *)onpart;
     f->nrm = (double *)onrm;
     f->coef = (double2 *)ocoef;
-    f->mbuf = mall ? (void *)om : nullptr;
+    f->mbuf = batched_net ? (void *)om : nullptr;
   }
   return o;
 }
