@@ -60,7 +60,16 @@ extern "C" {
 struct ihipStream_t;
 typedef struct ihipStream_t *qiral_stream_t; /* same type as hipStream_t */
 
-typedef enum {
+/* The enums below are 32-bit integers.  C++ gets them with that underlying
+ * type, so every int32_t value a caller passes is a value of the enum type and
+ * reaches the entry point's own check (which rejects those out of range). */
+#ifdef __cplusplus
+#define QIRAL_ENUM enum : int32_t
+#else
+#define QIRAL_ENUM enum
+#endif
+
+typedef QIRAL_ENUM {
   QIRAL_OK = 0,
   QIRAL_ERR_INVALID_ARG = 1,   /* null pointer, bad enum, nrhs < 1, ...            */
   QIRAL_ERR_BAD_DIMS = 2,      /* an extent odd or < 2, or the lattice too large    */
@@ -72,10 +81,10 @@ typedef enum {
   QIRAL_ERR_WORKSPACE = 7      /* workspace missing or smaller than its size query  */
 } qiral_status;
 
-typedef enum { QIRAL_F64 = 0, QIRAL_F32 = 1, QIRAL_F16S = 2 } qiral_prec;
-typedef enum { QIRAL_RECON18 = 18, QIRAL_RECON12 = 12 } qiral_recon;
-typedef enum { QIRAL_EVEN = 0, QIRAL_ODD = 1, QIRAL_FULL = 2 } qiral_subset;
-typedef enum {
+typedef QIRAL_ENUM { QIRAL_F64 = 0, QIRAL_F32 = 1, QIRAL_F16S = 2 } qiral_prec;
+typedef QIRAL_ENUM { QIRAL_RECON18 = 18, QIRAL_RECON12 = 12 } qiral_recon;
+typedef QIRAL_ENUM { QIRAL_EVEN = 0, QIRAL_ODD = 1, QIRAL_FULL = 2 } qiral_subset;
+typedef QIRAL_ENUM {
   QIRAL_OP_D = 0,        /* full-lattice D = A - kappa H (A = 1 + 2 i kappa mu g5)  */
   QIRAL_OP_DDAG = 1,     /* D^dagger = A^dagger - kappa H^dagger                    */
   QIRAL_OP_SCHUR = 2,    /* odd-site Schur complement S = A - kappa^2 H_oe A^-1 H_eo */
@@ -83,13 +92,13 @@ typedef enum {
 } qiral_op;
 /* The system a solver runs on (template chain "solver schur" or the solver on D
  * itself, Sec. 2 and Sec. 3.1). */
-typedef enum {
+typedef QIRAL_ENUM {
   QIRAL_SYSTEM_DEFAULT = 0, /* the solver's own: Schur for CGNR / BiCGStab / CRNR, D for FGMRES / FCG */
   QIRAL_SYSTEM_SCHUR = 1,   /* S x_o = b_hat on the odd sites, then x_e = A^-1 (b_e + kappa H_eo x_o) */
   QIRAL_SYSTEM_FULL = 2     /* D x = b on the whole lattice */
 } qiral_system;
 
-typedef enum {
+typedef QIRAL_ENUM {
   QIRAL_CGNR_EO = 0,     /* CGNR (Fig. "CG") on the Schur system ("schur" template) */
   QIRAL_BICGSTAB_EO = 1, /* BiCGStab (van der Vorst 1992) on the Schur system; with
                             precond, BiCGStab with the network as right preconditioner

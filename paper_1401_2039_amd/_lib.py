@@ -11,7 +11,9 @@ import os
 import torch  # noqa: F401  (must precede loading the library: shared HIP runtime)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqiral_hip.so")
+# QIRAL_LIB_PATH: another build of the same sources (the sanitizer build of the
+# host layer that the CPU tests load); by default the in-tree library
+LIB_PATH = os.environ.get("QIRAL_LIB_PATH") or os.path.join(HERE, "libqiral_hip.so")
 
 # enums (include/qiral.h)
 OK, ERR_INVALID_ARG, ERR_BAD_DIMS, ERR_UNSUPPORTED, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_WORKSPACE = range(8)

@@ -49,6 +49,54 @@ def build_library(jobs=None):
     return LIB
 
 
+# The host layer built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (the device code as in the product build): for the CPU tests of the C ABI.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out_dir, jobs=None):
+    """Compile every csrc/*.hip with the host sanitizers into out_dir and link
+    out_dir/libqiral_hip.so; returns its path.  Load it with the runtime of
+    asan_runtime() preloaded and QIRAL_LIB_PATH pointing at it."""
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = sources()
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *[f for f in CFLAGS if f != "-O3"], "-O2", "-g", *SAN_FLAGS, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2) // 2), 8)
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libqiral_hip.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", lib, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    return lib
+
+
+def asan_runtime():
+    """Path of the compiler's shared AddressSanitizer runtime, or None."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    for root in ("/opt/rocm/lib/llvm/lib/clang", "/opt/rocm/llvm/lib/clang"):
+        if os.path.isdir(root):
+            for ver in sorted(os.listdir(root), reverse=True):
+                cand = os.path.join(root, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+                if os.path.exists(cand):
+                    return cand
+    return None
+
+
 def kernel_resources(src):
     """Per-kernel register, scratch and LDS use of one source, as the compiler
     reports it for gfx950 (device-only compile, nothing written)."""
