@@ -121,6 +121,64 @@ def test_training_lowers_loss(setup):
     assert hist[-50:].mean() < hist[:50].mean()
 
 
+def _philox_field(seed, step):
+    lx, ly, lz, lt = DIMS
+    v = np.zeros(W.site_shape(DIMS) + (3, 4), dtype=np.complex128)
+    for t in range(lt):
+        for z in range(lz):
+            for y in range(ly):
+                for x in range(lx):
+                    r = site_normals(((t * lz + z) * ly + y) * lx + x, seed, step).reshape(3, 4, 2)
+                    v[t, z, y, x] = r[..., 0] + 1j * r[..., 1]
+    return v
+
+
+def _reals(ws):
+    """The weights as the interleaved (re, im) reals Adam updates."""
+    c = np.concatenate([np.asarray(w, dtype=np.complex128).ravel() for w in ws])
+    return np.stack([c.real, c.imag], -1).reshape(-1)
+
+
+def test_training_steps_match_oracle_adam(setup):
+    """Two training steps of a fresh network against the oracle: each pair is
+    (D v, v) with v the Philox vector of the step's counter, the loss is the
+    oracle's, and each weight moves by Adam's update (beta1 0.9, beta2 0.999,
+    eps 1e-8, bias-corrected) of the oracle's gradient at the weights the step
+    started from.  Adam's step has magnitude ~lr for every weight whose
+    gradient is not negligible, so a wrong sign, scale, pairing or counter
+    shows up at that size."""
+    cfg, lat, Ur = setup
+    say("nn training steps against the oracle's Adam")
+    kappa, seed, lr = 0.125, 0x5EED1401, 1e-3
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    net = q.Network(lat, 8)
+    w0 = net.get_weights()
+    h1 = net.train(1, lr=lr, seed=seed)
+    w1 = net.get_weights()
+    h2 = net.train(1, lr=lr, seed=seed)   # the second step draws counter 1
+    w2 = net.get_weights()
+    th0, th1, th2 = _reals(w0), _reals(w1), _reals(w2)
+    grads, losses = [], []
+    for step, w in ((0, w0), (1, w1)):
+        v = _philox_field(seed, step)
+        src = W.apply_D(Ur, kappa, 0.0, v)
+        L, G = ptc.loss_and_grad(Ur, [np.asarray(x, dtype=np.complex128) for x in w], src, v)
+        losses.append(L)
+        grads.append(_reals([2 * G[0], 2 * G[1]]))
+    assert abs(h1[0] - losses[0]) < 1e-5 * losses[0], (h1[0], losses[0])
+    assert abs(h2[0] - losses[1]) < 1e-5 * losses[1], (h2[0], losses[1])
+    g0, g1 = grads
+    m1, v1 = (1 - b1) * g0, (1 - b2) * g0 * g0
+    d1 = -lr * (m1 / (1 - b1)) / (np.sqrt(v1 / (1 - b2)) + eps)
+    m2, v2 = b1 * m1 + (1 - b1) * g1, b2 * v1 + (1 - b2) * g1 * g1
+    d2 = -lr * (m2 / (1 - b1 ** 2)) / (np.sqrt(v2 / (1 - b2 ** 2)) + eps)
+    for d_gpu, d_want, g in ((th1 - th0, d1, np.abs(g0)), (th2 - th1, d2, np.minimum(np.abs(g0), np.abs(g1)))):
+        assert np.all(np.isfinite(d_gpu)) and np.abs(d_gpu).max() <= 1.01 * lr * np.sqrt(1 / (1 - b2))
+        big = g > 1e-3 * np.abs(g0).max()
+        assert big.sum() > 100, big.sum()
+        assert np.abs(d_gpu[big] - d_want[big]).max() < 0.05 * lr, np.abs(d_gpu[big] - d_want[big]).max()
+
+
 def test_fgmres_with_network():
     say("fgmres")
     cfg = latgen.make_config(0)
