@@ -73,7 +73,7 @@ typedef QIRAL_ENUM {
   QIRAL_OK = 0,
   QIRAL_ERR_INVALID_ARG = 1,   /* null pointer, bad enum, nrhs < 1, ...            */
   QIRAL_ERR_BAD_DIMS = 2,      /* an extent odd or < 2, or the lattice too large    */
-  QIRAL_ERR_UNSUPPORTED = 3,   /* valid request this build does not implement       */
+  QIRAL_ERR_UNSUPPORTED = 3,   /* valid request the library does not implement      */
   QIRAL_ERR_HIP = 4,           /* a HIP runtime call failed (text in last_error)    */
   QIRAL_ERR_NOT_CONVERGED = 5, /* tolerance not met within maxiter; x and info hold
                                   the last iterate and its residual                */
