@@ -168,6 +168,29 @@ def test_bicgstab_lockstep_from_a_guess(lattice):
         assert S.true_rel_residual(L["U"], L["k"], L["mu"], host(x3)[r], B[r]) <= 1e-10
 
 
+def test_bicgstab_lockstep_many_systems(lattice):
+    """70 right-hand sides in lockstep (more than one 64-thread group of the
+    per-system scalar kernels): systems on either side of that boundary equal
+    their solves alone bit for bit, and every system converges."""
+    import torch
+    L = lattice
+    say("bicgstab lockstep, 70 systems")
+    rng = np.random.default_rng(17)
+    b1 = L["b"][0]
+    B = rng.standard_normal((70,) + b1.shape) + 1j * rng.standard_normal((70,) + b1.shape)
+    kw = dict(tol=1e-10, solver=q.BICGSTAB_EO, system=q.SYSTEM_SCHUR, precond=L["net"].handle, maxiter=2000,
+              fallback_cg=0)
+    x70, st, info = L["lat"].solve(dev(B), **kw)
+    x70 = x70.clone()
+    assert st == 0 and all(i["converged"] == 1 for i in info), [i for i in info if not i["converged"]][:3]
+    for r in (0, 63, 64, 69):
+        x1, st1, info1 = L["lat"].solve(dev(B[r:r + 1]), **kw)
+        assert st1 == 0 and info1[0]["iterations"] == info[r]["iterations"], (r, info1[0], info[r])
+        assert info1[0]["true_rel_resid"] == info[r]["true_rel_resid"], r
+        assert torch.equal(x70[r:r + 1], x1), r
+    assert S.true_rel_residual(L["U"], L["k"], L["mu"], host(x70)[69], B[69]) <= 1e-10
+
+
 def test_bicgstab_lockstep_larger_lattice():
     """The same on 12^3x16 (216 site blocks): large enough that the per-system
     state sits past the partial sums of a full-field norm."""
